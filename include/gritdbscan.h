@@ -1,0 +1,202 @@
+/*
+ * gritdbscan.h -- exact grid DBSCAN on one AMD MI355X (gfx950).
+ *
+ * The library implements the hot path of GriT-DBSCAN (Huang, Ma, Liu, Liu:
+ * "GriT-DBSCAN: A Spatial Clustering Algorithm for Very Large Databases"):
+ *
+ *   1. grids of side eps/sqrt(d) and their identifiers   (Section 4.1, Eq. (1))
+ *   2. radix sort of the points by identifier, runs of   (Section 4.1, Algorithm 1)
+ *      equal identifiers = the non-empty grids Gs
+ *   3. the grid tree over Gs and, per grid, the query    (Section 4.2, Algorithms 2-3,
+ *      for its non-empty neighbouring grids Nei(g)        Eq. (2))
+ *   4. core points: a grid with at least MinPts points   (Section 3.2 and Section 4.4,
+ *      is all core; other points count eps-neighbours     step 2)
+ *      over Nei(g) with early exit at MinPts
+ *   5. merging core grids: the pruned minimum-distance   (Section 4.3, Algorithms 4-5,
+ *      test FastMerging, union-find over core grids       Theorems 1-2; the union-find
+ *      visited in ascending core-count order              "LDF" variant of Section 5.2)
+ *   6. border / noise assignment                         (Section 3.2, Section 4.4 step 4)
+ *
+ * The result equals DBSCAN as Definitions 1-5 (Section 3.1) define it
+ * (Theorem 4), with canonical labels:
+ *   - a cluster's id is the smallest input index among its core points;
+ *   - a non-core point within eps of some core point joins the cluster of
+ *     its lowest-index core neighbour; every other point is noise (-1).
+ * Core flags and labels are therefore unique and bit-exact.
+ *
+ * Input rules: coordinates are float32 holding integers with |x| <= 2^24;
+ * eps is a positive integer (so eps^2 is exact) with eps <= GD_EPS_MAX;
+ * 1 <= d <= GD_D_MAX; the packed grid identifier (sum over dimensions of
+ * the bit length of the largest identifier) must fit 64 bits.
+ *
+ * Every entry point returns a gd_status.  On failure the outputs are
+ * unspecified and gd_last_error() describes the failure; the context stays
+ * usable.  One context per host thread; calls on one context are serial.
+ */
+#ifndef GRITDBSCAN_H
+#define GRITDBSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GD_D_MAX 8
+#define GD_EPS_MAX 21845 /* 9 * eps^2 < 2^32: squared distances between points
+                            of neighbouring grids fit 32 bits exactly */
+
+typedef enum {
+    GD_OK = 0,
+    GD_EINVAL = -1,       /* bad argument: NULL pointer, n < 0, d out of range,
+                             eps not a positive integer, minpts < 1          */
+    GD_ERANGE = -2,       /* a coordinate is not an integer of magnitude <= 2^24,
+                             eps > GD_EPS_MAX, or identifiers need > 64 bits  */
+    GD_ENOMEM = -3,       /* device workspace could not be allocated (or the
+                             context's workspace limit would be exceeded)     */
+    GD_EDEVICE = -4,      /* a HIP runtime call failed                        */
+    GD_EUNSUPPORTED = -5  /* valid input outside what this build handles     */
+} gd_status;
+
+typedef struct gd_ctx gd_ctx;
+
+/* Counters of the last dbscan() call (filled when stats are enabled, see
+ * gd_set_option(GD_OPT_STATS)); sizes are always filled. */
+typedef struct {
+    int64_t n;                 /* points */
+    int32_t d;
+    int32_t key_bits;          /* bits of the packed grid identifier */
+    int64_t grids;             /* |Gs|: non-empty grids */
+    int64_t neighbor_entries;  /* sum over grids of |Nei(g)| */
+    int64_t core_points;
+    int64_t core_grids;
+    int64_t dense_grids;       /* grids with >= MinPts points (all core) */
+    int64_t max_grid_points;
+    int64_t merge_pairs;       /* core-grid pairs considered by the merge step */
+    int64_t merge_skipped;     /* pairs skipped: already in the same set */
+    int64_t merge_tests;       /* FastMerging calls */
+    int64_t merge_yes;         /* FastMerging calls that answered yes */
+    int64_t merge_iterations;  /* sum of FastMerging iterations (kappa) */
+    int64_t merge_max_iterations;
+    int64_t merge_distances;   /* point-to-point distances evaluated by FastMerging */
+    int64_t core_distances;    /* distances evaluated while marking core points */
+    int64_t border_points;
+    int64_t noise_points;
+    int64_t clusters;
+    int64_t merge_set_points;  /* sum over FastMerging calls of |s_i| + |s_j| */
+} gd_stats;
+
+/* Create a context bound to HIP device `device` (the caller's current device
+ * is not changed permanently).  The caller owns *ctx and frees it with
+ * gd_destroy.  Returns GD_EINVAL for a NULL ctx or a bad device index. */
+int gd_create(gd_ctx **ctx, int device);
+
+/* Release the context and all device memory it holds.  NULL is a no-op. */
+void gd_destroy(gd_ctx *ctx);
+
+/*
+ * dbscan: cluster n points of dimension d (Algorithm 6 with the LDF merge
+ * order of Section 5.2).
+ *
+ *   points      DEVICE pointer, n*d float32, row-major (point i at
+ *               points[i*d .. i*d+d-1]); integer-valued, |x| <= 2^24.
+ *   n           number of points, 0 <= n < 2^31 (n == 0 returns GD_OK).
+ *   d           dimension, 1 <= d <= GD_D_MAX.
+ *   eps         radius; a positive integer <= GD_EPS_MAX.
+ *   minpts      density threshold, >= 1 (|N(p)| counts p itself).
+ *   labels      DEVICE pointer, n int32 out: cluster id (smallest input index
+ *               of the cluster's core points) or -1 for noise.
+ *   core_flags  DEVICE pointer, n uint8 out: 1 core, 0 not core.
+ *   stream      hipStream_t to run on (NULL: the default stream).
+ *
+ * The call is synchronous: it returns after the results are written.  The
+ * caller owns points, labels and core_flags; the context owns its
+ * workspace, which grows on demand and is kept for later calls.
+ */
+int dbscan(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps,
+           int32_t minpts, int32_t *labels, uint8_t *core_flags, void *stream);
+
+/* Options (gd_set_option). */
+typedef enum {
+    GD_OPT_STATS = 1,         /* 1: count merge/core work into gd_stats (slower) */
+    GD_OPT_LDF_ORDER = 2,     /* 1 (default): visit core grids in ascending
+                                 core-count order; 0: grid (identifier) order */
+    GD_OPT_WORKSPACE_LIMIT = 3,/* bytes of device workspace the context may hold;
+                                 0 = unlimited (default)                      */
+    GD_OPT_TIMING = 4         /* 1: record HIP events around every phase on the
+                                 call's stream (see gd_get_phase_times)       */
+} gd_option;
+
+int gd_set_option(gd_ctx *ctx, int option, int64_t value);
+
+/* Copy the counters of the last successful dbscan() call. */
+int gd_get_stats(gd_ctx *ctx, gd_stats *out);
+
+/* Phases of dbscan() timed with GD_OPT_TIMING. */
+#define GD_PHASE_COUNT 14
+
+/* Device time in milliseconds of each phase of the last dbscan() call made
+ * with GD_OPT_TIMING on (HOST array of up to `count` doubles; phases that
+ * did not run read 0).  Each phase is bracketed by HIP events on the call's
+ * stream, so the figure is the GPU time of its kernels. */
+int gd_get_phase_times(gd_ctx *ctx, double *ms, int32_t count);
+
+/* Name of phase i (0 <= i < GD_PHASE_COUNT), or NULL. */
+const char *gd_phase_name(int32_t i);
+
+/*
+ * Intermediate results of the last successful dbscan() call on this
+ * context, for checking each step on its own.  HOST output pointers; any may
+ * be NULL.  They stay valid until the next dbscan() call.
+ *
+ * gd_debug_grids (Section 4.1, Algorithm 1):
+ *   *n_grids        number of non-empty grids |Gs|
+ *   sorted_index    n: input index of the i-th point in sorted order (points
+ *                   sorted by grid identifier, ascending input index within a
+ *                   grid: the radix sort is stable)
+ *   grid_start      |Gs|+1: first sorted position of each grid
+ *   grid_ids        |Gs| x d row-major: identifiers of Eq. (1), grids in
+ *                   lexicographic order
+ * gd_debug_neighbors (Section 4.2.2, Algorithm 3):
+ *   offsets         |Gs|+1 (uint64): Nei(g) of grid g is
+ *   neighbors       neighbors[offsets[g] .. offsets[g+1]) (grid indices),
+ *                   ordered by the offset of Eq. (2), g itself excluded
+ * gd_debug_core: core_flags_sorted (n, sorted order), grid_label (|Gs|:
+ *   cluster id of a core grid, -1 otherwise).
+ */
+int gd_debug_grids(gd_ctx *ctx, int64_t *n_grids, uint32_t *sorted_index, uint32_t *grid_start,
+                   int32_t *grid_ids);
+int gd_debug_neighbors(gd_ctx *ctx, uint64_t *offsets, uint32_t *neighbors);
+int gd_debug_core(gd_ctx *ctx, uint8_t *core_flags_sorted, int32_t *grid_label);
+
+/*
+ * gd_merge_test: FastMerging (Algorithm 5 with Pruning, Algorithm 4) on
+ * caller-given point sets, one answer per pair: 1 iff MinDist(A, B) <= eps
+ * (Theorem 2).
+ *   points      DEVICE, d x m int32 structure-of-arrays (coordinate k of point
+ *               i at points[k*m + i]).
+ *   pairs       DEVICE, npairs x 4 uint32: a_begin, a_count, b_begin, b_count
+ *               (two runs of points; counts >= 1).
+ *   answers     DEVICE out, npairs uint8.
+ *   iterations  DEVICE out, npairs uint32 (FastMerging iterations), or NULL.
+ * The caller guarantees what holds for core sets of neighbouring grids:
+ * every coordinate difference between the two sets, and within a set, is
+ * below 2^24 in magnitude and every squared distance is below 2^32.
+ * Counts must not exceed 262144.  Synchronous on `stream`.
+ */
+int gd_merge_test(gd_ctx *ctx, const int32_t *points, int64_t m, int32_t d, double eps, const uint32_t *pairs,
+                  int64_t npairs, uint8_t *answers, uint32_t *iterations, void *stream);
+
+/* Text of the last error on this context ("" if none).  The pointer stays
+ * valid until the next call on the context. */
+const char *gd_last_error(gd_ctx *ctx);
+
+/* Name of a status code. */
+const char *gd_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRITDBSCAN_H */

@@ -119,6 +119,7 @@ typedef struct {
     int64_t *order;   /* n: point indices grouped by cell, ascending index within a cell */
     int64_t *cell_of; /* n: cell of each point */
     int32_t *pc;      /* n x d: cell coordinates of each point */
+    int32_t *xs;      /* n x d: coordinates in `order` (cell-grouped) order */
 } ecells;
 
 static const ecells *g_sort_ctx; /* qsort has no context argument */
@@ -134,7 +135,7 @@ static int cmp_point_cell(const void *a, const void *b) {
 }
 
 static void free_cells(ecells *c) {
-    free(c->cc); free(c->start); free(c->order); free(c->cell_of); free(c->pc);
+    free(c->cc); free(c->start); free(c->order); free(c->cell_of); free(c->pc); free(c->xs);
     memset(c, 0, sizeof(*c));
 }
 
@@ -148,7 +149,8 @@ static int build_cells(const int32_t *X, int64_t n, int32_t d, int64_t eps, ecel
     c->cell_of = (int64_t *)malloc(sizeof(int64_t) * nn);
     c->start = (int64_t *)malloc(sizeof(int64_t) * (nn + 1));
     c->cc = (int32_t *)malloc(sizeof(int32_t) * nn * d);
-    if (!c->pc || !c->order || !c->cell_of || !c->start || !c->cc) { free_cells(c); return ORACLE_ENOMEM; }
+    c->xs = (int32_t *)malloc(sizeof(int32_t) * nn * d);
+    if (!c->pc || !c->order || !c->cell_of || !c->start || !c->cc || !c->xs) { free_cells(c); return ORACLE_ENOMEM; }
     int32_t mn[16];
     for (int j = 0; j < d; ++j) mn[j] = n > 0 ? X[j] : 0;
     for (int64_t i = 0; i < n; ++i)
@@ -170,6 +172,7 @@ static int build_cells(const int32_t *X, int64_t n, int32_t d, int64_t eps, ecel
             c->start[ncell++] = r;
         }
         c->cell_of[i] = ncell - 1;
+        memcpy(c->xs + r * d, X + i * d, sizeof(int32_t) * d);
     }
     c->start[ncell] = n;
     c->ncell = ncell;
@@ -265,7 +268,7 @@ int oracle_dbscan(const int32_t *X, int64_t n, int32_t d, int64_t eps, int64_t m
                 int64_t cnt = 0;
                 for (int64_t a = 0; a < na && cnt < minpts; ++a)
                     for (int64_t s = c.start[adj[a]]; s < c.start[adj[a] + 1]; ++s)
-                        if (sqdist(X + p * d, X + c.order[s] * d, d) <= T) ++cnt;
+                        cnt += sqdist(c.xs + r * d, c.xs + s * d, d) <= T;
                 core[p] = (uint8_t)(cnt >= minpts);
                 par[p] = p;
             }
@@ -286,12 +289,15 @@ int oracle_dbscan(const int32_t *X, int64_t n, int32_t d, int64_t eps, int64_t m
             for (int64_t r = c.start[ci]; r < c.start[ci + 1]; ++r) {
                 int64_t p = c.order[r];
                 if (!core[p]) continue;
-                for (int64_t a = 0; a < na; ++a)
+                for (int64_t a = 0; a < na; ++a) {
+                    if (adj[a] < ci) continue; /* each pair of cells once */
                     for (int64_t s = c.start[adj[a]]; s < c.start[adj[a] + 1]; ++s) {
+                        if (s <= r) continue;  /* each pair of points once */
                         int64_t q = c.order[s];
-                        if (q > p && core[q] && sqdist(X + p * d, X + q * d, d) <= T)
+                        if (core[q] && sqdist(c.xs + r * d, c.xs + s * d, d) <= T)
                             uf_unite(par, p, q);
                     }
+                }
             }
         }
         free(adj);
@@ -316,7 +322,7 @@ int oracle_dbscan(const int32_t *X, int64_t n, int32_t d, int64_t eps, int64_t m
                 for (int64_t a = 0; a < na; ++a)
                     for (int64_t s = c.start[adj[a]]; s < c.start[adj[a] + 1]; ++s) {
                         int64_t q = c.order[s];
-                        if (core[q] && (best < 0 || q < best) && sqdist(X + p * d, X + q * d, d) <= T)
+                        if (core[q] && (best < 0 || q < best) && sqdist(c.xs + r * d, c.xs + s * d, d) <= T)
                             best = q;
                     }
                 labels[p] = best < 0 ? -1 : (int32_t)uf_find(par, best);

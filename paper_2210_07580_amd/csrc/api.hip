@@ -1,0 +1,623 @@
+// C ABI of the library (include/gritdbscan.h): argument checks, workspace,
+// and the launch sequence of Algorithm 6 with the LDF merge order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gritdbscan.h"
+#include "launch.hpp"
+#include "radix.hpp"
+#include "scan.hpp"
+
+using namespace gd;
+
+namespace {
+
+// Small results the host reads back between phases.
+struct Info {
+    int mn[kMaxD];
+    int mx[kMaxD];
+    uint32_t err;
+    uint32_t ncell;
+    uint32_t level_count[kMaxD];
+    uint32_t counts[4];  // ncore, core grids, max core points per grid, dense grids
+    uint64_t nei_total;
+    MergeStats merge;
+    unsigned long long core_dist;
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+class Status {
+   public:
+    int code = GD_OK;
+};
+
+enum Phase {
+    P_MINMAX, P_KEYS, P_SORT, P_GATHER, P_CELLS, P_TREE, P_NEI_COUNT, P_NEI_FILL,
+    P_CORE_MARK, P_CORE_COMPACT, P_LDF, P_MERGE, P_LABELS, P_OUTPUT, P_COUNT
+};
+static_assert(P_COUNT == GD_PHASE_COUNT, "phase table");
+const char* const kPhaseNames[P_COUNT] = {
+    "minmax", "keys", "radix_sort", "gather", "cells", "grid_tree", "nei_count", "nei_fill",
+    "core_mark", "core_compact", "ldf_order", "merge", "labels", "output"};
+
+}  // namespace
+
+struct gd_ctx {
+    int device = 0;
+    std::string err;
+    DevBuf arena;      // everything sized by n and d
+    DevBuf nei;        // the neighbour lists, sized by their total
+    Info* info_dev = nullptr;
+    Info* info_host = nullptr;
+    int64_t ws_limit = 0;
+    bool stats = false;
+    bool ldf = true;
+    gd_stats last{};
+    // what the last successful call left in the workspace (for gd_debug_*)
+    bool have_last = false;
+    int64_t last_n = 0, last_ncell = 0;
+    int last_d = 0;
+    uint64_t last_nei_total = 0;
+    const uint32_t* last_sidx = nullptr;
+    const uint32_t* last_cell_start = nullptr;
+    const int32_t* last_ck = nullptr;
+    const uint64_t* last_nei_off = nullptr;
+    const uint32_t* last_nei = nullptr;
+    const uint8_t* last_core = nullptr;
+    const int32_t* last_cell_label = nullptr;
+    // phase timing
+    bool timing = false;
+    bool events_ok = false;
+    hipEvent_t ev[P_COUNT][2] = {};
+    bool ran[P_COUNT] = {};
+    double phase_ms[P_COUNT] = {};
+    hipStream_t st = nullptr;
+
+    void mark(int phase, int which) {
+        if (!timing || !events_ok) return;
+        if (hipEventRecord(ev[phase][which], st) == hipSuccess && which == 1) ran[phase] = true;
+    }
+
+    int fail(int code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+#define GD_TRY(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return ctx->fail(GD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Bump allocator over one device buffer.
+struct Carve {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(int64_t count) {
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += align_up((size_t)std::max<int64_t>(count, 1) * sizeof(T));
+        return p;
+    }
+};
+
+int grow(gd_ctx* ctx, DevBuf& b, size_t need, size_t other_held) {
+    if (need <= b.cap) return GD_OK;
+    if (ctx->ws_limit > 0 && (int64_t)(need + other_held) > ctx->ws_limit)
+        return ctx->fail(GD_ENOMEM, "workspace of %zu bytes exceeds the context limit of %lld bytes", need + other_held,
+                         (long long)ctx->ws_limit);
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t sz = need + need / 8;  // some headroom for the next call
+    if (hipMalloc(&b.p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return ctx->fail(GD_ENOMEM, "hipMalloc of %zu bytes failed", sz);
+    }
+    b.cap = sz;
+    return GD_OK;
+}
+
+int bit_length(uint64_t v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
+
+uint64_t isqrt_u64(uint64_t y) {
+    uint64_t r = (uint64_t)std::sqrt((double)y);
+    while (r * r > y) --r;
+    while ((r + 1) * (r + 1) <= y) ++r;
+    return r;
+}
+
+// Workspace layout; with base == nullptr it only measures.
+struct Layout {
+    uint32_t* vals_a;
+    uint32_t* vals_b;
+    void* keys_a;
+    void* keys_b;
+    uint32_t* radix_scratch;
+    uint64_t* partial;
+    int32_t* crd;
+    uint32_t* excl;
+    uint32_t* cell_start;
+    int32_t* ck;
+    uint32_t* level_excl;
+    int32_t* tkey[kMaxD];
+    uint32_t* tchild[kMaxD];
+    uint32_t* off_counts;
+    uint64_t* nei_off;
+    uint8_t* core;
+    uint32_t* core_excl;
+    uint32_t* core_start;
+    int32_t* ccrd;
+    uint32_t* corig;
+    uint32_t* cell_min_core;
+    uint32_t* list;
+    uint32_t* rank;
+    uint32_t* parent;
+    uint32_t* root_min;
+    int32_t* cell_label;
+    size_t bytes;
+};
+
+Layout carve(char* base, int64_t n, int d) {
+    Layout L{};
+    Carve c{base};
+    L.keys_a = c.take<uint64_t>(n);
+    L.keys_b = c.take<uint64_t>(n);
+    L.vals_a = c.take<uint32_t>(n);
+    L.vals_b = c.take<uint32_t>(n);
+    const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)kRadixBins * radix_tiles(n));
+    L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
+    L.partial = c.take<uint64_t>(scan_blocks(big_scan) + 4);
+    L.crd = c.take<int32_t>((int64_t)d * n);
+    L.excl = c.take<uint32_t>(n + 1);
+    L.cell_start = c.take<uint32_t>(n + 1);
+    L.ck = c.take<int32_t>((int64_t)d * n);
+    L.level_excl = c.take<uint32_t>((int64_t)std::max(d - 1, 1) * (n + 1));
+    for (int l = 0; l + 1 < d; ++l) {
+        L.tkey[l] = c.take<int32_t>(n);
+        L.tchild[l] = c.take<uint32_t>(n + 1);
+    }
+    L.off_counts = c.take<uint32_t>((int64_t)d * n);
+    L.nei_off = c.take<uint64_t>(n + 1);
+    L.core = c.take<uint8_t>(n);
+    L.core_excl = c.take<uint32_t>(n + 1);
+    L.core_start = c.take<uint32_t>(n + 1);
+    L.ccrd = c.take<int32_t>((int64_t)d * n);
+    L.corig = c.take<uint32_t>(n);
+    L.cell_min_core = c.take<uint32_t>(n);
+    L.list = c.take<uint32_t>(n);
+    L.rank = c.take<uint32_t>(n);
+    L.parent = c.take<uint32_t>(n);
+    L.root_min = c.take<uint32_t>(n);
+    L.cell_label = c.take<int32_t>(n);
+    L.bytes = c.off;
+    return L;
+}
+
+template <typename K>
+int run_partition(gd_ctx* ctx, const float* x, int64_t n, const KeyParams& kp, int key_bits, Layout& L,
+                  const uint32_t** sidx_out, hipStream_t st) {
+    K* ka = (K*)L.keys_a;
+    K* kb = (K*)L.keys_b;
+    ctx->mark(P_KEYS, 0);
+    GD_TRY(launch_keys<K>(x, n, kp, ka, st));
+    ctx->mark(P_KEYS, 1);
+    RadixResult<K> res;
+    ctx->mark(P_SORT, 0);
+    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, n, key_bits, true, L.radix_scratch, st, &res));
+    ctx->mark(P_SORT, 1);
+    ctx->mark(P_GATHER, 0);
+    GD_TRY(launch_gather(x, n, kp, res.vals, L.crd, st));
+    ctx->mark(P_GATHER, 1);
+    ctx->mark(P_CELLS, 0);
+    GD_TRY(launch_cells<K>(res.keys, n, kp, L.excl, (uint32_t*)L.partial, &ctx->info_dev->ncell, L.cell_start,
+                           (uint32_t*)nullptr, L.ck, n, st));
+    ctx->mark(P_CELLS, 1);
+    *sidx_out = res.vals;
+    return GD_OK;
+}
+
+int readback(gd_ctx* ctx, hipStream_t st) {
+    GD_TRY(hipMemcpyAsync(ctx->info_host, ctx->info_dev, sizeof(Info), hipMemcpyDeviceToHost, st));
+    GD_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+}
+
+int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps_d, int32_t minpts, int32_t* labels,
+               uint8_t* core_flags, hipStream_t st) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) return ctx->fail(GD_EINVAL, "n = %lld out of range [0, 2^31)", (long long)n);
+    if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "d = %d out of range [1, %d]", d, GD_D_MAX);
+    if (!(eps_d > 0) || !std::isfinite(eps_d) || eps_d != std::floor(eps_d))
+        return ctx->fail(GD_EINVAL, "eps = %g must be a positive integer", eps_d);
+    if (eps_d > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "eps = %g exceeds %d", eps_d, GD_EPS_MAX);
+    if (minpts < 1) return ctx->fail(GD_EINVAL, "minpts = %d must be >= 1", minpts);
+    if (n > 0 && (!points || !labels || !core_flags)) return ctx->fail(GD_EINVAL, "NULL device pointer");
+    const int64_t eps = (int64_t)eps_d;
+    ctx->have_last = false;
+    std::memset(&ctx->last, 0, sizeof(ctx->last));
+    ctx->last.n = n;
+    ctx->last.d = d;
+    if (n == 0) return GD_OK;
+
+    // ---- workspace
+    Layout L = carve(nullptr, n, d);
+    int rc = grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
+    if (rc) return rc;
+    L = carve((char*)ctx->arena.p, n, d);
+    Info* I = ctx->info_dev;
+    Info* H = ctx->info_host;
+
+    // ---- mn_j and the input check (Eq. (1))
+    ctx->st = st;
+    for (int p = 0; p < P_COUNT; ++p) {
+        ctx->ran[p] = false;
+        ctx->phase_ms[p] = 0.0;
+    }
+    ctx->mark(P_MINMAX, 0);
+    GD_TRY(launch_minmax(points, n, d, I->mn, I->mx, &I->err, st));
+    ctx->mark(P_MINMAX, 1);
+    GD_TRY(fill<unsigned long long>(&I->merge.pairs, sizeof(MergeStats) / sizeof(unsigned long long), 0ull, st));
+    GD_TRY(fill<unsigned long long>(&I->core_dist, 1, 0ull, st));
+    if ((rc = readback(ctx, st))) return rc;
+    if (H->err & kErrNotInteger)
+        return ctx->fail(GD_ERANGE, "a coordinate is not a finite integer of magnitude <= 2^24");
+    KeyParams kp{};
+    kp.d = d;
+    kp.eps = eps;
+    int key_bits = 0;
+    for (int j = 0; j < d; ++j) {
+        kp.mn[j] = H->mn[j];
+        const uint64_t u = (uint64_t)((int64_t)H->mx[j] - H->mn[j]);
+        const uint64_t kmax = isqrt_u64((uint64_t)d * u * u) / (uint64_t)eps;
+        kp.bits[j] = bit_length(kmax);
+        key_bits += kp.bits[j];
+    }
+    if (key_bits > 64)
+        return ctx->fail(GD_ERANGE, "grid identifiers need %d bits (> 64): eps too small for the data's extent",
+                         key_bits);
+    for (int j = d - 1, s = 0; j >= 0; --j) {
+        kp.shift[j] = s;
+        s += kp.bits[j];
+    }
+    ctx->last.key_bits = key_bits;
+
+    // ---- Algorithm 1: identifiers, radix sort, grids
+    const uint32_t* sidx = nullptr;
+    if (key_bits <= 32)
+        rc = run_partition<uint32_t>(ctx, points, n, kp, key_bits, L, &sidx, st);
+    else
+        rc = run_partition<uint64_t>(ctx, points, n, kp, key_bits, L, &sidx, st);
+    if (rc) return rc;
+    if ((rc = readback(ctx, st))) return rc;
+    const int64_t ncell = H->ncell;
+
+    GridView g{};
+    g.n = n;
+    g.d = d;
+    g.T = eps * eps;
+    g.minpts = minpts;
+    g.crd = L.crd;
+    g.sidx = sidx;
+    g.ncell = ncell;
+    g.cell_start = L.cell_start;
+    g.ck = L.ck;
+    g.ck_stride = n;
+
+    // ---- Algorithm 2 (grid tree) and Algorithm 3 (Nei for every grid)
+    ctx->mark(P_TREE, 0);
+    GD_TRY(launch_tree(g, kp, L.level_excl, (uint32_t*)L.partial, I->level_count, L.tkey, L.tchild, st));
+    ctx->mark(P_TREE, 1);
+    TreeView t{};
+    for (int l = 0; l + 1 < d; ++l) {
+        t.key[l] = L.tkey[l];
+        t.child[l] = L.tchild[l];
+    }
+    t.key[d - 1] = L.ck + (int64_t)(d - 1) * n;
+    t.level_count = I->level_count;
+    ctx->mark(P_NEI_COUNT, 0);
+    GD_TRY(launch_nei_count(g, t, L.off_counts, st));
+    GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
+    ctx->mark(P_NEI_COUNT, 1);
+    GD_TRY(hipMemcpyAsync(&I->nei_total, L.nei_off + ncell, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    if ((rc = readback(ctx, st))) return rc;
+    const uint64_t nei_total = H->nei_total;
+    if ((rc = grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t), ctx->arena.cap)))
+        return rc;
+    uint32_t* nei = (uint32_t*)ctx->nei.p;
+    ctx->mark(P_NEI_FILL, 0);
+    GD_TRY(launch_nei_fill(g, t, L.off_counts, L.nei_off, nei, st));
+    ctx->mark(P_NEI_FILL, 1);
+
+    // ---- core points
+    ctx->mark(P_CORE_MARK, 0);
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? &I->core_dist : nullptr, st));
+    ctx->mark(P_CORE_MARK, 1);
+    CoreOut co{};
+    co.core = L.core;
+    co.core_excl = L.core_excl;
+    co.core_start = L.core_start;
+    co.ccrd = L.ccrd;
+    co.corig = L.corig;
+    co.cell_min_core = L.cell_min_core;
+    co.counts = I->counts;
+    ctx->mark(P_CORE_COMPACT, 0);
+    GD_TRY(launch_core_compact(g, co, (uint32_t*)L.partial, st));
+    ctx->mark(P_CORE_COMPACT, 1);
+    if ((rc = readback(ctx, st))) return rc;
+    const int64_t ncore = H->counts[0], ncc = H->counts[1], max_core = H->counts[2];
+    if (max_core > kMaxCoreBits)
+        return ctx->fail(GD_EUNSUPPORTED, "a grid holds %lld core points; the merge step handles at most %lld",
+                         (long long)max_core, (long long)kMaxCoreBits);
+
+    // ---- merging (Algorithm 5 + union-find, LDF order)
+    uint32_t* ldf = nullptr;
+    {
+        // the sorted keys are no longer needed: reuse their space
+        uint32_t* ka = (uint32_t*)L.keys_a;
+        uint32_t* kb = ka + n;
+        uint32_t* vb = (sidx == L.vals_a) ? L.vals_b : L.vals_a;
+        ctx->mark(P_LDF, 0);
+        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, bit_length((uint64_t)max_core), L.list, L.rank, ka, kb, vb,
+                                L.radix_scratch, L.excl, (uint32_t*)L.partial, &ldf, st));
+        GD_TRY((iota_kernel<uint32_t><<<dim3(grid_for(ncell)), dim3(kBlock), 0, st>>>(L.parent, ncell),
+                hipGetLastError()));
+        ctx->mark(P_LDF, 1);
+    }
+    ctx->mark(P_MERGE, 0);
+    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, max_core, eps, L.parent,
+                        ctx->stats ? &I->merge : nullptr, &I->err, st));
+    ctx->mark(P_MERGE, 1);
+    ctx->mark(P_LABELS, 0);
+    GD_TRY(launch_labels(g, co, L.parent, L.root_min, L.cell_label, st));
+    ctx->mark(P_LABELS, 1);
+
+    // ---- border / noise, output in input order
+    ctx->mark(P_OUTPUT, 0);
+    GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, labels, core_flags, st));
+    ctx->mark(P_OUTPUT, 1);
+    if ((rc = readback(ctx, st))) return rc;
+    if (ctx->timing && ctx->events_ok) {
+        for (int p = 0; p < P_COUNT; ++p) {
+            float ms = 0.f;
+            if (ctx->ran[p] && hipEventElapsedTime(&ms, ctx->ev[p][0], ctx->ev[p][1]) == hipSuccess)
+                ctx->phase_ms[p] = ms;
+        }
+    }
+    if (H->err & kErrMergeRunaway) return ctx->fail(GD_EDEVICE, "merge step exceeded its iteration bound");
+
+    ctx->have_last = true;
+    ctx->last_n = n;
+    ctx->last_d = d;
+    ctx->last_ncell = ncell;
+    ctx->last_nei_total = nei_total;
+    ctx->last_sidx = sidx;
+    ctx->last_cell_start = L.cell_start;
+    ctx->last_ck = L.ck;
+    ctx->last_nei_off = L.nei_off;
+    ctx->last_nei = nei;
+    ctx->last_core = L.core;
+    ctx->last_cell_label = L.cell_label;
+
+    gd_stats& s = ctx->last;
+    s.grids = ncell;
+    s.neighbor_entries = (int64_t)nei_total;
+    s.core_points = ncore;
+    s.core_grids = ncc;
+    s.dense_grids = H->counts[3];
+    s.max_grid_points = 0;
+    if (ctx->stats) {
+        s.merge_pairs = (int64_t)H->merge.pairs;
+        s.merge_skipped = (int64_t)H->merge.skipped;
+        s.merge_tests = (int64_t)H->merge.tests;
+        s.merge_yes = (int64_t)H->merge.yes;
+        s.merge_iterations = (int64_t)H->merge.iters;
+        s.merge_max_iterations = (int64_t)H->merge.max_iters;
+        s.merge_distances = (int64_t)H->merge.dists;
+        s.core_distances = (int64_t)H->core_dist;
+        s.merge_set_points = (int64_t)H->merge.set_points;
+    }
+    return GD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gd_create(gd_ctx** out, int device) {
+    if (!out) return GD_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GD_EINVAL;
+    gd_ctx* ctx = new gd_ctx();
+    ctx->device = device;
+    DeviceGuard guard(device);
+    if (!guard.ok || hipMalloc(&ctx->info_dev, sizeof(Info)) != hipSuccess ||
+        hipHostMalloc(&ctx->info_host, sizeof(Info), hipHostMallocDefault) != hipSuccess) {
+        if (ctx->info_dev) (void)hipFree(ctx->info_dev);
+        delete ctx;
+        return GD_EDEVICE;
+    }
+    ctx->events_ok = true;
+    for (int p = 0; p < P_COUNT; ++p)
+        for (int k = 0; k < 2; ++k)
+            if (hipEventCreate(&ctx->ev[p][k]) != hipSuccess) ctx->events_ok = false;
+    *out = ctx;
+    return GD_OK;
+}
+
+void gd_destroy(gd_ctx* ctx) {
+    if (!ctx) return;
+    DeviceGuard guard(ctx->device);
+    if (ctx->arena.p) (void)hipFree(ctx->arena.p);
+    if (ctx->nei.p) (void)hipFree(ctx->nei.p);
+    if (ctx->info_dev) (void)hipFree(ctx->info_dev);
+    if (ctx->info_host) (void)hipHostFree(ctx->info_host);
+    for (int p = 0; p < P_COUNT; ++p)
+        for (int k = 0; k < 2; ++k)
+            if (ctx->ev[p][k]) (void)hipEventDestroy(ctx->ev[p][k]);
+    delete ctx;
+}
+
+int dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, int32_t minpts, int32_t* labels,
+           uint8_t* core_flags, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    return run_dbscan(ctx, points, n, d, eps, minpts, labels, core_flags, (hipStream_t)stream);
+}
+
+int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
+    if (!ctx) return GD_EINVAL;
+    switch (option) {
+        case GD_OPT_STATS: ctx->stats = value != 0; return GD_OK;
+        case GD_OPT_LDF_ORDER: ctx->ldf = value != 0; return GD_OK;
+        case GD_OPT_TIMING: ctx->timing = value != 0; return GD_OK;
+        case GD_OPT_WORKSPACE_LIMIT:
+            if (value < 0) return ctx->fail(GD_EINVAL, "workspace limit must be >= 0");
+            ctx->ws_limit = value;
+            return GD_OK;
+        default: return ctx->fail(GD_EINVAL, "unknown option %d", option);
+    }
+}
+
+int gd_get_stats(gd_ctx* ctx, gd_stats* out) {
+    if (!ctx || !out) return GD_EINVAL;
+    *out = ctx->last;
+    return GD_OK;
+}
+
+static int copy_d2h(gd_ctx* ctx, void* dst, const void* src, size_t bytes) {
+    if (!dst || bytes == 0) return GD_OK;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+        return ctx->fail(GD_EDEVICE, "device-to-host copy failed");
+    return GD_OK;
+}
+
+int gd_debug_grids(gd_ctx* ctx, int64_t* n_grids, uint32_t* sorted_index, uint32_t* grid_start, int32_t* grid_ids) {
+    if (!ctx) return GD_EINVAL;
+    if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to inspect");
+    DeviceGuard guard(ctx->device);
+    if (n_grids) *n_grids = ctx->last_ncell;
+    const int64_t n = ctx->last_n, nc = ctx->last_ncell;
+    int rc;
+    if ((rc = copy_d2h(ctx, sorted_index, ctx->last_sidx, sizeof(uint32_t) * n))) return rc;
+    if ((rc = copy_d2h(ctx, grid_start, ctx->last_cell_start, sizeof(uint32_t) * (nc + 1)))) return rc;
+    if (grid_ids) {
+        std::vector<int32_t> col(nc);
+        for (int j = 0; j < ctx->last_d; ++j) {
+            if ((rc = copy_d2h(ctx, col.data(), ctx->last_ck + (int64_t)j * n, sizeof(int32_t) * nc))) return rc;
+            for (int64_t c = 0; c < nc; ++c) grid_ids[c * ctx->last_d + j] = col[c];
+        }
+    }
+    return GD_OK;
+}
+
+int gd_debug_neighbors(gd_ctx* ctx, uint64_t* offsets, uint32_t* neighbors) {
+    if (!ctx) return GD_EINVAL;
+    if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to inspect");
+    DeviceGuard guard(ctx->device);
+    int rc;
+    if ((rc = copy_d2h(ctx, offsets, ctx->last_nei_off, sizeof(uint64_t) * (ctx->last_ncell + 1)))) return rc;
+    return copy_d2h(ctx, neighbors, ctx->last_nei, sizeof(uint32_t) * ctx->last_nei_total);
+}
+
+int gd_debug_core(gd_ctx* ctx, uint8_t* core_flags_sorted, int32_t* grid_label) {
+    if (!ctx) return GD_EINVAL;
+    if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to inspect");
+    DeviceGuard guard(ctx->device);
+    int rc;
+    if ((rc = copy_d2h(ctx, core_flags_sorted, ctx->last_core, ctx->last_n))) return rc;
+    return copy_d2h(ctx, grid_label, ctx->last_cell_label, sizeof(int32_t) * ctx->last_ncell);
+}
+
+int gd_merge_test(gd_ctx* ctx, const int32_t* points, int64_t m, int32_t d, double eps, const uint32_t* pairs,
+                  int64_t npairs, uint8_t* answers, uint32_t* iterations, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "d = %d out of range [1, %d]", d, GD_D_MAX);
+    if (!(eps > 0) || !std::isfinite(eps) || eps != std::floor(eps))
+        return ctx->fail(GD_EINVAL, "eps = %g must be a positive integer", eps);
+    if (eps > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "eps = %g exceeds %d", eps, GD_EPS_MAX);
+    if (m < 0 || npairs < 0) return ctx->fail(GD_EINVAL, "negative size");
+    if (npairs == 0) return GD_OK;
+    if (!points || !pairs || !answers) return ctx->fail(GD_EINVAL, "NULL device pointer");
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<uint32_t> hp((size_t)npairs * 4);
+    GD_TRY(hipMemcpyAsync(hp.data(), pairs, hp.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GD_TRY(hipStreamSynchronize(st));
+    uint32_t mx = 1;
+    for (int64_t r = 0; r < npairs; ++r) {
+        for (int s = 0; s < 2; ++s) {
+            const uint64_t b = hp[4 * r + 2 * s], c = hp[4 * r + 2 * s + 1];
+            if (c < 1 || c > (uint64_t)kMaxCoreBits || b + c > (uint64_t)m)
+                return ctx->fail(GD_EINVAL, "pair %lld: run [%llu, +%llu) invalid for m = %lld", (long long)r,
+                                 (unsigned long long)b, (unsigned long long)c, (long long)m);
+            mx = std::max<uint32_t>(mx, (uint32_t)c);
+        }
+    }
+    GD_TRY(launch_merge_pairs(points, m, d, pairs, npairs, (int64_t)eps, mx, answers, iterations, st));
+    GD_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+}
+
+int gd_get_phase_times(gd_ctx* ctx, double* ms, int32_t count) {
+    if (!ctx || (!ms && count > 0) || count < 0) return GD_EINVAL;
+    for (int p = 0; p < count; ++p) ms[p] = p < P_COUNT ? ctx->phase_ms[p] : 0.0;
+    return GD_OK;
+}
+
+const char* gd_phase_name(int32_t i) { return (i >= 0 && i < P_COUNT) ? kPhaseNames[i] : nullptr; }
+
+const char* gd_last_error(gd_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+const char* gd_status_string(int status) {
+    switch (status) {
+        case GD_OK: return "GD_OK";
+        case GD_EINVAL: return "GD_EINVAL";
+        case GD_ERANGE: return "GD_ERANGE";
+        case GD_ENOMEM: return "GD_ENOMEM";
+        case GD_EDEVICE: return "GD_EDEVICE";
+        case GD_EUNSUPPORTED: return "GD_EUNSUPPORTED";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// Shared device helpers for the gfx950 kernels: wave64 primitives, exact
+// integer helpers and the launch-side error type.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gd {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                 // 4 waves per workgroup
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+// index of the lowest set bit (m != 0)
+__device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Orders LDS writes of a wave before its later LDS reads (no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int32_t readlane(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// Squared distance between points of neighbouring grids.  Every coordinate
+// difference is below 2^24 and the sum below 9 eps^2 < 2^32, so 24-bit
+// multiplies and a 32-bit sum are exact.
+__device__ __forceinline__ uint32_t sq24(int32_t a, int32_t b) {
+    const uint32_t t = (uint32_t)(a > b ? a - b : b - a);
+    return __umul24(t, t);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t t = __shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t t = __shfl_xor(v, o);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+// inclusive prefix sum across the 64 lanes
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T t = __shfl_up(v, o);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over a 256-thread block; `wsum` is 4 slots of shared
+// memory.  Every thread of the block must call it.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* wsum, T& total) {
+    T incl = wave_incl_scan(v);
+    if (lane_id() == kWave - 1) wsum[wave_id()] = incl;
+    __syncthreads();
+    T off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+        T s = wsum[w];
+        off += (w < wave_id()) ? s : T(0);
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+// Coherent (device-scope) access for data other workgroups update
+// concurrently, such as union-find parents.
+template <typename T>
+__device__ __forceinline__ T load_acq(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_rel(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// floor(u * sqrt(d) / eps) exactly, for integers 0 <= u <= 2^25, 1 <= d <= 8,
+// 1 <= eps: the largest k with (k * eps)^2 <= d * u^2 (all terms < 2^54).
+__device__ __forceinline__ uint32_t grid_coord(int64_t u, int d, int64_t eps) {
+    const int64_t y = (int64_t)d * u * u;
+    int64_t k = (int64_t)(sqrt((double)y) / (double)eps);
+    while ((k + 1) * eps * (k + 1) * eps <= y) ++k;
+    while (k > 0 && k * eps * k * eps > y) --k;
+    return (uint32_t)k;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void fill_kernel(T* p, int64_t n, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = v;
+}
+
+// Fill with a kernel rather than a memset node, so that the sequence can be
+// captured into a HIP graph.
+template <typename T>
+inline hipError_t fill(T* p, int64_t n, T v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    fill_kernel<T><<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+#define GD_DISPATCH_D(d, CALL)                         \
+    switch (d) {                                       \
+        case 1: { constexpr int D = 1; CALL; } break;  \
+        case 2: { constexpr int D = 2; CALL; } break;  \
+        case 3: { constexpr int D = 3; CALL; } break;  \
+        case 4: { constexpr int D = 4; CALL; } break;  \
+        case 5: { constexpr int D = 5; CALL; } break;  \
+        case 6: { constexpr int D = 6; CALL; } break;  \
+        case 7: { constexpr int D = 7; CALL; } break;  \
+        case 8: { constexpr int D = 8; CALL; } break;  \
+        default: return hipErrorInvalidValue;          \
+    }
+
+inline unsigned grid_for(int64_t n, int per_block = kBlock) {
+    int64_t b = (n + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace gd

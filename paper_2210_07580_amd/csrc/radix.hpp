@@ -1,0 +1,161 @@
+// Stable LSD radix sort of (key, u32 value) pairs, 8-bit digits, for the
+// grid identifiers of Section 4.1 (Algorithm 1 line 2 sorts the points by
+// identifier with a radix sort).
+//
+// Each pass is reduce-then-scan: (1) every workgroup builds the digit
+// histogram of its 4096-key tile in LDS (one sub-histogram per wave to cut
+// atomic contention); (2) a device-wide exclusive scan over the
+// digit-major [256][tiles] table gives every (digit, tile) its output base;
+// (3) every workgroup re-reads its tile in 16 rounds of 256 keys and ranks
+// each key among equal digits with wave64 ballots (eight ballots give the
+// lanes holding the same digit; the rank is the popcount below the lane),
+// then adds the counts of lower waves and of earlier rounds, kept in LDS.
+// Ranks follow input order, so every pass is stable.
+#pragma once
+
+#include "scan.hpp"
+
+namespace gd {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+static_assert(kBlock == kRadixBins, "one digit per thread in the scatter pass");
+
+inline int64_t radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
+// u32 entries of scratch needed for a sort of n keys
+inline int64_t radix_scratch_words(int64_t n) {
+    const int64_t t = radix_tiles(n);
+    return 2 * kRadixBins * t + scan_blocks(kRadixBins * t) + 4;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
+                                                            uint32_t* __restrict__ hist, int64_t tiles) {
+    __shared__ uint32_t h[kWavesPerBlock][kRadixBins];
+    for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int w = wave_id();
+#pragma unroll 4
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        if (i < n) {
+            const uint32_t dg = (uint32_t)(keys[i] >> shift) & (kRadixBins - 1);
+            atomicAdd(&h[w][dg], 1u);
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;  // one digit per thread (kBlock == kRadixBins)
+    uint32_t s = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWavesPerBlock; ++ww) s += h[ww][t];
+    hist[(int64_t)t * tiles + blockIdx.x] = s;
+}
+
+template <typename K, bool kIota>
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                               K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+                                                               int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                               int64_t tiles) {
+    __shared__ uint32_t run[kRadixBins];                    // next free slot per digit
+    __shared__ uint32_t wcnt[kWavesPerBlock][kRadixBins];   // keys per (wave, digit) this round
+    __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];   // first slot per (wave, digit) this round
+    const int t = threadIdx.x;
+    const int w = wave_id();
+    run[t] = offs[(int64_t)t * tiles + blockIdx.x];
+#pragma unroll
+    for (int ww = 0; ww < kWavesPerBlock; ++ww) wcnt[ww][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const uint64_t lt = lanemask_lt();
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock + t;
+        if (base + (int64_t)r * kBlock >= n) break;  // uniform across the block
+        const bool valid = i < n;
+        K k = valid ? keys[i] : K(0);
+        const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)popc64(peers & lt);
+        if (valid && rank == 0) wcnt[w][dg] = (uint32_t)popc64(peers);
+        __syncthreads();
+        {
+            uint32_t acc = run[t];
+#pragma unroll
+            for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+                const uint32_t c = wcnt[ww][t];
+                woff[ww][t] = acc;
+                acc += c;
+                wcnt[ww][t] = 0;
+            }
+            run[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = woff[w][dg] + rank;
+            keys_out[pos] = k;
+            vals_out[pos] = kIota ? (uint32_t)i : vals[i];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void iota_kernel(T* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = (T)i;
+}
+
+template <typename K>
+struct RadixResult {
+    K* keys;
+    uint32_t* vals;
+};
+
+// Sorts keys[0..n) (and vals) on their low `bits` bits.  keys/vals and
+// keys_alt/vals_alt are ping-pong buffers; the result lands in one of them.
+// If vals_iota, vals[] is not read and the values start as 0..n-1.
+// `scratch` needs radix_scratch_words(n) u32.
+template <typename K>
+hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
+                            bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K>* out) {
+    K* kin = keys;
+    uint32_t* vin = vals;
+    K* kout = keys_alt;
+    uint32_t* vout = vals_alt;
+    const int64_t tiles = radix_tiles(n);
+    uint32_t* hist = scratch;
+    uint32_t* offs = scratch + (int64_t)kRadixBins * tiles;
+    uint32_t* partial = offs + (int64_t)kRadixBins * tiles;
+    bool iota = vals_iota;
+    for (int shift = 0; shift < bits; shift += kRadixBits) {
+        if (n == 0) break;
+        radix_hist_kernel<K><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, n, shift, hist, tiles);
+        hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, (int64_t)kRadixBins * tiles, offs,
+                                                (uint32_t*)nullptr, partial, st);
+        if (e != hipSuccess) return e;
+        if (iota)
+            radix_scatter_kernel<K, true><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n, shift,
+                                                                                        offs, tiles);
+        else
+            radix_scatter_kernel<K, false><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n,
+                                                                                         shift, offs, tiles);
+        iota = false;
+        K* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+    }
+    if (iota && n > 0) {  // no pass ran: the values must still be 0..n-1
+        iota_kernel<uint32_t><<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(vin, n);
+    }
+    out->keys = kin;
+    out->vals = vin;
+    return hipGetLastError();
+}
+
+}  // namespace gd
