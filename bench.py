@@ -99,29 +99,32 @@ def main():
     core = torch.empty(n, dtype=torch.uint8, device=dev)
     ctx = G.Context(0)
     ctx.set_option(G.GD_OPT_TIMING, 1)
-    ctx.set_option(G.GD_OPT_STATS, 1)
     for i in range(args.warmup):
         ctx.dbscan(pts, w.eps, w.minpts, labels, core)
         log(f"bench: warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    phase_sum, stats_sum = {}, {}
+    phase_sum = {}
     t0 = time.perf_counter()
     for i in range(args.steps):
         ctx.dbscan(pts, w.eps, w.minpts, labels, core)
         for k, v in ctx.phase_times().items():
             phase_sum[k] = phase_sum.get(k, 0.0) + v
-        for k, v in ctx.stats().items():
-            stats_sum[k] = stats_sum.get(k, 0) + v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"bench: {args.steps} timed steps done")
+    # Work counters come from one more, untimed call with the device counters
+    # on (the union order, hence the number of merge tests, varies slightly
+    # from call to call).
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    ctx.dbscan(pts, w.eps, w.minpts, labels, core)
+    st = ctx.stats()
+    ctx.set_option(G.GD_OPT_STATS, 0)
 
     K = args.steps
     total = t1 - t0
     ms_per_step = 1000.0 * total / K
     phases = {k: v / K for k, v in phase_sum.items()}
-    st = {k: v / K for k, v in stats_sum.items()}
     key_bytes = 4 if st["key_bits"] <= 32 else 8
 
     table = []

@@ -28,8 +28,8 @@ struct Info {
     uint32_t level_count[kMaxD];
     uint32_t counts[4];  // ncore, core grids, max core points per grid, dense grids
     uint64_t nei_total;
-    MergeStats merge;
-    unsigned long long core_dist;
+    MergeStats merge[kStatSlots];
+    unsigned long long core_dist[kStatSlots];
 };
 
 struct DevBuf {
@@ -292,8 +292,10 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
     ctx->mark(P_MINMAX, 0);
     GD_TRY(launch_minmax(points, n, d, I->mn, I->mx, &I->err, st));
     ctx->mark(P_MINMAX, 1);
-    GD_TRY(fill<unsigned long long>(&I->merge.pairs, sizeof(MergeStats) / sizeof(unsigned long long), 0ull, st));
-    GD_TRY(fill<unsigned long long>(&I->core_dist, 1, 0ull, st));
+    if (ctx->stats) {
+        GD_TRY(fill<unsigned long long>(&I->merge[0].pairs, (int64_t)(sizeof(I->merge) / sizeof(unsigned long long)), 0ull, st));
+        GD_TRY(fill<unsigned long long>(I->core_dist, kStatSlots, 0ull, st));
+    }
     if ((rc = readback(ctx, st))) return rc;
     if (H->err & kErrNotInteger)
         return ctx->fail(GD_ERANGE, "a coordinate is not a finite integer of magnitude <= 2^24");
@@ -366,7 +368,7 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? &I->core_dist : nullptr, st));
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? I->core_dist : nullptr, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
@@ -401,7 +403,7 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
     }
     ctx->mark(P_MERGE, 0);
     GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, max_core, eps, L.parent,
-                        ctx->stats ? &I->merge : nullptr, &I->err, st));
+                        ctx->stats ? I->merge : nullptr, &I->err, st));
     ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);
     GD_TRY(launch_labels(g, co, L.parent, L.root_min, L.cell_label, st));
@@ -442,15 +444,18 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
     s.dense_grids = H->counts[3];
     s.max_grid_points = 0;
     if (ctx->stats) {
-        s.merge_pairs = (int64_t)H->merge.pairs;
-        s.merge_skipped = (int64_t)H->merge.skipped;
-        s.merge_tests = (int64_t)H->merge.tests;
-        s.merge_yes = (int64_t)H->merge.yes;
-        s.merge_iterations = (int64_t)H->merge.iters;
-        s.merge_max_iterations = (int64_t)H->merge.max_iters;
-        s.merge_distances = (int64_t)H->merge.dists;
-        s.core_distances = (int64_t)H->core_dist;
-        s.merge_set_points = (int64_t)H->merge.set_points;
+        for (int k = 0; k < kStatSlots; ++k) {
+            const MergeStats& m = H->merge[k];
+            s.merge_pairs += (int64_t)m.pairs;
+            s.merge_skipped += (int64_t)m.skipped;
+            s.merge_tests += (int64_t)m.tests;
+            s.merge_yes += (int64_t)m.yes;
+            s.merge_iterations += (int64_t)m.iters;
+            s.merge_max_iterations = std::max<int64_t>(s.merge_max_iterations, (int64_t)m.max_iters);
+            s.merge_distances += (int64_t)m.dists;
+            s.merge_set_points += (int64_t)m.set_points;
+            s.core_distances += (int64_t)H->core_dist[k];
+        }
     }
     return GD_OK;
 }

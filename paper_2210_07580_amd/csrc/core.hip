@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
         }
         if ((uint32_t)lane < nq) core[st + qb + lane] = ((active >> lane) & 1ull) ? 0 : 1;
     }
-    if (dist_counter && lane == 0) atomicAdd(dist_counter, ndist);
+    if (dist_counter && lane == 0) atomicAdd(&dist_counter[c & (kStatSlots - 1)], ndist);
 }
 
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,

@@ -96,6 +96,7 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
                             hipStream_t st);
 
 // ---- merge.hip (Algorithms 4-5, union-find)
+constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats)
 struct MergeStats {
     unsigned long long pairs, skipped, tests, yes, iters, max_iters, dists, set_points;
 };

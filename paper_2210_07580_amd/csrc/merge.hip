@@ -76,24 +76,41 @@ __device__ __forceinline__ void load_point(const PointSet& s, uint32_t pos, int3
     for (int k = 0; k < D; ++k) x[k] = s.crd[(int64_t)k * s.stride + s.base + pos];
 }
 
+constexpr uint32_t kUnroll = 4;  // words of a set whose loads are issued together
+
+// Loads the point of this lane in word w (position clamped into the set so
+// the address is always valid; callers ignore lanes whose bit is clear).
+template <int D>
+__device__ __forceinline__ void load_lane_point(const PointSet& s, uint32_t w, int32_t (&x)[D]) {
+    uint32_t pos = w * kWave + lane_id();
+    pos = pos < s.m ? pos : s.m - 1;
+    load_point<D>(s, pos, x);
+}
+
 // argmin over live y of D(p, y): returns (D << 32 | position)
 template <int D>
 __device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p)[D], unsigned long long& ndist) {
     const int lane = lane_id();
     uint64_t best = ~0ull;
-    for (uint32_t w = 0; w < s.words; ++w) {
-        const uint64_t m = s.alive[w];
-        if (m == 0) continue;
-        ndist += (unsigned long long)popc64(m);
-        if ((m >> lane) & 1ull) {
-            const uint32_t pos = w * kWave + lane;
-            int32_t y[D];
-            load_point<D>(s, pos, y);
-            uint32_t dd = 0;
+    for (uint32_t w0 = 0; w0 < s.words; w0 += kUnroll) {
+        uint64_t mk[kUnroll];
+        int32_t y[kUnroll][D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) dd += sq24(y[k], p[k]);
-            const uint64_t cand = ((uint64_t)dd << 32) | pos;
-            best = cand < best ? cand : best;
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t w = w0 + u;
+            mk[u] = w < s.words ? s.alive[w] : 0ull;
+            if (mk[u]) load_lane_point<D>(s, w, y[u]);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            ndist += (unsigned long long)popc64(mk[u]);
+            if ((mk[u] >> lane) & 1ull) {
+                uint32_t dd = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) dd += sq24(y[u][k], p[k]);
+                const uint64_t cand = ((uint64_t)dd << 32) | ((w0 + u) * kWave + lane);
+                best = cand < best ? cand : best;
+            }
         }
     }
     return wave_min_u64(best);
@@ -124,21 +141,27 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
     // lambda over the live points of b
     double cmin = 2.0;
     bool off = false;
-    for (uint32_t w = 0; w < b.words; ++w) {
-        const uint64_t m = b.alive[w];
-        if (m == 0) continue;
-        ndist += (unsigned long long)popc64(m);
-        if ((m >> lane) & 1ull) {
-            int32_t y[D];
-            load_point<D>(b, w * kWave + lane, y);
+    for (uint32_t w0 = 0; w0 < b.words; w0 += kUnroll) {
+        uint64_t mk[kUnroll];
+        int32_t yy[kUnroll][D];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t w = w0 + u;
+            mk[u] = w < b.words ? b.alive[w] : 0ull;
+            if (mk[u]) load_lane_point<D>(b, w, yy[u]);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            ndist += (unsigned long long)popc64(mk[u]);
+            if (!((mk[u] >> lane) & 1ull)) continue;
             int32_t py[D];
             int64_t dot = 0;
             uint32_t b2 = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                py[k] = y[k] - p[k];
+                py[k] = yy[u][k] - p[k];
                 dot += (int64_t)pq[k] * py[k];
-                b2 += sq24(y[k], p[k]);
+                b2 += sq24(yy[u][k], p[k]);
             }
             const double dotd = (double)dot;
             const double h2 = (double)(b2 - T);  // b^2 - eps^2 > 0 since b^2 >= dpq > T
@@ -162,32 +185,40 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
     cmin = wave_min_f64(cmin);
     const double thr = cmin - 1e-10;
     uint64_t any = 0;
-    for (uint32_t w = 0; w < a.words; ++w) {
-        const uint64_t m = a.alive[w];
-        if (m == 0) continue;
-        ndist += (unsigned long long)popc64(m);
-        bool keep = false;
-        if ((m >> lane) & 1ull) {
-            int32_t x[D];
-            load_point<D>(a, w * kWave + lane, x);
-            uint32_t ax = 0;
-            int64_t dotx = 0;
+    for (uint32_t w0 = 0; w0 < a.words; w0 += kUnroll) {
+        uint64_t mk[kUnroll];
+        int32_t xx[kUnroll][D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                ax += sq24(x[k], p[k]);
-                dotx += (int64_t)pq[k] * (x[k] - p[k]);
-            }
-            const int64_t s = (int64_t)dpq - (int64_t)T - (int64_t)ax;
-            const bool tri = s > 0 && (uint64_t)4 * (uint64_t)T * (uint64_t)ax < (uint64_t)s * (uint64_t)s;
-            keep = !tri;
-            if (keep && !off && ax > 0) {
-                const double cth = (double)dotx / (na * sqrt((double)ax));
-                if (cth < thr) keep = false;
-            }
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t w = w0 + u;
+            mk[u] = w < a.words ? a.alive[w] : 0ull;
+            if (mk[u]) load_lane_point<D>(a, w, xx[u]);
         }
-        const uint64_t nm = ballot(keep);
-        if (lane == 0) a.alive[w] = nm;
-        any |= nm;
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            if (!mk[u]) continue;
+            ndist += (unsigned long long)popc64(mk[u]);
+            bool keep = false;
+            if ((mk[u] >> lane) & 1ull) {
+                uint32_t ax = 0;
+                int64_t dotx = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    ax += sq24(xx[u][k], p[k]);
+                    dotx += (int64_t)pq[k] * (xx[u][k] - p[k]);
+                }
+                const int64_t s = (int64_t)dpq - (int64_t)T - (int64_t)ax;
+                const bool tri = s > 0 && (uint64_t)4 * (uint64_t)T * (uint64_t)ax < (uint64_t)s * (uint64_t)s;
+                keep = !tri;
+                if (keep && !off && ax > 0) {
+                    const double cth = (double)dotx / (na * sqrt((double)ax));
+                    if (cth < thr) keep = false;
+                }
+            }
+            const uint64_t nm = ballot(keep);
+            if (lane == 0) a.alive[w0 + u] = nm;
+            any |= nm;
+        }
     }
     wave_sync();
     return any != 0;
@@ -250,26 +281,28 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GridView gv, CoreOut co, 
     PointSet sj{co.ccrd, gv.n, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    // Root of g_i, found by every lane at once (one address per step).
+    uint32_t ri = uf_find(parent, ci);
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
-        uint32_t cj = 0, rj = kNone;
+        uint32_t cj = 0;
+        bool cand = false;
         if (idx < e1) {
             cj = nei[idx];
-            rj = rank[cj];
+            const uint32_t rj = rank[cj];
+            cand = rj != kNone && rj > (uint32_t)r;
         }
-        uint64_t cand = ballot(rj != kNone && rj > (uint32_t)r);
-        while (cand) {
-            const int l = ffs64(cand);
-            cand &= cand - 1ull;
+        // Each lane resolves its own candidate's root: the pairs already in
+        // one set are dropped in a single parallel round.
+        bool pend_l = cand && uf_find(parent, cj) != ri;
+        const uint64_t cands = ballot(cand);
+        uint64_t pend = ballot(pend_l);
+        n_pairs += (unsigned long long)popc64(cands);
+        n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
+        while (pend) {
+            const int l = ffs64(pend);
+            pend &= pend - 1ull;
             const uint32_t j = readlane(cj, l);
-            ++n_pairs;
-            uint32_t same = 0;
-            if (lane == 0) same = uf_find(parent, ci) == uf_find(parent, j);
-            same = uniform(same);
-            if (same) {
-                ++n_skip;
-                continue;
-            }
             sj.base = co.core_start[j];
             sj.m = co.core_start[j + 1] - sj.base;
             sj.words = (sj.m + kWave - 1) / kWave;
@@ -286,18 +319,29 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GridView gv, CoreOut co, 
             if (yes) {
                 ++n_yes;
                 if (lane == 0) uf_union(parent, ci, j);
+                ri = uf_find(parent, ci);
+                if (pend) {
+                    // the union may have joined g_i to other pending grids' sets
+                    const bool still = ((pend >> lane) & 1ull) && uf_find(parent, cj) != ri;
+                    const uint64_t np = ballot(still);
+                    n_skip += (unsigned long long)(popc64(pend) - popc64(np));
+                    pend = np;
+                }
             }
         }
     }
     if (stats && lane == 0) {
-        atomicAdd(&stats->pairs, n_pairs);
-        atomicAdd(&stats->skipped, n_skip);
-        atomicAdd(&stats->tests, n_test);
-        atomicAdd(&stats->yes, n_yes);
-        atomicAdd(&stats->iters, n_iter);
-        atomicAdd(&stats->dists, n_dist);
-        atomicMax(&stats->max_iters, max_it);
-        atomicAdd(&stats->set_points, n_pts);
+        // counters are spread over kStatSlots copies (summed on the host) so
+        // that same-address atomics do not serialise the kernel
+        MergeStats* sl = stats + ((uint64_t)r & (kStatSlots - 1));
+        atomicAdd(&sl->pairs, n_pairs);
+        atomicAdd(&sl->skipped, n_skip);
+        atomicAdd(&sl->tests, n_test);
+        atomicAdd(&sl->yes, n_yes);
+        atomicAdd(&sl->iters, n_iter);
+        atomicAdd(&sl->dists, n_dist);
+        atomicMax(&sl->max_iters, max_it);
+        atomicAdd(&sl->set_points, n_pts);
     }
 }
 

@@ -1,0 +1,80 @@
+"""Full-size parity on the benchmark workloads, in the configuration the
+benchmark times (one dbscan() call on the whole workload).
+
+The oracle's full-size results are stored as SHA-256 digests in
+tests/golden/oracle_digests.json, written by
+tests/golden/make_oracle_digests.py (which runs only the generators and the
+oracle).  Beside the digest check, core flags of sampled points are checked
+against brute-force neighbour counts over all n points, and the canonical
+label properties are checked on every point.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
+
+
+def _digests():
+    if not os.path.exists(DIGESTS):
+        return {}
+    with open(DIGESTS) as f:
+        return json.load(f)
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2210_07580_amd as G
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "H", "cfg4", "cfg2"])
+def test_full_size_matches_oracle_digest(ctx, name):
+    rec = _digests().get(name)
+    if rec is None:
+        pytest.skip(f"no stored oracle digest for {name}")
+    w = W.WORKLOADS[name]
+    x = W.make_points(w)
+    assert sha(x) == rec["points_sha256"], "generator output changed: regenerate the digests"
+    print(f"case {name} n={len(x)} d={w.d} eps={w.eps} minpts={w.minpts}", flush=True)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    lab, core = ctx.dbscan(t, w.eps, w.minpts)
+    lab = lab.cpu().numpy()
+    core = core.cpu().numpy()
+    # properties that hold at any size
+    ncl = np.unique(lab[lab >= 0]).size
+    assert int(core.sum()) == rec["core_points"]
+    assert int((lab < 0).sum()) == rec["noise_points"]
+    assert ncl == rec["clusters"]
+    core_idx = np.nonzero(core)[0]
+    # a cluster id is a core point whose own label is itself
+    ids = np.unique(lab[lab >= 0])
+    assert core[ids].all() and (lab[ids] == ids).all()
+    # every core point's label is at most its own index
+    assert (lab[core_idx] <= core_idx).all()
+    # sampled core flags against brute-force counts over all points
+    rng = np.random.default_rng(5)
+    q = rng.choice(len(x), size=48, replace=False)
+    cnt = oracle.neighbor_count_brute(x, w.eps, q)
+    assert np.array_equal(cnt >= w.minpts, core[q].astype(bool))
+    # bit-exact against the oracle's stored result
+    assert sha(core.astype(np.uint8)) == rec["core_sha256"]
+    assert sha(lab.astype("<i4")) == rec["labels_sha256"]
