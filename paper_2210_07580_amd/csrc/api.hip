@@ -26,7 +26,7 @@ struct Info {
     uint32_t err;
     uint32_t ncell;
     uint32_t level_count[kMaxD];
-    uint32_t counts[4];  // ncore, core grids, max core points per grid, dense grids
+    uint32_t counts[5];  // ncore, core grids, max core points per grid, dense grids, tiny core grids
     uint64_t nei_total;
     MergeStats merge[kStatSlots];
     unsigned long long core_dist[kStatSlots];
@@ -218,7 +218,7 @@ Layout carve(char* base, int64_t n, int d) {
     L.core = c.take<uint8_t>(n);
     L.core_excl = c.take<uint32_t>(n + 1);
     L.core_start = c.take<uint32_t>(n + 1);
-    L.ccrd = c.take<int32_t>((int64_t)d * n);
+    L.ccrd = c.take<int32_t>((int64_t)(d <= 4 ? 4 : 8) * n);
     L.corig = c.take<uint32_t>(n);
     L.cell_min_core = c.take<uint32_t>(n);
     L.list = c.take<uint32_t>(n);
@@ -375,6 +375,7 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
     co.core_excl = L.core_excl;
     co.core_start = L.core_start;
     co.ccrd = L.ccrd;
+    co.cstride = d <= 4 ? 4 : 8;
     co.corig = L.corig;
     co.cell_min_core = L.cell_min_core;
     co.counts = I->counts;
@@ -402,7 +403,8 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
         ctx->mark(P_LDF, 1);
     }
     ctx->mark(P_MERGE, 0);
-    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, max_core, eps, L.parent,
+    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, ctx->ldf ? (int64_t)H->counts[4] : -1, max_core,
+                        eps, L.parent,
                         ctx->stats ? I->merge : nullptr, &I->err, st));
     ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
                 const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
                 int32_t y[D];
 #pragma unroll
-                for (int jj = 0; jj < D; ++jj) y[jj] = tv ? co.ccrd[(int64_t)jj * n + q] : 0;
+                for (int jj = 0; jj < D; ++jj) y[jj] = tv ? co.ccrd[(int64_t)q * co.cstride + jj] : 0;
                 const uint64_t cand = tv ? (((uint64_t)co.corig[q] << 32) | (uint32_t)s_lab[w][j]) : ~0ull;
                 uint64_t act = open;
                 while (act) {

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void core_scatter_kernel(GridView gv, CoreO
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= gv.n || !co.core[s]) return;
     const uint32_t pos = co.core_excl[s];
-    for (int j = 0; j < gv.d; ++j) co.ccrd[(int64_t)j * gv.n + pos] = gv.crd[(int64_t)j * gv.n + s];
+    for (int j = 0; j < gv.d; ++j) co.ccrd[(int64_t)pos * co.cstride + j] = gv.crd[(int64_t)j * gv.n + s];
     co.corig[pos] = gv.sidx[s];
 }
 
@@ -128,16 +128,18 @@ __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut
     }
     const uint64_t has = ballot(v && cnt > 0);
     const uint64_t dense = ballot(v && size >= (uint32_t)gv.minpts);
+    const uint64_t tiny = ballot(v && cnt > 0 && cnt <= kTinyCore);
     const uint32_t mx = wave_max_u32(cnt);
     if (lane_id() == 0) {
         if (has) atomicAdd(&co.counts[1], (uint32_t)popc64(has));
         if (dense) atomicAdd(&co.counts[3], (uint32_t)popc64(dense));
+        if (tiny) atomicAdd(&co.counts[4], (uint32_t)popc64(tiny));
         if (mx) atomicMax(&co.counts[2], mx);
     }
 }
 
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st) {
-    hipError_t e = fill<uint32_t>(c.counts, 4, 0u, st);
+    hipError_t e = fill<uint32_t>(c.counts, 5, 0u, st);
     if (e != hipSuccess) return e;
     // core_excl[n] = number of core points, also copied to counts[0]
     e = scan_exclusive<uint32_t>(CoreFlag{c.core, g.n}, g.n + 1, c.core_excl, c.counts, partial, st);

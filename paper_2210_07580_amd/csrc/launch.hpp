@@ -79,10 +79,12 @@ struct CoreOut {
     uint8_t* core;              // n, sorted order
     uint32_t* core_excl;        // n + 1: exclusive scan of core flags
     uint32_t* core_start;       // ncell + 1: first compacted core point of each grid
-    int32_t* ccrd;              // d x n SoA: core points' coordinates, compacted
+    int32_t* ccrd;              // core points' coordinates, compacted, cstride int32 per point
+    int cstride;                // 4 (d <= 4) or 8: padded point record
     uint32_t* corig;            // n: input index of each compacted core point
     uint32_t* cell_min_core;    // ncell: smallest input index of a core point (kNone if none)
-    uint32_t* counts;           // device counters: [0] ncore, [1] ncorecell, [2] max core/grid, [3] dense grids
+    uint32_t* counts;           // device counters: [0] ncore, [1] ncorecell, [2] max core/grid, [3] dense grids,
+                                // [4] core grids with at most kTinyCore core points
 };
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
                             unsigned long long* dist_counter, hipStream_t st);
@@ -105,9 +107,11 @@ enum : uint32_t {
 };
 // Largest core set a grid may hold (LDS bitmaps of the merge step).
 constexpr int64_t kMaxCoreBits = 262144;
+constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                        const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t max_core,
-                        int64_t eps, uint32_t* parent, MergeStats* stats, uint32_t* err, hipStream_t st);
+                        const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
+                        int64_t max_core, int64_t eps, uint32_t* parent, MergeStats* stats, uint32_t* err,
+                        hipStream_t st);
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, const uint32_t* pairs, int64_t npairs,
                               int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
                               hipStream_t st);

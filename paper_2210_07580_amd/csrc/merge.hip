@@ -61,9 +61,11 @@ __device__ __forceinline__ void uf_union(uint32_t* parent, uint32_t a, uint32_t 
     }
 }
 
+// A run of points: coordinate k of position i at crd[k * kstride + (base + i) * pstride].
 struct PointSet {
-    const int32_t* crd;   // compacted core coordinates, d x n
-    int64_t stride;       // n
+    const int32_t* crd;
+    int64_t kstride;
+    int64_t pstride;
     uint32_t base;        // first position of the set
     uint32_t m;           // size
     uint64_t* alive;      // LDS bitmap, ceil(m / 64) words
@@ -72,8 +74,9 @@ struct PointSet {
 
 template <int D>
 __device__ __forceinline__ void load_point(const PointSet& s, uint32_t pos, int32_t (&x)[D]) {
+    const int32_t* p = s.crd + (int64_t)(s.base + pos) * s.pstride;
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = s.crd[(int64_t)k * s.stride + s.base + pos];
+    for (int k = 0; k < D; ++k) x[k] = p[(int64_t)k * s.kstride];
 }
 
 constexpr uint32_t kUnroll = 4;  // words of a set whose loads are issued together
@@ -260,41 +263,144 @@ __device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T
     }
 }
 
+constexpr uint32_t kSmallSet = kTinyCore;
+
+__device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsigned long long pairs,
+                                            unsigned long long skip, unsigned long long test,
+                                            unsigned long long yes, unsigned long long iter,
+                                            unsigned long long max_it, unsigned long long dist,
+                                            unsigned long long pts) {
+    // counters are spread over kStatSlots copies (summed on the host) so
+    // that same-address atomics do not serialise the kernel
+    MergeStats* sl = stats + ((uint64_t)r & (kStatSlots - 1));
+    atomicAdd(&sl->pairs, pairs);
+    atomicAdd(&sl->skipped, skip);
+    atomicAdd(&sl->tests, test);
+    atomicAdd(&sl->yes, yes);
+    atomicAdd(&sl->iters, iter);
+    atomicAdd(&sl->dists, dist);
+    atomicMax(&sl->max_iters, max_it);
+    atomicAdd(&sl->set_points, pts);
+}
+
+// Pairs of tiny core sets (both at most kSmallSet points).  One wave per tiny
+// core grid g_i; every lane takes one neighbouring tiny core grid g_j that
+// comes later in the visiting order and decides the pair by evaluating its
+// |s_i| x |s_j| distances directly: the answer FastMerging gives (Theorem
+// 2), without its wave-level iteration.  Only pairs that answer yes touch the
+// union-find.  s_i lives in scalar registers.
 template <int D>
-__global__ __launch_bounds__(kBlock) void merge_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
-                                                       const uint32_t* __restrict__ nei,
-                                                       const uint32_t* __restrict__ ldf,
-                                                       const uint32_t* __restrict__ rank, int64_t ncc, uint32_t words,
-                                                       double eps, uint32_t* parent, MergeStats* stats,
-                                                       uint32_t* err) {
+__global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+                                                             const uint32_t* __restrict__ nei,
+                                                             const uint32_t* __restrict__ ldf,
+                                                             const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
+                                                             uint32_t* parent, MergeStats* stats) {
+    const int lane = lane_id();
+    const int64_t r = r0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (r >= r1) return;
+    const uint32_t T = (uint32_t)gv.T;
+    const uint32_t ci = ldf[r];
+    const uint32_t bi = co.core_start[ci];
+    const uint32_t mi = co.core_start[ci + 1] - bi;
+    if (mi > kSmallSet) return;
+    const int P = co.cstride;
+    int32_t pi[kSmallSet][D];
+#pragma unroll
+    for (int a = 0; a < (int)kSmallSet; ++a)
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+            pi[a][k] = uniform((uint32_t)a < mi ? co.ccrd[(int64_t)(bi + a) * P + k] : 0);
+    unsigned long long n_pairs = 0, n_yes = 0, n_dist = 0, n_pts = 0;
+    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    for (uint64_t e = e0; e < e1; e += kWave) {
+        const uint64_t idx = e + lane;
+        bool cand = false;
+        uint32_t cj = 0, bj = 0, mj = 0;
+        if (idx < e1) {
+            cj = nei[idx];
+            const uint32_t rj = rank[cj];
+            if (rj != kNone && rj > (uint32_t)r) {
+                bj = co.core_start[cj];
+                mj = co.core_start[cj + 1] - bj;
+                cand = mj <= kSmallSet;
+            }
+        }
+        bool yes = false;
+        if (cand) {
+            for (uint32_t b = 0; b < mj && !yes; ++b) {
+                int32_t y[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) y[k] = co.ccrd[(int64_t)(bj + b) * P + k];
+#pragma unroll
+                for (int a = 0; a < (int)kSmallSet; ++a) {
+                    if ((uint32_t)a < mi) {
+                        uint32_t dd = 0;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) dd += sq24(y[k], pi[a][k]);
+                        yes |= dd <= T;
+                    }
+                }
+            }
+            if (yes && uf_find(parent, ci) != uf_find(parent, cj)) uf_union(parent, ci, cj);
+        }
+        if (stats) {
+            const unsigned long long np = (unsigned long long)popc64(ballot(cand));
+            const unsigned long long sj = (unsigned long long)wave_sum(cand ? mj : 0u);
+            n_pairs += np;
+            n_yes += (unsigned long long)popc64(ballot(yes));
+            n_dist += (unsigned long long)mi * sj;
+            n_pts += np * mi + sj;
+        }
+    }
+    // each one-lane test counts as one FastMerging iteration
+    if (stats && lane == 0)
+        flush_stats(stats, r, n_pairs, 0, n_pairs, n_yes, n_pairs, n_pairs ? 1 : 0, n_dist, n_pts);
+}
+
+// Every other pair: one wave per core grid g_i with more than kSmallSet core
+// points, in the visiting order.  It takes the neighbouring core grids g_j
+// that are tiny (those pairs are tested from this side) or that come later
+// in the order, drops the ones already in g_i's set (each lane resolves its
+// candidate's root in the same round) and runs FastMerging on the wave for
+// each remaining pair, unioning on yes.
+template <int D>
+__global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+                                                           const uint32_t* __restrict__ nei,
+                                                           const uint32_t* __restrict__ ldf,
+                                                           const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
+                                                           uint32_t words, double eps, uint32_t* parent,
+                                                           MergeStats* stats, uint32_t* err) {
     extern __shared__ uint64_t smem[];
     const int lane = lane_id();
     const int wpb = (int)(blockDim.x / kWave);
     const int w = wave_id();
-    const int64_t r = (int64_t)blockIdx.x * wpb + w;
-    if (r >= ncc) return;
+    const int64_t r = r0 + (int64_t)blockIdx.x * wpb + w;
+    if (r >= r1) return;
     const uint32_t T = (uint32_t)gv.T;
     const uint32_t ci = ldf[r];
-    PointSet si{co.ccrd, gv.n, co.core_start[ci], co.core_start[ci + 1] - co.core_start[ci],
+    const int64_t P = co.cstride;
+    PointSet si{co.ccrd, 1, P, co.core_start[ci], co.core_start[ci + 1] - co.core_start[ci],
                 smem + (int64_t)w * 2 * words, 0};
+    if (si.m <= kSmallSet) return;
     si.words = (si.m + kWave - 1) / kWave;
-    PointSet sj{co.ccrd, gv.n, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
+    PointSet sj{co.ccrd, 1, P, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
-    // Root of g_i, found by every lane at once (one address per step).
     uint32_t ri = uf_find(parent, ci);
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
-        uint32_t cj = 0;
+        uint32_t cj = 0, bj = 0, mj = 0;
         bool cand = false;
         if (idx < e1) {
             cj = nei[idx];
             const uint32_t rj = rank[cj];
-            cand = rj != kNone && rj > (uint32_t)r;
+            if (rj != kNone) {
+                bj = co.core_start[cj];
+                mj = co.core_start[cj + 1] - bj;
+                cand = mj <= kSmallSet || rj > (uint32_t)r;
+            }
         }
-        // Each lane resolves its own candidate's root: the pairs already in
-        // one set are dropped in a single parallel round.
-        bool pend_l = cand && uf_find(parent, cj) != ri;
+        const bool pend_l = cand && uf_find(parent, cj) != ri;
         const uint64_t cands = ballot(cand);
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
@@ -303,8 +409,8 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GridView gv, CoreOut co, 
             const int l = ffs64(pend);
             pend &= pend - 1ull;
             const uint32_t j = readlane(cj, l);
-            sj.base = co.core_start[j];
-            sj.m = co.core_start[j + 1] - sj.base;
+            sj.base = readlane(bj, l);
+            sj.m = readlane(mj, l);
             sj.words = (sj.m + kWave - 1) / kWave;
             uint32_t it = 0;
             const int yes = fast_merging<D>(si, sj, 0u, T, eps, n_dist, it);
@@ -330,25 +436,23 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(GridView gv, CoreOut co, 
             }
         }
     }
-    if (stats && lane == 0) {
-        // counters are spread over kStatSlots copies (summed on the host) so
-        // that same-address atomics do not serialise the kernel
-        MergeStats* sl = stats + ((uint64_t)r & (kStatSlots - 1));
-        atomicAdd(&sl->pairs, n_pairs);
-        atomicAdd(&sl->skipped, n_skip);
-        atomicAdd(&sl->tests, n_test);
-        atomicAdd(&sl->yes, n_yes);
-        atomicAdd(&sl->iters, n_iter);
-        atomicAdd(&sl->dists, n_dist);
-        atomicMax(&sl->max_iters, max_it);
-        atomicAdd(&sl->set_points, n_pts);
-    }
+    if (stats && lane == 0) flush_stats(stats, r, n_pairs, n_skip, n_test, n_yes, n_iter, max_it, n_dist, n_pts);
 }
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                        const uint32_t* ldf_list, const uint32_t* rank, int64_t ncc, int64_t max_core, int64_t eps,
-                        uint32_t* parent, MergeStats* stats, uint32_t* err, hipStream_t st) {
+                        const uint32_t* ldf_list, const uint32_t* rank, int64_t ncc, int64_t n_small, int64_t max_core,
+                        int64_t eps, uint32_t* parent, MergeStats* stats, uint32_t* err, hipStream_t st) {
     if (ncc == 0) return hipSuccess;
+    // n_small >= 0: the visiting order puts the n_small tiny core grids first
+    // (ascending core count); otherwise every wave checks its grid's size.
+    const int64_t s1 = n_small >= 0 ? n_small : ncc;
+    const int64_t b0 = n_small >= 0 ? n_small : 0;
+    if (s1 > 0) {
+        const unsigned blocks = (unsigned)((s1 + kWavesPerBlock - 1) / kWavesPerBlock);
+        GD_DISPATCH_D(g.d, (merge_small_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, c, nei_off, nei, ldf_list, rank, 0, s1, parent, stats)));
+    }
+    if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
     const uint32_t words = (uint32_t)((max_core + kWave - 1) / kWave);
     int wpb = kWavesPerBlock;
     size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
@@ -357,9 +461,9 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
         lds = (size_t)2 * words * sizeof(uint64_t);
     }
     if (lds > 65536) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)((ncc + wpb - 1) / wpb);
-    GD_DISPATCH_D(g.d, (merge_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                           g, c, nei_off, nei, ldf_list, rank, ncc, words, (double)eps, parent, stats, err)));
+    const unsigned blocks = (unsigned)((ncc - b0 + wpb - 1) / wpb);
+    GD_DISPATCH_D(g.d, (merge_big_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                           g, c, nei_off, nei, ldf_list, rank, b0, ncc, words, (double)eps, parent, stats, err)));
     return hipGetLastError();
 }
 
@@ -374,8 +478,8 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     const int w = wave_id();
     const int64_t r = (int64_t)blockIdx.x * wpb + w;
     if (r >= npairs) return;
-    PointSet a{pts, m, pairs[4 * r], pairs[4 * r + 1], smem + (int64_t)w * 2 * words, 0};
-    PointSet b{pts, m, pairs[4 * r + 2], pairs[4 * r + 3], smem + (int64_t)w * 2 * words + words, 0};
+    PointSet a{pts, m, 1, pairs[4 * r], pairs[4 * r + 1], smem + (int64_t)w * 2 * words, 0};
+    PointSet b{pts, m, 1, pairs[4 * r + 2], pairs[4 * r + 3], smem + (int64_t)w * 2 * words + words, 0};
     a.words = (a.m + kWave - 1) / kWave;
     b.words = (b.m + kWave - 1) / kWave;
     unsigned long long nd = 0;
