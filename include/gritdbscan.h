@@ -117,6 +117,32 @@ void gd_destroy(gd_ctx *ctx);
 int dbscan(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps,
            int32_t minpts, int32_t *labels, uint8_t *core_flags, void *stream);
 
+/* One instance of a batch (dbscan_batched).  Pointers are DEVICE pointers
+ * with the same meaning as dbscan()'s arguments. */
+typedef struct {
+    const float *points;   /* n*d float32 row-major, integer-valued, |x| <= 2^24 */
+    int64_t n;
+    int32_t d;             /* 1 <= d <= GD_D_MAX; instances may differ */
+    int32_t minpts;        /* >= 1 */
+    double eps;            /* positive integer <= GD_EPS_MAX */
+    int32_t *labels;       /* n int32 out: smallest core index of the cluster
+                              (an index into this instance's points) or -1 */
+    uint8_t *core_flags;   /* n uint8 out */
+} gd_instance;
+
+#define GD_BATCH_MAX 65536
+
+/*
+ * dbscan_batched: cluster `count` independent instances (HOST array of
+ * descriptors) in one pass of the pipeline: every phase is launched once for
+ * the whole batch.  Each instance gets exactly the result dbscan() would
+ * give it.  The instances' points, labels and flags are DEVICE memory owned
+ * by the caller; the sum of n must stay below 2^31.  Synchronous on
+ * `stream`.  On error no output is valid; gd_last_error() names the first
+ * offending instance.
+ */
+int dbscan_batched(gd_ctx *ctx, const gd_instance *inst, int32_t count, void *stream);
+
 /* Options (gd_set_option). */
 typedef enum {
     GD_OPT_STATS = 1,         /* 1: count merge/core work into gd_stats (slower) */
@@ -187,6 +213,65 @@ int gd_debug_core(gd_ctx *ctx, uint8_t *core_flags_sorted, int32_t *grid_label);
  */
 int gd_merge_test(gd_ctx *ctx, const int32_t *points, int64_t m, int32_t d, double eps, const uint32_t *pairs,
                   int64_t npairs, uint8_t *answers, uint32_t *iterations, void *stream);
+
+/*
+ * Learned proposal (this project's addition to the method).  A
+ * 16 -> 64 -> 64 -> 2 ReLU perceptron scores pairs of neighbouring core
+ * grids: output 0 is the logit that they merge, output 1 the logit that
+ * FastMerging is cheaper started from the second grid.  With a proposal set,
+ * the merge step tests each chunk's remaining pairs in descending merge
+ * logit and starts FastMerging on the side and at the point the proposal
+ * picks.  FastMerging still decides every pair exactly (Theorem 2): labels
+ * and core flags are identical with and without a proposal.
+ *
+ * Parameter vector (GD_MLP_PARAMS values): W1 [64 x 16] row-major, b1 [64],
+ * W2 [64 x 64], b2 [64], W3 [2 x 64], b3 [2]; the blob is these in IEEE
+ * binary16, the master copy in float32.
+ */
+#define GD_MLP_PARAMS 5378
+#define GD_MLP_FEATURES 16
+
+/* Use the FP16 blob (HOST, GD_MLP_PARAMS halves) in later dbscan() /
+ * dbscan_batched() calls; NULL switches the proposal off. */
+int gd_set_proposal(gd_ctx *ctx, const uint16_t *fp16_params);
+
+/*
+ * Harvest training pairs from the last successful dbscan() call: core grid
+ * pairs (a, b), a < b, each kept when a hash of (a, b, seed) is divisible by
+ * keep_mod, at most `cap` of them.  For each pair FastMerging runs from a's
+ * first core point (the plain method), from a's and from b's starting
+ * candidate.  Outputs (DEVICE): features [cap x 16] FP16, targets [cap x 3]
+ * float32 (merged, b-side cheaper, sides differ), costs [cap x 3] float32
+ * distance evaluations of the three runs (may be NULL).  *count (HOST)
+ * receives the number of pairs written.
+ */
+int gd_proposal_harvest(gd_ctx *ctx, uint32_t seed, uint32_t keep_mod, int64_t cap, uint16_t *features,
+                        float *targets, float *costs, int64_t *count, void *stream);
+
+/*
+ * Train the scorer on the GPU: `steps` Adam steps (beta 0.9 / 0.999) over
+ * mini-batches of `batch` samples; order (DEVICE, steps*batch indices into
+ * the S samples) fixes the batches.  params / adam_m / adam_v (DEVICE,
+ * GD_MLP_PARAMS float32 each) are read and updated; adam_t0 is the number of
+ * steps they already took.  loss (DEVICE, steps floats) receives each step's
+ * mean loss; blob (DEVICE, GD_MLP_PARAMS halves) the final FP16 weights.
+ * Either may be NULL.  The forward pass uses the weights rounded to FP16,
+ * FP16 inputs and hidden activations, FP32 accumulation.
+ */
+int gd_mlp_train(gd_ctx *ctx, const uint16_t *features, const float *targets, int64_t S, const uint32_t *order,
+                 int32_t steps, int32_t batch, float lr, int32_t adam_t0, float *params, float *adam_m,
+                 float *adam_v, float *loss, uint16_t *blob, void *stream);
+
+/* Gradient (DEVICE out, GD_MLP_PARAMS float32) and mean loss (DEVICE out, 1
+ * float) of one batch (the samples order[0..batch)), with the training
+ * kernel's arithmetic and no update. */
+int gd_mlp_grad(gd_ctx *ctx, const uint16_t *features, const float *targets, const uint32_t *order,
+                int32_t batch, const float *params, float *grad, float *loss, void *stream);
+
+/* Scorer logits (DEVICE out, B x 2 float32) for features (DEVICE, B x 16
+ * FP16) with the FP16 parameter blob (DEVICE). */
+int gd_mlp_forward(gd_ctx *ctx, const uint16_t *features, int64_t B, const uint16_t *blob, float *logits,
+                   void *stream);
 
 /* Text of the last error on this context ("" if none).  The pointer stays
  * valid until the next call on the context. */

@@ -42,11 +42,20 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
+                ("minpts", ctypes.c_int32), ("eps", ctypes.c_double), ("labels", ctypes.c_void_p),
+                ("core_flags", ctypes.c_void_p)]
+
+
 _lib = None
 
-EXPORTS = ("gd_create", "gd_destroy", "dbscan", "gd_set_option", "gd_get_stats",
+EXPORTS = ("gd_create", "gd_destroy", "dbscan", "dbscan_batched", "gd_set_option", "gd_get_stats",
            "gd_debug_grids", "gd_debug_neighbors", "gd_debug_core", "gd_merge_test",
-           "gd_get_phase_times", "gd_phase_name", "gd_last_error", "gd_status_string")
+           "gd_get_phase_times", "gd_phase_name", "gd_set_proposal", "gd_proposal_harvest",
+           "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string")
+MLP_PARAMS = 5378
+MLP_FEATURES = 16
 
 
 def load_library(path: str = LIB_PATH):
@@ -65,6 +74,8 @@ def load_library(path: str = LIB_PATH):
     lib.gd_destroy.restype = None
     lib.dbscan.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, vp]
     lib.dbscan.restype = ctypes.c_int
+    lib.dbscan_batched.argtypes = [vp, ctypes.POINTER(Instance), i32, vp]
+    lib.dbscan_batched.restype = ctypes.c_int
     lib.gd_set_option.argtypes = [vp, ctypes.c_int, i64]
     lib.gd_set_option.restype = ctypes.c_int
     lib.gd_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -81,6 +92,17 @@ def load_library(path: str = LIB_PATH):
     lib.gd_get_phase_times.restype = ctypes.c_int
     lib.gd_phase_name.argtypes = [i32]
     lib.gd_phase_name.restype = ctypes.c_char_p
+    lib.gd_set_proposal.argtypes = [vp, vp]
+    lib.gd_set_proposal.restype = ctypes.c_int
+    lib.gd_proposal_harvest.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, i64, vp, vp, vp,
+                                        ctypes.POINTER(i64), vp]
+    lib.gd_proposal_harvest.restype = ctypes.c_int
+    lib.gd_mlp_train.argtypes = [vp, vp, vp, i64, vp, i32, i32, ctypes.c_float, i32, vp, vp, vp, vp, vp, vp]
+    lib.gd_mlp_train.restype = ctypes.c_int
+    lib.gd_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.gd_mlp_grad.restype = ctypes.c_int
+    lib.gd_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.gd_mlp_forward.restype = ctypes.c_int
     lib.gd_last_error.argtypes = [vp]
     lib.gd_last_error.restype = ctypes.c_char_p
     lib.gd_status_string.argtypes = [ctypes.c_int]
@@ -158,6 +180,84 @@ class Context:
                                    _ptr(labels), _ptr(core_flags), _stream_handle(stream))
         self._check(rc)
         return labels, core_flags
+
+    def dbscan_batched(self, problems, stream=None):
+        """Cluster many instances in one pass.  ``problems``: list of
+        (points float32 [n_k, d_k] on the device, eps_k, minpts_k).  Returns
+        a list of (labels, core_flags) device tensors, one per instance."""
+        import torch
+        descs = (Instance * max(len(problems), 1))()
+        outs, keep = [], []
+        for k, (pts, eps, minpts) in enumerate(problems):
+            if pts.dtype != torch.float32 or pts.dim() != 2 or pts.device.type != "cuda":
+                raise ValueError(f"instance {k}: points must be a float32 [n, d] GPU tensor")
+            pts = pts.contiguous()
+            n, d = pts.shape
+            lab = torch.empty(n, dtype=torch.int32, device=pts.device)
+            core = torch.empty(n, dtype=torch.uint8, device=pts.device)
+            descs[k] = Instance(_ptr(pts) if n else None, int(n), int(d), int(minpts), float(eps),
+                                _ptr(lab) if n else None, _ptr(core) if n else None)
+            keep.append(pts)
+            outs.append((lab, core))
+        rc = load_library().dbscan_batched(self._h, descs, len(problems), _stream_handle(stream))
+        self._check(rc)
+        return outs
+
+    def set_proposal(self, fp16_params):
+        """Use the learned proposal (numpy float16 [5378]); None switches it off."""
+        lib = load_library()
+        if fp16_params is None:
+            self._check(lib.gd_set_proposal(self._h, None))
+            return
+        blob = np.ascontiguousarray(np.asarray(fp16_params, dtype=np.float16))
+        if blob.shape != (MLP_PARAMS,):
+            raise ValueError(f"proposal needs {MLP_PARAMS} FP16 values")
+        self._check(lib.gd_set_proposal(self._h, blob.ctypes.data))
+
+    def harvest(self, cap: int, keep_mod: int = 1, seed: int = 0, stream=None):
+        """Training pairs from the last dbscan() call: (features fp16 [k,16],
+        targets f32 [k,3], costs f32 [k,3]) device tensors."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        X = torch.empty((max(cap, 1), MLP_FEATURES), dtype=torch.float16, device=dev)
+        T = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        C = torch.empty((max(cap, 1), 3), dtype=torch.float32, device=dev)
+        cnt = ctypes.c_int64()
+        rc = load_library().gd_proposal_harvest(self._h, int(seed), int(keep_mod), int(cap), _ptr(X), _ptr(T),
+                                                _ptr(C), ctypes.byref(cnt), _stream_handle(stream))
+        self._check(rc)
+        k = cnt.value
+        return X[:k], T[:k], C[:k]
+
+    def mlp_train(self, X, T, order, steps: int, batch: int, lr: float, params, adam_m, adam_v,
+                  adam_t0: int = 0, stream=None):
+        """Adam steps on the GPU; returns (losses f32 [steps], blob fp16 [5378])."""
+        import torch
+        loss = torch.empty(max(steps, 1), dtype=torch.float32, device=params.device)
+        blob = torch.empty(MLP_PARAMS, dtype=torch.float16, device=params.device)
+        rc = load_library().gd_mlp_train(self._h, _ptr(X), _ptr(T), int(X.shape[0]), _ptr(order), int(steps),
+                                         int(batch), float(lr), int(adam_t0), _ptr(params), _ptr(adam_m),
+                                         _ptr(adam_v), _ptr(loss), _ptr(blob), _stream_handle(stream))
+        self._check(rc)
+        return loss[:steps], blob
+
+    def mlp_grad(self, X, T, order, batch: int, params, stream=None):
+        """(gradient f32 [5378], mean loss) of one batch, no update."""
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=params.device)
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        rc = load_library().gd_mlp_grad(self._h, _ptr(X), _ptr(T), _ptr(order), int(batch), _ptr(params),
+                                        _ptr(g), _ptr(loss), _stream_handle(stream))
+        self._check(rc)
+        return g, float(loss.item())
+
+    def mlp_forward(self, X, blob, stream=None):
+        import torch
+        Z = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+        rc = load_library().gd_mlp_forward(self._h, _ptr(X), int(X.shape[0]), _ptr(blob), _ptr(Z),
+                                           _stream_handle(stream))
+        self._check(rc)
+        return Z
 
     def stats(self) -> dict:
         s = Stats()

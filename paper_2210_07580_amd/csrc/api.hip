@@ -1,8 +1,10 @@
 // C ABI of the library (include/gritdbscan.h): argument checks, workspace,
-// and the launch sequence of Algorithm 6 with the LDF merge order.
+// and the launch sequence of Algorithm 6 (with the LDF merge order) for a
+// batch of instances; dbscan() is a batch of one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -12,6 +14,7 @@
 
 #include "gritdbscan.h"
 #include "launch.hpp"
+#include "learned.hpp"
 #include "radix.hpp"
 #include "scan.hpp"
 
@@ -19,15 +22,8 @@ using namespace gd;
 
 namespace {
 
-// Small results the host reads back between phases.
-struct Info {
-    int mn[kMaxD];
-    int mx[kMaxD];
-    uint32_t err;
-    uint32_t ncell;
-    uint32_t level_count[kMaxD];
-    uint32_t counts[5];  // ncore, core grids, max core points per grid, dense grids, tiny core grids
-    uint64_t nei_total;
+// Device counters of the optional statistics.
+struct StatBlock {
     MergeStats merge[kStatSlots];
     unsigned long long core_dist[kStatSlots];
 };
@@ -35,11 +31,6 @@ struct Info {
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
-};
-
-class Status {
-   public:
-    int code = GD_OK;
 };
 
 enum Phase {
@@ -56,10 +47,15 @@ const char* const kPhaseNames[P_COUNT] = {
 struct gd_ctx {
     int device = 0;
     std::string err;
-    DevBuf arena;      // everything sized by n and d
-    DevBuf nei;        // the neighbour lists, sized by their total
-    Info* info_dev = nullptr;
-    Info* info_host = nullptr;
+    DevBuf arena;  // everything sized by the batch's points and dimension
+    DevBuf nei;    // the neighbour lists, sized by their total
+    Header* hdr_dev = nullptr;
+    Header* hdr_host = nullptr;  // pinned
+    StatBlock* stats_dev = nullptr;
+    StatBlock* stats_host = nullptr;  // pinned
+    Inst* inst_dev = nullptr;
+    Inst* inst_host = nullptr;  // pinned
+    int inst_cap = 0;
     int64_t ws_limit = 0;
     bool stats = false;
     bool ldf = true;
@@ -72,10 +68,20 @@ struct gd_ctx {
     const uint32_t* last_sidx = nullptr;
     const uint32_t* last_cell_start = nullptr;
     const int32_t* last_ck = nullptr;
+    int64_t last_ck_stride = 0;
     const uint64_t* last_nei_off = nullptr;
     const uint32_t* last_nei = nullptr;
     const uint8_t* last_core = nullptr;
     const int32_t* last_cell_label = nullptr;
+    GridView last_g{};
+    CoreOut last_co{};
+    int64_t last_max_core = 0;
+    bool last_summaries = false;
+    // learned proposal
+    __half* proposal_dev = nullptr;  // GD_MLP_PARAMS halves
+    bool proposal_on = false;
+    DevBuf sumbuf;                   // CellSummary per grid
+    unsigned long long* counter_dev = nullptr;
     // phase timing
     bool timing = false;
     bool events_ok = false;
@@ -114,9 +120,9 @@ struct DeviceGuard {
     }
 };
 
-#define GD_TRY(call)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
+#define GD_TRY(call)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (call);                                                                             \
         if (e_ != hipSuccess) return ctx->fail(GD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
@@ -156,13 +162,6 @@ int grow(gd_ctx* ctx, DevBuf& b, size_t need, size_t other_held) {
 
 int bit_length(uint64_t v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
 
-uint64_t isqrt_u64(uint64_t y) {
-    uint64_t r = (uint64_t)std::sqrt((double)y);
-    while (r * r > y) --r;
-    while ((r + 1) * (r + 1) <= y) ++r;
-    return r;
-}
-
 // Workspace layout; with base == nullptr it only measures.
 struct Layout {
     uint32_t* vals_a;
@@ -176,8 +175,8 @@ struct Layout {
     uint32_t* cell_start;
     int32_t* ck;
     uint32_t* level_excl;
-    int32_t* tkey[kMaxD];
-    uint32_t* tchild[kMaxD];
+    int32_t* tkey[kMaxLevels];
+    uint32_t* tchild[kMaxLevels];
     uint32_t* off_counts;
     uint64_t* nei_off;
     uint8_t* core;
@@ -194,7 +193,7 @@ struct Layout {
     size_t bytes;
 };
 
-Layout carve(char* base, int64_t n, int d) {
+Layout carve(char* base, int64_t n, int D) {
     Layout L{};
     Carve c{base};
     L.keys_a = c.take<uint64_t>(n);
@@ -204,21 +203,21 @@ Layout carve(char* base, int64_t n, int d) {
     const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)kRadixBins * radix_tiles(n));
     L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
     L.partial = c.take<uint64_t>(scan_blocks(big_scan) + 4);
-    L.crd = c.take<int32_t>((int64_t)d * n);
+    L.crd = c.take<int32_t>((int64_t)D * n);
     L.excl = c.take<uint32_t>(n + 1);
     L.cell_start = c.take<uint32_t>(n + 1);
-    L.ck = c.take<int32_t>((int64_t)d * n);
-    L.level_excl = c.take<uint32_t>((int64_t)std::max(d - 1, 1) * (n + 1));
-    for (int l = 0; l + 1 < d; ++l) {
+    L.ck = c.take<int32_t>((int64_t)(D + 1) * n);
+    L.level_excl = c.take<uint32_t>((int64_t)D * (n + 1));
+    for (int l = 0; l < D; ++l) {
         L.tkey[l] = c.take<int32_t>(n);
         L.tchild[l] = c.take<uint32_t>(n + 1);
     }
-    L.off_counts = c.take<uint32_t>((int64_t)d * n);
+    L.off_counts = c.take<uint32_t>((int64_t)D * n);
     L.nei_off = c.take<uint64_t>(n + 1);
     L.core = c.take<uint8_t>(n);
     L.core_excl = c.take<uint32_t>(n + 1);
     L.core_start = c.take<uint32_t>(n + 1);
-    L.ccrd = c.take<int32_t>((int64_t)(d <= 4 ? 4 : 8) * n);
+    L.ccrd = c.take<int32_t>((int64_t)(D <= 4 ? 4 : 8) * n);
     L.corig = c.take<uint32_t>(n);
     L.cell_min_core = c.take<uint32_t>(n);
     L.list = c.take<uint32_t>(n);
@@ -230,155 +229,146 @@ Layout carve(char* base, int64_t n, int d) {
     return L;
 }
 
+int readback(gd_ctx* ctx, hipStream_t st) {
+    GD_TRY(hipMemcpyAsync(ctx->hdr_host, ctx->hdr_dev, sizeof(Header), hipMemcpyDeviceToHost, st));
+    GD_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+}
+
 template <typename K>
-int run_partition(gd_ctx* ctx, const float* x, int64_t n, const KeyParams& kp, int key_bits, Layout& L,
-                  const uint32_t** sidx_out, hipStream_t st) {
+int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const uint32_t** sidx_out, hipStream_t st) {
     K* ka = (K*)L.keys_a;
     K* kb = (K*)L.keys_b;
     ctx->mark(P_KEYS, 0);
-    GD_TRY(launch_keys<K>(x, n, kp, ka, st));
+    GD_TRY(launch_keys<K>(b, ka, st));
     ctx->mark(P_KEYS, 1);
     RadixResult<K> res;
     ctx->mark(P_SORT, 0);
-    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, n, key_bits, true, L.radix_scratch, st, &res));
+    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, b.n, key_bits, true, L.radix_scratch, st, &res));
     ctx->mark(P_SORT, 1);
     ctx->mark(P_GATHER, 0);
-    GD_TRY(launch_gather(x, n, kp, res.vals, L.crd, st));
+    GD_TRY(launch_gather(b, res.vals, L.crd, st));
     ctx->mark(P_GATHER, 1);
     ctx->mark(P_CELLS, 0);
-    GD_TRY(launch_cells<K>(res.keys, n, kp, L.excl, (uint32_t*)L.partial, &ctx->info_dev->ncell, L.cell_start,
-                           (uint32_t*)nullptr, L.ck, n, st));
+    GD_TRY(launch_cells<K>(b, res.keys, L.excl, (uint32_t*)L.partial, L.cell_start, L.ck, b.n, st));
     ctx->mark(P_CELLS, 1);
     *sidx_out = res.vals;
     return GD_OK;
 }
 
-int readback(gd_ctx* ctx, hipStream_t st) {
-    GD_TRY(hipMemcpyAsync(ctx->info_host, ctx->info_dev, sizeof(Info), hipMemcpyDeviceToHost, st));
-    GD_TRY(hipStreamSynchronize(st));
-    return GD_OK;
-}
-
-int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps_d, int32_t minpts, int32_t* labels,
-               uint8_t* core_flags, hipStream_t st) {
-    if (n < 0 || n >= ((int64_t)1 << 31)) return ctx->fail(GD_EINVAL, "n = %lld out of range [0, 2^31)", (long long)n);
-    if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "d = %d out of range [1, %d]", d, GD_D_MAX);
-    if (!(eps_d > 0) || !std::isfinite(eps_d) || eps_d != std::floor(eps_d))
-        return ctx->fail(GD_EINVAL, "eps = %g must be a positive integer", eps_d);
-    if (eps_d > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "eps = %g exceeds %d", eps_d, GD_EPS_MAX);
-    if (minpts < 1) return ctx->fail(GD_EINVAL, "minpts = %d must be >= 1", minpts);
-    if (n > 0 && (!points || !labels || !core_flags)) return ctx->fail(GD_EINVAL, "NULL device pointer");
-    const int64_t eps = (int64_t)eps_d;
+// Validated batch in ctx->inst_host[0..count): run every phase.
+int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream_t st) {
     ctx->have_last = false;
     std::memset(&ctx->last, 0, sizeof(ctx->last));
     ctx->last.n = n;
-    ctx->last.d = d;
+    ctx->last.d = D;
     if (n == 0) return GD_OK;
 
     // ---- workspace
-    Layout L = carve(nullptr, n, d);
+    Layout L = carve(nullptr, n, D);
     int rc = grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
     if (rc) return rc;
-    L = carve((char*)ctx->arena.p, n, d);
-    Info* I = ctx->info_dev;
-    Info* H = ctx->info_host;
+    L = carve((char*)ctx->arena.p, n, D);
+    Header* Hd = ctx->hdr_dev;
+    Header* H = ctx->hdr_host;
 
-    // ---- mn_j and the input check (Eq. (1))
+    Batch b{};
+    b.inst = ctx->inst_dev;
+    b.count = count;
+    b.D = D;
+    b.n = n;
+    b.tiles = tiles;
+    b.hdr = Hd;
+
     ctx->st = st;
     for (int p = 0; p < P_COUNT; ++p) {
         ctx->ran[p] = false;
         ctx->phase_ms[p] = 0.0;
     }
+
+    // ---- instance table, mn_j and the input check (Eq. (1)), identifier layout
+    GD_TRY(hipMemcpyAsync(ctx->inst_dev, ctx->inst_host, sizeof(Inst) * count, hipMemcpyHostToDevice, st));
+    GD_TRY(fill<uint32_t>((uint32_t*)Hd, (int64_t)(sizeof(Header) / sizeof(uint32_t)), 0u, st));
+    if (ctx->stats)
+        GD_TRY(fill<unsigned long long>(&ctx->stats_dev->merge[0].pairs,
+                                        (int64_t)(sizeof(StatBlock) / sizeof(unsigned long long)), 0ull, st));
     ctx->mark(P_MINMAX, 0);
-    GD_TRY(launch_minmax(points, n, d, I->mn, I->mx, &I->err, st));
+    GD_TRY(launch_minmax(b, st));
+    GD_TRY(launch_layout(b, st));
     ctx->mark(P_MINMAX, 1);
-    if (ctx->stats) {
-        GD_TRY(fill<unsigned long long>(&I->merge[0].pairs, (int64_t)(sizeof(I->merge) / sizeof(unsigned long long)), 0ull, st));
-        GD_TRY(fill<unsigned long long>(I->core_dist, kStatSlots, 0ull, st));
-    }
     if ((rc = readback(ctx, st))) return rc;
-    if (H->err & kErrNotInteger)
-        return ctx->fail(GD_ERANGE, "a coordinate is not a finite integer of magnitude <= 2^24");
-    KeyParams kp{};
-    kp.d = d;
-    kp.eps = eps;
-    int key_bits = 0;
-    for (int j = 0; j < d; ++j) {
-        kp.mn[j] = H->mn[j];
-        const uint64_t u = (uint64_t)((int64_t)H->mx[j] - H->mn[j]);
-        const uint64_t kmax = isqrt_u64((uint64_t)d * u * u) / (uint64_t)eps;
-        kp.bits[j] = bit_length(kmax);
-        key_bits += kp.bits[j];
+    if (H->err & kErrNotInteger) {
+        GD_TRY(hipMemcpyAsync(ctx->inst_host, ctx->inst_dev, sizeof(Inst) * count, hipMemcpyDeviceToHost, st));
+        GD_TRY(hipStreamSynchronize(st));
+        int bad = 0;
+        while (bad < count && !(ctx->inst_host[bad].err & kErrNotInteger)) ++bad;
+        return ctx->fail(GD_ERANGE, "instance %d: a coordinate is not a finite integer of magnitude <= 2^24", bad);
     }
-    if (key_bits > 64)
+    if (H->err & kErrKeyBits)
         return ctx->fail(GD_ERANGE, "grid identifiers need %d bits (> 64): eps too small for the data's extent",
-                         key_bits);
-    for (int j = d - 1, s = 0; j >= 0; --j) {
-        kp.shift[j] = s;
-        s += kp.bits[j];
-    }
+                         H->total_bits);
+    const int key_bits = H->total_bits;
     ctx->last.key_bits = key_bits;
 
     // ---- Algorithm 1: identifiers, radix sort, grids
     const uint32_t* sidx = nullptr;
     if (key_bits <= 32)
-        rc = run_partition<uint32_t>(ctx, points, n, kp, key_bits, L, &sidx, st);
+        rc = run_partition<uint32_t>(ctx, b, key_bits, L, &sidx, st);
     else
-        rc = run_partition<uint64_t>(ctx, points, n, kp, key_bits, L, &sidx, st);
+        rc = run_partition<uint64_t>(ctx, b, key_bits, L, &sidx, st);
     if (rc) return rc;
     if ((rc = readback(ctx, st))) return rc;
     const int64_t ncell = H->ncell;
 
     GridView g{};
+    g.b = b;
     g.n = n;
-    g.d = d;
-    g.T = eps * eps;
-    g.minpts = minpts;
+    g.D = D;
     g.crd = L.crd;
     g.sidx = sidx;
     g.ncell = ncell;
+    g.ncell_dev = &Hd->ncell;
     g.cell_start = L.cell_start;
     g.ck = L.ck;
     g.ck_stride = n;
 
     // ---- Algorithm 2 (grid tree) and Algorithm 3 (Nei for every grid)
     ctx->mark(P_TREE, 0);
-    GD_TRY(launch_tree(g, kp, L.level_excl, (uint32_t*)L.partial, I->level_count, L.tkey, L.tchild, st));
+    GD_TRY(launch_tree(g, L.level_excl, (uint32_t*)L.partial, L.tkey, L.tchild, st));
     ctx->mark(P_TREE, 1);
     TreeView t{};
-    for (int l = 0; l + 1 < d; ++l) {
+    for (int l = 0; l < D; ++l) {
         t.key[l] = L.tkey[l];
         t.child[l] = L.tchild[l];
     }
-    t.key[d - 1] = L.ck + (int64_t)(d - 1) * n;
-    t.level_count = I->level_count;
+    t.key[D] = L.ck + (int64_t)D * n;
+    t.level_count = Hd->level_count;
     ctx->mark(P_NEI_COUNT, 0);
     GD_TRY(launch_nei_count(g, t, L.off_counts, st));
     GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
     ctx->mark(P_NEI_COUNT, 1);
-    GD_TRY(hipMemcpyAsync(&I->nei_total, L.nei_off + ncell, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     if ((rc = readback(ctx, st))) return rc;
     const uint64_t nei_total = H->nei_total;
     if ((rc = grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t), ctx->arena.cap)))
         return rc;
     uint32_t* nei = (uint32_t*)ctx->nei.p;
     ctx->mark(P_NEI_FILL, 0);
-    GD_TRY(launch_nei_fill(g, t, L.off_counts, L.nei_off, nei, st));
+    GD_TRY(launch_nei_fill(g, t, L.off_counts, L.nei_off, nei, nei_total, st));
     ctx->mark(P_NEI_FILL, 1);
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? I->core_dist : nullptr, st));
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? ctx->stats_dev->core_dist : nullptr, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
     co.core_excl = L.core_excl;
     co.core_start = L.core_start;
     co.ccrd = L.ccrd;
-    co.cstride = d <= 4 ? 4 : 8;
+    co.cstride = D <= 4 ? 4 : 8;
     co.corig = L.corig;
     co.cell_min_core = L.cell_min_core;
-    co.counts = I->counts;
+    co.counts = Hd->counts;
     ctx->mark(P_CORE_COMPACT, 0);
     GD_TRY(launch_core_compact(g, co, (uint32_t*)L.partial, st));
     ctx->mark(P_CORE_COMPACT, 1);
@@ -402,10 +392,22 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
                 hipGetLastError()));
         ctx->mark(P_LDF, 1);
     }
+    CellSummary* sum = nullptr;
+    ctx->last_summaries = false;
+    if (ctx->proposal_on) {
+        if ((rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(ncell, 1),
+                       ctx->arena.cap + ctx->nei.cap)))
+            return rc;
+        sum = (CellSummary*)ctx->sumbuf.p;
+    }
     ctx->mark(P_MERGE, 0);
+    if (sum) {
+        GD_TRY(launch_summaries(g, co, sum, st));
+        ctx->last_summaries = true;
+    }
     GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, ctx->ldf ? (int64_t)H->counts[4] : -1, max_core,
-                        eps, L.parent,
-                        ctx->stats ? I->merge : nullptr, &I->err, st));
+                        L.parent, ctx->stats ? ctx->stats_dev->merge : nullptr,
+                        ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
     ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);
     GD_TRY(launch_labels(g, co, L.parent, L.root_min, L.cell_label, st));
@@ -413,9 +415,14 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
 
     // ---- border / noise, output in input order
     ctx->mark(P_OUTPUT, 0);
-    GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, labels, core_flags, st));
+    GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
     ctx->mark(P_OUTPUT, 1);
+    if (ctx->stats)
+        GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
     if ((rc = readback(ctx, st))) return rc;
+    if (H->err & kErrMergeRunaway) return ctx->fail(GD_EDEVICE, "merge step exceeded its iteration bound");
+    if (H->err & (kErrNeiOverflow | kErrCoreCap))
+        return ctx->fail(GD_EDEVICE, "internal capacity check failed (error bits 0x%x)", H->err);
     if (ctx->timing && ctx->events_ok) {
         for (int p = 0; p < P_COUNT; ++p) {
             float ms = 0.f;
@@ -423,20 +430,23 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
                 ctx->phase_ms[p] = ms;
         }
     }
-    if (H->err & kErrMergeRunaway) return ctx->fail(GD_EDEVICE, "merge step exceeded its iteration bound");
 
     ctx->have_last = true;
     ctx->last_n = n;
-    ctx->last_d = d;
+    ctx->last_d = D;
     ctx->last_ncell = ncell;
     ctx->last_nei_total = nei_total;
     ctx->last_sidx = sidx;
     ctx->last_cell_start = L.cell_start;
     ctx->last_ck = L.ck;
+    ctx->last_ck_stride = n;
     ctx->last_nei_off = L.nei_off;
     ctx->last_nei = nei;
     ctx->last_core = L.core;
     ctx->last_cell_label = L.cell_label;
+    ctx->last_g = g;
+    ctx->last_co = co;
+    ctx->last_max_core = max_core;
 
     gd_stats& s = ctx->last;
     s.grids = ncell;
@@ -446,8 +456,9 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
     s.dense_grids = H->counts[3];
     s.max_grid_points = 0;
     if (ctx->stats) {
+        const StatBlock* sb = ctx->stats_host;
         for (int k = 0; k < kStatSlots; ++k) {
-            const MergeStats& m = H->merge[k];
+            const MergeStats& m = sb->merge[k];
             s.merge_pairs += (int64_t)m.pairs;
             s.merge_skipped += (int64_t)m.skipped;
             s.merge_tests += (int64_t)m.tests;
@@ -456,10 +467,76 @@ int run_dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double ep
             s.merge_max_iterations = std::max<int64_t>(s.merge_max_iterations, (int64_t)m.max_iters);
             s.merge_distances += (int64_t)m.dists;
             s.merge_set_points += (int64_t)m.set_points;
-            s.core_distances += (int64_t)H->core_dist[k];
+            s.core_distances += (int64_t)sb->core_dist[k];
         }
     }
     return GD_OK;
+}
+
+int check_params(gd_ctx* ctx, int k, int64_t n, int32_t d, double eps, int32_t minpts, const void* points,
+                 const void* labels, const void* core) {
+    if (n < 0 || n >= ((int64_t)1 << 31))
+        return ctx->fail(GD_EINVAL, "instance %d: n = %lld out of range [0, 2^31)", k, (long long)n);
+    if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "instance %d: d = %d out of range [1, %d]", k, d, GD_D_MAX);
+    if (!(eps > 0) || !std::isfinite(eps) || eps != std::floor(eps))
+        return ctx->fail(GD_EINVAL, "instance %d: eps = %g must be a positive integer", k, eps);
+    if (eps > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "instance %d: eps = %g exceeds %d", k, eps, GD_EPS_MAX);
+    if (minpts < 1) return ctx->fail(GD_EINVAL, "instance %d: minpts = %d must be >= 1", k, minpts);
+    if (n > 0 && (!points || !labels || !core)) return ctx->fail(GD_EINVAL, "instance %d: NULL device pointer", k);
+    return GD_OK;
+}
+
+int ensure_inst_capacity(gd_ctx* ctx, int count) {
+    if (count <= ctx->inst_cap) return GD_OK;
+    if (ctx->inst_dev) (void)hipFree(ctx->inst_dev);
+    if (ctx->inst_host) (void)hipHostFree(ctx->inst_host);
+    ctx->inst_dev = nullptr;
+    ctx->inst_host = nullptr;
+    ctx->inst_cap = 0;
+    const int cap = std::max(count, 16);
+    if (hipMalloc(&ctx->inst_dev, sizeof(Inst) * cap) != hipSuccess ||
+        hipHostMalloc(&ctx->inst_host, sizeof(Inst) * cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return ctx->fail(GD_ENOMEM, "instance table allocation failed");
+    }
+    ctx->inst_cap = cap;
+    return GD_OK;
+}
+
+// Fill an instance record from the caller's description.
+void set_inst(Inst& I, const float* x, int64_t n, int32_t d, double eps, int32_t minpts, int32_t* labels,
+              uint8_t* core) {
+    std::memset(&I, 0, sizeof(I));
+    I.x = x;
+    I.labels = labels;
+    I.core = core;
+    I.n = n;
+    I.d = d;
+    I.eps = (int64_t)eps;
+    I.T = (uint32_t)(I.eps * I.eps);
+    I.minpts = minpts;
+    for (int j = 0; j < kMaxD; ++j) {
+        I.mn[j] = INT_MAX;
+        I.mx[j] = INT_MIN;
+    }
+}
+
+// Global offsets and point tiles of the instances.
+void finish_table(gd_ctx* ctx, int count, int* D, int64_t* n, uint32_t* tiles) {
+    int64_t off = 0;
+    uint32_t t = 0;
+    int dm = 1;
+    for (int k = 0; k < count; ++k) {
+        Inst& I = ctx->inst_host[k];
+        I.off = off;
+        I.tile0 = t;
+        off += I.n;
+        t += (uint32_t)((I.n + kPointTile - 1) / kPointTile);
+        dm = std::max(dm, I.d);
+    }
+    *D = dm;
+    *n = off;
+    *tiles = t;
 }
 
 }  // namespace
@@ -473,17 +550,27 @@ int gd_create(gd_ctx** out, int device) {
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GD_EINVAL;
     gd_ctx* ctx = new gd_ctx();
     ctx->device = device;
-    DeviceGuard guard(device);
-    if (!guard.ok || hipMalloc(&ctx->info_dev, sizeof(Info)) != hipSuccess ||
-        hipHostMalloc(&ctx->info_host, sizeof(Info), hipHostMallocDefault) != hipSuccess) {
-        if (ctx->info_dev) (void)hipFree(ctx->info_dev);
-        delete ctx;
+    bool ok;
+    {
+        DeviceGuard guard(device);
+        ok = guard.ok && hipMalloc(&ctx->hdr_dev, sizeof(Header)) == hipSuccess &&
+             hipHostMalloc(&ctx->hdr_host, sizeof(Header), hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&ctx->stats_dev, sizeof(StatBlock)) == hipSuccess &&
+             hipHostMalloc(&ctx->stats_host, sizeof(StatBlock), hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&ctx->proposal_dev, sizeof(__half) * kParams) == hipSuccess &&
+             hipMalloc(&ctx->counter_dev, sizeof(unsigned long long)) == hipSuccess &&
+             ensure_inst_capacity(ctx, 16) == GD_OK;
+        if (ok) {
+            ctx->events_ok = true;
+            for (int p = 0; p < P_COUNT; ++p)
+                for (int k = 0; k < 2; ++k)
+                    if (hipEventCreate(&ctx->ev[p][k]) != hipSuccess) ctx->events_ok = false;
+        }
+    }
+    if (!ok) {
+        gd_destroy(ctx);
         return GD_EDEVICE;
     }
-    ctx->events_ok = true;
-    for (int p = 0; p < P_COUNT; ++p)
-        for (int k = 0; k < 2; ++k)
-            if (hipEventCreate(&ctx->ev[p][k]) != hipSuccess) ctx->events_ok = false;
     *out = ctx;
     return GD_OK;
 }
@@ -493,8 +580,15 @@ void gd_destroy(gd_ctx* ctx) {
     DeviceGuard guard(ctx->device);
     if (ctx->arena.p) (void)hipFree(ctx->arena.p);
     if (ctx->nei.p) (void)hipFree(ctx->nei.p);
-    if (ctx->info_dev) (void)hipFree(ctx->info_dev);
-    if (ctx->info_host) (void)hipHostFree(ctx->info_host);
+    if (ctx->hdr_dev) (void)hipFree(ctx->hdr_dev);
+    if (ctx->hdr_host) (void)hipHostFree(ctx->hdr_host);
+    if (ctx->stats_dev) (void)hipFree(ctx->stats_dev);
+    if (ctx->stats_host) (void)hipHostFree(ctx->stats_host);
+    if (ctx->inst_dev) (void)hipFree(ctx->inst_dev);
+    if (ctx->inst_host) (void)hipHostFree(ctx->inst_host);
+    if (ctx->proposal_dev) (void)hipFree(ctx->proposal_dev);
+    if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
+    if (ctx->sumbuf.p) (void)hipFree(ctx->sumbuf.p);
     for (int p = 0; p < P_COUNT; ++p)
         for (int k = 0; k < 2; ++k)
             if (ctx->ev[p][k]) (void)hipEventDestroy(ctx->ev[p][k]);
@@ -505,9 +599,44 @@ int dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, i
            uint8_t* core_flags, void* stream) {
     if (!ctx) return GD_EINVAL;
     ctx->err.clear();
+    int rc = check_params(ctx, 0, n, d, eps, minpts, points, labels, core_flags);
+    if (rc) return rc;
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    return run_dbscan(ctx, points, n, d, eps, minpts, labels, core_flags, (hipStream_t)stream);
+    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags);
+    int D;
+    int64_t total;
+    uint32_t tiles;
+    finish_table(ctx, 1, &D, &total, &tiles);
+    return run_batch(ctx, 1, D, total, tiles, (hipStream_t)stream);
+}
+
+int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (count < 0 || (count > 0 && !inst)) return ctx->fail(GD_EINVAL, "bad instance array");
+    if (count > GD_BATCH_MAX) return ctx->fail(GD_EINVAL, "count = %d exceeds %d", count, GD_BATCH_MAX);
+    int64_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        const gd_instance& q = inst[k];
+        int rc = check_params(ctx, k, q.n, q.d, q.eps, q.minpts, q.points, q.labels, q.core_flags);
+        if (rc) return rc;
+        total += q.n;
+    }
+    if (total >= ((int64_t)1 << 31)) return ctx->fail(GD_EINVAL, "batch holds %lld points (>= 2^31)", (long long)total);
+    if (count == 0) return GD_OK;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    int rc = ensure_inst_capacity(ctx, count);
+    if (rc) return rc;
+    for (int k = 0; k < count; ++k) {
+        const gd_instance& q = inst[k];
+        set_inst(ctx->inst_host[k], q.points, q.n, q.d, q.eps, q.minpts, q.labels, q.core_flags);
+    }
+    int D;
+    uint32_t tiles;
+    finish_table(ctx, count, &D, &total, &tiles);
+    return run_batch(ctx, count, D, total, tiles, (hipStream_t)stream);
 }
 
 int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
@@ -547,9 +676,12 @@ int gd_debug_grids(gd_ctx* ctx, int64_t* n_grids, uint32_t* sorted_index, uint32
     if ((rc = copy_d2h(ctx, sorted_index, ctx->last_sidx, sizeof(uint32_t) * n))) return rc;
     if ((rc = copy_d2h(ctx, grid_start, ctx->last_cell_start, sizeof(uint32_t) * (nc + 1)))) return rc;
     if (grid_ids) {
+        // rows 1..D of the identifier table (row 0 is the instance)
         std::vector<int32_t> col(nc);
         for (int j = 0; j < ctx->last_d; ++j) {
-            if ((rc = copy_d2h(ctx, col.data(), ctx->last_ck + (int64_t)j * n, sizeof(int32_t) * nc))) return rc;
+            if ((rc = copy_d2h(ctx, col.data(), ctx->last_ck + (int64_t)(j + 1) * ctx->last_ck_stride,
+                               sizeof(int32_t) * nc)))
+                return rc;
             for (int64_t c = 0; c < nc; ++c) grid_ids[c * ctx->last_d + j] = col[c];
         }
     }
@@ -602,6 +734,112 @@ int gd_merge_test(gd_ctx* ctx, const int32_t* points, int64_t m, int32_t d, doub
     }
     GD_TRY(launch_merge_pairs(points, m, d, pairs, npairs, (int64_t)eps, mx, answers, iterations, st));
     GD_TRY(hipStreamSynchronize(st));
+    return GD_OK;
+}
+
+int gd_set_proposal(gd_ctx* ctx, const uint16_t* fp16_params) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (!fp16_params) {
+        ctx->proposal_on = false;
+        return GD_OK;
+    }
+    DeviceGuard guard(ctx->device);
+    if (hipMemcpy(ctx->proposal_dev, fp16_params, sizeof(__half) * kParams, hipMemcpyHostToDevice) != hipSuccess)
+        return ctx->fail(GD_EDEVICE, "copy of the proposal weights failed");
+    ctx->proposal_on = true;
+    return GD_OK;
+}
+
+int gd_proposal_harvest(gd_ctx* ctx, uint32_t seed, uint32_t keep_mod, int64_t cap, uint16_t* features,
+                        float* targets, float* costs, int64_t* count, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to harvest from");
+    if (keep_mod < 1 || cap < 0 || (cap > 0 && (!features || !targets)) || !count)
+        return ctx->fail(GD_EINVAL, "bad harvest arguments");
+    DeviceGuard guard(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const GridView& g = ctx->last_g;
+    int rc;
+    if ((rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(g.ncell, 1),
+                   ctx->arena.cap + ctx->nei.cap)))
+        return rc;
+    CellSummary* sum = (CellSummary*)ctx->sumbuf.p;
+    GD_TRY(fill<unsigned long long>(ctx->counter_dev, 1, 0ull, st));
+    GD_TRY(launch_summaries(g, ctx->last_co, sum, st));
+    GD_TRY(launch_harvest(g, ctx->last_co, sum, ctx->last_nei_off, ctx->last_nei, seed, keep_mod, cap,
+                          ctx->last_max_core, (__half*)features, targets, costs, ctx->counter_dev, st));
+    unsigned long long got = 0;
+    GD_TRY(hipMemcpyAsync(&got, ctx->counter_dev, sizeof(got), hipMemcpyDeviceToHost, st));
+    GD_TRY(hipStreamSynchronize(st));
+    *count = (int64_t)std::min<unsigned long long>(got, (unsigned long long)cap);
+    return GD_OK;
+}
+
+int gd_mlp_train(gd_ctx* ctx, const uint16_t* features, const float* targets, int64_t S, const uint32_t* order,
+                 int32_t steps, int32_t batch, float lr, int32_t adam_t0, float* params, float* adam_m,
+                 float* adam_v, float* loss, uint16_t* blob, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (S < 1 || steps < 0 || batch < 1 || !features || !targets || !order || !params || !adam_m || !adam_v ||
+        !(lr > 0.f) || adam_t0 < 0)
+        return ctx->fail(GD_EINVAL, "bad training arguments");
+    DeviceGuard guard(ctx->device);
+    TrainArgs a{};
+    a.x = (const __half*)features;
+    a.t = targets;
+    a.order = order;
+    a.steps = steps;
+    a.batch = batch;
+    a.lr = lr;
+    a.adam_t0 = adam_t0;
+    a.params = params;
+    a.m = adam_m;
+    a.v = adam_v;
+    a.loss = loss;
+    a.grad = nullptr;
+    a.update = 1;
+    a.blob = (__half*)blob;
+    GD_TRY(launch_mlp_train(a, (hipStream_t)stream));
+    GD_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return GD_OK;
+}
+
+int gd_mlp_grad(gd_ctx* ctx, const uint16_t* features, const float* targets, const uint32_t* order, int32_t batch,
+                const float* params, float* grad, float* loss, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (batch < 1 || !features || !targets || !order || !params || !grad)
+        return ctx->fail(GD_EINVAL, "bad gradient arguments");
+    DeviceGuard guard(ctx->device);
+    TrainArgs a{};
+    a.x = (const __half*)features;
+    a.t = targets;
+    a.order = order;
+    a.steps = 1;
+    a.batch = batch;
+    a.lr = 1.f;
+    a.params = const_cast<float*>(params);  // not written: update = 0
+    a.m = nullptr;
+    a.v = nullptr;
+    a.loss = loss;
+    a.grad = grad;
+    a.update = 0;
+    a.blob = nullptr;
+    GD_TRY(launch_mlp_train(a, (hipStream_t)stream));
+    GD_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return GD_OK;
+}
+
+int gd_mlp_forward(gd_ctx* ctx, const uint16_t* features, int64_t B, const uint16_t* blob, float* logits,
+                   void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    if (B < 0 || (B > 0 && (!features || !blob || !logits))) return ctx->fail(GD_EINVAL, "bad forward arguments");
+    DeviceGuard guard(ctx->device);
+    GD_TRY(launch_mlp_forward((const __half*)features, B, (const __half*)blob, logits, (hipStream_t)stream));
+    GD_TRY(hipStreamSynchronize((hipStream_t)stream));
     return GD_OK;
 }
 

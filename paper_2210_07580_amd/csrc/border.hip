@@ -17,20 +17,23 @@ namespace gd {
 template <int D>
 __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                         const uint32_t* __restrict__ nei,
-                                                        const int32_t* __restrict__ cell_label,
-                                                        int32_t* __restrict__ labels, uint8_t* __restrict__ core_flags) {
+                                                        const int32_t* __restrict__ cell_label) {
     __shared__ uint32_t s_start[kWavesPerBlock][kWave];
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     __shared__ int32_t s_lab[kWavesPerBlock][kWave];
     const int w = wave_id(), lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
-    if (c >= gv.ncell) return;
+    if (c >= (int64_t)*gv.ncell_dev) return;
     const int64_t n = gv.n;
+    const Inst& I = cell_inst(gv, c);
+    const uint32_t off = (uint32_t)I.off;  // cluster ids and output slots are local to the instance
+    int32_t* __restrict__ labels = I.labels;
+    uint8_t* __restrict__ core_flags = I.core;
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
-    const uint32_t T = (uint32_t)gv.T;
+    const uint32_t T = I.T;
     const uint64_t own_best = own_min == kNone ? ~0ull : (((uint64_t)own_min << 32) | (uint32_t)own_label);
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     for (uint32_t qb = 0; qb < k; qb += kWave) {
@@ -38,8 +41,9 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
         const bool v = qb + lane < k;
         const uint8_t isc = v ? co.core[s] : 1;
         if (v && isc) {
-            labels[gv.sidx[s]] = own_label;
-            core_flags[gv.sidx[s]] = 1;
+            const uint32_t o = gv.sidx[s] - off;
+            labels[o] = own_label - (int32_t)off;
+            core_flags[o] = 1;
         }
         uint64_t open = ballot(v && !isc);  // non-core queries of this batch
         if (!open) continue;
@@ -99,18 +103,18 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
             wave_sync();
         }
         if (v && !isc) {
-            labels[gv.sidx[s]] = best == ~0ull ? -1 : (int32_t)(uint32_t)best;
-            core_flags[gv.sidx[s]] = 0;
+            const uint32_t o = gv.sidx[s] - off;
+            labels[o] = best == ~0ull ? -1 : (int32_t)((uint32_t)best - off);
+            core_flags[o] = 0;
         }
     }
 }
 
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, int32_t* labels, uint8_t* core_flags, hipStream_t st) {
+                         const int32_t* cell_label, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    GD_DISPATCH_D(g.d, (output_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, c, nei_off, nei, cell_label,
-                                                                                 labels, core_flags)));
+    GD_DISPATCH_D(g.D, (output_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, c, nei_off, nei, cell_label)));
     return hipGetLastError();
 }
 

@@ -25,17 +25,18 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     const int w = wave_id(), lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
-    if (c >= gv.ncell) return;
+    if (c >= (int64_t)*gv.ncell_dev) return;
+    const Inst& I = cell_inst(gv, c);
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
-    const uint32_t minpts = (uint32_t)gv.minpts;
+    const uint32_t minpts = (uint32_t)I.minpts;
     const int64_t n = gv.n;
     if (k >= minpts) {
         for (uint32_t i = lane; i < k; i += kWave) core[st + i] = 1;
         return;
     }
     const uint32_t need = minpts - k;
-    const uint32_t T = (uint32_t)gv.T;
+    const uint32_t T = I.T;
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     unsigned long long ndist = 0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
@@ -92,7 +93,7 @@ hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const ui
                             unsigned long long* dist_counter, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    GD_DISPATCH_D(g.d, (core_mark_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core, dist_counter)));
+    GD_DISPATCH_D(g.D, (core_mark_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core, dist_counter)));
     return hipGetLastError();
 }
 
@@ -106,28 +107,29 @@ __global__ __launch_bounds__(kBlock) void core_scatter_kernel(GridView gv, CoreO
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= gv.n || !co.core[s]) return;
     const uint32_t pos = co.core_excl[s];
-    for (int j = 0; j < gv.d; ++j) co.ccrd[(int64_t)pos * co.cstride + j] = gv.crd[(int64_t)j * gv.n + s];
+    for (int j = 0; j < gv.D; ++j) co.ccrd[(int64_t)pos * co.cstride + j] = gv.crd[(int64_t)j * gv.n + s];
     co.corig[pos] = gv.sidx[s];
 }
 
 __global__ __launch_bounds__(kBlock) void core_start_kernel(GridView gv, CoreOut co) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c > gv.ncell) return;
+    if (c > (int64_t)*gv.ncell_dev) return;
     co.core_start[c] = co.core_excl[gv.cell_start[c]];
 }
 
 __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut co) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool v = c < gv.ncell;
-    uint32_t cnt = 0, size = 0;
+    const bool v = c < (int64_t)*gv.ncell_dev;
+    uint32_t cnt = 0, size = 0, minpts = 0;
     if (v) {
         const uint32_t a = co.core_start[c];
         cnt = co.core_start[c + 1] - a;
         size = gv.cell_start[c + 1] - gv.cell_start[c];
+        minpts = (uint32_t)cell_inst(gv, c).minpts;
         co.cell_min_core[c] = cnt ? co.corig[a] : kNone;
     }
     const uint64_t has = ballot(v && cnt > 0);
-    const uint64_t dense = ballot(v && size >= (uint32_t)gv.minpts);
+    const uint64_t dense = ballot(v && size >= minpts);
     const uint64_t tiny = ballot(v && cnt > 0 && cnt <= kTinyCore);
     const uint32_t mx = wave_max_u32(cnt);
     if (lane_id() == 0) {
@@ -153,17 +155,17 @@ hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* pa
 
 struct CoreCellFlag {
     const uint32_t* core_start;
-    int64_t ncell;
+    const uint32_t* ncell;
     __device__ uint32_t operator()(int64_t c) const {
-        return c < ncell && core_start[c + 1] > core_start[c];
+        return c < (int64_t)*ncell && core_start[c + 1] > core_start[c];
     }
 };
 
-__global__ __launch_bounds__(kBlock) void core_list_kernel(int64_t ncell, const uint32_t* core_start,
+__global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell_dev, const uint32_t* core_start,
                                                            const uint32_t* excl, uint32_t* list, uint32_t* keys,
                                                            uint32_t* rank) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncell) return;
+    if (c >= (int64_t)*ncell_dev) return;
     const uint32_t cnt = core_start[c + 1] - core_start[c];
     rank[c] = kNone;
     if (cnt) {
@@ -183,10 +185,10 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
                             hipStream_t st) {
     *sorted_list = list;
     if (g.ncell == 0) return hipSuccess;
-    hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_start, g.ncell}, g.ncell, excl, (uint32_t*)nullptr,
-                                            partial, st);
+    hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_start, g.ncell_dev}, g.ncell, excl,
+                                            (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
-    core_list_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell, c.core_start, excl, list, keys_a,
+    core_list_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_start, excl, list, keys_a,
                                                                       rank);
     if (by_count && ncc > 1) {
         RadixResult<uint32_t> res;

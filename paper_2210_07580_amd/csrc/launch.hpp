@@ -1,78 +1,139 @@
 // Host-side launchers of the pipeline phases, shared between the
 // translation units.  Every launcher takes plain device pointers and a
 // stream and returns the launch status.
+//
+// A call clusters a batch of independent instances (a plain dbscan() call is
+// a batch of one).  Points of instance k occupy the global index range
+// [off_k, off_k + n_k); the packed grid identifier carries k in its top
+// field, so the single stable sort keeps every instance's points in that
+// same range, grids never mix instances, and each grid finds its instance's
+// eps, MinPts and d through the table below.
 #pragma once
 
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace gd {
 
 constexpr int kMaxD = 8;
+constexpr int kMaxLevels = kMaxD + 1;  // grid tree: instance level + one level per dimension
+constexpr int kPointTile = 4096;       // points per workgroup in the point-indexed kernels
 
 // Error bits raised by kernels into the device error word.
 enum : uint32_t {
-    kErrNotInteger = 1u,   // a coordinate is not a finite integer of magnitude <= 2^24
+    kErrNotInteger = 1u,    // a coordinate is not a finite integer of magnitude <= 2^24
+    kErrMergeRunaway = 2u,  // FastMerging exceeded its iteration bound (cannot happen; checked anyway)
+    kErrKeyBits = 4u,       // packed identifiers need more than 64 bits
+    kErrNeiOverflow = 8u,   // neighbour lists exceed the buffer given to a sync-free run
+    kErrCoreCap = 16u,      // a grid's core set exceeds the merge step's LDS bitmap
 };
 
-struct KeyParams {
-    int d;
+// One clustering instance.  The host fills the first part; the layout
+// kernel fills the identifier layout from the data.
+struct Inst {
+    const float* x;    // DEVICE, n x d row-major
+    int32_t* labels;   // DEVICE out, n
+    uint8_t* core;     // DEVICE out, n
+    int64_t off;       // first global point index
+    int64_t n;
     int64_t eps;
-    int mn[kMaxD];     // per-dimension minimum of the input
-    int bits[kMaxD];   // bits of the identifier in each dimension
-    int shift[kMaxD];  // position of dimension j's field (dimension 0 highest)
+    int32_t d;
+    int32_t minpts;
+    uint32_t T;        // eps^2
+    uint32_t tile0;    // first point tile of the instance (tiles never straddle instances)
+    // filled on the device
+    int32_t mn[kMaxD];
+    int32_t mx[kMaxD];
+    int32_t bits[kMaxD];
+    int32_t shift[kMaxD];
+    int32_t key_bits;
+    uint32_t err;
 };
 
-// Grid tree (Section 4.2.1) as flat level arrays.  Level l (0-based, l < d)
-// holds one node per distinct identifier prefix of length l+1, in
-// lexicographic order; key[l][a] is the node's identifier in dimension l.
-// For l < d-1 the children of node a are the level-(l+1) nodes
-// [child[l][a], child[l][a+1]); level d-1 nodes are the grids themselves.
+// Batch-wide identifier layout and counters (device).
+struct Header {
+    int32_t inst_shift;   // position of the instance field (max over instances of key_bits)
+    int32_t total_bits;   // bits of the packed identifier
+    uint32_t err;         // OR of all error bits
+    uint32_t ncell;       // |Gs| over the batch
+    uint32_t level_count[kMaxLevels];
+    uint32_t counts[5];   // core points, core grids, max core points per grid, dense grids, tiny core grids
+    uint32_t pad;
+    uint64_t nei_total;
+};
+
+struct Batch {
+    const Inst* inst;     // device table
+    int32_t count;
+    int32_t D;            // largest d in the batch (coordinate rows; shorter points are padded with 0)
+    int64_t n;            // total points
+    uint32_t tiles;       // point tiles over the batch
+    Header* hdr;          // device
+};
+
+// Instance of point tile `tile` (uniform per workgroup): the last k with tile0 <= tile.
+__device__ __forceinline__ int tile_instance(const Batch& b, uint32_t tile) {
+    int lo = 0, hi = b.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.inst[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Grid tree (Section 4.2.1) as flat level arrays.  Level 0 holds one node
+// per instance present; level l >= 1 holds one node per distinct prefix
+// (instance, g_1, ..., g_l), in lexicographic order; key[l][a] is the node's
+// identifier in dimension l (the instance id at level 0).  For l < L-1 the
+// children of node a are the level-(l+1) nodes [child[l][a], child[l][a+1]);
+// the nodes of the last level are the grids themselves.
 struct TreeView {
-    const int32_t* key[kMaxD];
-    const uint32_t* child[kMaxD];
-    const uint32_t* level_count;  // device: nodes per level (level 0 = root's children)
+    const int32_t* key[kMaxLevels];
+    const uint32_t* child[kMaxLevels];
+    const uint32_t* level_count;  // device: nodes per level
 };
 
 // Sorted points and grids.
 struct GridView {
-    int64_t n;
-    int d;
-    int64_t T;                 // eps^2
-    int minpts;
-    const int32_t* crd;        // d x n, SoA: coordinate minus the minimum, sorted by grid
-    const uint32_t* sidx;      // n: input index of each sorted point
-    int64_t ncell;
+    Batch b;
+    int64_t n;                   // total points
+    int D;                       // coordinate rows
+    const int32_t* crd;          // D x n, SoA: coordinate minus the instance minimum, sorted by grid
+    const uint32_t* sidx;        // n: global input index of each sorted point
+    int64_t ncell;               // grids (exact, or an upper bound when the launch is sync-free)
+    const uint32_t* ncell_dev;   // device: exact number of grids
     const uint32_t* cell_start;  // ncell + 1
-    const int32_t* ck;         // d x ck_stride: grid identifiers, SoA
+    const int32_t* ck;           // (D + 1) x ck_stride: row 0 instance id, rows 1..D identifiers
     int64_t ck_stride;
 };
 
+__device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) { return g.b.inst[g.ck[c]]; }
+
 // ---- partition.hip
-hipError_t launch_minmax(const float* x, int64_t n, int d, int* mn, int* mx, uint32_t* err, hipStream_t st);
+hipError_t launch_minmax(const Batch& b, hipStream_t st);
+hipError_t launch_layout(const Batch& b, hipStream_t st);
 template <typename K>
-hipError_t launch_keys(const float* x, int64_t n, const KeyParams& kp, K* keys, hipStream_t st);
-hipError_t launch_gather(const float* x, int64_t n, const KeyParams& kp, const uint32_t* sidx, int32_t* crd,
-                         hipStream_t st);
-// Runs of equal keys: cell_start[0..ncell], cell_of[n]; *ncell_dev written.
+hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st);
+hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st);
+// Runs of equal keys: cell_start[0..ncell], identifiers; header ncell written.
 template <typename K>
-hipError_t launch_cells(const K* skeys, int64_t n, const KeyParams& kp, uint32_t* excl, uint32_t* partial,
-                        uint32_t* ncell_dev, uint32_t* cell_start, uint32_t* cell_of, int32_t* ck, int64_t ck_stride,
-                        hipStream_t st);
-// Grid tree levels over the ncell sorted grids.  level_excl: d x (ncell+1)
-// scratch; keys / child arrays are written into the given level buffers.
-hipError_t launch_tree(const GridView& g, const KeyParams& kp, uint32_t* level_excl, uint32_t* partial,
-                       uint32_t* level_count_dev, int32_t* const* tkey, uint32_t* const* tchild, hipStream_t st);
+hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
+                        int32_t* ck, int64_t ck_stride, hipStream_t st);
+// Grid tree levels over the sorted grids.  level_excl: D x (ncell+1) scratch.
+hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partial, int32_t* const* tkey,
+                       uint32_t* const* tchild, hipStream_t st);
 
 // ---- neighbors.hip (Algorithm 3)
-// Pass 1: per-grid neighbour count per offset value (ncell x d, u32) and in total.
+// Pass 1: per-grid neighbour count per offset value (ncell x D, u32).
 hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, hipStream_t st);
-// Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1).
+// Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1); total into the header.
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st);
-// Pass 2: write Nei(g) ordered by offset.
+// Pass 2: write Nei(g) ordered by offset (skipped, with kErrNeiOverflow, if
+// the total exceeds `capacity` entries).
 hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint64_t* nei_off,
-                           uint32_t* nei, hipStream_t st);
+                           uint32_t* nei, uint64_t capacity, hipStream_t st);
 
 // ---- core.hip
 struct CoreOut {
@@ -80,18 +141,18 @@ struct CoreOut {
     uint32_t* core_excl;        // n + 1: exclusive scan of core flags
     uint32_t* core_start;       // ncell + 1: first compacted core point of each grid
     int32_t* ccrd;              // core points' coordinates, compacted, cstride int32 per point
-    int cstride;                // 4 (d <= 4) or 8: padded point record
-    uint32_t* corig;            // n: input index of each compacted core point
+    int cstride;                // 4 (D <= 4) or 8: padded point record
+    uint32_t* corig;            // n: global input index of each compacted core point
     uint32_t* cell_min_core;    // ncell: smallest input index of a core point (kNone if none)
-    uint32_t* counts;           // device counters: [0] ncore, [1] ncorecell, [2] max core/grid, [3] dense grids,
-                                // [4] core grids with at most kTinyCore core points
+    uint32_t* counts;           // header counts
 };
+constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
                             unsigned long long* dist_counter, hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
-// index); rank[g] = position (kNone for non-core grids).  Needs ncell-sized
-// scratch buffers.
+// index); rank[g] = position (kNone for non-core grids).  ncc: number of
+// core grids (or an upper bound); count_bits: bits of the largest count.
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
                             uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_b,
                             uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial, uint32_t** sorted_list,
@@ -102,24 +163,30 @@ constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats
 struct MergeStats {
     unsigned long long pairs, skipped, tests, yes, iters, max_iters, dists, set_points;
 };
-enum : uint32_t {
-    kErrMergeRunaway = 2u,  // FastMerging exceeded its iteration bound (cannot happen; checked anyway)
-};
 // Largest core set a grid may hold (LDS bitmaps of the merge step).
 constexpr int64_t kMaxCoreBits = 262144;
-constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
+struct CellSummary;
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, int64_t eps, uint32_t* parent, MergeStats* stats, uint32_t* err,
-                        hipStream_t st);
+                        int64_t max_core, uint32_t* parent, MergeStats* stats, const __half* proposal,
+                        const CellSummary* sum, hipStream_t st);
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, const uint32_t* pairs, int64_t npairs,
                               int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
                               hipStream_t st);
 hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, uint32_t* root_min,
                          int32_t* cell_label, hipStream_t st);
 
+// ---- learned.hip (the learned proposal)
+hipError_t launch_summaries(const GridView& g, const CoreOut& c, CellSummary* out, hipStream_t st);
+hipError_t launch_harvest(const GridView& g, const CoreOut& c, const CellSummary* sum, const uint64_t* nei_off,
+                          const uint32_t* nei, uint32_t seed, uint32_t keep_mod, int64_t cap, int64_t max_core,
+                          __half* X, float* Tg, float* C, unsigned long long* counter, hipStream_t st);
+hipError_t launch_mlp_forward(const __half* X, int64_t B, const __half* params, float* Z, hipStream_t st);
+struct TrainArgs;
+hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
+
 // ---- border.hip
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, int32_t* labels, uint8_t* core_flags, hipStream_t st);
+                         const int32_t* cell_label, hipStream_t st);
 
 }  // namespace gd

@@ -1,17 +1,21 @@
 // Partitioning (Section 4.1, Algorithm 1) and the grid tree (Section 4.2.1,
-// Algorithm 2) on gfx950.
+// Algorithm 2) on gfx950, for a batch of instances.
 //
-//   minmax  : mn_j = min over P (Eq. (1)) and the input check (integers,
-//             |x| <= 2^24), one pass with LDS + device atomics
+//   minmax  : mn_j = min over each instance's points (Eq. (1)) and the input
+//             check (finite integers, |x| <= 2^24); one workgroup per tile of
+//             4096 points, LDS + device atomics
+//   layout  : per instance, the bit width of each identifier field; the
+//             instance id goes above the widest instance's fields
 //   keys    : identifiers of Eq. (1), exact (see grid_coord), packed into one
-//             integer with dimension 1 in the highest bits, so that integer
-//             order is the lexicographic order the paper's radix sort makes
-//   gather  : sorted points as d separate int32 arrays (SoA) for coalesced
-//             loads in the later phases
+//             integer with the instance in the top field and dimension 1
+//             highest below it, so integer order is the lexicographic order
+//             the paper's radix sort produces, instance by instance
+//   gather  : sorted points as D separate int32 arrays (SoA) for coalesced
+//             loads in the later phases (instances with d < D padded with 0)
 //   cells   : runs of equal identifiers = the non-empty grids Gs
-//   tree    : one level per dimension; level l holds the distinct identifier
-//             prefixes of length l+1 in sorted order, so every node's
-//             children are contiguous and its child keys ascend
+//   tree    : level 0 = instances, level l = distinct prefixes of length l,
+//             each level in sorted order, so every node's children are
+//             contiguous and their keys ascend
 #include <climits>
 
 #include "launch.hpp"
@@ -19,14 +23,18 @@
 
 namespace gd {
 
-__global__ __launch_bounds__(kBlock) void minmax_kernel(const float* __restrict__ x, int64_t n, int d, int* mn,
-                                                        int* mx, uint32_t* err) {
+__global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
     __shared__ int smn[kMaxD], smx[kMaxD];
+    const int k = tile_instance(b, blockIdx.x);
+    Inst& I = const_cast<Inst&>(b.inst[k]);
+    const int d = I.d;
     if (threadIdx.x < kMaxD) {
         smn[threadIdx.x] = INT_MAX;
         smx[threadIdx.x] = INT_MIN;
     }
     __syncthreads();
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
+    const int64_t hi = min(I.n, lo + kPointTile);
     int lmn[kMaxD], lmx[kMaxD];
 #pragma unroll
     for (int j = 0; j < kMaxD; ++j) {
@@ -34,93 +42,150 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(const float* __restrict_
         lmx[j] = INT_MIN;
     }
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
 #pragma unroll
         for (int j = 0; j < kMaxD; ++j) {
             if (j < d) {
-                const float v = x[i * d + j];
+                const float v = I.x[i * d + j];
                 const bool ok = (v == rintf(v)) && fabsf(v) <= 16777216.0f;
                 bad |= !ok;
-                const int iv = ok ? (int)v : 0;
-                lmn[j] = min(lmn[j], ok ? iv : INT_MAX);
-                lmx[j] = max(lmx[j], ok ? iv : INT_MIN);
+                lmn[j] = min(lmn[j], ok ? (int)v : INT_MAX);
+                lmx[j] = max(lmx[j], ok ? (int)v : INT_MIN);
             }
         }
     }
 #pragma unroll
     for (int j = 0; j < kMaxD; ++j) {
         if (j < d) {
-            int a = lmn[j], b = lmx[j];
+            int a = lmn[j], c = lmx[j];
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
                 a = min(a, __shfl_xor(a, o));
-                b = max(b, __shfl_xor(b, o));
+                c = max(c, __shfl_xor(c, o));
             }
             if (lane_id() == 0) {
                 atomicMin(&smn[j], a);
-                atomicMax(&smx[j], b);
+                atomicMax(&smx[j], c);
             }
         }
     }
-    if (bad) atomicOr(err, kErrNotInteger);
+    if (ballot(bad) && lane_id() == 0) atomicOr(&I.err, kErrNotInteger);
     __syncthreads();
     if (threadIdx.x < (unsigned)d) {
-        atomicMin(&mn[threadIdx.x], smn[threadIdx.x]);
-        atomicMax(&mx[threadIdx.x], smx[threadIdx.x]);
+        atomicMin(&I.mn[threadIdx.x], smn[threadIdx.x]);
+        atomicMax(&I.mx[threadIdx.x], smx[threadIdx.x]);
     }
 }
 
-hipError_t launch_minmax(const float* x, int64_t n, int d, int* mn, int* mx, uint32_t* err, hipStream_t st) {
-    hipError_t e = fill<int>(mn, kMaxD, INT_MAX, st);
-    if (e != hipSuccess) return e;
-    if ((e = fill<int>(mx, kMaxD, INT_MIN, st)) != hipSuccess) return e;
-    if ((e = fill<uint32_t>(err, 1, 0u, st)) != hipSuccess) return e;
-    if (n == 0) return hipSuccess;
-    int64_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 2048) blocks = 2048;
-    minmax_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(x, n, d, mn, mx, err);
+hipError_t launch_minmax(const Batch& b, hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    minmax_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b);
     return hipGetLastError();
 }
 
-template <typename K>
-__global__ __launch_bounds__(kBlock) void keys_kernel(const float* __restrict__ x, int64_t n, KeyParams kp,
-                                                      K* __restrict__ keys) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    K key = 0;
-#pragma unroll
-    for (int j = 0; j < kMaxD; ++j) {
-        if (j < kp.d) {
-            const int64_t u = (int64_t)(int)x[i * kp.d + j] - kp.mn[j];
-            key |= (K)grid_coord(u, kp.d, kp.eps) << kp.shift[j];
+__device__ __forceinline__ int bit_length_u64(uint64_t v) { return v == 0 ? 0 : 64 - __clzll((long long)v); }
+
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t y) {
+    uint64_t r = (uint64_t)sqrt((double)y);
+    while (r * r > y) --r;
+    while ((r + 1) * (r + 1) <= y) ++r;
+    return r;
+}
+
+// One workgroup: per-instance field widths, then the batch-wide layout.
+__global__ __launch_bounds__(kBlock) void layout_kernel(Batch b) {
+    __shared__ int s_max;
+    __shared__ uint32_t s_err;
+    if (threadIdx.x == 0) {
+        s_max = 0;
+        s_err = 0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < b.count; k += kBlock) {
+        Inst& I = const_cast<Inst&>(b.inst[k]);
+        int total = 0;
+        for (int j = 0; j < I.d; ++j) {
+            const uint64_t u = I.n > 0 ? (uint64_t)((int64_t)I.mx[j] - I.mn[j]) : 0;
+            const uint64_t kmax = isqrt_u64((uint64_t)I.d * u * u) / (uint64_t)I.eps;
+            I.bits[j] = bit_length_u64(kmax);
+            total += I.bits[j];
         }
+        for (int j = I.d - 1, s = 0; j >= 0; --j) {
+            I.shift[j] = s;
+            s += I.bits[j];
+        }
+        I.key_bits = total;
+        atomicMax(&s_max, total);
+        if (I.err) atomicOr(&s_err, I.err);
     }
-    keys[i] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int inst_bits = bit_length_u64((uint64_t)(b.count - 1));
+        b.hdr->inst_shift = s_max;
+        b.hdr->total_bits = s_max + inst_bits;
+        uint32_t e = s_err;
+        if (s_max + inst_bits > 64) e |= kErrKeyBits;
+        b.hdr->err = e;
+    }
+}
+
+hipError_t launch_layout(const Batch& b, hipStream_t st) {
+    layout_kernel<<<1, kBlock, 0, st>>>(b);
+    return hipGetLastError();
 }
 
 template <typename K>
-hipError_t launch_keys(const float* x, int64_t n, const KeyParams& kp, K* keys, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    keys_kernel<K><<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(x, n, kp, keys);
+__global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int d = I.d;
+    const int ishift = b.hdr->inst_shift;
+    const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
+    const int64_t hi = min(I.n, lo + kPointTile);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        K key = top;
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j) {
+            if (j < d) {
+                const int64_t u = (int64_t)(int)I.x[i * d + j] - I.mn[j];
+                key |= (K)grid_coord(u, d, I.eps) << I.shift[j];
+            }
+        }
+        keys[I.off + i] = key;
+    }
+}
+
+template <typename K>
+hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    keys_kernel<K><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, keys);
     return hipGetLastError();
 }
-template hipError_t launch_keys<uint32_t>(const float*, int64_t, const KeyParams&, uint32_t*, hipStream_t);
-template hipError_t launch_keys<uint64_t>(const float*, int64_t, const KeyParams&, uint64_t*, hipStream_t);
+template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, hipStream_t);
+template hipError_t launch_keys<uint64_t>(const Batch&, uint64_t*, hipStream_t);
 
-__global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict__ x, int64_t n, KeyParams kp,
-                                                        const uint32_t* __restrict__ sidx, int32_t* __restrict__ crd) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n) return;
-    const int64_t o = sidx[s];
+// Sorted position s of instance k lies in [off_k, off_k + n_k): the same
+// tiles as the input order.
+__global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t* __restrict__ sidx,
+                                                        int32_t* __restrict__ crd) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int d = I.d;
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
+    const int64_t hi = min(I.n, lo + kPointTile);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const int64_t s = I.off + i;
+        const int64_t o = (int64_t)sidx[s] - I.off;
 #pragma unroll
-    for (int j = 0; j < kMaxD; ++j)
-        if (j < kp.d) crd[(int64_t)j * n + s] = (int)x[o * kp.d + j] - kp.mn[j];
+        for (int j = 0; j < kMaxD; ++j)
+            if (j < b.D) crd[(int64_t)j * b.n + s] = j < d ? (int)I.x[o * d + j] - I.mn[j] : 0;
+    }
 }
 
-hipError_t launch_gather(const float* x, int64_t n, const KeyParams& kp, const uint32_t* sidx, int32_t* crd,
-                         hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    gather_kernel<<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(x, n, kp, sidx, crd);
+hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    gather_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, sidx, crd);
     return hipGetLastError();
 }
 
@@ -132,51 +197,57 @@ struct KeyChange {
 };
 
 template <typename K>
-__global__ __launch_bounds__(kBlock) void cells_kernel(const K* __restrict__ skeys, int64_t n, KeyParams kp,
+__global__ __launch_bounds__(kBlock) void cells_kernel(Batch b, const K* __restrict__ skeys,
                                                        const uint32_t* __restrict__ excl, uint32_t* cell_start,
-                                                       uint32_t* cell_of, int32_t* ck, int64_t ck_stride) {
+                                                       int32_t* ck, int64_t ck_stride) {
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n) return;
+    if (s >= b.n) return;
     const K key = skeys[s];
     const bool first = s == 0 || skeys[s - 1] != key;
     const uint32_t c = excl[s] + (first ? 1u : 0u) - 1u;
-    if (cell_of) cell_of[s] = c;
     if (first) {
         cell_start[c] = (uint32_t)s;
+        const int ishift = b.hdr->inst_shift;
+        const int k = ishift >= 64 ? 0 : (int)((uint64_t)key >> ishift);
+        const Inst& I = b.inst[k];
+        ck[c] = k;
 #pragma unroll
         for (int j = 0; j < kMaxD; ++j) {
-            if (j < kp.d) {
-                const K mask = (kp.bits[j] >= (int)(8 * sizeof(K))) ? ~K(0) : ((K(1) << kp.bits[j]) - 1);
-                ck[(int64_t)j * ck_stride + c] = (int32_t)((key >> kp.shift[j]) & mask);
+            if (j < b.D) {
+                int32_t v = 0;
+                if (j < I.d) {
+                    const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
+                    v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
+                }
+                ck[(int64_t)(j + 1) * ck_stride + c] = v;
             }
         }
     }
-    if (s == n - 1) cell_start[c + 1] = (uint32_t)n;
+    if (s == b.n - 1) cell_start[c + 1] = (uint32_t)b.n;
 }
 
 template <typename K>
-hipError_t launch_cells(const K* skeys, int64_t n, const KeyParams& kp, uint32_t* excl, uint32_t* partial,
-                        uint32_t* ncell_dev, uint32_t* cell_start, uint32_t* cell_of, int32_t* ck, int64_t ck_stride,
-                        hipStream_t st) {
-    hipError_t e = scan_exclusive<uint32_t>(KeyChange<K>{skeys, n}, n, excl, ncell_dev, partial, st);
-    if (e != hipSuccess || n == 0) return e;
-    cells_kernel<K><<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(skeys, n, kp, excl, cell_start, cell_of, ck,
-                                                                ck_stride);
+hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
+                        int32_t* ck, int64_t ck_stride, hipStream_t st) {
+    hipError_t e = scan_exclusive<uint32_t>(KeyChange<K>{skeys, b.n}, b.n, excl, &b.hdr->ncell, partial, st);
+    if (e != hipSuccess || b.n == 0) return e;
+    cells_kernel<K><<<dim3(grid_for(b.n)), dim3(kBlock), 0, st>>>(b, skeys, excl, cell_start, ck, ck_stride);
     return hipGetLastError();
 }
-template hipError_t launch_cells<uint32_t>(const uint32_t*, int64_t, const KeyParams&, uint32_t*, uint32_t*,
-                                           uint32_t*, uint32_t*, uint32_t*, int32_t*, int64_t, hipStream_t);
-template hipError_t launch_cells<uint64_t>(const uint64_t*, int64_t, const KeyParams&, uint32_t*, uint32_t*,
-                                           uint32_t*, uint32_t*, uint32_t*, int32_t*, int64_t, hipStream_t);
+template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,
+                                           int64_t, hipStream_t);
+template hipError_t launch_cells<uint64_t>(const Batch&, const uint64_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,
+                                           int64_t, hipStream_t);
 
 // A grid starts a new node at level l iff it differs from the previous grid
-// in one of dimensions 0..l (grids are in lexicographic order).
+// in one of the identifier rows 0..l (grids are in lexicographic order).
 struct LevelFlag {
     const int32_t* ck;
-    int64_t stride, ncell;
-    int d, l;
+    int64_t stride;
+    const uint32_t* ncell;
+    int l;
     __device__ uint32_t operator()(int64_t c) const {
-        if (c >= ncell) return 0;
+        if (c >= (int64_t)*ncell) return 0;
         if (c == 0) return 1;
         for (int j = 0; j <= l; ++j)
             if (ck[(int64_t)j * stride + c] != ck[(int64_t)j * stride + c - 1]) return 1;
@@ -185,46 +256,47 @@ struct LevelFlag {
 };
 
 struct TreeBuild {
-    int32_t* key[kMaxD];
-    uint32_t* child[kMaxD];
-    const uint32_t* excl[kMaxD];  // per level: nodes before grid c (c in [0, ncell])
+    int32_t* key[kMaxLevels];
+    uint32_t* child[kMaxLevels];
+    const uint32_t* excl[kMaxLevels];  // per level: nodes before grid c (c in [0, ncell])
 };
 
-__global__ __launch_bounds__(kBlock) void tree_kernel(const int32_t* __restrict__ ck, int64_t stride, int64_t ncell,
-                                                      int d, TreeBuild tb) {
+__global__ __launch_bounds__(kBlock) void tree_kernel(const int32_t* __restrict__ ck, int64_t stride,
+                                                      const uint32_t* ncell_dev, int levels, TreeBuild tb) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t ncell = *ncell_dev;
     if (c > ncell) return;
-    for (int l = 0; l + 1 < d; ++l) {
-        LevelFlag f{ck, stride, ncell, d, l};
+    for (int l = 0; l + 1 < levels; ++l) {
+        LevelFlag f{ck, stride, ncell_dev, l};
         if (c == ncell || f(c)) {
             const uint32_t a = tb.excl[l][c];
             if (c < ncell) tb.key[l][a] = ck[(int64_t)l * stride + c];
-            // children: the level-(l+1) node that starts at grid c; level d-1 nodes are the grids
-            tb.child[l][a] = (l + 2 < d) ? tb.excl[l + 1][c] : (uint32_t)c;
+            // children: the level-(l+1) node that starts at grid c; the last level's nodes are the grids
+            tb.child[l][a] = (l + 2 < levels) ? tb.excl[l + 1][c] : (uint32_t)c;
         }
     }
 }
 
-hipError_t launch_tree(const GridView& g, const KeyParams& kp, uint32_t* level_excl, uint32_t* partial,
-                       uint32_t* level_count_dev, int32_t* const* tkey, uint32_t* const* tchild, hipStream_t st) {
-    const int d = g.d;
-    const int64_t stride = g.ck_stride;
+__global__ void copy_u32_kernel(const uint32_t* src, uint32_t* dst) { *dst = *src; }
+
+hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partial, int32_t* const* tkey,
+                       uint32_t* const* tchild, hipStream_t st) {
+    const int levels = g.D + 1;
+    uint32_t* level_count = g.b.hdr->level_count;
     TreeBuild tb{};
-    hipError_t e;
-    // level d-1 are the grids: ncell nodes
-    if ((e = fill<uint32_t>(level_count_dev + (d - 1), 1, (uint32_t)g.ncell, st)) != hipSuccess) return e;
-    for (int l = 0; l + 1 < d; ++l) {
+    // the last level's nodes are the grids
+    copy_u32_kernel<<<1, 1, 0, st>>>(g.ncell_dev, level_count + (levels - 1));
+    for (int l = 0; l + 1 < levels; ++l) {
         uint32_t* ex = level_excl + (int64_t)l * (g.ncell + 1);
-        e = scan_exclusive<uint32_t>(LevelFlag{g.ck, stride, g.ncell, d, l}, g.ncell + 1, ex, level_count_dev + l,
-                                     partial, st);
+        hipError_t e = scan_exclusive<uint32_t>(LevelFlag{g.ck, g.ck_stride, g.ncell_dev, l}, g.ncell + 1, ex,
+                                                level_count + l, partial, st);
         if (e != hipSuccess) return e;
         tb.key[l] = tkey[l];
         tb.child[l] = tchild[l];
         tb.excl[l] = ex;
     }
-    if (d == 1 || g.ncell == 0) return hipSuccess;
-    tree_kernel<<<dim3(grid_for(g.ncell + 1)), dim3(kBlock), 0, st>>>(g.ck, stride, g.ncell, d, tb);
-    (void)kp;
+    if (g.ncell == 0) return hipGetLastError();
+    tree_kernel<<<dim3(grid_for(g.ncell + 1)), dim3(kBlock), 0, st>>>(g.ck, g.ck_stride, g.ncell_dev, levels, tb);
     return hipGetLastError();
 }
 

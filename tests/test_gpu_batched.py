@@ -1,0 +1,79 @@
+"""Batched clustering: many instances of uneven n, d, eps and MinPts in one
+pass of the pipeline.  Every instance must get exactly the oracle's result
+(and the single-instance call's result)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2210_07580_amd as G
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _check(outs, problems):
+    for k, ((lab, core), (x, eps, minpts)) in enumerate(zip(outs, problems)):
+        wl, wc = oracle.dbscan(x, eps, minpts)
+        gl, gc = lab.cpu().numpy(), core.cpu().numpy()
+        assert np.array_equal(gc, wc), f"instance {k}: core flags differ"
+        assert np.array_equal(gl, wl), f"instance {k}: labels differ"
+
+
+def test_small_mixed_batch(ctx):
+    rng = np.random.default_rng(77)
+    problems = []
+    for k in range(40):
+        d = int(rng.integers(1, 6))
+        n = int(rng.integers(0, 900))
+        x = rng.integers(0, 500, size=(n, d)).astype(np.int32)
+        eps = int(rng.integers(5, 60))
+        minpts = int(rng.integers(1, 12))
+        problems.append((x, eps, minpts))
+    print(f"case: 40 random instances, d in 1..5", flush=True)
+    outs = ctx.dbscan_batched([(torch.from_numpy(x.astype(np.float32)).cuda(), e, m) for x, e, m in problems])
+    _check(outs, problems)
+
+
+def test_batch_workload_prefix(ctx):
+    # the first 24 instances of the 256-instance batch workload, capped in size
+    ws = W.batch_workloads()[:24]
+    problems = [(W.make_points(w, n=min(w.n, 60_000)), w.eps, w.minpts) for w in ws]
+    print(f"case: batch prefix, total n = {sum(len(p[0]) for p in problems)}", flush=True)
+    outs = ctx.dbscan_batched([(torch.from_numpy(x.astype(np.float32)).cuda(), e, m) for x, e, m in problems])
+    _check(outs, problems)
+
+
+def test_batch_equals_single_calls(ctx):
+    ws = W.batch_workloads()[24:40]
+    problems = [(W.make_points(w, n=min(w.n, 40_000)), w.eps, w.minpts) for w in ws]
+    tens = [(torch.from_numpy(x.astype(np.float32)).cuda(), e, m) for x, e, m in problems]
+    outs = ctx.dbscan_batched(tens)
+    for (lab, core), (t, e, m) in zip(outs, tens):
+        l1, c1 = ctx.dbscan(t, e, m)
+        assert torch.equal(lab, l1) and torch.equal(core, c1)
+
+
+def test_batch_errors(ctx):
+    import paper_2210_07580_amd as G
+    good = torch.zeros((5, 2), dtype=torch.float32, device="cuda")
+    bad = good + 0.25
+    with pytest.raises(G.GDError) as e:
+        ctx.dbscan_batched([(good, 3, 2), (bad, 3, 2)])
+    assert e.value.status == G.GD_ERANGE and "instance 1" in str(e.value)
+    with pytest.raises(G.GDError) as e:
+        ctx.dbscan_batched([(good, 3, 2), (good, 2.5, 2)])
+    assert e.value.status == G.GD_EINVAL
+    assert ctx.dbscan_batched([]) == []
+    outs = ctx.dbscan_batched([(good, 3, 2), (torch.zeros((0, 3), dtype=torch.float32, device="cuda"), 3, 2)])
+    assert (outs[0][1].cpu().numpy() == 1).all() and outs[1][0].numel() == 0

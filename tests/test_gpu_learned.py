@@ -1,0 +1,134 @@
+"""The learned proposal: FP16 kernels against the FP64 reference, training,
+harvesting, and exactness (labels identical with and without a proposal)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2210_07580_amd as G
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = G.Context(0)
+    yield c
+    c.close()
+
+
+def _fp16(a):
+    return np.asarray(a, dtype=np.float16)
+
+
+def test_forward_matches_fp64(ctx):
+    rng = np.random.default_rng(1)
+    theta = _fp16(mlp.init(2))
+    X = _fp16(rng.standard_normal((700, 16)))
+    Z = ctx.mlp_forward(torch.from_numpy(X).cuda(), torch.from_numpy(theta).cuda()).cpu().numpy()
+    want, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64))
+    assert np.all(np.abs(Z - want) <= 2e-2 * (1 + np.abs(want)))
+
+
+def test_gradient_matches_fp64(ctx):
+    rng = np.random.default_rng(3)
+    theta32 = mlp.init(4).astype(np.float32)
+    X = _fp16(rng.standard_normal((256, 16)))
+    T = np.stack([rng.integers(0, 2, 256), rng.integers(0, 2, 256), rng.integers(0, 2, 256)], 1).astype(np.float32)
+    order = np.arange(256, dtype=np.int32)
+    g, loss = ctx.mlp_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(order).cuda(),
+                           256, torch.from_numpy(theta32).cuda())
+    g = g.cpu().numpy()
+    th16 = theta32.astype(np.float16).astype(np.float64)  # the kernel computes with FP16-rounded weights
+    want = mlp.grad(th16, X.astype(np.float64), T)
+    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+    assert rel < 3e-2, rel
+    assert abs(loss - mlp.loss(th16, X.astype(np.float64), T)) < 1e-2
+    # every parameter block carries gradient
+    assert np.abs(g[:1024]).sum() > 0 and np.abs(g[1088:5184]).sum() > 0 and np.abs(g[5248:5376]).sum() > 0
+
+
+def test_training_reduces_loss(ctx):
+    from paper_2210_07580_amd import proposal as P
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((4096, 16))
+    y = (X[:, 0] - 0.7 * X[:, 3] > 0).astype(np.float32)
+    s = (X[:, 1] > 0).astype(np.float32)
+    T = np.stack([y, s, np.ones_like(y)], 1).astype(np.float32)
+    blob, losses = P.train(ctx, torch.from_numpy(_fp16(X)).cuda(), torch.from_numpy(T).cuda(), steps=600,
+                           batch=128, lr=3e-3)
+    assert losses[-50:].mean() < 0.35 * losses[:20].mean()
+    Z = ctx.mlp_forward(torch.from_numpy(_fp16(X)).cuda(), torch.from_numpy(blob).cuda()).cpu().numpy()
+    assert ((Z[:, 0] > 0) == (y > 0.5)).mean() > 0.95
+
+
+def test_harvest_targets_are_consistent(ctx):
+    w = W.WORKLOADS["cfg1"].with_n(200_000)
+    x = W.make_points(w)
+    ctx.dbscan(torch.from_numpy(x.astype(np.float32)).cuda(), w.eps, w.minpts)
+    X, T, C = ctx.harvest(cap=4000, keep_mod=3, seed=1)
+    X, T, C = X.cpu().numpy(), T.cpu().numpy(), C.cpu().numpy()
+    assert 100 < len(X) <= 4000
+    assert np.isfinite(X.astype(np.float32)).all()
+    assert set(np.unique(T)) <= {0.0, 1.0}
+    assert (C >= 1).all()
+    assert np.array_equal(T[:, 1] > 0.5, C[:, 2] < C[:, 1])
+    assert np.array_equal(T[:, 2] > 0.5, C[:, 2] != C[:, 1])
+    assert 0.0 < T[:, 0].mean() <= 1.0
+
+
+def _random_blob(seed):
+    return _fp16(mlp.init(seed))
+
+
+@pytest.mark.parametrize("name,n", [("H", 150_000), ("cfg4", 200_000), ("cfg1", 150_000), ("cfg0", 10_000)])
+def test_proposal_keeps_exact_labels(ctx, name, n):
+    from paper_2210_07580_amd import proposal as P
+    w = W.WORKLOADS[name].with_n(n)
+    x = W.make_points(w)
+    want = oracle.dbscan(x, w.eps, w.minpts)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    blobs = [_random_blob(5)]
+    if os.path.exists(P.BLOB_PATH):
+        blobs.append(P.load_blob())
+    try:
+        for blob in blobs:
+            ctx.set_proposal(blob)
+            lab, core = ctx.dbscan(t, w.eps, w.minpts)
+            assert np.array_equal(core.cpu().numpy(), want[1])
+            assert np.array_equal(lab.cpu().numpy(), want[0])
+    finally:
+        ctx.set_proposal(None)
+
+
+def test_trained_proposal_gain(ctx):
+    """What the trained scorer buys over the plain method on the dense
+    seed-spreader workload (300 points per step), at identical labels."""
+    import paper_2210_07580_amd as G
+    from paper_2210_07580_amd import proposal as P
+    if not os.path.exists(P.BLOB_PATH):
+        pytest.skip("no trained proposal committed")
+    w = W.WORKLOADS["cfg4"].with_n(2_000_000)
+    x = W.make_points(w)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    try:
+        l0, c0 = ctx.dbscan(t, w.eps, w.minpts)
+        s0 = ctx.stats()
+        ctx.set_proposal(P.load_blob())
+        l1, c1 = ctx.dbscan(t, w.eps, w.minpts)
+        s1 = ctx.stats()
+    finally:
+        ctx.set_proposal(None)
+        ctx.set_option(G.GD_OPT_STATS, 0)
+    assert torch.equal(l0, l1) and torch.equal(c0, c1)
+    print(f"plain: tests {s0['merge_tests']} distances {s0['merge_distances']}; "
+          f"learned: tests {s1['merge_tests']} distances {s1['merge_distances']}", flush=True)
+    assert s1["merge_distances"] < s0["merge_distances"]
