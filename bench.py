@@ -72,6 +72,100 @@ def cpu_baseline(w, sample_n):
     }
 
 
+def time_calls(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(G, steps, warmup, max_instances):
+    """The 256-instance workload: one dbscan_batched() call versus one
+    dbscan() call per instance, same GPU, identical results."""
+    import torch
+    ws = W.batch_workloads()[:max_instances]
+    log(f"bench: generating {len(ws)} batch instances")
+    probs = []
+    for w in ws:
+        x = W.make_points(w)
+        probs.append((torch.from_numpy(x.astype(np.float32)).cuda(), w.eps, w.minpts))
+    total = sum(int(p[0].shape[0]) for p in probs)
+    ctx = G.Context(0)
+    outs = ctx.dbscan_batched(probs)
+    for (t, e, m), (lab, core) in zip(probs[:8], outs[:8]):
+        l1, c1 = ctx.dbscan(t, e, m)
+        if not (torch.equal(l1, lab) and torch.equal(c1, core)):
+            raise RuntimeError("batched and single-instance results differ")
+    t_batch = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
+    log(f"bench: batched {1e3 * t_batch:.2f} ms")
+
+    def each():
+        for (t, e, m), (lab, core) in zip(probs, outs):
+            ctx.dbscan(t, e, m, lab, core)
+    t_each = time_calls(each, max(1, steps // 2), 1)
+    log(f"bench: one call per instance {1e3 * t_each:.2f} ms")
+    ctx.close()
+    return {
+        "workload": f"{len(ws)} instances: n log-uniform [1e3,1e6], d in {{2,3}}, gaussian blobs + 10% noise, "
+                    "eps in [50,300], minpts in [5,50]",
+        "instances": len(ws), "points": total,
+        "value": round(total / t_batch, 1), "ms_per_batch": round(1e3 * t_batch, 3),
+        "plain_value": round(total / t_each, 1), "plain_ms_per_batch": round(1e3 * t_each, 3),
+        "speedup_vs_plain": round(t_each / t_batch, 3), "unit": "points/s",
+    }
+
+
+def bench_learned(G, steps, warmup):
+    """The dense seed-spreader workload (n=20M, d=3): the trained proposal
+    versus the plain merge, same GPU, identical labels."""
+    import torch
+    from paper_2210_07580_amd import proposal as P
+    w = W.WORKLOADS["cfg4"]
+    log(f"bench: generating {w.name} n={w.n:,}")
+    x = W.make_points(w)
+    pts = torch.from_numpy(x.astype(np.float32)).cuda()
+    n = x.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    core = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx = G.Context(0)
+    res = {}
+    ref = None
+    for name, blob in (("plain", None), ("learned", P.load_blob())):
+        ctx.set_proposal(blob)
+        ctx.set_option(G.GD_OPT_TIMING, 1)
+        merge_ms = []
+
+        def call():
+            ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+            merge_ms.append(ctx.phase_times()["merge"])
+        t = time_calls(call, steps, warmup)
+        ctx.set_option(G.GD_OPT_TIMING, 0)
+        ctx.set_option(G.GD_OPT_STATS, 1)
+        ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+        st = ctx.stats()
+        ctx.set_option(G.GD_OPT_STATS, 0)
+        out = (lab.clone(), core.clone())
+        if ref is None:
+            ref = out
+        elif not (torch.equal(ref[0], out[0]) and torch.equal(ref[1], out[1])):
+            raise RuntimeError("learned proposal changed the labels")
+        res[name] = {"value": round(n / t, 1), "ms_per_step": round(1e3 * t, 3),
+                     "merge_ms": round(float(np.mean(merge_ms[warmup:] or merge_ms)), 4),
+                     "merge_tests": st["merge_tests"], "merge_distances": st["merge_distances"],
+                     "merge_iterations": st["merge_iterations"]}
+        log(f"bench: {name} {res[name]}")
+    ctx.close()
+    return {"workload": "seed-spreader n=20M d=3 eps=150 minpts=50 (300 pts/step)", "unit": "points/s",
+            "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
+            "speedup_vs_plain": round(res["learned"]["value"] / res["plain"]["value"], 3),
+            "plain": res["plain"], "learned": res["learned"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +174,8 @@ def main():
     ap.add_argument("--workload", default="H", choices=sorted(W.WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the batched and learned comparisons")
+    ap.add_argument("--batch-instances", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -168,6 +264,13 @@ def main():
                                     "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
                                     "merge_max_iterations")},
     }
+    ctx.close()
+    del pts, labels, core
+    torch.cuda.empty_cache()
+    if not args.no_variants:
+        out["batched"] = bench_batched(G, max(2, args.steps // 2), 1, args.batch_instances)
+        torch.cuda.empty_cache()
+        out["learned"] = bench_learned(G, max(2, args.steps // 2), 1)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle on a sample of n={args.cpu_sample:,}")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
