@@ -180,10 +180,9 @@ struct Layout {
     uint32_t* off_counts;
     uint64_t* nei_off;
     uint8_t* core;
-    uint32_t* core_excl;
-    uint32_t* core_start;
-    int32_t* ccrd;
-    uint32_t* corig;
+    uint32_t* core_cnt;
+    uint32_t* core_begin;
+    uint32_t* side_off;
     uint32_t* cell_min_core;
     uint32_t* list;
     uint32_t* rank;
@@ -198,12 +197,14 @@ Layout carve(char* base, int64_t n, int D) {
     Carve c{base};
     L.keys_a = c.take<uint64_t>(n);
     L.keys_b = c.take<uint64_t>(n);
-    L.vals_a = c.take<uint32_t>(n);
-    L.vals_b = c.take<uint32_t>(n);
+    // the sorted index doubles as the row -> input index map of the core
+    // sets, whose side area follows row n
+    L.vals_a = c.take<uint32_t>(2 * n);
+    L.vals_b = c.take<uint32_t>(2 * n);
     const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)kRadixBins * radix_tiles(n));
     L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
     L.partial = c.take<uint64_t>(scan_blocks(big_scan) + 4);
-    L.crd = c.take<int32_t>((int64_t)D * n);
+    L.crd = c.take<int32_t>((int64_t)row_stride(D) * 2 * n);  // sorted rows, then the side area
     L.excl = c.take<uint32_t>(n + 1);
     L.cell_start = c.take<uint32_t>(n + 1);
     L.ck = c.take<int32_t>((int64_t)(D + 1) * n);
@@ -215,10 +216,9 @@ Layout carve(char* base, int64_t n, int D) {
     L.off_counts = c.take<uint32_t>((int64_t)D * n);
     L.nei_off = c.take<uint64_t>(n + 1);
     L.core = c.take<uint8_t>(n);
-    L.core_excl = c.take<uint32_t>(n + 1);
-    L.core_start = c.take<uint32_t>(n + 1);
-    L.ccrd = c.take<int32_t>((int64_t)(D <= 4 ? 4 : 8) * n);
-    L.corig = c.take<uint32_t>(n);
+    L.core_cnt = c.take<uint32_t>(n);
+    L.core_begin = c.take<uint32_t>(n);
+    L.side_off = c.take<uint32_t>(n + 1);
     L.cell_min_core = c.take<uint32_t>(n);
     L.list = c.take<uint32_t>(n);
     L.rank = c.take<uint32_t>(n);
@@ -358,15 +358,16 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, ctx->stats ? ctx->stats_dev->core_dist : nullptr, st));
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, ctx->stats ? ctx->stats_dev->core_dist : nullptr,
+                            st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
-    co.core_excl = L.core_excl;
-    co.core_start = L.core_start;
-    co.ccrd = L.ccrd;
-    co.cstride = D <= 4 ? 4 : 8;
-    co.corig = L.corig;
+    co.core_cnt = L.core_cnt;
+    co.core_begin = L.core_begin;
+    co.ccrd = L.crd;
+    co.corig = const_cast<uint32_t*>(sidx);
+    co.side_off = L.side_off;
     co.cell_min_core = L.cell_min_core;
     co.counts = Hd->counts;
     ctx->mark(P_CORE_COMPACT, 0);
@@ -732,8 +733,15 @@ int gd_merge_test(gd_ctx* ctx, const int32_t* points, int64_t m, int32_t d, doub
             mx = std::max<uint32_t>(mx, (uint32_t)c);
         }
     }
-    GD_TRY(launch_merge_pairs(points, m, d, pairs, npairs, (int64_t)eps, mx, answers, iterations, st));
-    GD_TRY(hipStreamSynchronize(st));
+    int32_t* rows = nullptr;
+    if (hipMalloc(&rows, sizeof(int32_t) * (size_t)row_stride(d) * (size_t)std::max<int64_t>(m, 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ctx->fail(GD_ENOMEM, "row buffer allocation failed");
+    }
+    hipError_t e = launch_merge_pairs(points, m, d, rows, pairs, npairs, (int64_t)eps, mx, answers, iterations, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(rows);
+    if (e != hipSuccess) return ctx->fail(GD_EDEVICE, "merge test failed: %s", hipGetErrorString(e));
     return GD_OK;
 }
 

@@ -5,7 +5,7 @@
 // non-core point joins the cluster of its lowest-index core neighbour: the
 // candidates are the grid's own core points (all within eps, the smallest
 // index is precomputed) and the core points of Nei(g).  The wave streams the
-// compacted core points of Nei(g) as one flat list (as in core marking),
+// core sets of Nei(g) as one flat list (as in core marking),
 // skipping grids whose smallest core index cannot improve any open query;
 // for each non-core query a ballot finds the candidates within eps and a
 // wave minimum over (input index << 32 | label) keeps the lowest index.
@@ -24,7 +24,6 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
     const int w = wave_id(), lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
     if (c >= (int64_t)*gv.ncell_dev) return;
-    const int64_t n = gv.n;
     const Inst& I = cell_inst(gv, c);
     const uint32_t off = (uint32_t)I.off;  // cluster ids and output slots are local to the instance
     int32_t* __restrict__ labels = I.labels;
@@ -48,8 +47,7 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
         uint64_t open = ballot(v && !isc);  // non-core queries of this batch
         if (!open) continue;
         int32_t qx[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) qx[j] = (v && !isc) ? gv.crd[(int64_t)j * n + s] : 0;
+        load_row<D>(gv.crd, v ? s : st, qx);
         uint64_t best = own_best;  // lane i: best candidate of query i
         for (uint64_t e = e0; e < e1; e += kWave) {
             // largest best among open queries: grids whose smallest core index is not below it cannot help
@@ -62,8 +60,8 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
                 const uint32_t cc = nei[idx];
                 const uint32_t mc = co.cell_min_core[cc];
                 if (mc != kNone && (worst == ~0ull || mc < worst_idx)) {
-                    cs = co.core_start[cc];
-                    cn = co.core_start[cc + 1] - cs;
+                    cs = co.core_begin[cc];
+                    cn = co.core_cnt[cc];
                     lab = cell_label[cc];
                 }
             }
@@ -83,8 +81,7 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
                     if (s_excl[w][j + step] <= t) j += step;
                 const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
                 int32_t y[D];
-#pragma unroll
-                for (int jj = 0; jj < D; ++jj) y[jj] = tv ? co.ccrd[(int64_t)q * co.cstride + jj] : 0;
+                load_row<D>(co.ccrd, tv ? q : 0u, y);
                 const uint64_t cand = tv ? (((uint64_t)co.corig[q] << 32) | (uint32_t)s_lab[w][j]) : ~0ull;
                 uint64_t act = open;
                 while (act) {

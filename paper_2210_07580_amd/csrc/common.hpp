@@ -113,13 +113,69 @@ __device__ __forceinline__ void store_rel(T* p, T v) {
 }
 
 // floor(u * sqrt(d) / eps) exactly, for integers 0 <= u <= 2^25, 1 <= d <= 8,
-// 1 <= eps: the largest k with (k * eps)^2 <= d * u^2 (all terms < 2^54).
-__device__ __forceinline__ uint32_t grid_coord(int64_t u, int d, int64_t eps) {
-    const int64_t y = (int64_t)d * u * u;
-    int64_t k = (int64_t)(sqrt((double)y) / (double)eps);
-    while ((k + 1) * eps * (k + 1) * eps <= y) ++k;
-    while (k > 0 && k * eps * k * eps > y) --k;
-    return (uint32_t)k;
+// 1 <= eps < 2^15: the largest k with (k * eps)^2 <= d * u^2.  A float
+// estimate (scale = sqrt(d) / eps) is corrected by exact 64-bit integer
+// tests; d * u^2 < 2^54 and k * eps stays below 2^32.
+__device__ __forceinline__ uint32_t grid_coord(uint32_t u, uint32_t d, uint32_t eps, float scale) {
+    const uint64_t y = (uint64_t)(d * u) * u;
+    uint32_t k = (uint32_t)((float)u * scale);
+    for (;;) {
+        const uint64_t ke = (uint64_t)k * eps;
+        if (k == 0 || ke * ke <= y) break;
+        --k;
+    }
+    for (;;) {
+        const uint64_t ke = (uint64_t)(k + 1) * eps;
+        if (ke * ke > y) break;
+        ++k;
+    }
+    return k;
+}
+
+// Point rows: the coordinates of a point as one padded record of
+// row_stride(D) int32 (1, 2, 4 or 8), so that one vector load fetches it.
+constexpr int row_stride(int D) { return D <= 1 ? 1 : D == 2 ? 2 : D <= 4 ? 4 : 8; }
+
+template <int D>
+__device__ __forceinline__ void load_row(const int32_t* __restrict__ rows, int64_t r, int32_t (&y)[D]) {
+    constexpr int S = row_stride(D);
+    if constexpr (S == 1) {
+        y[0] = rows[r];
+    } else if constexpr (S == 2) {
+        const int2 t = reinterpret_cast<const int2*>(rows)[r];
+        y[0] = t.x;
+        y[1] = t.y;
+    } else if constexpr (S == 4) {
+        const int4 t = reinterpret_cast<const int4*>(rows)[r];
+        const int32_t v[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int k = 0; k < D; ++k) y[k] = v[k];
+    } else {
+        const int4 a = reinterpret_cast<const int4*>(rows)[2 * r];
+        const int4 b = reinterpret_cast<const int4*>(rows)[2 * r + 1];
+        const int32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int k = 0; k < D; ++k) y[k] = v[k];
+    }
+}
+
+// Store a row; the padding is written as 0.
+template <int D>
+__device__ __forceinline__ void store_row(int32_t* __restrict__ rows, int64_t r, const int32_t (&y)[D]) {
+    constexpr int S = row_stride(D);
+    int32_t v[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) v[k] = k < D ? y[k < D ? k : 0] : 0;
+    if constexpr (S == 1) {
+        rows[r] = v[0];
+    } else if constexpr (S == 2) {
+        reinterpret_cast<int2*>(rows)[r] = make_int2(v[0], v[1]);
+    } else if constexpr (S == 4) {
+        reinterpret_cast<int4*>(rows)[r] = make_int4(v[0], v[1], v[2], v[3]);
+    } else {
+        reinterpret_cast<int4*>(rows)[2 * r] = make_int4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<int4*>(rows)[2 * r + 1] = make_int4(v[4], v[5], v[6], v[7]);
+    }
 }
 
 template <typename T>

@@ -2,6 +2,10 @@
 // 4.4 step 2) and the per-grid core sets s_i used by the merge (Section
 // 4.3.1), plus the low-density-first order of the LDF variant (Section 5.2).
 //
+// A core set is a run of point rows (see CoreOut): a grid whose points are
+// all core uses its sorted rows as they are, so only grids that mix core and
+// non-core points copy anything.
+//
 // Marking runs one wave per grid.  A grid with at least MinPts points is all
 // core (its diameter is below eps).  In a sparser grid every point already
 // has the grid's own points as neighbours; the wave then streams the points
@@ -20,6 +24,7 @@ namespace gd {
 template <int D>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
+                                                           uint32_t* __restrict__ core_cnt,
                                                            unsigned long long* dist_counter) {
     __shared__ uint32_t s_start[kWavesPerBlock][kWave];
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
@@ -30,21 +35,21 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
     const uint32_t minpts = (uint32_t)I.minpts;
-    const int64_t n = gv.n;
     if (k >= minpts) {
         for (uint32_t i = lane; i < k; i += kWave) core[st + i] = 1;
+        if (lane == 0) core_cnt[c] = k;
         return;
     }
     const uint32_t need = minpts - k;
     const uint32_t T = I.T;
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     unsigned long long ndist = 0;
+    uint32_t m = 0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
         const uint32_t nq = min((uint32_t)kWave, k - qb);
         uint64_t active = nq == (uint32_t)kWave ? ~0ull : ((1ull << nq) - 1ull);
         int32_t qx[D];
-#pragma unroll
-        for (int j = 0; j < D; ++j) qx[j] = (uint32_t)lane < nq ? gv.crd[(int64_t)j * n + st + qb + lane] : 0;
+        load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
         uint32_t mycnt = 0;
         for (uint64_t e = e0; e < e1 && active; e += kWave) {
             const uint64_t idx = e + lane;
@@ -66,8 +71,7 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                     if (s_excl[w][j + step] <= t) j += step;
                 const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
                 int32_t y[D];
-#pragma unroll
-                for (int jj = 0; jj < D; ++jj) y[jj] = tv ? gv.crd[(int64_t)jj * n + q] : 0;
+                load_row<D>(gv.crd, tv ? q : st, y);
                 uint64_t act = active;
                 const int nv = popc64(ballot(tv));
                 while (act) {
@@ -84,55 +88,59 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
             }
             wave_sync();
         }
-        if ((uint32_t)lane < nq) core[st + qb + lane] = ((active >> lane) & 1ull) ? 0 : 1;
+        const bool is_core = (uint32_t)lane < nq && !((active >> lane) & 1ull);
+        if ((uint32_t)lane < nq) core[st + qb + lane] = is_core ? 1 : 0;
+        m += (uint32_t)popc64(ballot(is_core));
     }
-    if (dist_counter && lane == 0) atomicAdd(&dist_counter[c & (kStatSlots - 1)], ndist);
+    if (lane == 0) {
+        core_cnt[c] = m;
+        if (dist_counter) atomicAdd(&dist_counter[c & (kStatSlots - 1)], ndist);
+    }
 }
 
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            unsigned long long* dist_counter, hipStream_t st) {
+                            uint32_t* core_cnt, unsigned long long* dist_counter, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    GD_DISPATCH_D(g.D, (core_mark_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core, dist_counter)));
+    GD_DISPATCH_D(g.D, (core_mark_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core, core_cnt,
+                                                                                  dist_counter)));
     return hipGetLastError();
 }
 
-struct CoreFlag {
-    const uint8_t* core;
-    int64_t n;
-    __device__ uint32_t operator()(int64_t i) const { return i < n ? (uint32_t)core[i] : 0u; }
+// Side rows of grid c: its core count if it also holds non-core points.
+struct SideRows {
+    const uint32_t* cnt;
+    const uint32_t* cell_start;
+    const uint32_t* ncell;
+    __device__ uint32_t operator()(int64_t c) const {
+        if (c >= (int64_t)*ncell) return 0u;
+        const uint32_t m = cnt[c];
+        return (m != 0 && m != cell_start[c + 1] - cell_start[c]) ? m : 0u;
+    }
 };
 
-__global__ __launch_bounds__(kBlock) void core_scatter_kernel(GridView gv, CoreOut co) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= gv.n || !co.core[s]) return;
-    const uint32_t pos = co.core_excl[s];
-    for (int j = 0; j < gv.D; ++j) co.ccrd[(int64_t)pos * co.cstride + j] = gv.crd[(int64_t)j * gv.n + s];
-    co.corig[pos] = gv.sidx[s];
-}
-
-__global__ __launch_bounds__(kBlock) void core_start_kernel(GridView gv, CoreOut co) {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c > (int64_t)*gv.ncell_dev) return;
-    co.core_start[c] = co.core_excl[gv.cell_start[c]];
-}
-
+// One thread per grid: where its core set starts, the smallest input index
+// of its core points (grids without side rows), and the header counts.
 __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut co) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool v = c < (int64_t)*gv.ncell_dev;
     uint32_t cnt = 0, size = 0, minpts = 0;
     if (v) {
-        const uint32_t a = co.core_start[c];
-        cnt = co.core_start[c + 1] - a;
-        size = gv.cell_start[c + 1] - gv.cell_start[c];
+        const uint32_t st = gv.cell_start[c];
+        cnt = co.core_cnt[c];
+        size = gv.cell_start[c + 1] - st;
         minpts = (uint32_t)cell_inst(gv, c).minpts;
-        co.cell_min_core[c] = cnt ? co.corig[a] : kNone;
+        const bool side = cnt != 0 && cnt != size;
+        co.core_begin[c] = side ? (uint32_t)gv.n + co.side_off[c] : st;
+        if (!side) co.cell_min_core[c] = cnt ? gv.sidx[st] : kNone;
     }
     const uint64_t has = ballot(v && cnt > 0);
     const uint64_t dense = ballot(v && size >= minpts);
     const uint64_t tiny = ballot(v && cnt > 0 && cnt <= kTinyCore);
     const uint32_t mx = wave_max_u32(cnt);
+    const uint32_t tot = wave_sum(cnt);
     if (lane_id() == 0) {
+        if (tot) atomicAdd(&co.counts[0], tot);
         if (has) atomicAdd(&co.counts[1], (uint32_t)popc64(has));
         if (dense) atomicAdd(&co.counts[3], (uint32_t)popc64(dense));
         if (tiny) atomicAdd(&co.counts[4], (uint32_t)popc64(tiny));
@@ -140,33 +148,62 @@ __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut
     }
 }
 
+// One wave per grid holding both core and non-core points: copy its core
+// rows, in sorted order, to the side area.
+template <int D>
+__global__ __launch_bounds__(kBlock) void side_copy_kernel(GridView gv, CoreOut co) {
+    const int lane = lane_id();
+    const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (c >= (int64_t)*gv.ncell_dev) return;
+    const uint32_t st = gv.cell_start[c];
+    const uint32_t k = gv.cell_start[c + 1] - st;
+    const uint32_t m = co.core_cnt[c];
+    if (m == 0 || m == k) return;
+    const uint32_t base = (uint32_t)gv.n + co.side_off[c];
+    uint32_t done = 0, first = kNone;
+    for (uint32_t qb = 0; qb < k; qb += kWave) {
+        const bool v = qb + lane < k;
+        const bool f = v && co.core[st + qb + lane];
+        const uint32_t orig = v ? gv.sidx[st + qb + lane] : 0u;
+        const uint64_t bal = ballot(f);
+        if (f) {
+            const uint32_t r = base + done + (uint32_t)popc64(bal & lanemask_lt());
+            int32_t y[D];
+            load_row<D>(gv.crd, st + qb + lane, y);
+            store_row<D>(co.ccrd, r, y);
+            co.corig[r] = orig;
+        }
+        // sorted order within a grid is input order: the first core point has the smallest index
+        if (first == kNone && bal) first = readlane(orig, ffs64(bal));
+        done += (uint32_t)popc64(bal);
+    }
+    if (lane == 0) co.cell_min_core[c] = first;
+}
+
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st) {
     hipError_t e = fill<uint32_t>(c.counts, 5, 0u, st);
     if (e != hipSuccess) return e;
-    // core_excl[n] = number of core points, also copied to counts[0]
-    e = scan_exclusive<uint32_t>(CoreFlag{c.core, g.n}, g.n + 1, c.core_excl, c.counts, partial, st);
+    if (g.ncell == 0) return hipSuccess;
+    e = scan_exclusive<uint32_t>(SideRows{c.core_cnt, g.cell_start, g.ncell_dev}, g.ncell + 1, c.side_off,
+                                 (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
-    if (g.n == 0) return hipSuccess;
-    core_scatter_kernel<<<dim3(grid_for(g.n)), dim3(kBlock), 0, st>>>(g, c);
-    core_start_kernel<<<dim3(grid_for(g.ncell + 1)), dim3(kBlock), 0, st>>>(g, c);
     core_cells_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c);
+    GD_DISPATCH_D(g.D, (side_copy_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(g, c)));
     return hipGetLastError();
 }
 
 struct CoreCellFlag {
-    const uint32_t* core_start;
+    const uint32_t* core_cnt;
     const uint32_t* ncell;
-    __device__ uint32_t operator()(int64_t c) const {
-        return c < (int64_t)*ncell && core_start[c + 1] > core_start[c];
-    }
+    __device__ uint32_t operator()(int64_t c) const { return c < (int64_t)*ncell && core_cnt[c] > 0; }
 };
 
-__global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell_dev, const uint32_t* core_start,
+__global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell_dev, const uint32_t* core_cnt,
                                                            const uint32_t* excl, uint32_t* list, uint32_t* keys,
                                                            uint32_t* rank) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= (int64_t)*ncell_dev) return;
-    const uint32_t cnt = core_start[c + 1] - core_start[c];
+    const uint32_t cnt = core_cnt[c];
     rank[c] = kNone;
     if (cnt) {
         list[excl[c]] = (uint32_t)c;
@@ -185,10 +222,10 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
                             hipStream_t st) {
     *sorted_list = list;
     if (g.ncell == 0) return hipSuccess;
-    hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_start, g.ncell_dev}, g.ncell, excl,
+    hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_cnt, g.ncell_dev}, g.ncell, excl,
                                             (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
-    core_list_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_start, excl, list, keys_a,
+    core_list_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, excl, list, keys_a,
                                                                       rank);
     if (by_count && ncc > 1) {
         RadixResult<uint32_t> res;

@@ -63,12 +63,10 @@ __device__ __forceinline__ void uf_union(uint32_t* parent, uint32_t a, uint32_t 
     }
 }
 
-// A run of points: coordinate k of position i at crd[k * kstride + (base + i) * pstride].
+// A run of point rows (row_stride(D) int32 each): position i is row base + i.
 struct PointSet {
-    const int32_t* crd;
-    int64_t kstride;
-    int64_t pstride;
-    uint32_t base;        // first position of the set
+    const int32_t* rows;
+    uint32_t base;        // first row of the set
     uint32_t m;           // size
     uint64_t* alive;      // LDS bitmap, ceil(m / 64) words
     uint32_t words;
@@ -76,9 +74,7 @@ struct PointSet {
 
 template <int D>
 __device__ __forceinline__ void load_point(const PointSet& s, uint32_t pos, int32_t (&x)[D]) {
-    const int32_t* p = s.crd + (int64_t)(s.base + pos) * s.pstride;
-#pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = p[(int64_t)k * s.kstride];
+    load_row<D>(s.rows, (int64_t)s.base + pos, x);
 }
 
 constexpr uint32_t kUnroll = 4;  // words of a set whose loads are issued together

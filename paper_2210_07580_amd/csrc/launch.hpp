@@ -98,8 +98,9 @@ struct TreeView {
 struct GridView {
     Batch b;
     int64_t n;                   // total points
-    int D;                       // coordinate rows
-    const int32_t* crd;          // D x n, SoA: coordinate minus the instance minimum, sorted by grid
+    int D;                       // coordinates per row (shorter points padded with 0)
+    const int32_t* crd;          // rows of row_stride(D) int32: coordinates minus the instance minimum,
+                                 // sorted by grid (row s = sorted point s)
     const uint32_t* sidx;        // n: global input index of each sorted point
     int64_t ncell;               // grids (exact, or an upper bound when the launch is sync-free)
     const uint32_t* ncell_dev;   // device: exact number of grids
@@ -115,6 +116,7 @@ hipError_t launch_minmax(const Batch& b, hipStream_t st);
 hipError_t launch_layout(const Batch& b, hipStream_t st);
 template <typename K>
 hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st);
+// Sorted point rows: crd row s = point sidx[s] (see GridView::crd).
 hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st);
 // Runs of equal keys: cell_start[0..ncell], identifiers; header ncell written.
 template <typename K>
@@ -136,19 +138,24 @@ hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t*
                            uint32_t* nei, uint64_t capacity, hipStream_t st);
 
 // ---- core.hip
+// Core sets s_i as runs of point rows.  A grid whose points are all core
+// (every dense grid, and most others) uses its own sorted rows; only a grid
+// holding both core and non-core points gets its core rows copied, in
+// sorted order, to the side area behind row n.
 struct CoreOut {
     uint8_t* core;              // n, sorted order
-    uint32_t* core_excl;        // n + 1: exclusive scan of core flags
-    uint32_t* core_start;       // ncell + 1: first compacted core point of each grid
-    int32_t* ccrd;              // core points' coordinates, compacted, cstride int32 per point
-    int cstride;                // 4 (D <= 4) or 8: padded point record
-    uint32_t* corig;            // n: global input index of each compacted core point
+    uint32_t* core_cnt;         // ncell: core points of each grid (m_i)
+    uint32_t* core_begin;       // ncell: first row of each grid's core set
+    int32_t* ccrd;              // the row space: rows [0, n) = GridView::crd, then the side area
+    uint32_t* corig;            // row -> global input index (rows [0, n) = the sorted index)
+    uint32_t* side_off;         // ncell + 1: exclusive scan of the side rows of each grid
     uint32_t* cell_min_core;    // ncell: smallest input index of a core point (kNone if none)
     uint32_t* counts;           // header counts
 };
 constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
+// Core flags (sorted order) and m_i per grid.
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            unsigned long long* dist_counter, hipStream_t st);
+                            uint32_t* core_cnt, unsigned long long* dist_counter, hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = position (kNone for non-core grids).  ncc: number of
@@ -170,8 +177,9 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                         const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
                         int64_t max_core, uint32_t* parent, MergeStats* stats, const __half* proposal,
                         const CellSummary* sum, hipStream_t st);
-hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, const uint32_t* pairs, int64_t npairs,
-                              int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
+// pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).
+hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
+                              int64_t npairs, int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
                               hipStream_t st);
 hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, uint32_t* root_min,
                          int32_t* cell_label, hipStream_t st);

@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
     const int lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (c >= (int64_t)*gv.ncell_dev) return;
-    const uint32_t b = co.core_start[c], m = co.core_start[c + 1] - b;
+    const uint32_t b = co.core_begin[c], m = co.core_cnt[c];
     if (m == 0) return;
     double sum[D];
     uint64_t lo[D], hi[D];
@@ -25,7 +25,8 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
         hi[k] = 0ull;
     }
     for (uint32_t i = lane; i < m; i += kWave) {
-        const int32_t* p = co.ccrd + (int64_t)(b + i) * co.cstride;
+        int32_t p[D];
+        load_row<D>(co.ccrd, b + i, p);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const uint32_t v = (uint32_t)p[k];
@@ -82,11 +83,10 @@ __global__ __launch_bounds__(kBlock) void harvest_kernel(GridView gv, CoreOut co
     const int w = wave_id();
     const int64_t a = (int64_t)blockIdx.x * kWavesPerBlock + w;
     if (a >= (int64_t)*gv.ncell_dev) return;
-    const uint32_t ba = co.core_start[a], ma = co.core_start[a + 1] - ba;
+    const uint32_t ba = co.core_begin[a], ma = co.core_cnt[a];
     if (ma == 0 || ma > 64u * words) return;
     const Inst& I = cell_inst(gv, a);
     const double eps = (double)I.eps;
-    const int64_t P = co.cstride;
     uint64_t* bits_a = smem + (int64_t)w * 2 * words;
     uint64_t* bits_b = bits_a + words;
     const uint64_t e0 = nei_off[a], e1 = nei_off[a + 1];
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void harvest_kernel(GridView gv, CoreOut co
         if (idx < e1) {
             cb = nei[idx];
             if (cb > (uint32_t)a) {
-                const uint32_t mb = co.core_start[cb + 1] - co.core_start[cb];
+                const uint32_t mb = co.core_cnt[cb];
                 uint32_t h = (uint32_t)a * 0x9E3779B1u ^ (cb + seed) * 0x85EBCA77u;
                 h ^= h >> 15;
                 h *= 0xC2B2AE3Du;
@@ -117,9 +117,9 @@ __global__ __launch_bounds__(kBlock) void harvest_kernel(GridView gv, CoreOut co
             float f[kFeat];
             uint32_t ra, rb;
             pair_setup<D>(gv, co, sum, (uint32_t)a, b, eps, f, ra, rb);
-            const uint32_t bb = co.core_start[b], mb = co.core_start[b + 1] - bb;
-            PointSet sa{co.ccrd, 1, P, ba, ma, bits_a, (ma + kWave - 1) / kWave};
-            PointSet sb{co.ccrd, 1, P, bb, mb, bits_b, (mb + kWave - 1) / kWave};
+            const uint32_t bb = co.core_begin[b], mb = co.core_cnt[b];
+            PointSet sa{co.ccrd, ba, ma, bits_a, (ma + kWave - 1) / kWave};
+            PointSet sb{co.ccrd, bb, mb, bits_b, (mb + kWave - 1) / kWave};
             unsigned long long c0 = 0, c1 = 0, c2 = 0;
             uint32_t it;
             const int y = fast_merging<D>(sa, sb, 0u, I.T, eps, c0, it);

@@ -193,15 +193,20 @@ __device__ inline void pair_setup(const GridView& gv, const CoreOut& co, const C
     const CellSummary& B = sum[b];
     rep_a = rep_towards(A, B, D);
     rep_b = rep_towards(B, A, D);
-    const uint32_t ba = co.core_start[a], ma = co.core_start[a + 1] - ba;
-    const uint32_t bb = co.core_start[b], mb = co.core_start[b + 1] - bb;
+    const uint32_t ba = co.core_begin[a], ma = co.core_cnt[a];
+    const uint32_t bb = co.core_begin[b], mb = co.core_cnt[b];
     const uint32_t na = gv.cell_start[a + 1] - gv.cell_start[a];
     const uint32_t nb = gv.cell_start[b + 1] - gv.cell_start[b];
-    int32_t pa[kMaxD], pb[kMaxD];
+    int32_t pa[kMaxD] = {}, pb[kMaxD] = {};
+    {
+        int32_t ta[D], tb[D];
+        load_row<D>(co.ccrd, ba + rep_a, ta);
+        load_row<D>(co.ccrd, bb + rep_b, tb);
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        pa[k] = co.ccrd[(int64_t)(ba + rep_a) * co.cstride + k];
-        pb[k] = co.ccrd[(int64_t)(bb + rep_b) * co.cstride + k];
+        for (int k = 0; k < D; ++k) {
+            pa[k] = ta[k];
+            pb[k] = tb[k];
+        }
     }
     pair_features(A, B, D, eps, ma, mb, na, nb, grid_offset(gv, a, b, D), pa, pb, f);
 }

@@ -47,16 +47,17 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     if (r >= r1 || r >= (int64_t)co.counts[1]) return;
     const uint32_t ci = ldf[r];
     const uint32_t T = cell_inst(gv, ci).T;
-    const uint32_t bi = co.core_start[ci];
-    const uint32_t mi = co.core_start[ci + 1] - bi;
+    const uint32_t bi = co.core_begin[ci];
+    const uint32_t mi = co.core_cnt[ci];
     if (mi > kSmallSet) return;
-    const int P = co.cstride;
     int32_t pi[kSmallSet][D];
 #pragma unroll
-    for (int a = 0; a < (int)kSmallSet; ++a)
+    for (int a = 0; a < (int)kSmallSet; ++a) {
+        int32_t t[D];
+        load_row<D>(co.ccrd, (uint32_t)a < mi ? bi + a : bi, t);
 #pragma unroll
-        for (int k = 0; k < D; ++k)
-            pi[a][k] = uniform((uint32_t)a < mi ? co.ccrd[(int64_t)(bi + a) * P + k] : 0);
+        for (int k = 0; k < D; ++k) pi[a][k] = uniform((uint32_t)a < mi ? t[k] : 0);
+    }
     unsigned long long n_pairs = 0, n_yes = 0, n_dist = 0, n_pts = 0;
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     for (uint64_t e = e0; e < e1; e += kWave) {
@@ -67,8 +68,8 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
             cj = nei[idx];
             const uint32_t rj = rank[cj];
             if (rj != kNone && rj > (uint32_t)r) {
-                bj = co.core_start[cj];
-                mj = co.core_start[cj + 1] - bj;
+                bj = co.core_begin[cj];
+                mj = co.core_cnt[cj];
                 cand = mj <= kSmallSet;
             }
         }
@@ -76,8 +77,7 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
         if (cand) {
             for (uint32_t b = 0; b < mj && !yes; ++b) {
                 int32_t y[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) y[k] = co.ccrd[(int64_t)(bj + b) * P + k];
+                load_row<D>(co.ccrd, bj + b, y);
 #pragma unroll
                 for (int a = 0; a < (int)kSmallSet; ++a) {
                     if ((uint32_t)a < mi) {
@@ -148,16 +148,14 @@ __global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut 
     const Inst& I = cell_inst(gv, ci);
     const uint32_t T = I.T;
     const double eps = (double)I.eps;
-    const int64_t P = co.cstride;
-    PointSet si{co.ccrd, 1, P, co.core_start[ci], co.core_start[ci + 1] - co.core_start[ci],
-                smem + (int64_t)w * 2 * words, 0};
+    PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
     if (si.m <= kSmallSet) return;
     if (si.m > 64u * words) {  // larger than the LDS bitmaps this launch was given
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
         return;
     }
     si.words = (si.m + kWave - 1) / kWave;
-    PointSet sj{co.ccrd, 1, P, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
+    PointSet sj{co.ccrd, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     uint32_t ri = uf_find(parent, ci);
@@ -169,8 +167,8 @@ __global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut 
             cj = nei[idx];
             const uint32_t rj = rank[cj];
             if (rj != kNone) {
-                bj = co.core_start[cj];
-                mj = co.core_start[cj + 1] - bj;
+                bj = co.core_begin[cj];
+                mj = co.core_cnt[cj];
                 cand = mj <= kSmallSet || rj > (uint32_t)r;
             }
         }
@@ -293,9 +291,21 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     return hipGetLastError();
 }
 
+// Caller's d x m structure-of-arrays points to padded rows.
+template <int D>
+__global__ __launch_bounds__(kBlock) void soa_rows_kernel(const int32_t* __restrict__ pts, int64_t m,
+                                                          int32_t* __restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    int32_t y[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) y[k] = pts[(int64_t)k * m + i];
+    store_row<D>(rows, i, y);
+}
+
 // FastMerging on caller-given pairs of point runs (one wave per pair).
 template <int D>
-__global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __restrict__ pts, int64_t m,
+__global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __restrict__ pts,
                                                              const uint32_t* __restrict__ pairs, int64_t npairs,
                                                              uint32_t T, double eps, uint32_t words,
                                                              uint8_t* __restrict__ answers, uint32_t* iterations) {
@@ -304,8 +314,8 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     const int w = wave_id();
     const int64_t r = (int64_t)blockIdx.x * wpb + w;
     if (r >= npairs) return;
-    PointSet a{pts, m, 1, pairs[4 * r], pairs[4 * r + 1], smem + (int64_t)w * 2 * words, 0};
-    PointSet b{pts, m, 1, pairs[4 * r + 2], pairs[4 * r + 3], smem + (int64_t)w * 2 * words + words, 0};
+    PointSet a{pts, pairs[4 * r], pairs[4 * r + 1], smem + (int64_t)w * 2 * words, 0};
+    PointSet b{pts, pairs[4 * r + 2], pairs[4 * r + 3], smem + (int64_t)w * 2 * words + words, 0};
     a.words = (a.m + kWave - 1) / kWave;
     b.words = (b.m + kWave - 1) / kWave;
     unsigned long long nd = 0;
@@ -317,10 +327,11 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     }
 }
 
-hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, const uint32_t* pairs, int64_t npairs,
-                              int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
+hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
+                              int64_t npairs, int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
                               hipStream_t st) {
     if (npairs == 0) return hipSuccess;
+    if (m > 0) GD_DISPATCH_D(d, (soa_rows_kernel<D><<<dim3(grid_for(m)), dim3(kBlock), 0, st>>>(pts, m, rows)));
     const uint32_t words = (max_count + kWave - 1) / kWave;
     int wpb = kWavesPerBlock;
     size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
@@ -331,24 +342,24 @@ hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, const uint32
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((npairs + wpb - 1) / wpb);
     GD_DISPATCH_D(d, (merge_pairs_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                         pts, m, pairs, npairs, (uint32_t)(eps * eps), (double)eps, words, answers, iterations)));
+                         rows, pairs, npairs, (uint32_t)(eps * eps), (double)eps, words, answers, iterations)));
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void root_min_kernel(const uint32_t* ncell, const uint32_t* core_start,
+__global__ __launch_bounds__(kBlock) void root_min_kernel(const uint32_t* ncell, const uint32_t* core_cnt,
                                                           const uint32_t* cell_min_core, uint32_t* parent,
                                                           uint32_t* root_min) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)*ncell || core_start[c + 1] == core_start[c]) return;
+    if (c >= (int64_t)*ncell || core_cnt[c] == 0) return;
     atomicMin(&root_min[uf_find(parent, (uint32_t)c)], cell_min_core[c]);
 }
 
-__global__ __launch_bounds__(kBlock) void cell_label_kernel(const uint32_t* ncell, const uint32_t* core_start,
+__global__ __launch_bounds__(kBlock) void cell_label_kernel(const uint32_t* ncell, const uint32_t* core_cnt,
                                                             uint32_t* parent, const uint32_t* root_min,
                                                             int32_t* cell_label) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= (int64_t)*ncell) return;
-    cell_label[c] = core_start[c + 1] == core_start[c] ? -1 : (int32_t)root_min[uf_find(parent, (uint32_t)c)];
+    cell_label[c] = core_cnt[c] == 0 ? -1 : (int32_t)root_min[uf_find(parent, (uint32_t)c)];
 }
 
 hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, uint32_t* root_min,
@@ -356,9 +367,9 @@ hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, 
     if (g.ncell == 0) return hipSuccess;
     hipError_t e = fill<uint32_t>(root_min, g.ncell, kNone, st);
     if (e != hipSuccess) return e;
-    root_min_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_start, c.cell_min_core,
+    root_min_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, c.cell_min_core,
                                                                       parent, root_min);
-    cell_label_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_start, parent, root_min,
+    cell_label_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, parent, root_min,
                                                                         cell_label);
     return hipGetLastError();
 }

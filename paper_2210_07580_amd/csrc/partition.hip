@@ -10,8 +10,8 @@
 //             integer with the instance in the top field and dimension 1
 //             highest below it, so integer order is the lexicographic order
 //             the paper's radix sort produces, instance by instance
-//   gather  : sorted points as D separate int32 arrays (SoA) for coalesced
-//             loads in the later phases (instances with d < D padded with 0)
+//   gather  : sorted points as padded int32 rows (one vector load per point
+//             in the later phases; instances with d < D padded with 0)
 //   cells   : runs of equal identifiers = the non-empty grids Gs
 //   tree    : level 0 = instances, level l = distinct prefixes of length l,
 //             each level in sorted order, so every node's children are
@@ -22,6 +22,82 @@
 #include "scan.hpp"
 
 namespace gd {
+
+// Visit the points [lo, hi) of instance I (lo a multiple of 4): each thread
+// takes groups of four consecutive points, read as d float4 loads when the
+// rows are 16-byte aligned (four rows of d floats span exactly d float4),
+// then the remainder one point at a time.  f(i, row) gets the point index and
+// its d coordinates.
+template <int D, typename F>
+__device__ __forceinline__ void for_points(const Inst& I, int64_t lo, int64_t hi, F&& f) {
+    const float* __restrict__ x = I.x;
+    int64_t rest = lo;
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) == 0) {
+        const int64_t groups = (hi - lo) >> 2;
+        const float4* __restrict__ xv = reinterpret_cast<const float4*>(x + lo * D);
+#pragma unroll 2
+        for (int64_t gi = threadIdx.x; gi < groups; gi += kBlock) {
+            float v[4 * D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const float4 t = xv[gi * D + q];
+                v[4 * q + 0] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                float row[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) row[j] = v[p * D + j];
+                f(lo + 4 * gi + p, row);
+            }
+        }
+        rest = lo + 4 * groups;
+    }
+    for (int64_t i = rest + threadIdx.x; i < hi; i += kBlock) {
+        float row[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) row[j] = x[i * D + j];
+        f(i, row);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void minmax_tile(Inst& I, int64_t lo, int64_t hi, int* smn, int* smx) {
+    int lmn[D], lmx[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lmn[j] = INT_MAX;
+        lmx[j] = INT_MIN;
+    }
+    bool bad = false;
+    for_points<D>(I, lo, hi, [&](int64_t, const float (&row)[D]) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float v = row[j];
+            const bool ok = (v == rintf(v)) && fabsf(v) <= 16777216.0f;
+            bad |= !ok;
+            lmn[j] = min(lmn[j], ok ? (int)v : INT_MAX);
+            lmx[j] = max(lmx[j], ok ? (int)v : INT_MIN);
+        }
+    });
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        int a = lmn[j], c = lmx[j];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a = min(a, __shfl_xor(a, o));
+            c = max(c, __shfl_xor(c, o));
+        }
+        if (lane_id() == 0) {
+            atomicMin(&smn[j], a);
+            atomicMax(&smx[j], c);
+        }
+    }
+    if (ballot(bad) && lane_id() == 0) atomicOr(&I.err, kErrNotInteger);
+}
 
 __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
     __shared__ int smn[kMaxD], smx[kMaxD];
@@ -35,41 +111,16 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
     __syncthreads();
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
     const int64_t hi = min(I.n, lo + kPointTile);
-    int lmn[kMaxD], lmx[kMaxD];
-#pragma unroll
-    for (int j = 0; j < kMaxD; ++j) {
-        lmn[j] = INT_MAX;
-        lmx[j] = INT_MIN;
+    switch (d) {
+        case 1: minmax_tile<1>(I, lo, hi, smn, smx); break;
+        case 2: minmax_tile<2>(I, lo, hi, smn, smx); break;
+        case 3: minmax_tile<3>(I, lo, hi, smn, smx); break;
+        case 4: minmax_tile<4>(I, lo, hi, smn, smx); break;
+        case 5: minmax_tile<5>(I, lo, hi, smn, smx); break;
+        case 6: minmax_tile<6>(I, lo, hi, smn, smx); break;
+        case 7: minmax_tile<7>(I, lo, hi, smn, smx); break;
+        default: minmax_tile<8>(I, lo, hi, smn, smx); break;
     }
-    bool bad = false;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-#pragma unroll
-        for (int j = 0; j < kMaxD; ++j) {
-            if (j < d) {
-                const float v = I.x[i * d + j];
-                const bool ok = (v == rintf(v)) && fabsf(v) <= 16777216.0f;
-                bad |= !ok;
-                lmn[j] = min(lmn[j], ok ? (int)v : INT_MAX);
-                lmx[j] = max(lmx[j], ok ? (int)v : INT_MIN);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxD; ++j) {
-        if (j < d) {
-            int a = lmn[j], c = lmx[j];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                a = min(a, __shfl_xor(a, o));
-                c = max(c, __shfl_xor(c, o));
-            }
-            if (lane_id() == 0) {
-                atomicMin(&smn[j], a);
-                atomicMax(&smx[j], c);
-            }
-        }
-    }
-    if (ballot(bad) && lane_id() == 0) atomicOr(&I.err, kErrNotInteger);
     __syncthreads();
     if (threadIdx.x < (unsigned)d) {
         atomicMin(&I.mn[threadIdx.x], smn[threadIdx.x]);
@@ -134,25 +185,42 @@ hipError_t launch_layout(const Batch& b, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int D, typename K>
+__device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi, K top, K* __restrict__ keys) {
+    int32_t mn[D], sh[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        mn[j] = I.mn[j];
+        sh[j] = I.shift[j];
+    }
+    const uint32_t eps = (uint32_t)I.eps;
+    const float scale = (float)(sqrt((double)D) / (double)I.eps);
+    K* __restrict__ out = keys + I.off;
+    for_points<D>(I, lo, hi, [&](int64_t i, const float (&row)[D]) {
+        K key = top;
+#pragma unroll
+        for (int j = 0; j < D; ++j) key |= (K)grid_coord((uint32_t)((int)row[j] - mn[j]), D, eps, scale) << sh[j];
+        out[i] = key;
+    });
+}
+
 template <typename K>
 __global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys) {
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
-    const int d = I.d;
     const int ishift = b.hdr->inst_shift;
     const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
     const int64_t hi = min(I.n, lo + kPointTile);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        K key = top;
-#pragma unroll
-        for (int j = 0; j < kMaxD; ++j) {
-            if (j < d) {
-                const int64_t u = (int64_t)(int)I.x[i * d + j] - I.mn[j];
-                key |= (K)grid_coord(u, d, I.eps) << I.shift[j];
-            }
-        }
-        keys[I.off + i] = key;
+    switch (I.d) {
+        case 1: keys_tile<1, K>(I, lo, hi, top, keys); break;
+        case 2: keys_tile<2, K>(I, lo, hi, top, keys); break;
+        case 3: keys_tile<3, K>(I, lo, hi, top, keys); break;
+        case 4: keys_tile<4, K>(I, lo, hi, top, keys); break;
+        case 5: keys_tile<5, K>(I, lo, hi, top, keys); break;
+        case 6: keys_tile<6, K>(I, lo, hi, top, keys); break;
+        case 7: keys_tile<7, K>(I, lo, hi, top, keys); break;
+        default: keys_tile<8, K>(I, lo, hi, top, keys); break;
     }
 }
 
@@ -165,27 +233,66 @@ hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st) {
 template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, hipStream_t);
 template hipError_t launch_keys<uint64_t>(const Batch&, uint64_t*, hipStream_t);
 
+template <int D>
+struct FRow {
+    float v[D];
+};
+
 // Sorted position s of instance k lies in [off_k, off_k + n_k): the same
-// tiles as the input order.
+// tiles as the input order.  Each thread keeps four rows in flight; a row of
+// the input is fetched with one load of d floats.
+template <int DB>
 __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t* __restrict__ sidx,
                                                         int32_t* __restrict__ crd) {
+    constexpr int U = 4;
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
     const int d = I.d;
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
     const int64_t hi = min(I.n, lo + kPointTile);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const int64_t s = I.off + i;
-        const int64_t o = (int64_t)sidx[s] - I.off;
+    int32_t mn[DB];
 #pragma unroll
-        for (int j = 0; j < kMaxD; ++j)
-            if (j < b.D) crd[(int64_t)j * b.n + s] = j < d ? (int)I.x[o * d + j] - I.mn[j] : 0;
+    for (int j = 0; j < DB; ++j) mn[j] = j < d ? I.mn[j] : 0;
+    const float* __restrict__ x = I.x;
+    if (d == DB) {
+        const FRow<DB>* __restrict__ xr = reinterpret_cast<const FRow<DB>*>(x);
+        for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kBlock) {
+            uint32_t o[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + (int64_t)u * kBlock;
+                o[u] = i < hi ? (uint32_t)((int64_t)sidx[I.off + i] - I.off) : 0u;
+            }
+            FRow<DB> r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + (int64_t)u * kBlock < hi) r[u] = xr[o[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + (int64_t)u * kBlock;
+                if (i < hi) {
+                    int32_t y[DB];
+#pragma unroll
+                    for (int j = 0; j < DB; ++j) y[j] = (int)r[u].v[j] - mn[j];
+                    store_row<DB>(crd, I.off + i, y);
+                }
+            }
+        }
+    } else {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+            const int64_t s = I.off + i;
+            const int64_t o = (int64_t)sidx[s] - I.off;
+            int32_t y[DB];
+#pragma unroll
+            for (int j = 0; j < DB; ++j) y[j] = j < d ? (int)x[o * d + j] - mn[j] : 0;
+            store_row<DB>(crd, s, y);
+        }
     }
 }
 
 hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st) {
     if (b.tiles == 0) return hipSuccess;
-    gather_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, sidx, crd);
+    GD_DISPATCH_D(b.D, (gather_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, sidx, crd)));
     return hipGetLastError();
 }
 

@@ -6,11 +6,14 @@
 // histogram of its 4096-key tile in LDS (one sub-histogram per wave to cut
 // atomic contention); (2) a device-wide exclusive scan over the
 // digit-major [256][tiles] table gives every (digit, tile) its output base;
-// (3) every workgroup re-reads its tile in 16 rounds of 256 keys and ranks
-// each key among equal digits with wave64 ballots (eight ballots give the
-// lanes holding the same digit; the rank is the popcount below the lane),
-// then adds the counts of lower waves and of earlier rounds, kept in LDS.
-// Ranks follow input order, so every pass is stable.
+// (3) every workgroup re-reads its tile; each wave takes a run of 1024
+// consecutive keys and ranks them among equal digits with wave64 ballots
+// (eight ballots give the lanes holding the same digit; the rank is the
+// popcount below the lane plus the wave's running count of that digit, kept
+// in LDS), one scan over (digit, wave) turns the counts into local slots, the
+// keys are placed in LDS in digit order and written out run by run, so that
+// neighbouring lanes store to neighbouring addresses.  Ranks follow input
+// order, so every pass is stable.
 #pragma once
 
 #include "scan.hpp"
@@ -59,23 +62,39 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
                                                                K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                                int64_t tiles) {
-    __shared__ uint32_t run[kRadixBins];                    // next free slot per digit
-    __shared__ uint32_t wcnt[kWavesPerBlock][kRadixBins];   // keys per (wave, digit) this round
-    __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];   // first slot per (wave, digit) this round
+    constexpr int kPerWave = kRadixTile / kWavesPerBlock;  // 1024 consecutive keys per wave
+    constexpr int kIters = kPerWave / kWave;               // 16
+    __shared__ K skey[kRadixTile];                          // the tile, ordered by digit (stable)
+    __shared__ uint32_t sval[kRadixTile];
+    __shared__ uint32_t wcnt[kWavesPerBlock][kRadixBins];   // keys per (wave, digit), then first local slot
+    __shared__ uint32_t gbase[kRadixBins];                  // global slot of a digit's first key, minus its local start
+    __shared__ uint32_t wsum[kWavesPerBlock];
     const int t = threadIdx.x;
     const int w = wave_id();
-    run[t] = offs[(int64_t)t * tiles + blockIdx.x];
+    const int lane = lane_id();
 #pragma unroll
     for (int ww = 0; ww < kWavesPerBlock; ++ww) wcnt[ww][t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int tile_n = (int)min((int64_t)kRadixTile, n - base);
     const uint64_t lt = lanemask_lt();
-    for (int r = 0; r < kRadixItems; ++r) {
-        const int64_t i = base + (int64_t)r * kBlock + t;
-        if (base + (int64_t)r * kBlock >= n) break;  // uniform across the block
-        const bool valid = i < n;
-        K k = valid ? keys[i] : K(0);
-        const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
+    // 1. each wave ranks its own run of keys among equal digits, in order,
+    //    with wave-private counters (no workgroup barrier)
+    K k[kIters];
+    uint32_t v[kIters];
+    uint32_t dr[kIters];  // digit << 16 | rank within the wave
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        const int li = w * kPerWave + it * kWave + lane;
+        const bool valid = li < tile_n;
+        k[it] = valid ? keys[base + li] : K(0);
+        v[it] = valid ? (kIota ? (uint32_t)(base + li) : vals[base + li]) : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        const int li = w * kPerWave + it * kWave + lane;
+        const bool valid = li < tile_n;
+        const uint32_t dg = (uint32_t)(k[it] >> shift) & (kRadixBins - 1);
         uint64_t peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
@@ -83,26 +102,50 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
             const uint64_t m = ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = (uint32_t)popc64(peers & lt);
-        if (valid && rank == 0) wcnt[w][dg] = (uint32_t)popc64(peers);
-        __syncthreads();
-        {
-            uint32_t acc = run[t];
+        const uint32_t before = valid ? wcnt[w][dg] : 0u;
+        wave_sync();
+        const uint32_t rank = before + (uint32_t)popc64(peers & lt);
+        if (valid && (peers & lt) == 0) wcnt[w][dg] = before + (uint32_t)popc64(peers);
+        wave_sync();
+        dr[it] = (dg << 16) | rank;
+    }
+    __syncthreads();
+    // 2. local start of each (wave, digit): digits in order, waves in order
+    {
+        uint32_t c[kWavesPerBlock], tot = 0;
 #pragma unroll
-            for (int ww = 0; ww < kWavesPerBlock; ++ww) {
-                const uint32_t c = wcnt[ww][t];
-                woff[ww][t] = acc;
-                acc += c;
-                wcnt[ww][t] = 0;
-            }
-            run[t] = acc;
+        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+            c[ww] = wcnt[ww][t];
+            tot += c[ww];
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = woff[w][dg] + rank;
-            keys_out[pos] = k;
-            vals_out[pos] = kIota ? (uint32_t)i : vals[i];
+        uint32_t all;
+        uint32_t acc = block_excl_scan(tot, wsum, all);
+        gbase[t] = offs[(int64_t)t * tiles + blockIdx.x] - acc;
+#pragma unroll
+        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+            wcnt[ww][t] = acc;
+            acc += c[ww];
         }
+    }
+    __syncthreads();
+    // 3. place the keys in LDS in digit order
+#pragma unroll
+    for (int it = 0; it < kIters; ++it) {
+        const int li = w * kPerWave + it * kWave + lane;
+        if (li < tile_n) {
+            const uint32_t pos = wcnt[w][dr[it] >> 16] + (dr[it] & 0xFFFFu);
+            skey[pos] = k[it];
+            sval[pos] = v[it];
+        }
+    }
+    __syncthreads();
+    // 4. write the digit runs out in order: consecutive threads, consecutive slots
+    for (int j = t; j < tile_n; j += kBlock) {
+        const K kk = skey[j];
+        const uint32_t dg = (uint32_t)(kk >> shift) & (kRadixBins - 1);
+        const uint32_t pos = gbase[dg] + (uint32_t)j;
+        keys_out[pos] = kk;
+        vals_out[pos] = sval[j];
     }
 }
 
