@@ -81,6 +81,7 @@ struct gd_ctx {
     __half* proposal_dev = nullptr;  // GD_MLP_PARAMS halves
     bool proposal_on = false;
     DevBuf sumbuf;                   // CellSummary per grid
+    DevBuf table;                    // identifier -> label hash table of the output pass
     unsigned long long* counter_dev = nullptr;
     // phase timing
     bool timing = false;
@@ -168,6 +169,7 @@ struct Layout {
     uint32_t* vals_b;
     void* keys_a;
     void* keys_b;
+    void* keys_c;
     uint32_t* radix_scratch;
     uint64_t* partial;
     int32_t* crd;
@@ -195,8 +197,9 @@ struct Layout {
 Layout carve(char* base, int64_t n, int D) {
     Layout L{};
     Carve c{base};
-    L.keys_a = c.take<uint64_t>(n);
+    L.keys_a = c.take<uint64_t>(n);  // identifiers in input order (kept for the output pass)
     L.keys_b = c.take<uint64_t>(n);
+    L.keys_c = c.take<uint64_t>(n);
     // the sorted index doubles as the row -> input index map of the core
     // sets, whose side area follows row n
     L.vals_a = c.take<uint32_t>(2 * n);
@@ -236,7 +239,8 @@ int readback(gd_ctx* ctx, hipStream_t st) {
 }
 
 template <typename K>
-int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const uint32_t** sidx_out, hipStream_t st) {
+int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const uint32_t** sidx_out, void** skeys_out,
+                  hipStream_t st) {
     K* ka = (K*)L.keys_a;
     K* kb = (K*)L.keys_b;
     ctx->mark(P_KEYS, 0);
@@ -244,7 +248,8 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
     ctx->mark(P_KEYS, 1);
     RadixResult<K> res;
     ctx->mark(P_SORT, 0);
-    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, b.n, key_bits, true, L.radix_scratch, st, &res));
+    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, b.n, key_bits, true, L.radix_scratch, st, &res,
+                               (K*)L.keys_c));
     ctx->mark(P_SORT, 1);
     ctx->mark(P_GATHER, 0);
     GD_TRY(launch_gather(b, res.vals, L.crd, st));
@@ -253,6 +258,7 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
     GD_TRY(launch_cells<K>(b, res.keys, L.excl, (uint32_t*)L.partial, L.cell_start, L.ck, b.n, st));
     ctx->mark(P_CELLS, 1);
     *sidx_out = res.vals;
+    *skeys_out = res.keys;
     return GD_OK;
 }
 
@@ -312,10 +318,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- Algorithm 1: identifiers, radix sort, grids
     const uint32_t* sidx = nullptr;
-    if (key_bits <= 32)
-        rc = run_partition<uint32_t>(ctx, b, key_bits, L, &sidx, st);
+    void* skeys = nullptr;
+    const bool k32 = key_bits <= 32;
+    if (k32)
+        rc = run_partition<uint32_t>(ctx, b, key_bits, L, &sidx, &skeys, st);
     else
-        rc = run_partition<uint64_t>(ctx, b, key_bits, L, &sidx, st);
+        rc = run_partition<uint64_t>(ctx, b, key_bits, L, &sidx, &skeys, st);
     if (rc) return rc;
     if ((rc = readback(ctx, st))) return rc;
     const int64_t ncell = H->ncell;
@@ -382,8 +390,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     // ---- merging (Algorithm 5 + union-find, LDF order)
     uint32_t* ldf = nullptr;
     {
-        // the sorted keys are no longer needed: reuse their space
-        uint32_t* ka = (uint32_t*)L.keys_a;
+        // the sort buffer that does not hold the sorted identifiers is free
+        uint32_t* ka = (uint32_t*)(skeys == L.keys_b ? L.keys_c : L.keys_b);
         uint32_t* kb = ka + n;
         uint32_t* vb = (sidx == L.vals_a) ? L.vals_b : L.vals_a;
         ctx->mark(P_LDF, 0);
@@ -415,7 +423,18 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->mark(P_LABELS, 1);
 
     // ---- border / noise, output in input order
+    int hbits = 10;
+    while (((int64_t)1 << hbits) < 2 * ncell) ++hbits;
+    if ((rc = grow(ctx, ctx->table, output_table_bytes(hbits, k32 ? 4 : 8),
+                   ctx->arena.cap + ctx->nei.cap + ctx->sumbuf.cap)))
+        return rc;
     ctx->mark(P_OUTPUT, 0);
+    if (k32)
+        GD_TRY(launch_output_direct<uint32_t>(g, co, (const uint32_t*)L.keys_a, (const uint32_t*)skeys, L.cell_label,
+                                              ctx->table.p, hbits, st));
+    else
+        GD_TRY(launch_output_direct<uint64_t>(g, co, (const uint64_t*)L.keys_a, (const uint64_t*)skeys, L.cell_label,
+                                              ctx->table.p, hbits, st));
     GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
     ctx->mark(P_OUTPUT, 1);
     if (ctx->stats)
@@ -590,6 +609,7 @@ void gd_destroy(gd_ctx* ctx) {
     if (ctx->proposal_dev) (void)hipFree(ctx->proposal_dev);
     if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
     if (ctx->sumbuf.p) (void)hipFree(ctx->sumbuf.p);
+    if (ctx->table.p) (void)hipFree(ctx->table.p);
     for (int p = 0; p < P_COUNT; ++p)
         for (int k = 0; k < 2; ++k)
             if (ctx->ev[p][k]) (void)hipEventDestroy(ctx->ev[p][k]);

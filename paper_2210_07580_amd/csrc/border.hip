@@ -9,10 +9,133 @@
 // skipping grids whose smallest core index cannot improve any open query;
 // for each non-core query a ballot finds the candidates within eps and a
 // wave minimum over (input index << 32 | label) keeps the lowest index.
+//
+// Writing in input order: grids whose points are all core (nearly every
+// point in dense data) do not scatter their output through the sort
+// permutation.  A hash table maps each grid's identifier to its label; one
+// pass over the points in input order re-reads each point's identifier
+// (kept from before the sort), looks the label up and writes labels and
+// flags with coalesced stores.  Only grids holding a non-core point go
+// through the wave-per-grid kernel, which writes through the permutation.
+#include <algorithm>
+
 #include "launch.hpp"
 #include "scan.hpp"
 
 namespace gd {
+
+constexpr int32_t kDeferred = -2;  // grid output written by the wave-per-grid kernel
+
+template <typename K>
+struct HashSlot;
+template <>
+struct alignas(8) HashSlot<uint32_t> {
+    uint32_t key;
+    int32_t val;
+};
+template <>
+struct alignas(16) HashSlot<uint64_t> {
+    uint64_t key;
+    int32_t val;
+    int32_t pad;
+};
+
+template <typename K>
+__device__ __forceinline__ uint64_t hash_slot(K key, int bits) {
+    return ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - bits);
+}
+
+__device__ __forceinline__ uint32_t cas_key(uint32_t* p, uint32_t cmp, uint32_t v) { return atomicCAS(p, cmp, v); }
+__device__ __forceinline__ uint64_t cas_key(uint64_t* p, uint64_t cmp, uint64_t v) {
+    return (uint64_t)atomicCAS(reinterpret_cast<unsigned long long*>(p), (unsigned long long)cmp,
+                               (unsigned long long)v);
+}
+
+// The all-ones identifier marks an empty slot; a grid with that identifier
+// keeps its label in the extra slot at index 2^bits.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void hash_clear_kernel(HashSlot<K>* tab, int64_t slots) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kBlock) {
+        tab[i].key = ~K(0);
+        tab[i].val = kDeferred;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut co, const K* __restrict__ skeys,
+                                                            const int32_t* __restrict__ cell_label,
+                                                            HashSlot<K>* tab, int bits) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)*gv.ncell_dev) return;
+    const uint32_t st = gv.cell_start[c];
+    const uint32_t k = gv.cell_start[c + 1] - st;
+    const int32_t val = co.core_cnt[c] == k ? cell_label[c] : kDeferred;
+    const K key = skeys[st];
+    const uint64_t mask = (1ull << bits) - 1ull;
+    if (key == ~K(0)) {
+        tab[mask + 1].val = val;
+        return;
+    }
+    for (uint64_t h = hash_slot(key, bits);; h = (h + 1) & mask) {
+        if (cas_key(&tab[h].key, ~K(0), key) == ~K(0)) {
+            tab[h].val = val;
+            return;
+        }
+    }
+}
+
+// Points in input order, instance tiles as in the identifier pass.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
+                                                               const HashSlot<K>* __restrict__ tab, int bits) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
+    const int64_t hi = min(I.n, lo + kPointTile);
+    const uint64_t mask = (1ull << bits) - 1ull;
+    const int32_t off = (int32_t)I.off;
+    int32_t* __restrict__ labels = I.labels;
+    uint8_t* __restrict__ flags = I.core;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const K key = keys[I.off + i];
+        int32_t val;
+        if (key == ~K(0)) {
+            val = tab[mask + 1].val;
+        } else {
+            uint64_t h = hash_slot(key, bits);
+            HashSlot<K> e = tab[h];
+            while (e.key != key) {  // every identifier of the batch is in the table
+                h = (h + 1) & mask;
+                e = tab[h];
+            }
+            val = e.val;
+        }
+        if (val != kDeferred) {
+            labels[i] = val - off;
+            flags[i] = 1;
+        }
+    }
+}
+
+template <typename K>
+hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* keys_in, const K* skeys,
+                                const int32_t* cell_label, void* table, int bits, hipStream_t st) {
+    if (g.ncell == 0) return hipSuccess;
+    HashSlot<K>* tab = reinterpret_cast<HashSlot<K>*>(table);
+    const int64_t slots = (1ll << bits) + 1;
+    hash_clear_kernel<K><<<dim3((unsigned)std::min<int64_t>(grid_for(slots), 4096)), dim3(kBlock), 0, st>>>(tab, slots);
+    hash_build_kernel<K><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, skeys, cell_label, tab, bits);
+    output_direct_kernel<K><<<dim3(g.b.tiles), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits);
+    return hipGetLastError();
+}
+template hipError_t launch_output_direct<uint32_t>(const GridView&, const CoreOut&, const uint32_t*, const uint32_t*,
+                                                   const int32_t*, void*, int, hipStream_t);
+template hipError_t launch_output_direct<uint64_t>(const GridView&, const CoreOut&, const uint64_t*, const uint64_t*,
+                                                   const int32_t*, void*, int, hipStream_t);
+
+size_t output_table_bytes(int bits, int key_bytes) {
+    return (size_t)((1ll << bits) + 1) * (key_bytes == 4 ? 8 : 16);
+}
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
@@ -30,6 +153,7 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
     uint8_t* __restrict__ core_flags = I.core;
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
+    if (co.core_cnt[c] == k) return;  // written in input order by output_direct_kernel
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
     const uint32_t T = I.T;

@@ -194,7 +194,15 @@ struct TrainArgs;
 hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
 
 // ---- border.hip
+// Grids with a non-core point: border search and output through the permutation.
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                          const int32_t* cell_label, hipStream_t st);
+// All-core grids: output in input order through an identifier -> label hash
+// table of 2^bits slots (+1) in `table` (output_table_bytes).  keys_in: the
+// identifiers in input order; skeys: sorted.
+template <typename K>
+hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* keys_in, const K* skeys,
+                                const int32_t* cell_label, void* table, int bits, hipStream_t st);
+size_t output_table_bytes(int bits, int key_bytes);
 
 }  // namespace gd

@@ -163,15 +163,19 @@ struct RadixResult {
 
 // Sorts keys[0..n) (and vals) on their low `bits` bits.  keys/vals and
 // keys_alt/vals_alt are ping-pong buffers; the result lands in one of them.
+// With keys_spare, the passes after the first alternate between keys_alt
+// and keys_spare, so keys[] keeps the input order.
 // If vals_iota, vals[] is not read and the values start as 0..n-1.
 // `scratch` needs radix_scratch_words(n) u32.
 template <typename K>
 hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
-                            bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K>* out) {
+                            bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K>* out,
+                            K* keys_spare = nullptr) {
     K* kin = keys;
     uint32_t* vin = vals;
     K* kout = keys_alt;
     uint32_t* vout = vals_alt;
+    bool first = true;
     const int64_t tiles = radix_tiles(n);
     uint32_t* hist = scratch;
     uint32_t* offs = scratch + (int64_t)kRadixBins * tiles;
@@ -190,7 +194,8 @@ hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals
             radix_scatter_kernel<K, false><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n,
                                                                                          shift, offs, tiles);
         iota = false;
-        K* tk = kin; kin = kout; kout = tk;
+        K* tk = kin; kin = kout; kout = (first && keys_spare) ? keys_spare : tk;
+        first = false;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
     if (iota && n > 0) {  // no pass ran: the values must still be 0..n-1
