@@ -102,7 +102,11 @@ def bench_batched(G, steps, warmup, max_instances):
         if not (torch.equal(l1, lab) and torch.equal(c1, core)):
             raise RuntimeError("batched and single-instance results differ")
     t_batch = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
-    log(f"bench: batched {1e3 * t_batch:.2f} ms")
+    replayed = ctx.stats()["graph_replays"] == 1
+    log(f"bench: batched {1e3 * t_batch:.2f} ms (graph replay: {replayed})")
+    ctx.set_option(G.GD_OPT_GRAPH, 0)
+    t_batch_eager = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
+    log(f"bench: batched without graph {1e3 * t_batch_eager:.2f} ms")
 
     def each():
         for (t, e, m), (lab, core) in zip(probs, outs):
@@ -117,6 +121,8 @@ def bench_batched(G, steps, warmup, max_instances):
         "value": round(total / t_batch, 1), "ms_per_batch": round(1e3 * t_batch, 3),
         "plain_value": round(total / t_each, 1), "plain_ms_per_batch": round(1e3 * t_each, 3),
         "speedup_vs_plain": round(t_each / t_batch, 3), "unit": "points/s",
+        "graph_replay": replayed, "no_graph_value": round(total / t_batch_eager, 1),
+        "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3),
     }
 
 
@@ -219,6 +225,13 @@ def main():
     ctx.dbscan(pts, w.eps, w.minpts, labels, core)
     st = ctx.stats()
     ctx.set_option(G.GD_OPT_STATS, 0)
+    # the same step replayed from a captured HIP graph (no host synchronisation between phases)
+    ctx.set_option(G.GD_OPT_TIMING, 0)
+    ctx.set_option(G.GD_OPT_GRAPH, 2)
+    t_graph = time_calls(lambda: ctx.dbscan(pts, w.eps, w.minpts, labels, core), args.steps, args.warmup)
+    graph_ok = ctx.stats()["graph_replays"] == 1
+    ctx.set_option(G.GD_OPT_GRAPH, 1)
+    log(f"bench: graph replay {1e3 * t_graph:.3f} ms/step (replayed: {graph_ok})")
 
     K = args.steps
     total = t1 - t0
@@ -265,6 +278,8 @@ def main():
         "config": {"workload": WORKLOAD_DESC.get(w.name, w.name), "n": int(n), "d": int(d),
                    "eps": w.eps, "minpts": w.minpts, "seed": w.seed},
         "roofline": roofline,
+        "graph_replay": {"value": round(n / t_graph, 1), "ms_per_step": round(1e3 * t_graph, 3),
+                         "replayed": graph_ok},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "work": {k: st[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids",
                                     "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",

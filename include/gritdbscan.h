@@ -85,6 +85,8 @@ typedef struct {
     int64_t noise_points;
     int64_t clusters;
     int64_t merge_set_points;  /* sum over FastMerging calls of |s_i| + |s_j| */
+    int64_t graph_replays;     /* 1 if the call replayed a captured HIP graph
+                                  (then only the size fields are filled) */
 } gd_stats;
 
 /* Create a context bound to HIP device `device` (the caller's current device
@@ -140,6 +142,16 @@ typedef struct {
  * by the caller; the sum of n must stay below 2^31.  Synchronous on
  * `stream`.  On error no output is valid; gd_last_error() names the first
  * offending instance.
+ *
+ * Graph replay (GD_OPT_GRAPH, on by default for this call): the first call
+ * for a batch shape (instance count, each n and d) runs with host
+ * synchronisation between phases, then captures a synchronisation-free run,
+ * sized from that call's grid, neighbour and core-set counts plus headroom,
+ * into a HIP graph on a stream of the context.  Later calls with the same
+ * shape replay the graph (any coordinates, eps, MinPts and pointers) after
+ * the caller's stream's prior work; a replay whose data outgrow the captured
+ * sizes is detected on the device and the call reruns without the graph, so
+ * the result is always exact.  Graph replays need no per-call allocation.
  */
 int dbscan_batched(gd_ctx *ctx, const gd_instance *inst, int32_t count, void *stream);
 
@@ -150,8 +162,12 @@ typedef enum {
                                  core-count order; 0: grid (identifier) order */
     GD_OPT_WORKSPACE_LIMIT = 3,/* bytes of device workspace the context may hold;
                                  0 = unlimited (default)                      */
-    GD_OPT_TIMING = 4         /* 1: record HIP events around every phase on the
+    GD_OPT_TIMING = 4,        /* 1: record HIP events around every phase on the
                                  call's stream (see gd_get_phase_times)       */
+    GD_OPT_GRAPH = 5          /* graph replay (see dbscan_batched): 0 never,
+                                 1 (default) dbscan_batched only, 2 also
+                                 dbscan(); calls with GD_OPT_STATS or
+                                 GD_OPT_TIMING on always run without it      */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);

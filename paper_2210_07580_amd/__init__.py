@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING = 1, 2, 3, 4
+GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
 PHASE_COUNT = 14
 EPS_MAX = 21845
 D_MAX = 8
@@ -36,7 +36,7 @@ class Stats(ctypes.Structure):
             "grids", "neighbor_entries", "core_points", "core_grids", "dense_grids",
             "max_grid_points", "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
             "merge_iterations", "merge_max_iterations", "merge_distances", "core_distances",
-            "border_points", "noise_points", "clusters", "merge_set_points")]
+            "border_points", "noise_points", "clusters", "merge_set_points", "graph_replays")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -83,6 +83,16 @@ struct gd_ctx {
     DevBuf sumbuf;                   // CellSummary per grid
     DevBuf table;                    // identifier -> label hash table of the output pass
     unsigned long long* counter_dev = nullptr;
+    // sync-free runs captured into a HIP graph and replayed
+    int graph_mode = 1;              // 0 never, 1 dbscan_batched, 2 every call
+    uint64_t generation = 0;         // bumped whenever a buffer is reallocated
+    hipStream_t gstream = nullptr;   // capture and replay stream
+    hipEvent_t gev = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gsig;       // batch shape the graph was captured for
+    uint64_t ggen = 0;
+    int last_key_bits = 0;
+    bool marking = true;
     // phase timing
     bool timing = false;
     bool events_ok = false;
@@ -92,7 +102,7 @@ struct gd_ctx {
     hipStream_t st = nullptr;
 
     void mark(int phase, int which) {
-        if (!timing || !events_ok) return;
+        if (!timing || !events_ok || !marking) return;
         if (hipEventRecord(ev[phase][which], st) == hipSuccess && which == 1) ran[phase] = true;
     }
 
@@ -152,6 +162,7 @@ int grow(gd_ctx* ctx, DevBuf& b, size_t need, size_t other_held) {
         b.cap = 0;
     }
     const size_t sz = need + need / 8;  // some headroom for the next call
+    ++ctx->generation;                  // a captured graph that used the old buffer is stale
     if (hipMalloc(&b.p, sz) != hipSuccess) {
         (void)hipGetLastError();
         b.p = nullptr;
@@ -162,6 +173,22 @@ int grow(gd_ctx* ctx, DevBuf& b, size_t need, size_t other_held) {
 }
 
 int bit_length(uint64_t v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
+
+// Capacities of a sync-free run (see run_batch).
+struct Plan {
+    int key_bits;      // identifier bits sorted (a multiple of 8)
+    int64_t ncell;     // grids
+    uint64_t nei;      // neighbour-list entries
+    int64_t ncc;       // core grids
+    int64_t max_core;  // largest core set
+};
+
+// Output hash table: 2^bits slots for ncell grids (load <= 1/2).
+int table_bits(int64_t ncell) {
+    int b = 10;
+    while (((int64_t)1 << b) < 2 * ncell) ++b;
+    return b;
+}
 
 // Workspace layout; with base == nullptr it only measures.
 struct Layout {
@@ -262,8 +289,11 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
     return GD_OK;
 }
 
-// Validated batch in ctx->inst_host[0..count): run every phase.
-int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream_t st) {
+// Validated batch in ctx->inst_host[0..count): run every phase.  With a
+// plan the run is sync-free (every buffer already grown, capacities from
+// the plan, no host readback until the end) so that it can be captured into
+// a HIP graph; device-side checks raise kErrPlan when the data outgrow it.
+int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream_t st, const Plan* plan) {
     ctx->have_last = false;
     std::memset(&ctx->last, 0, sizeof(ctx->last));
     ctx->last.n = n;
@@ -272,7 +302,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- workspace
     Layout L = carve(nullptr, n, D);
-    int rc = grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
+    int rc = plan ? GD_OK : grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
     if (rc) return rc;
     L = carve((char*)ctx->arena.p, n, D);
     Header* Hd = ctx->hdr_dev;
@@ -287,6 +317,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     b.hdr = Hd;
 
     ctx->st = st;
+    ctx->marking = !plan;
     for (int p = 0; p < P_COUNT; ++p) {
         ctx->ran[p] = false;
         ctx->phase_ms[p] = 0.0;
@@ -295,25 +326,26 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     // ---- instance table, mn_j and the input check (Eq. (1)), identifier layout
     GD_TRY(hipMemcpyAsync(ctx->inst_dev, ctx->inst_host, sizeof(Inst) * count, hipMemcpyHostToDevice, st));
     GD_TRY(fill<uint32_t>((uint32_t*)Hd, (int64_t)(sizeof(Header) / sizeof(uint32_t)), 0u, st));
-    if (ctx->stats)
+    const bool stats = ctx->stats && !plan;
+    if (stats)
         GD_TRY(fill<unsigned long long>(&ctx->stats_dev->merge[0].pairs,
                                         (int64_t)(sizeof(StatBlock) / sizeof(unsigned long long)), 0ull, st));
     ctx->mark(P_MINMAX, 0);
     GD_TRY(launch_minmax(b, st));
-    GD_TRY(launch_layout(b, st));
+    GD_TRY(launch_layout(b, plan ? plan->key_bits : 64, st));
     ctx->mark(P_MINMAX, 1);
-    if ((rc = readback(ctx, st))) return rc;
-    if (H->err & kErrNotInteger) {
+    if (!plan && (rc = readback(ctx, st))) return rc;
+    if (!plan && (H->err & kErrNotInteger)) {
         GD_TRY(hipMemcpyAsync(ctx->inst_host, ctx->inst_dev, sizeof(Inst) * count, hipMemcpyDeviceToHost, st));
         GD_TRY(hipStreamSynchronize(st));
         int bad = 0;
         while (bad < count && !(ctx->inst_host[bad].err & kErrNotInteger)) ++bad;
         return ctx->fail(GD_ERANGE, "instance %d: a coordinate is not a finite integer of magnitude <= 2^24", bad);
     }
-    if (H->err & kErrKeyBits)
+    if (!plan && (H->err & kErrKeyBits))
         return ctx->fail(GD_ERANGE, "grid identifiers need %d bits (> 64): eps too small for the data's extent",
                          H->total_bits);
-    const int key_bits = H->total_bits;
+    const int key_bits = plan ? plan->key_bits : H->total_bits;
     ctx->last.key_bits = key_bits;
 
     // ---- Algorithm 1: identifiers, radix sort, grids
@@ -325,8 +357,11 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     else
         rc = run_partition<uint64_t>(ctx, b, key_bits, L, &sidx, &skeys, st);
     if (rc) return rc;
-    if ((rc = readback(ctx, st))) return rc;
-    const int64_t ncell = H->ncell;
+    if (plan)
+        GD_TRY(launch_plan_check(Hd, 0, plan->ncell, 0, st));
+    else if ((rc = readback(ctx, st)))
+        return rc;
+    const int64_t ncell = plan ? plan->ncell : (int64_t)H->ncell;
 
     GridView g{};
     g.b = b;
@@ -355,9 +390,13 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     GD_TRY(launch_nei_count(g, t, L.off_counts, st));
     GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
     ctx->mark(P_NEI_COUNT, 1);
-    if ((rc = readback(ctx, st))) return rc;
-    const uint64_t nei_total = H->nei_total;
-    if ((rc = grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t), ctx->arena.cap)))
+    if (plan)
+        GD_TRY(launch_plan_check(Hd, 1, (int64_t)plan->nei, 0, st));
+    else if ((rc = readback(ctx, st)))
+        return rc;
+    const uint64_t nei_total = plan ? plan->nei : H->nei_total;
+    if (!plan && (rc = grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t),
+                            ctx->arena.cap)))
         return rc;
     uint32_t* nei = (uint32_t*)ctx->nei.p;
     ctx->mark(P_NEI_FILL, 0);
@@ -366,8 +405,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, ctx->stats ? ctx->stats_dev->core_dist : nullptr,
-                            st));
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core_dist : nullptr, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
@@ -381,8 +419,13 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->mark(P_CORE_COMPACT, 0);
     GD_TRY(launch_core_compact(g, co, (uint32_t*)L.partial, st));
     ctx->mark(P_CORE_COMPACT, 1);
-    if ((rc = readback(ctx, st))) return rc;
-    const int64_t ncore = H->counts[0], ncc = H->counts[1], max_core = H->counts[2];
+    if (plan)
+        GD_TRY(launch_plan_check(Hd, 2, plan->ncc, plan->max_core, st));
+    else if ((rc = readback(ctx, st)))
+        return rc;
+    const int64_t ncore = plan ? 0 : (int64_t)H->counts[0];
+    const int64_t ncc = plan ? plan->ncc : (int64_t)H->counts[1];
+    const int64_t max_core = plan ? plan->max_core : (int64_t)H->counts[2];
     if (max_core > kMaxCoreBits)
         return ctx->fail(GD_EUNSUPPORTED, "a grid holds %lld core points; the merge step handles at most %lld",
                          (long long)max_core, (long long)kMaxCoreBits);
@@ -395,7 +438,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         uint32_t* kb = ka + n;
         uint32_t* vb = (sidx == L.vals_a) ? L.vals_b : L.vals_a;
         ctx->mark(P_LDF, 0);
-        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, bit_length((uint64_t)max_core), L.list, L.rank, ka, kb, vb,
+        // a planned run sorts ncc slots, the unused ones last under an all-ones key
+        const int count_bits = bit_length((uint64_t)max_core) + (plan ? 1 : 0);
+        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, ka, kb, vb,
                                 L.radix_scratch, L.excl, (uint32_t*)L.partial, &ldf, st));
         GD_TRY((iota_kernel<uint32_t><<<dim3(grid_for(ncell)), dim3(kBlock), 0, st>>>(L.parent, ncell),
                 hipGetLastError()));
@@ -404,8 +449,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     CellSummary* sum = nullptr;
     ctx->last_summaries = false;
     if (ctx->proposal_on) {
-        if ((rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(ncell, 1),
-                       ctx->arena.cap + ctx->nei.cap)))
+        if (!plan && (rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(ncell, 1),
+                                ctx->arena.cap + ctx->nei.cap)))
             return rc;
         sum = (CellSummary*)ctx->sumbuf.p;
     }
@@ -414,8 +459,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(launch_summaries(g, co, sum, st));
         ctx->last_summaries = true;
     }
-    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, ctx->ldf ? (int64_t)H->counts[4] : -1, max_core,
-                        L.parent, ctx->stats ? ctx->stats_dev->merge : nullptr,
+    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, (ctx->ldf && !plan) ? (int64_t)H->counts[4] : -1,
+                        max_core, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                         ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
     ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);
@@ -423,10 +468,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->mark(P_LABELS, 1);
 
     // ---- border / noise, output in input order
-    int hbits = 10;
-    while (((int64_t)1 << hbits) < 2 * ncell) ++hbits;
-    if ((rc = grow(ctx, ctx->table, output_table_bytes(hbits, k32 ? 4 : 8),
-                   ctx->arena.cap + ctx->nei.cap + ctx->sumbuf.cap)))
+    const int hbits = table_bits(ncell);
+    if (!plan && (rc = grow(ctx, ctx->table, output_table_bytes(hbits, k32 ? 4 : 8),
+                            ctx->arena.cap + ctx->nei.cap + ctx->sumbuf.cap)))
         return rc;
     ctx->mark(P_OUTPUT, 0);
     if (k32)
@@ -437,8 +481,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
                                               ctx->table.p, hbits, st));
     GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
     ctx->mark(P_OUTPUT, 1);
-    if (ctx->stats)
-        GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
+    if (stats) GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
+    if (plan) {
+        // the caller synchronises and checks the header
+        GD_TRY(hipMemcpyAsync(ctx->hdr_host, ctx->hdr_dev, sizeof(Header), hipMemcpyDeviceToHost, st));
+        return GD_OK;
+    }
     if ((rc = readback(ctx, st))) return rc;
     if (H->err & kErrMergeRunaway) return ctx->fail(GD_EDEVICE, "merge step exceeded its iteration bound");
     if (H->err & (kErrNeiOverflow | kErrCoreCap))
@@ -467,6 +515,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->last_g = g;
     ctx->last_co = co;
     ctx->last_max_core = max_core;
+    ctx->last_key_bits = key_bits;
 
     gd_stats& s = ctx->last;
     s.grids = ncell;
@@ -559,6 +608,119 @@ void finish_table(gd_ctx* ctx, int count, int* D, int64_t* n, uint32_t* tiles) {
     *tiles = t;
 }
 
+// Shape of the batch a graph is valid for: instance sizes and dimensions
+// plus the options that change the launch sequence.  Coordinates, eps,
+// MinPts and the caller's pointers live in the device instance table, which
+// the graph re-reads from pinned host memory on every replay.
+std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
+    std::vector<int64_t> sig;
+    sig.reserve(2 * (size_t)count + 3);
+    sig.push_back(count);
+    sig.push_back(ctx->ldf ? 1 : 0);
+    sig.push_back(ctx->proposal_on ? 1 : 0);
+    for (int k = 0; k < count; ++k) {
+        sig.push_back(ctx->inst_host[k].n);
+        sig.push_back(ctx->inst_host[k].d);
+    }
+    return sig;
+}
+
+void drop_graph(gd_ctx* ctx) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->gsig.clear();
+}
+
+// Capture a planned run sized from the eager call that just finished.
+// Failure to capture is not an error: the call's result is already there.
+void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std::vector<int64_t>&& sig) {
+    drop_graph(ctx);
+    const gd_stats& e = ctx->last;
+    Plan p{};
+    const int kb = std::max(ctx->last_key_bits, 1);
+    p.key_bits = std::min((kb + 7) / 8 * 8, kb <= 32 ? 32 : 64);
+    p.ncell = std::min<int64_t>(n, e.grids + e.grids / 4 + 1024);
+    p.nei = (uint64_t)e.neighbor_entries + (uint64_t)e.neighbor_entries / 4 + 4096;
+    p.ncc = std::min<int64_t>(p.ncell, e.core_grids + e.core_grids / 4 + 256);
+    p.max_core = std::min<int64_t>(std::min<int64_t>(n, kMaxCoreBits), ctx->last_max_core + ctx->last_max_core / 4 + 64);
+    if (!ctx->gstream) {
+        if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->gev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+    }
+    const std::string saved_err = ctx->err;
+    const uint64_t gen0 = ctx->generation;
+    struct Invalidate {  // debug views of the eager call may point into reallocated buffers
+        gd_ctx* c;
+        uint64_t g;
+        ~Invalidate() {
+            if (c->generation != g) c->have_last = false;
+        }
+    } inval{ctx, gen0};
+    if (grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(p.nei, 1) * sizeof(uint32_t), ctx->arena.cap) ||
+        grow(ctx, ctx->table, output_table_bytes(table_bits(p.ncell), p.key_bits <= 32 ? 4 : 8),
+             ctx->arena.cap + ctx->nei.cap) ||
+        (ctx->proposal_on && grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(p.ncell, 1),
+                                  ctx->arena.cap + ctx->nei.cap + ctx->table.cap))) {
+        ctx->err = saved_err;
+        return;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const int rc = run_batch(ctx, count, D, n, tiles, ctx->gstream, &p);
+    const hipError_t ce = hipStreamEndCapture(ctx->gstream, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (rc == GD_OK && ce == hipSuccess && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        ctx->gexec = exec;
+        ctx->gsig = std::move(sig);
+        ctx->ggen = ctx->generation;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    ctx->err = saved_err;
+}
+
+// One call: replay the captured graph when the batch has its shape, else run
+// eagerly (and capture for the next call).  A replay whose data outgrew the
+// plan, or that met bad input, is discarded and the call runs eagerly.
+int run_call(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream_t st, bool batched) {
+    const bool want = n > 0 && !ctx->stats && !ctx->timing &&
+                      (ctx->graph_mode == 2 || (ctx->graph_mode == 1 && batched));
+    if (!want) return run_batch(ctx, count, D, n, tiles, st, nullptr);
+    std::vector<int64_t> sig = batch_signature(ctx, count);
+    if (ctx->gexec && ctx->ggen == ctx->generation && sig == ctx->gsig) {
+        GD_TRY(hipEventRecord(ctx->gev, st));
+        GD_TRY(hipStreamWaitEvent(ctx->gstream, ctx->gev, 0));
+        GD_TRY(hipGraphLaunch(ctx->gexec, ctx->gstream));
+        GD_TRY(hipStreamSynchronize(ctx->gstream));
+        const Header* H = ctx->hdr_host;
+        if (!(H->err & (kErrPlan | kErrNotInteger | kErrKeyBits | kErrNeiOverflow | kErrCoreCap | kErrMergeRunaway))) {
+            ctx->have_last = false;  // the debug views describe eager calls only
+            std::memset(&ctx->last, 0, sizeof(ctx->last));
+            ctx->last.n = n;
+            ctx->last.d = D;
+            ctx->last.key_bits = ctx->last_key_bits;
+            ctx->last.grids = H->ncell;
+            ctx->last.neighbor_entries = (int64_t)H->nei_total;
+            ctx->last.core_points = H->counts[0];
+            ctx->last.core_grids = H->counts[1];
+            ctx->last.dense_grids = H->counts[3];
+            ctx->last.graph_replays = 1;
+            return GD_OK;
+        }
+        drop_graph(ctx);  // run eagerly below; the next call captures anew
+    }
+    const int rc = run_batch(ctx, count, D, n, tiles, st, nullptr);
+    if (rc == GD_OK) capture_graph(ctx, count, D, n, tiles, std::move(sig));
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -610,6 +772,9 @@ void gd_destroy(gd_ctx* ctx) {
     if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
     if (ctx->sumbuf.p) (void)hipFree(ctx->sumbuf.p);
     if (ctx->table.p) (void)hipFree(ctx->table.p);
+    drop_graph(ctx);
+    if (ctx->gev) (void)hipEventDestroy(ctx->gev);
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
     for (int p = 0; p < P_COUNT; ++p)
         for (int k = 0; k < 2; ++k)
             if (ctx->ev[p][k]) (void)hipEventDestroy(ctx->ev[p][k]);
@@ -629,7 +794,7 @@ int dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, i
     int64_t total;
     uint32_t tiles;
     finish_table(ctx, 1, &D, &total, &tiles);
-    return run_batch(ctx, 1, D, total, tiles, (hipStream_t)stream);
+    return run_call(ctx, 1, D, total, tiles, (hipStream_t)stream, false);
 }
 
 int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* stream) {
@@ -657,7 +822,7 @@ int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* st
     int D;
     uint32_t tiles;
     finish_table(ctx, count, &D, &total, &tiles);
-    return run_batch(ctx, count, D, total, tiles, (hipStream_t)stream);
+    return run_call(ctx, count, D, total, tiles, (hipStream_t)stream, true);
 }
 
 int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
@@ -666,6 +831,14 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
         case GD_OPT_STATS: ctx->stats = value != 0; return GD_OK;
         case GD_OPT_LDF_ORDER: ctx->ldf = value != 0; return GD_OK;
         case GD_OPT_TIMING: ctx->timing = value != 0; return GD_OK;
+        case GD_OPT_GRAPH:
+            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "graph mode must be 0, 1 or 2");
+            ctx->graph_mode = (int)value;
+            if (value == 0) {
+                DeviceGuard guard(ctx->device);
+                drop_graph(ctx);
+            }
+            return GD_OK;
         case GD_OPT_WORKSPACE_LIMIT:
             if (value < 0) return ctx->fail(GD_EINVAL, "workspace limit must be >= 0");
             ctx->ws_limit = value;

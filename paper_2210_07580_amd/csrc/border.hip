@@ -88,6 +88,7 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
 template <typename K>
 __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
                                                                const HashSlot<K>* __restrict__ tab, int bits) {
+    if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
@@ -104,11 +105,12 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
         } else {
             uint64_t h = hash_slot(key, bits);
             HashSlot<K> e = tab[h];
-            while (e.key != key) {  // every identifier of the batch is in the table
+            // every identifier of the batch is in the table; the bound only guards the loop
+            for (uint64_t probes = 0; e.key != key && probes <= mask; ++probes) {
                 h = (h + 1) & mask;
                 e = tab[h];
             }
-            val = e.val;
+            val = e.key == key ? e.val : kDeferred;
         }
         if (val != kDeferred) {
             labels[i] = val - off;

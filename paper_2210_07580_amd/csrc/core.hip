@@ -211,17 +211,21 @@ __global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell
     }
 }
 
-__global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, int64_t m, uint32_t* rank) {
+__global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, const uint32_t* m, uint32_t* rank) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < m) rank[sorted[r]] = (uint32_t)r;
+    if (r < (int64_t)*m) rank[sorted[r]] = (uint32_t)r;
 }
 
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_b,
-                            uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial, uint32_t** sorted_list,
-                            hipStream_t st) {
+                            bool pad_tail, uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b,
+                            uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
+                            uint32_t** sorted_list, hipStream_t st) {
     *sorted_list = list;
     if (g.ncell == 0) return hipSuccess;
+    if (by_count && pad_tail && ncc > 0) {
+        hipError_t e = fill<uint32_t>(keys_a, ncc, (uint32_t)((1ull << count_bits) - 1ull), st);
+        if (e != hipSuccess) return e;
+    }
     hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_cnt, g.ncell_dev}, g.ncell, excl,
                                             (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
@@ -233,7 +237,7 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
         if (e != hipSuccess) return e;
         *sorted_list = res.vals;
     }
-    if (ncc > 0) rank_kernel<<<dim3(grid_for(ncc)), dim3(kBlock), 0, st>>>(*sorted_list, ncc, rank);
+    if (ncc > 0) rank_kernel<<<dim3(grid_for(ncc)), dim3(kBlock), 0, st>>>(*sorted_list, &c.counts[1], rank);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ enum : uint32_t {
     kErrKeyBits = 4u,       // packed identifiers need more than 64 bits
     kErrNeiOverflow = 8u,   // neighbour lists exceed the buffer given to a sync-free run
     kErrCoreCap = 16u,      // a grid's core set exceeds the merge step's LDS bitmap
+    kErrPlan = 32u,         // a sync-free run met more data than it was planned for (or bad input)
 };
 
 // One clustering instance.  The host fills the first part; the layout
@@ -113,7 +114,13 @@ __device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) {
 
 // ---- partition.hip
 hipError_t launch_minmax(const Batch& b, hipStream_t st);
-hipError_t launch_layout(const Batch& b, hipStream_t st);
+// plan_bits: identifier bits a sync-free run sorts (64 otherwise); more raise kErrPlan.
+hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st);
+// Sync-free runs: compare the device counts with the capacities the run was
+// planned with (stage 0: grids; 1: neighbour entries; 2: core grids and the
+// largest core set).  On overflow, or after an input error, kErrPlan goes up
+// and the grid count drops to zero, so every later kernel finds no work.
+hipError_t launch_plan_check(Header* hdr, int stage, int64_t cap_a, int64_t cap_b, hipStream_t st);
 template <typename K>
 hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st);
 // Sorted point rows: crd row s = point sidx[s] (see GridView::crd).
@@ -159,11 +166,13 @@ hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const ui
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = position (kNone for non-core grids).  ncc: number of
-// core grids (or an upper bound); count_bits: bits of the largest count.
+// core grids, or an upper bound (then pad_tail: the slots past the device
+// count sort last, under the key 2^count_bits - 1); count_bits: bits of the
+// sort keys.
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_b,
-                            uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial, uint32_t** sorted_list,
-                            hipStream_t st);
+                            bool pad_tail, uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b,
+                            uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
+                            uint32_t** sorted_list, hipStream_t st);
 
 // ---- merge.hip (Algorithms 4-5, union-find)
 constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats)

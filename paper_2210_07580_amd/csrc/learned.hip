@@ -13,7 +13,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co, CellSummary* __restrict__ out) {
     const int lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
-    if (c >= (int64_t)*gv.ncell_dev) return;
+    if (c >= (int64_t)*gv.ncell_dev || c >= gv.ncell) return;  // out[] holds gv.ncell summaries
     const uint32_t b = co.core_begin[c], m = co.core_cnt[c];
     if (m == 0) return;
     double sum[D];

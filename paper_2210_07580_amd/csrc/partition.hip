@@ -144,7 +144,7 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t y) {
 }
 
 // One workgroup: per-instance field widths, then the batch-wide layout.
-__global__ __launch_bounds__(kBlock) void layout_kernel(Batch b) {
+__global__ __launch_bounds__(kBlock) void layout_kernel(Batch b, int plan_bits) {
     __shared__ int s_max;
     __shared__ uint32_t s_err;
     if (threadIdx.x == 0) {
@@ -176,12 +176,34 @@ __global__ __launch_bounds__(kBlock) void layout_kernel(Batch b) {
         b.hdr->total_bits = s_max + inst_bits;
         uint32_t e = s_err;
         if (s_max + inst_bits > 64) e |= kErrKeyBits;
+        if (s_max + inst_bits > plan_bits) e |= kErrPlan;
         b.hdr->err = e;
     }
 }
 
-hipError_t launch_layout(const Batch& b, hipStream_t st) {
-    layout_kernel<<<1, kBlock, 0, st>>>(b);
+hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st) {
+    layout_kernel<<<1, kBlock, 0, st>>>(b, plan_bits);
+    return hipGetLastError();
+}
+
+__global__ void plan_check_kernel(Header* h, int stage, int64_t cap_a, int64_t cap_b) {
+    bool bad = (h->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) != 0;
+    if (stage == 0)
+        bad |= (int64_t)h->ncell > cap_a;
+    else if (stage == 1)
+        bad |= h->nei_total > (uint64_t)cap_a;
+    else
+        bad |= (int64_t)h->counts[1] > cap_a || (int64_t)h->counts[2] > cap_b;
+    if (bad) {
+        h->err |= kErrPlan;
+        h->ncell = 0;
+        h->nei_total = 0;
+        h->counts[1] = 0;
+    }
+}
+
+hipError_t launch_plan_check(Header* hdr, int stage, int64_t cap_a, int64_t cap_b, hipStream_t st) {
+    plan_check_kernel<<<1, 1, 0, st>>>(hdr, stage, cap_a, cap_b);
     return hipGetLastError();
 }
 
@@ -208,6 +230,15 @@ template <typename K>
 __global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys) {
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
+    if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) {
+        // a sync-free run on input it cannot handle (its result is discarded):
+        // the instance id alone keeps every instance's points in its own
+        // range through the sort, so later kernels stay within bounds
+        const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
+        const int64_t hi = min(I.n, lo + kPointTile);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) keys[I.off + i] = (K)k;
+        return;
+    }
     const int ishift = b.hdr->inst_shift;
     const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
@@ -261,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t*
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t i = i0 + (int64_t)u * kBlock;
-                o[u] = i < hi ? (uint32_t)((int64_t)sidx[I.off + i] - I.off) : 0u;
+                // sidx of this range always lies in the instance; the clamp only guards the read
+                o[u] = i < hi ? min((uint32_t)((int64_t)sidx[I.off + i] - I.off), (uint32_t)(I.n - 1)) : 0u;
             }
             FRow<DB> r[U];
 #pragma unroll
@@ -281,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t*
     } else {
         for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
             const int64_t s = I.off + i;
-            const int64_t o = (int64_t)sidx[s] - I.off;
+            const int64_t o = (int64_t)min((uint32_t)((int64_t)sidx[s] - I.off), (uint32_t)(I.n - 1));
             int32_t y[DB];
 #pragma unroll
             for (int j = 0; j < DB; ++j) y[j] = j < d ? (int)x[o * d + j] - mn[j] : 0;
@@ -315,7 +347,8 @@ __global__ __launch_bounds__(kBlock) void cells_kernel(Batch b, const K* __restr
     if (first) {
         cell_start[c] = (uint32_t)s;
         const int ishift = b.hdr->inst_shift;
-        const int k = ishift >= 64 ? 0 : (int)((uint64_t)key >> ishift);
+        int k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
+        if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
         const Inst& I = b.inst[k];
         ck[c] = k;
 #pragma unroll
