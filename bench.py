@@ -96,6 +96,8 @@ def bench_batched(G, steps, warmup, max_instances):
         probs.append((torch.from_numpy(x.astype(np.float32)).cuda(), w.eps, w.minpts))
     total = sum(int(p[0].shape[0]) for p in probs)
     ctx = G.Context(0)
+    tuned, trials = ctx.autotune(probs)
+    log(f"bench: autotuned {tuned}")
     outs = ctx.dbscan_batched(probs)
     for (t, e, m), (lab, core) in zip(probs[:8], outs[:8]):
         l1, c1 = ctx.dbscan(t, e, m)
@@ -121,6 +123,8 @@ def bench_batched(G, steps, warmup, max_instances):
         "value": round(total / t_batch, 1), "ms_per_batch": round(1e3 * t_batch, 3),
         "plain_value": round(total / t_each, 1), "plain_ms_per_batch": round(1e3 * t_each, 3),
         "speedup_vs_plain": round(t_each / t_batch, 3), "unit": "points/s",
+        "autotuned": tuned, "autotune_trials_ms": {f"{r['tile_points']}x{r['merge_waves']}": round(r["ms"], 3)
+                                                   for r in trials},
         "graph_replay": replayed, "no_graph_value": round(total / t_batch_eager, 1),
         "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3),
     }

@@ -164,13 +164,38 @@ typedef enum {
                                  0 = unlimited (default)                      */
     GD_OPT_TIMING = 4,        /* 1: record HIP events around every phase on the
                                  call's stream (see gd_get_phase_times)       */
-    GD_OPT_GRAPH = 5          /* graph replay (see dbscan_batched): 0 never,
+    GD_OPT_GRAPH = 5,         /* graph replay (see dbscan_batched): 0 never,
                                  1 (default) dbscan_batched only, 2 also
                                  dbscan(); calls with GD_OPT_STATS or
                                  GD_OPT_TIMING on always run without it      */
+    GD_OPT_TILE_POINTS = 6,   /* points per workgroup of the point-indexed
+                                 kernels: a multiple of 256 in [256, 65536]
+                                 (default 4096)                               */
+    GD_OPT_MERGE_WAVES = 7    /* waves per workgroup of the FastMerging
+                                 kernel: 1, 2 or 4 (default 4)                */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);
+
+/* One configuration tried by gd_autotune. */
+typedef struct {
+    int32_t tile_points;   /* GD_OPT_TILE_POINTS */
+    int32_t merge_waves;   /* GD_OPT_MERGE_WAVES */
+    double ms;             /* best wall time of the call, milliseconds */
+} gd_tuning;
+
+/*
+ * gd_autotune: time dbscan_batched() on the caller's batch (HOST descriptor
+ * array, as for dbscan_batched) under every tunable configuration (tile
+ * points 1024/2048/4096/8192 x merge waves 1/2/4; two calls each, without
+ * graph replay) and keep the fastest in the context.  Every configuration
+ * gives the same result; the outputs hold the last run's.  `results` (HOST,
+ * up to max_results entries, may be NULL) receives the timings and
+ * *n_results their number.  The tunables are not saved across contexts: a
+ * caller that wants to keep them reads the timings and sets the options.
+ */
+int gd_autotune(gd_ctx *ctx, const gd_instance *inst, int32_t count, void *stream, gd_tuning *results,
+                int32_t max_results, int32_t *n_results);
 
 /* Copy the counters of the last successful dbscan() call. */
 int gd_get_stats(gd_ctx *ctx, gd_stats *out);

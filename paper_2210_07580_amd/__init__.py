@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
+GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES = 6, 7
 PHASE_COUNT = 14
 EPS_MAX = 21845
 D_MAX = 8
@@ -42,6 +43,10 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_points", ctypes.c_int32), ("merge_waves", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32),
                 ("minpts", ctypes.c_int32), ("eps", ctypes.c_double), ("labels", ctypes.c_void_p),
@@ -53,7 +58,7 @@ _lib = None
 EXPORTS = ("gd_create", "gd_destroy", "dbscan", "dbscan_batched", "gd_set_option", "gd_get_stats",
            "gd_debug_grids", "gd_debug_neighbors", "gd_debug_core", "gd_merge_test",
            "gd_get_phase_times", "gd_phase_name", "gd_set_proposal", "gd_proposal_harvest",
-           "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string")
+           "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string", "gd_autotune")
 MLP_PARAMS = 5378
 MLP_FEATURES = 16
 
@@ -103,6 +108,9 @@ def load_library(path: str = LIB_PATH):
     lib.gd_mlp_grad.restype = ctypes.c_int
     lib.gd_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.gd_mlp_forward.restype = ctypes.c_int
+    lib.gd_autotune.argtypes = [vp, ctypes.POINTER(Instance), i32, vp, ctypes.POINTER(Tuning), i32,
+                                ctypes.POINTER(i32)]
+    lib.gd_autotune.restype = ctypes.c_int
     lib.gd_last_error.argtypes = [vp]
     lib.gd_last_error.restype = ctypes.c_char_p
     lib.gd_status_string.argtypes = [ctypes.c_int]
@@ -180,6 +188,40 @@ class Context:
                                    _ptr(labels), _ptr(core_flags), _stream_handle(stream))
         self._check(rc)
         return labels, core_flags
+
+    def _descriptors(self, problems, outs=None):
+        import torch
+        descs = (Instance * max(len(problems), 1))()
+        given, res, keep = outs, [], []
+        for k, (pts, eps, minpts) in enumerate(problems):
+            if pts.dtype != torch.float32 or pts.dim() != 2 or pts.device.type != "cuda":
+                raise ValueError(f"instance {k}: points must be a float32 [n, d] GPU tensor")
+            pts = pts.contiguous()
+            n, d = pts.shape
+            if given is not None:
+                lab, core = given[k]
+                if lab.numel() != n or core.numel() != n or lab.dtype != torch.int32 or core.dtype != torch.uint8:
+                    raise ValueError(f"instance {k}: output tensors must be int32 [n] and uint8 [n]")
+            else:
+                lab = torch.empty(n, dtype=torch.int32, device=pts.device)
+                core = torch.empty(n, dtype=torch.uint8, device=pts.device)
+            descs[k] = Instance(_ptr(pts) if n else None, int(n), int(d), int(minpts), float(eps),
+                                _ptr(lab) if n else None, _ptr(core) if n else None)
+            keep.append(pts)
+            res.append((lab, core))
+        return descs, res, keep
+
+    def autotune(self, problems, stream=None):
+        """Time the batch under every tunable configuration and keep the
+        fastest.  Returns (chosen {tile_points, merge_waves}, all timings)."""
+        descs, _, keep = self._descriptors(problems)
+        res = (Tuning * 64)()
+        cnt = ctypes.c_int32()
+        self._check(load_library().gd_autotune(self._h, descs, len(problems), _stream_handle(stream), res, 64,
+                                               ctypes.byref(cnt)))
+        rows = [{"tile_points": r.tile_points, "merge_waves": r.merge_waves, "ms": r.ms} for r in res[:cnt.value]]
+        best = min(rows, key=lambda r: r["ms"]) if rows else None
+        return ({"tile_points": best["tile_points"], "merge_waves": best["merge_waves"]} if best else None), rows
 
     def dbscan_batched(self, problems, stream=None, outs=None):
         """Cluster many instances in one pass.  ``problems``: list of

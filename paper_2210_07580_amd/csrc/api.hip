@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -85,6 +86,9 @@ struct gd_ctx {
     unsigned long long* counter_dev = nullptr;
     // sync-free runs captured into a HIP graph and replayed
     int graph_mode = 1;              // 0 never, 1 dbscan_batched, 2 every call
+    // launch tunables (gd_autotune)
+    int tile_pts = kPointTile;       // points per workgroup of the point kernels
+    int merge_waves = kWavesPerBlock; // waves per workgroup of the FastMerging kernel
     uint64_t generation = 0;         // bumped whenever a buffer is reallocated
     hipStream_t gstream = nullptr;   // capture and replay stream
     hipEvent_t gev = nullptr;
@@ -314,6 +318,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     b.D = D;
     b.n = n;
     b.tiles = tiles;
+    b.tile_pts = (uint32_t)ctx->tile_pts;
     b.hdr = Hd;
 
     ctx->st = st;
@@ -460,7 +465,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         ctx->last_summaries = true;
     }
     GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, (ctx->ldf && !plan) ? (int64_t)H->counts[4] : -1,
-                        max_core, L.parent, stats ? ctx->stats_dev->merge : nullptr,
+                        max_core, ctx->merge_waves, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                         ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
     ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);
@@ -600,7 +605,7 @@ void finish_table(gd_ctx* ctx, int count, int* D, int64_t* n, uint32_t* tiles) {
         I.off = off;
         I.tile0 = t;
         off += I.n;
-        t += (uint32_t)((I.n + kPointTile - 1) / kPointTile);
+        t += (uint32_t)((I.n + ctx->tile_pts - 1) / ctx->tile_pts);
         dm = std::max(dm, I.d);
     }
     *D = dm;
@@ -618,6 +623,8 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
     sig.push_back(count);
     sig.push_back(ctx->ldf ? 1 : 0);
     sig.push_back(ctx->proposal_on ? 1 : 0);
+    sig.push_back(ctx->tile_pts);
+    sig.push_back(ctx->merge_waves);
     for (int k = 0; k < count; ++k) {
         sig.push_back(ctx->inst_host[k].n);
         sig.push_back(ctx->inst_host[k].d);
@@ -825,12 +832,70 @@ int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* st
     return run_call(ctx, count, D, total, tiles, (hipStream_t)stream, true);
 }
 
+int gd_autotune(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* stream, gd_tuning* results,
+                int32_t max_results, int32_t* n_results) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    static const int kTiles[] = {1024, 2048, 4096, 8192};
+    static const int kWaves[] = {1, 2, 4};
+    const int saved_tile = ctx->tile_pts, saved_waves = ctx->merge_waves, saved_graph = ctx->graph_mode;
+    const bool saved_stats = ctx->stats, saved_timing = ctx->timing;
+    ctx->graph_mode = 0;
+    ctx->stats = false;
+    ctx->timing = false;
+    double best = 1e300;
+    int best_tile = saved_tile, best_waves = saved_waves, k = 0, rc = GD_OK;
+    for (int tile : kTiles) {
+        for (int waves : kWaves) {
+            ctx->tile_pts = tile;
+            ctx->merge_waves = waves;
+            double ms = 1e300;
+            for (int rep = 0; rep < 2 && rc == GD_OK; ++rep) {  // the first run also warms the workspace
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = dbscan_batched(ctx, inst, count, stream);
+                const auto t1 = std::chrono::steady_clock::now();
+                ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+            }
+            if (rc != GD_OK) break;
+            if (results && k < max_results) results[k] = gd_tuning{tile, waves, ms};
+            ++k;
+            if (ms < best) {
+                best = ms;
+                best_tile = tile;
+                best_waves = waves;
+            }
+        }
+        if (rc != GD_OK) break;
+    }
+    ctx->graph_mode = saved_graph;
+    ctx->stats = saved_stats;
+    ctx->timing = saved_timing;
+    if (n_results) *n_results = std::min(k, max_results);
+    if (rc != GD_OK) {
+        ctx->tile_pts = saved_tile;
+        ctx->merge_waves = saved_waves;
+        return rc;
+    }
+    ctx->tile_pts = best_tile;
+    ctx->merge_waves = best_waves;
+    return GD_OK;
+}
+
 int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
     if (!ctx) return GD_EINVAL;
     switch (option) {
         case GD_OPT_STATS: ctx->stats = value != 0; return GD_OK;
         case GD_OPT_LDF_ORDER: ctx->ldf = value != 0; return GD_OK;
         case GD_OPT_TIMING: ctx->timing = value != 0; return GD_OK;
+        case GD_OPT_TILE_POINTS:
+            if (value < 256 || value > 65536 || value % 256)
+                return ctx->fail(GD_EINVAL, "tile size must be a multiple of 256 in [256, 65536]");
+            ctx->tile_pts = (int)value;
+            return GD_OK;
+        case GD_OPT_MERGE_WAVES:
+            if (value != 1 && value != 2 && value != 4) return ctx->fail(GD_EINVAL, "merge waves must be 1, 2 or 4");
+            ctx->merge_waves = (int)value;
+            return GD_OK;
         case GD_OPT_GRAPH:
             if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "graph mode must be 0, 1 or 2");
             ctx->graph_mode = (int)value;

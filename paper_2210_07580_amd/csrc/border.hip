@@ -91,8 +91,8 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
     if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
-    const int64_t hi = min(I.n, lo + kPointTile);
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
     const uint64_t mask = (1ull << bits) - 1ull;
     const int32_t off = (int32_t)I.off;
     int32_t* __restrict__ labels = I.labels;

@@ -18,7 +18,7 @@ namespace gd {
 
 constexpr int kMaxD = 8;
 constexpr int kMaxLevels = kMaxD + 1;  // grid tree: instance level + one level per dimension
-constexpr int kPointTile = 4096;       // points per workgroup in the point-indexed kernels
+constexpr int kPointTile = 4096;       // default points per workgroup in the point-indexed kernels
 
 // Error bits raised by kernels into the device error word.
 enum : uint32_t {
@@ -70,6 +70,7 @@ struct Batch {
     int32_t D;            // largest d in the batch (coordinate rows; shorter points are padded with 0)
     int64_t n;            // total points
     uint32_t tiles;       // point tiles over the batch
+    uint32_t tile_pts;    // points per tile (a multiple of 256): one workgroup each
     Header* hdr;          // device
 };
 
@@ -182,9 +183,11 @@ struct MergeStats {
 // Largest core set a grid may hold (LDS bitmaps of the merge step).
 constexpr int64_t kMaxCoreBits = 262144;
 struct CellSummary;
+// waves: waves per workgroup of the FastMerging kernel (1, 2 or 4; fewer
+// if the LDS bitmaps do not fit).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, uint32_t* parent, MergeStats* stats, const __half* proposal,
+                        int64_t max_core, int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
                         const CellSummary* sum, hipStream_t st);
 // pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,

@@ -1,6 +1,7 @@
 // Merging core grids (Section 4.3) with union-find over core grids visited
 // in ascending core-count order (the LDF variant of Section 5.2); the
 // FastMerging test itself is in fastmerge.hpp.
+#include <algorithm>
 #include <type_traits>
 
 #include "fastmerge.hpp"
@@ -255,8 +256,8 @@ __global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut 
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint32_t* rank, int64_t ncc, int64_t n_small, int64_t max_core,
-                        uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
-                        hipStream_t st) {
+                        int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
+                        const CellSummary* sum, hipStream_t st) {
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
     // n_small >= 0: the visiting order puts the n_small tiny core grids first
@@ -270,12 +271,9 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
     const uint32_t words = (uint32_t)((max_core + kWave - 1) / kWave);
-    int wpb = kWavesPerBlock;
-    size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
-    if (lds > 65536) {
-        wpb = 1;
-        lds = (size_t)2 * words * sizeof(uint64_t);
-    }
+    int wpb = std::max(1, std::min(waves, kWavesPerBlock));
+    while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
+    const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((ncc - b0 + wpb - 1) / wpb);
     // the scorer's weights take static LDS beside the bitmaps; if both do not

@@ -109,8 +109,8 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
         smx[threadIdx.x] = INT_MIN;
     }
     __syncthreads();
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
-    const int64_t hi = min(I.n, lo + kPointTile);
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
     switch (d) {
         case 1: minmax_tile<1>(I, lo, hi, smn, smx); break;
         case 2: minmax_tile<2>(I, lo, hi, smn, smx); break;
@@ -234,15 +234,15 @@ __global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ k
         // a sync-free run on input it cannot handle (its result is discarded):
         // the instance id alone keeps every instance's points in its own
         // range through the sort, so later kernels stay within bounds
-        const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
-        const int64_t hi = min(I.n, lo + kPointTile);
+        const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+        const int64_t hi = min(I.n, lo + b.tile_pts);
         for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) keys[I.off + i] = (K)k;
         return;
     }
     const int ishift = b.hdr->inst_shift;
     const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
-    const int64_t hi = min(I.n, lo + kPointTile);
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
     switch (I.d) {
         case 1: keys_tile<1, K>(I, lo, hi, top, keys); break;
         case 2: keys_tile<2, K>(I, lo, hi, top, keys); break;
@@ -279,8 +279,8 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t*
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
     const int d = I.d;
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * kPointTile;
-    const int64_t hi = min(I.n, lo + kPointTile);
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
     int32_t mn[DB];
 #pragma unroll
     for (int j = 0; j < DB; ++j) mn[j] = j < d ? I.mn[j] : 0;
