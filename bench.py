@@ -186,6 +186,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the batched and learned comparisons")
     ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -194,6 +196,15 @@ def main():
 
     import torch
     import paper_2210_07580_amd as G
+
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration: 2 copies of 512 MiB")
+        del src, dst
 
     w = W.WORKLOADS[args.workload]
     log(f"bench: generating {w.name} n={w.n:,} d={w.d}")

@@ -87,6 +87,9 @@ typedef struct {
     int64_t merge_set_points;  /* sum over FastMerging calls of |s_i| + |s_j| */
     int64_t graph_replays;     /* 1 if the call replayed a captured HIP graph
                                   (then only the size fields are filled) */
+    int64_t core_candidates;   /* candidate points streamed while marking core
+                                  points (once per batch of 64 queries) */
+    int64_t core_neighbor_grids; /* neighbour grids opened while marking */
 } gd_stats;
 
 /* Create a context bound to HIP device `device` (the caller's current device

@@ -37,7 +37,8 @@ class Stats(ctypes.Structure):
             "grids", "neighbor_entries", "core_points", "core_grids", "dense_grids",
             "max_grid_points", "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
             "merge_iterations", "merge_max_iterations", "merge_distances", "core_distances",
-            "border_points", "noise_points", "clusters", "merge_set_points", "graph_replays")]
+            "border_points", "noise_points", "clusters", "merge_set_points", "graph_replays",
+            "core_candidates", "core_neighbor_grids")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

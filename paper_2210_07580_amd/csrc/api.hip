@@ -26,7 +26,7 @@ namespace {
 // Device counters of the optional statistics.
 struct StatBlock {
     MergeStats merge[kStatSlots];
-    unsigned long long core_dist[kStatSlots];
+    CoreStats core[kStatSlots];
 };
 
 struct DevBuf {
@@ -410,7 +410,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core_dist : nullptr, st));
+    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
@@ -541,7 +541,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
             s.merge_max_iterations = std::max<int64_t>(s.merge_max_iterations, (int64_t)m.max_iters);
             s.merge_distances += (int64_t)m.dists;
             s.merge_set_points += (int64_t)m.set_points;
-            s.core_distances += (int64_t)sb->core_dist[k];
+            s.core_distances += (int64_t)sb->core[k].dists;
+            s.core_candidates += (int64_t)sb->core[k].points;
+            s.core_neighbor_grids += (int64_t)sb->core[k].grids;
         }
     }
     return GD_OK;

@@ -40,15 +40,59 @@ struct alignas(16) HashSlot<uint64_t> {
     int32_t pad;
 };
 
+// Buckets of 64 bytes (8 slots of u32 identifiers, 4 of u64): a lookup
+// reads one bucket with four 16-byte loads and almost always ends there.
 template <typename K>
-__device__ __forceinline__ uint64_t hash_slot(K key, int bits) {
-    return ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - bits);
+constexpr int kBucketSlots = 64 / (int)sizeof(HashSlot<K>);
+template <typename K>
+constexpr int kBucketShift = sizeof(K) == 4 ? 3 : 2;
+
+template <typename K>
+__device__ __forceinline__ uint64_t hash_bucket(K key, int bbits) {
+    return ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - bbits);
 }
 
 __device__ __forceinline__ uint32_t cas_key(uint32_t* p, uint32_t cmp, uint32_t v) { return atomicCAS(p, cmp, v); }
 __device__ __forceinline__ uint64_t cas_key(uint64_t* p, uint64_t cmp, uint64_t v) {
     return (uint64_t)atomicCAS(reinterpret_cast<unsigned long long*>(p), (unsigned long long)cmp,
                                (unsigned long long)v);
+}
+
+// Look `key` up in one loaded bucket: 1 found (val set), 0 absent (the
+// bucket has an empty slot), -1 look in the next bucket.
+__device__ __forceinline__ int bucket_match(const uint4 (&q)[4], uint32_t key, int32_t& val) {
+    const uint32_t w[16] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w,
+                            q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+    int r = -1;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        if (w[2 * j] == ~0u) r = r == 1 ? 1 : 0;
+        if (w[2 * j] == key) {
+            r = 1;
+            val = (int32_t)w[2 * j + 1];
+        }
+    }
+    return r;
+}
+__device__ __forceinline__ int bucket_match(const uint4 (&q)[4], uint64_t key, int32_t& val) {
+    int r = -1;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+        const uint64_t kj = (uint64_t)q[j].x | ((uint64_t)q[j].y << 32);
+        if (kj == ~0ull) r = r == 1 ? 1 : 0;
+        if (kj == key) {
+            r = 1;
+            val = (int32_t)q[j].z;
+        }
+    }
+    return r;
+}
+
+template <typename K>
+__device__ __forceinline__ void load_bucket(const HashSlot<K>* tab, uint64_t b, uint4 (&q)[4]) {
+    const uint4* p = reinterpret_cast<const uint4*>(tab + (b << kBucketShift<K>));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[j] = p[j];
 }
 
 // The all-ones identifier marks an empty slot; a grid with that identifier
@@ -71,50 +115,76 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
     const uint32_t k = gv.cell_start[c + 1] - st;
     const int32_t val = co.core_cnt[c] == k ? cell_label[c] : kDeferred;
     const K key = skeys[st];
-    const uint64_t mask = (1ull << bits) - 1ull;
     if (key == ~K(0)) {
-        tab[mask + 1].val = val;
+        tab[1ull << bits].val = val;
         return;
     }
-    for (uint64_t h = hash_slot(key, bits);; h = (h + 1) & mask) {
-        if (cas_key(&tab[h].key, ~K(0), key) == ~K(0)) {
-            tab[h].val = val;
-            return;
+    const int bbits = bits - kBucketShift<K>;
+    const uint64_t bmask = (1ull << bbits) - 1ull;
+    // load <= 1/2, so a free slot is always found
+    for (uint64_t b = hash_bucket(key, bbits);; b = (b + 1) & bmask) {
+        HashSlot<K>* bucket = tab + (b << kBucketShift<K>);
+        for (int j = 0; j < kBucketSlots<K>; ++j) {
+            if (cas_key(&bucket[j].key, ~K(0), key) == ~K(0)) {
+                bucket[j].val = val;
+                return;
+            }
         }
     }
 }
 
-// Points in input order, instance tiles as in the identifier pass.
+// Points in input order, instance tiles as in the identifier pass; each
+// thread resolves U points at a time so that their loads overlap.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
                                                                const HashSlot<K>* __restrict__ tab, int bits) {
+    constexpr int U = 4;
     if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
     const int64_t hi = min(I.n, lo + b.tile_pts);
-    const uint64_t mask = (1ull << bits) - 1ull;
+    const int bbits = bits - kBucketShift<K>;
+    const uint64_t bmask = (1ull << bbits) - 1ull;
     const int32_t off = (int32_t)I.off;
     int32_t* __restrict__ labels = I.labels;
     uint8_t* __restrict__ flags = I.core;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const K key = keys[I.off + i];
-        int32_t val;
-        if (key == ~K(0)) {
-            val = tab[mask + 1].val;
-        } else {
-            uint64_t h = hash_slot(key, bits);
-            HashSlot<K> e = tab[h];
-            // every identifier of the batch is in the table; the bound only guards the loop
-            for (uint64_t probes = 0; e.key != key && probes <= mask; ++probes) {
-                h = (h + 1) & mask;
-                e = tab[h];
-            }
-            val = e.key == key ? e.val : kDeferred;
+    const int32_t special = tab[1ull << bits].val;
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kBlock) {
+        K key[U];
+        uint64_t bk[U];
+        uint4 q[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            key[u] = i < hi ? keys[I.off + i] : ~K(0);
         }
-        if (val != kDeferred) {
-            labels[i] = val - off;
-            flags[i] = 1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            bk[u] = hash_bucket(key[u], bbits);
+            if (key[u] != ~K(0)) load_bucket(tab, bk[u], q[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i >= hi) continue;
+            int32_t val = kDeferred;
+            if (key[u] == ~K(0)) {
+                val = special;
+            } else {
+                int r = bucket_match(q[u], key[u], val);
+                // every identifier of the batch is in the table; the bound only guards the loop
+                for (uint64_t probes = 0; r < 0 && probes < bmask; ++probes) {
+                    bk[u] = (bk[u] + 1) & bmask;
+                    load_bucket(tab, bk[u], q[u]);
+                    r = bucket_match(q[u], key[u], val);
+                }
+                if (r != 1) val = kDeferred;
+            }
+            if (val != kDeferred) {
+                labels[i] = val - off;
+                flags[i] = 1;
+            }
         }
     }
 }

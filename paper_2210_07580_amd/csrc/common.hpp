@@ -13,7 +13,9 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+// The wave's index in its workgroup, visibly uniform (per-wave values derived
+// from it stay in scalar registers).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
@@ -30,6 +32,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A 64-bit value that is the same in every lane, made visibly uniform so the
+// compiler keeps it (and loops over its bits) in scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ int32_t readlane(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }

@@ -21,11 +21,24 @@
 
 namespace gd {
 
+// Squared distance of two points of neighbouring grids: every coordinate
+// difference is below 2 eps < 2^23, so one signed 24-bit multiply-add per
+// coordinate is exact.
 template <int D>
+__device__ __forceinline__ uint32_t sqdist_nb(const int32_t (&a)[D], const int32_t (&b)[D]) {
+    int32_t dd = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const int32_t t = a[j] - b[j];
+        dd = __mul24(t, t) + dd;
+    }
+    return (uint32_t)dd;
+}
+
+template <int D, bool kStats>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
-                                                           uint32_t* __restrict__ core_cnt,
-                                                           unsigned long long* dist_counter) {
+                                                           uint32_t* __restrict__ core_cnt, CoreStats* stats) {
     __shared__ uint32_t s_start[kWavesPerBlock][kWave];
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     const int w = wave_id(), lane = lane_id();
@@ -43,14 +56,14 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     const uint32_t need = minpts - k;
     const uint32_t T = I.T;
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
-    unsigned long long ndist = 0;
+    unsigned long long ndist = 0, npts = 0, ncells = 0;
     uint32_t m = 0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
         const uint32_t nq = min((uint32_t)kWave, k - qb);
         uint64_t active = nq == (uint32_t)kWave ? ~0ull : ((1ull << nq) - 1ull);
         int32_t qx[D];
         load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
-        uint32_t mycnt = 0;
+        uint32_t mycnt = 0;  // lane i: hits of query i
         for (uint64_t e = e0; e < e1 && active; e += kWave) {
             const uint64_t idx = e + lane;
             const bool v = idx < e1;
@@ -72,20 +85,24 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                 const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
                 int32_t y[D];
                 load_row<D>(gv.crd, tv ? q : st, y);
-                uint64_t act = active;
-                const int nv = popc64(ballot(tv));
+                const uint64_t tvm = ballot(tv);
+                uint64_t act = uniform64(active), closed = 0;
                 while (act) {
                     const int qi = ffs64(act);
                     act &= act - 1ull;
-                    uint32_t dd = 0;
+                    int32_t p[D];
 #pragma unroll
-                    for (int jj = 0; jj < D; ++jj) dd += sq24(y[jj], readlane(qx[jj], qi));
-                    const uint32_t hits = (uint32_t)popc64(ballot(tv && dd <= T));
-                    if (lane == qi) mycnt += hits;
-                    if (readlane(mycnt, qi) >= need) active &= ~(1ull << qi);
-                    ndist += (unsigned long long)nv;
+                    for (int jj = 0; jj < D; ++jj) p[jj] = readlane(qx[jj], qi);
+                    const uint32_t hits = (uint32_t)popc64(ballot(sqdist_nb<D>(y, p) <= T) & tvm);
+                    const uint32_t cnt = readlane(mycnt, qi) + hits;
+                    mycnt = lane == qi ? cnt : mycnt;
+                    if (cnt >= need) closed |= 1ull << qi;
+                    if constexpr (kStats) ndist += min(tot - t0, (uint32_t)kWave);
                 }
+                active &= ~closed;
+                if constexpr (kStats) npts += min(tot - t0, (uint32_t)kWave);
             }
+            if constexpr (kStats) ncells += (unsigned long long)min(e1 - e, (uint64_t)kWave);
             wave_sync();
         }
         const bool is_core = (uint32_t)lane < nq && !((active >> lane) & 1ull);
@@ -94,16 +111,26 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     }
     if (lane == 0) {
         core_cnt[c] = m;
-        if (dist_counter) atomicAdd(&dist_counter[c & (kStatSlots - 1)], ndist);
+        if constexpr (kStats) {
+            CoreStats& sl = stats[c & (kStatSlots - 1)];
+            atomicAdd(&sl.dists, ndist);
+            atomicAdd(&sl.points, npts);
+            atomicAdd(&sl.grids, ncells);
+        }
     }
 }
 
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, unsigned long long* dist_counter, hipStream_t st) {
+                            uint32_t* core_cnt, CoreStats* stats, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    GD_DISPATCH_D(g.D, (core_mark_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core, core_cnt,
-                                                                                  dist_counter)));
+    if (stats) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core,
+                                                                                            core_cnt, stats)));
+    } else {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core,
+                                                                                             core_cnt, stats)));
+    }
     return hipGetLastError();
 }
 

@@ -161,9 +161,15 @@ struct CoreOut {
     uint32_t* counts;           // header counts
 };
 constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
+// Work counters of core marking (one copy per stat slot).
+struct CoreStats {
+    unsigned long long dists;   // distances evaluated
+    unsigned long long points;  // candidate points streamed (once per batch of 64 queries)
+    unsigned long long grids;   // neighbour grids opened
+};
 // Core flags (sorted order) and m_i per grid.
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, unsigned long long* dist_counter, hipStream_t st);
+                            uint32_t* core_cnt, CoreStats* stats, hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = position (kNone for non-core grids).  ncc: number of

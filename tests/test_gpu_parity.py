@@ -209,6 +209,9 @@ def test_stats(ctx, G):
     finally:
         ctx.set_option(G.GD_OPT_STATS, 0)
     assert s["n"] == len(x) and s["core_points"] == int(core.sum())
+    # every streamed candidate is tested against at least one and at most 64 open queries
+    assert 0 < s["core_candidates"] <= s["core_distances"] <= 64 * s["core_candidates"]
+    assert s["core_neighbor_grids"] > 0
     assert s["merge_pairs"] == s["merge_skipped"] + s["merge_tests"]
     assert 0 < s["merge_yes"] <= s["merge_tests"]
     assert s["merge_max_iterations"] >= 1
