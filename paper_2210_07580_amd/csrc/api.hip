@@ -235,7 +235,7 @@ Layout carve(char* base, int64_t n, int D) {
     // sets, whose side area follows row n
     L.vals_a = c.take<uint32_t>(2 * n);
     L.vals_b = c.take<uint32_t>(2 * n);
-    const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)kRadixBins * radix_tiles(n));
+    const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)radix_max_bins<uint32_t>() * radix_tiles(n));
     L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
     L.partial = c.take<uint64_t>(scan_blocks(big_scan) + 4);
     L.crd = c.take<int32_t>((int64_t)row_stride(D) * 2 * n);  // sorted rows, then the side area

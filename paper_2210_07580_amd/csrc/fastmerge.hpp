@@ -26,9 +26,10 @@
 //       cos(lambda_y) = (pq.py sqrt(b^2 - eps^2) - eps |pq x py|) / (|pq| b^2)
 //     lambda = max_y lambda_y, i.e. cos(lambda) = min_y cos(lambda_y); if
 //     some lambda_y reaches pi the rule is switched off for this call.
-//     x is dropped when cos(theta_x) < cos(lambda) - 1e-10: the margin is far
-//     above the float64 rounding of these terms, so rounding can only keep a
-//     point, never drop one wrongly, and the answer stays exact (Theorem 2).
+//     The cosines are evaluated in single precision and x is dropped when
+//     cos(theta_x) < cos(lambda) - 1e-4: the margin is far above the
+//     rounding of these terms (see kAngleMargin), so rounding can only keep
+//     a point, never drop one wrongly, and the answer stays exact (Theorem 2).
 //   The start point p is the first core point of s_i (the paper picks one at
 //   random; the choice does not change the answer).  If a Pruning call
 //   empties a set the answer is "no" at once.
@@ -117,30 +118,40 @@ __device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p
     return wave_min_u64(best);
 }
 
-__device__ __forceinline__ double wave_min_f64(double v) {
+__device__ __forceinline__ float wave_min_f32(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        const double t = __shfl_xor(v, o);
+        const float t = __shfl_xor(v, o);
         v = t < v ? t : v;
     }
     return v;
 }
+
+// Rounding slack of the single-precision angle rule.  Every operand is an
+// integer (coordinates, dot products, 2x2 minors, squared norms, all below
+// 2^36) converted to float with relative error 2^-24, and square roots and
+// reciprocals are within two ulps, so each computed cosine is within 1e-6 of
+// the exact one (both terms of the cos(lambda_y) numerator are bounded by its
+// denominator).  With a margin of 1e-4 a point is only dropped when the exact
+// test drops it too.
+constexpr float kAngleMargin = 1e-4f;
 
 // Algorithm 4: remove from `a` the points that cannot be within eps of any
 // live point of `b`, given anchor p in a and q = argmin_{y in b} D(p, y) with
 // D(p, q) = dpq > T.  Returns whether `a` keeps any point.
 template <int D>
 __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, const int32_t (&p)[D],
-                                        const int32_t (&q)[D], uint32_t dpq, uint32_t T, double eps,
+                                        const int32_t (&q)[D], uint32_t dpq, uint32_t T, double eps_d,
                                         unsigned long long& ndist) {
     const int lane = lane_id();
     int32_t pq[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) pq[k] = q[k] - p[k];
-    const double a2 = (double)dpq;
-    const double na = sqrt(a2);
+    const float eps = (float)eps_d;
+    const float a2 = (float)dpq;
+    const float rna = __builtin_amdgcn_rsqf(a2);  // 1 / |pq|
     // lambda over the live points of b
-    double cmin = 2.0;
+    float cmin = 2.f;
     bool off = false;
     for (uint32_t w0 = 0; w0 < b.words; w0 += kUnroll) {
         uint64_t mk[kUnroll];
@@ -164,27 +175,29 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
                 dot += (int64_t)pq[k] * py[k];
                 b2 += sq24(yy[u][k], p[k]);
             }
-            const double dotd = (double)dot;
-            const double h2 = (double)(b2 - T);  // b^2 - eps^2 > 0 since b^2 >= dpq > T
-            if (dot < 0 && dotd * dotd >= a2 * h2 * (1.0 - 1e-9)) {
-                off = true;  // lambda_y >= pi (or too close to tell)
+            const float dotf = (float)dot;
+            const float h2 = (float)(b2 - T);  // b^2 - eps^2 > 0 since b^2 >= dpq > T
+            // lambda_y >= pi, or too close to tell: the rule is off for this call
+            if (dot < 0 && dotf * dotf >= a2 * h2 * (1.f - 1e-3f)) {
+                off = true;
             } else {
-                double cross = 0.0;  // |pq|^2 |py|^2 - (pq.py)^2 as a sum of squared 2x2 minors
+                float cross = 0.f;  // |pq|^2 |py|^2 - (pq.py)^2 as a sum of squared 2x2 minors
 #pragma unroll
                 for (int k = 0; k < D; ++k)
 #pragma unroll
                     for (int l = k + 1; l < D; ++l) {
-                        const double mnr = (double)((int64_t)pq[k] * py[l] - (int64_t)pq[l] * py[k]);
+                        const float mnr = (float)((int64_t)pq[k] * py[l] - (int64_t)pq[l] * py[k]);
                         cross += mnr * mnr;
                     }
-                const double c = (dotd * sqrt(h2) - eps * sqrt(cross)) / (na * (double)b2);
+                const float num = dotf * __builtin_amdgcn_sqrtf(h2) - eps * __builtin_amdgcn_sqrtf(cross);
+                const float c = num * rna * __builtin_amdgcn_rcpf((float)b2);
                 cmin = c < cmin ? c : cmin;
             }
         }
     }
     off = ballot(off) != 0;
-    cmin = wave_min_f64(cmin);
-    const double thr = cmin - 1e-10;
+    cmin = wave_min_f32(cmin);
+    const float thr = cmin - kAngleMargin;
     uint64_t any = 0;
     for (uint32_t w0 = 0; w0 < a.words; w0 += kUnroll) {
         uint64_t mk[kUnroll];
@@ -212,7 +225,7 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
                 const bool tri = s > 0 && (uint64_t)4 * (uint64_t)T * (uint64_t)ax < (uint64_t)s * (uint64_t)s;
                 keep = !tri;
                 if (keep && !off && ax > 0) {
-                    const double cth = (double)dotx / (na * sqrt((double)ax));
+                    const float cth = (float)dotx * rna * __builtin_amdgcn_rsqf((float)ax);
                     if (cth < thr) keep = false;
                 }
             }

@@ -335,44 +335,48 @@ struct KeyChange {
     __device__ uint32_t operator()(int64_t i) const { return i < n && (i == 0 || k[i] != k[i - 1]); }
 };
 
+// Runs of equal identifiers, written from the scan of "identifier changes
+// here": the grid of sorted point s is (changes up to s) - 1.
 template <typename K>
-__global__ __launch_bounds__(kBlock) void cells_kernel(Batch b, const K* __restrict__ skeys,
-                                                       const uint32_t* __restrict__ excl, uint32_t* cell_start,
-                                                       int32_t* ck, int64_t ck_stride) {
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= b.n) return;
-    const K key = skeys[s];
-    const bool first = s == 0 || skeys[s - 1] != key;
-    const uint32_t c = excl[s] + (first ? 1u : 0u) - 1u;
-    if (first) {
-        cell_start[c] = (uint32_t)s;
-        const int ishift = b.hdr->inst_shift;
-        int k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
-        if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
-        const Inst& I = b.inst[k];
-        ck[c] = k;
+struct CellWriter {
+    Batch b;
+    const K* skeys;
+    uint32_t* cell_start;
+    int32_t* ck;
+    int64_t ck_stride;
+    __device__ void operator()(int64_t s, uint32_t ex) const {
+        const K key = skeys[s];
+        const bool first = s == 0 || skeys[s - 1] != key;
+        const uint32_t c = ex + (first ? 1u : 0u) - 1u;
+        if (first) {
+            cell_start[c] = (uint32_t)s;
+            const int ishift = b.hdr->inst_shift;
+            int k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
+            if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
+            const Inst& I = b.inst[k];
+            ck[c] = k;
 #pragma unroll
-        for (int j = 0; j < kMaxD; ++j) {
-            if (j < b.D) {
-                int32_t v = 0;
-                if (j < I.d) {
-                    const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
-                    v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
+            for (int j = 0; j < kMaxD; ++j) {
+                if (j < b.D) {
+                    int32_t v = 0;
+                    if (j < I.d) {
+                        const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
+                        v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
+                    }
+                    ck[(int64_t)(j + 1) * ck_stride + c] = v;
                 }
-                ck[(int64_t)(j + 1) * ck_stride + c] = v;
             }
         }
+        if (s == b.n - 1) cell_start[c + 1] = (uint32_t)b.n;
     }
-    if (s == b.n - 1) cell_start[c + 1] = (uint32_t)b.n;
-}
+};
 
 template <typename K>
 hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st) {
-    hipError_t e = scan_exclusive<uint32_t>(KeyChange<K>{skeys, b.n}, b.n, excl, &b.hdr->ncell, partial, st);
-    if (e != hipSuccess || b.n == 0) return e;
-    cells_kernel<K><<<dim3(grid_for(b.n)), dim3(kBlock), 0, st>>>(b, skeys, excl, cell_start, ck, ck_stride);
-    return hipGetLastError();
+    (void)excl;
+    return scan_apply<uint32_t>(KeyChange<K>{skeys, b.n}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
+                                &b.hdr->ncell, partial, st);
 }
 template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,
                                            int64_t, hipStream_t);

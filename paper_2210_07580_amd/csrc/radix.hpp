@@ -1,79 +1,92 @@
-// Stable LSD radix sort of (key, u32 value) pairs, 8-bit digits, for the
-// grid identifiers of Section 4.1 (Algorithm 1 line 2 sorts the points by
-// identifier with a radix sort).
+// Stable LSD radix sort of (key, u32 value) pairs for the grid identifiers
+// of Section 4.1 (Algorithm 1 line 2 sorts the points by identifier with a
+// radix sort).  A sort of B bits takes ceil(B / 8) passes of equal digits
+// of at most 8 bits (wider digits cost more per pass than the pass they
+// save: a 4x larger offset table to scan, more ranking ballots and less
+// occupancy).
 //
 // Each pass is reduce-then-scan: (1) every workgroup builds the digit
 // histogram of its 4096-key tile in LDS (one sub-histogram per wave to cut
 // atomic contention); (2) a device-wide exclusive scan over the
-// digit-major [256][tiles] table gives every (digit, tile) its output base;
+// digit-major [bins][tiles] table gives every (digit, tile) its output base;
 // (3) every workgroup re-reads its tile; each wave takes a run of 1024
 // consecutive keys and ranks them among equal digits with wave64 ballots
-// (eight ballots give the lanes holding the same digit; the rank is the
-// popcount below the lane plus the wave's running count of that digit, kept
-// in LDS), one scan over (digit, wave) turns the counts into local slots, the
-// keys are placed in LDS in digit order and written out run by run, so that
-// neighbouring lanes store to neighbouring addresses.  Ranks follow input
-// order, so every pass is stable.
+// (one ballot per digit bit gives the lanes holding the same digit; the rank
+// is the popcount below the lane plus the wave's running count of that
+// digit, kept in LDS), one scan over (digit, wave) turns the counts into
+// local slots, the keys are placed in LDS in digit order and written out run
+// by run, so that neighbouring lanes store to neighbouring addresses.  Ranks
+// follow input order, so every pass is stable.
 #pragma once
 
 #include "scan.hpp"
 
 namespace gd {
 
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kBlock * kRadixItems;
-static_assert(kBlock == kRadixBins, "one digit per thread in the scatter pass");
+
+template <typename K>
+constexpr int radix_max_bits() { return 8; }
+template <typename K>
+constexpr int radix_max_bins() { return 1 << radix_max_bits<K>(); }
 
 inline int64_t radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
-// u32 entries of scratch needed for a sort of n keys
+// u32 entries of scratch needed for a sort of n keys (any key type)
 inline int64_t radix_scratch_words(int64_t n) {
     const int64_t t = radix_tiles(n);
-    return 2 * kRadixBins * t + scan_blocks(kRadixBins * t) + 4;
+    constexpr int64_t bins = 1 << 8;
+    return 2 * bins * t + scan_blocks(bins * t) + 4;
 }
 
 template <typename K>
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift, int rbits,
                                                             uint32_t* __restrict__ hist, int64_t tiles) {
-    __shared__ uint32_t h[kWavesPerBlock][kRadixBins];
-    for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock) (&h[0][0])[i] = 0;
+    constexpr int kMaxBins = radix_max_bins<K>();
+    __shared__ uint32_t h[kWavesPerBlock][kMaxBins];
+    const int bins = 1 << rbits;
+    for (int i = threadIdx.x; i < kWavesPerBlock * kMaxBins; i += kBlock) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const int w = wave_id();
+    const uint32_t mask = (uint32_t)bins - 1u;
 #pragma unroll 4
     for (int r = 0; r < kRadixItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
         if (i < n) {
-            const uint32_t dg = (uint32_t)(keys[i] >> shift) & (kRadixBins - 1);
+            const uint32_t dg = (uint32_t)(keys[i] >> shift) & mask;
             atomicAdd(&h[w][dg], 1u);
         }
     }
     __syncthreads();
-    const int t = threadIdx.x;  // one digit per thread (kBlock == kRadixBins)
-    uint32_t s = 0;
+    for (int t = threadIdx.x; t < bins; t += kBlock) {
+        uint32_t s = 0;
 #pragma unroll
-    for (int ww = 0; ww < kWavesPerBlock; ++ww) s += h[ww][t];
-    hist[(int64_t)t * tiles + blockIdx.x] = s;
+        for (int ww = 0; ww < kWavesPerBlock; ++ww) s += h[ww][t];
+        hist[(int64_t)t * tiles + blockIdx.x] = s;
+    }
 }
 
 template <typename K, bool kIota>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                                K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-                                                               int64_t n, int shift, const uint32_t* __restrict__ offs,
-                                                               int64_t tiles) {
+                                                               int64_t n, int shift, int rbits,
+                                                               const uint32_t* __restrict__ offs, int64_t tiles) {
+    constexpr int kMaxBins = radix_max_bins<K>();
+    constexpr int kDigitsPerThread = kMaxBins / kBlock;  // 4 or 2
     constexpr int kPerWave = kRadixTile / kWavesPerBlock;  // 1024 consecutive keys per wave
     constexpr int kIters = kPerWave / kWave;               // 16
     __shared__ K skey[kRadixTile];                          // the tile, ordered by digit (stable)
     __shared__ uint32_t sval[kRadixTile];
-    __shared__ uint32_t wcnt[kWavesPerBlock][kRadixBins];   // keys per (wave, digit), then first local slot
-    __shared__ uint32_t gbase[kRadixBins];                  // global slot of a digit's first key, minus its local start
+    __shared__ uint32_t wcnt[kWavesPerBlock][kMaxBins];     // keys per (wave, digit), then first local slot
+    __shared__ uint32_t gbase[kMaxBins];                    // global slot of a digit's first key, minus its local start
     __shared__ uint32_t wsum[kWavesPerBlock];
     const int t = threadIdx.x;
     const int w = wave_id();
     const int lane = lane_id();
-#pragma unroll
-    for (int ww = 0; ww < kWavesPerBlock; ++ww) wcnt[ww][t] = 0;
+    const int bins = 1 << rbits;
+    const uint32_t mask = (uint32_t)bins - 1u;
+    for (int i = t; i < kWavesPerBlock * kMaxBins; i += kBlock) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const int tile_n = (int)min((int64_t)kRadixTile, n - base);
@@ -94,10 +107,9 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     for (int it = 0; it < kIters; ++it) {
         const int li = w * kPerWave + it * kWave + lane;
         const bool valid = li < tile_n;
-        const uint32_t dg = (uint32_t)(k[it] >> shift) & (kRadixBins - 1);
+        const uint32_t dg = (uint32_t)(k[it] >> shift) & mask;
         uint64_t peers = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < rbits; ++b) {
             const bool bit = (dg >> b) & 1u;
             const uint64_t m = ballot(bit);
             peers &= bit ? m : ~m;
@@ -110,21 +122,34 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
         dr[it] = (dg << 16) | rank;
     }
     __syncthreads();
-    // 2. local start of each (wave, digit): digits in order, waves in order
+    // 2. local start of each (wave, digit): digits in order, waves in order;
+    //    thread t owns digits [t * kDigitsPerThread, +kDigitsPerThread)
     {
-        uint32_t c[kWavesPerBlock], tot = 0;
+        uint32_t c[kDigitsPerThread][kWavesPerBlock], tot[kDigitsPerThread], mine = 0;
 #pragma unroll
-        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
-            c[ww] = wcnt[ww][t];
-            tot += c[ww];
+        for (int q = 0; q < kDigitsPerThread; ++q) {
+            const int dg = t * kDigitsPerThread + q;
+            tot[q] = 0;
+#pragma unroll
+            for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+                c[q][ww] = dg < bins ? wcnt[ww][dg] : 0u;
+                tot[q] += c[q][ww];
+            }
+            mine += tot[q];
         }
         uint32_t all;
-        uint32_t acc = block_excl_scan(tot, wsum, all);
-        gbase[t] = offs[(int64_t)t * tiles + blockIdx.x] - acc;
+        uint32_t acc = block_excl_scan(mine, wsum, all);
 #pragma unroll
-        for (int ww = 0; ww < kWavesPerBlock; ++ww) {
-            wcnt[ww][t] = acc;
-            acc += c[ww];
+        for (int q = 0; q < kDigitsPerThread; ++q) {
+            const int dg = t * kDigitsPerThread + q;
+            if (dg < bins) {
+                gbase[dg] = offs[(int64_t)dg * tiles + blockIdx.x] - acc;
+#pragma unroll
+                for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+                    wcnt[ww][dg] = acc;
+                    acc += c[q][ww];
+                }
+            }
         }
     }
     __syncthreads();
@@ -142,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     // 4. write the digit runs out in order: consecutive threads, consecutive slots
     for (int j = t; j < tile_n; j += kBlock) {
         const K kk = skey[j];
-        const uint32_t dg = (uint32_t)(kk >> shift) & (kRadixBins - 1);
+        const uint32_t dg = (uint32_t)(kk >> shift) & mask;
         const uint32_t pos = gbase[dg] + (uint32_t)j;
         keys_out[pos] = kk;
         vals_out[pos] = sval[j];
@@ -178,21 +203,24 @@ hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals
     bool first = true;
     const int64_t tiles = radix_tiles(n);
     uint32_t* hist = scratch;
-    uint32_t* offs = scratch + (int64_t)kRadixBins * tiles;
-    uint32_t* partial = offs + (int64_t)kRadixBins * tiles;
+    uint32_t* offs = scratch + (int64_t)radix_max_bins<uint32_t>() * tiles;
+    uint32_t* partial = offs + (int64_t)radix_max_bins<uint32_t>() * tiles;
     bool iota = vals_iota;
-    for (int shift = 0; shift < bits; shift += kRadixBits) {
+    const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
+    const int rbits = passes ? (bits + passes - 1) / passes : 0;
+    for (int p = 0, shift = 0; p < passes; ++p, shift += rbits) {
         if (n == 0) break;
-        radix_hist_kernel<K><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, n, shift, hist, tiles);
-        hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, (int64_t)kRadixBins * tiles, offs,
-                                                (uint32_t*)nullptr, partial, st);
+        const int64_t bins = (int64_t)1 << rbits;
+        radix_hist_kernel<K><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, n, shift, rbits, hist, tiles);
+        hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, bins * tiles, offs, (uint32_t*)nullptr,
+                                                partial, st);
         if (e != hipSuccess) return e;
         if (iota)
             radix_scatter_kernel<K, true><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                        offs, tiles);
+                                                                                        rbits, offs, tiles);
         else
             radix_scatter_kernel<K, false><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n,
-                                                                                         shift, offs, tiles);
+                                                                                         shift, rbits, offs, tiles);
         iota = false;
         K* tk = kin; kin = kout; kout = (first && keys_spare) ? keys_spare : tk;
         first = false;

@@ -48,8 +48,15 @@ __global__ __launch_bounds__(kBlock) void scan_partials_kernel(T* partial, int64
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-template <typename T, typename F>
-__global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const T* partial, T* out) {
+// Output of a scan: store the exclusive prefix (or hand it to a functor).
+template <typename T>
+struct StoreOut {
+    T* out;
+    __device__ void operator()(int64_t i, T ex) const { out[i] = ex; }
+};
+
+template <typename T, typename F, typename O>
+__global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const T* partial, O o) {
     __shared__ T wsum[kWavesPerBlock];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     T carry = partial[blockIdx.x];
@@ -59,23 +66,76 @@ __global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const
         T v = i < n ? f(i) : T(0);
         T tot;
         T ex = block_excl_scan(v, wsum, tot);
-        if (i < n) out[i] = carry + ex;
+        if (i < n) o(i, carry + ex);
         carry += tot;
     }
 }
 
-// out[i] = sum_{k < i} f(k) for 0 <= i < n; *total = sum of all (device).
+// Short scans (up to kSingleScanMax elements) run in one workgroup of 1024
+// threads: rounds of 4096 elements, four consecutive ones per thread, one
+// workgroup scan per round.  One launch instead of three.
+constexpr int kSingleScanThreads = 1024;
+constexpr int64_t kSingleScanMax = 1 << 13;  // above this, three launches over many workgroups are faster
+
+template <typename T, typename F, typename O>
+__global__ __launch_bounds__(kSingleScanThreads) void scan_single_kernel(F f, int64_t n, O o, T* total) {
+    constexpr int kW = kSingleScanThreads / kWave;
+    __shared__ T wsum[kW];
+    const int t = threadIdx.x, lane = lane_id(), w = wave_id();
+    T carry = 0;
+    for (int64_t base = 0; base < n; base += 4 * kSingleScanThreads) {
+        const int64_t i0 = base + 4 * (int64_t)t;
+        T v[4];
+        T run = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < n ? f(i0 + k) : T(0);
+            run += v[k];
+        }
+        const T incl = wave_incl_scan(run);
+        if (lane == kWave - 1) wsum[w] = incl;
+        __syncthreads();
+        T off = 0, tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < kW; ++ww) {
+            const T x = wsum[ww];
+            off += ww < w ? x : T(0);
+            tot += x;
+        }
+        __syncthreads();
+        T acc = carry + off + incl - run;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < n) o(i0 + k, acc);
+            acc += v[k];
+        }
+        carry += tot;
+    }
+    if (t == 0 && total) *total = carry;
+}
+
+// o(i, sum_{k < i} f(k)) for 0 <= i < n; *total = sum of all (device).
 // `partial` needs scan_blocks(n) elements.
-template <typename T, typename F>
-hipError_t scan_exclusive(F f, int64_t n, T* out, T* total, T* partial, hipStream_t st) {
+template <typename T, typename F, typename O>
+hipError_t scan_apply(F f, int64_t n, O o, T* total, T* partial, hipStream_t st) {
     const int64_t nb = scan_blocks(n);
     if (nb == 0) {
         return total ? fill<T>(total, 1, T(0), st) : hipSuccess;
     }
+    if (n <= kSingleScanMax) {
+        scan_single_kernel<T, F, O><<<1, kSingleScanThreads, 0, st>>>(f, n, o, total);
+        return hipGetLastError();
+    }
     scan_reduce_kernel<T, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
     scan_partials_kernel<T><<<1, kBlock, 0, st>>>(partial, nb, total);
-    scan_down_kernel<T, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, out);
+    scan_down_kernel<T, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o);
     return hipGetLastError();
+}
+
+// out[i] = sum_{k < i} f(k) for 0 <= i < n; *total = sum of all (device).
+template <typename T, typename F>
+hipError_t scan_exclusive(F f, int64_t n, T* out, T* total, T* partial, hipStream_t st) {
+    return scan_apply<T>(f, n, StoreOut<T>{out}, total, partial, st);
 }
 
 template <typename T>
