@@ -648,10 +648,10 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
     Plan p{};
     const int kb = std::max(ctx->last_key_bits, 1);
     p.key_bits = std::min((kb + 7) / 8 * 8, kb <= 32 ? 32 : 64);
-    p.ncell = std::min<int64_t>(n, e.grids + e.grids / 4 + 1024);
-    p.nei = (uint64_t)e.neighbor_entries + (uint64_t)e.neighbor_entries / 4 + 4096;
-    p.ncc = std::min<int64_t>(p.ncell, e.core_grids + e.core_grids / 4 + 256);
-    p.max_core = std::min<int64_t>(std::min<int64_t>(n, kMaxCoreBits), ctx->last_max_core + ctx->last_max_core / 4 + 64);
+    p.ncell = std::min<int64_t>(n, e.grids + e.grids / 16 + 1024);
+    p.nei = (uint64_t)e.neighbor_entries + (uint64_t)e.neighbor_entries / 16 + 4096;
+    p.ncc = std::min<int64_t>(p.ncell, e.core_grids + e.core_grids / 16 + 256);
+    p.max_core = std::min<int64_t>(std::min<int64_t>(n, kMaxCoreBits), ctx->last_max_core + ctx->last_max_core / 16 + 64);
     if (!ctx->gstream) {
         if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ctx->gev, hipEventDisableTiming) != hipSuccess) {

@@ -8,7 +8,8 @@ namespace gd {
 
 // ---------------------------------------------------------------- summaries
 // One wave per core grid: centroid, bounding box and the positions of the
-// extreme core points along every axis.
+// extreme core points along every axis, over a sample of at most 64 core
+// points (the features only guide the merge; any core point may start it).
 template <int D>
 __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co, CellSummary* __restrict__ out) {
     const int lane = lane_id();
@@ -24,7 +25,10 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
         lo[k] = ~0ull;
         hi[k] = 0ull;
     }
-    for (uint32_t i = lane; i < m; i += kWave) {
+    // the first (at most) 64 core points: in input order within the grid, a
+    // uniform sample of its core set
+    const uint32_t ms = min(m, (uint32_t)kWave);
+    for (uint32_t i = lane; i < ms; i += kWave) {
         int32_t p[D];
         load_row<D>(co.ccrd, b + i, p);
 #pragma unroll
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
         const double tot = wave_sum(sum[k]);
         const uint64_t l = wave_min_u64(lo[k]);
         const uint64_t h = ~wave_min_u64(~hi[k]);
-        s.cen[k] = (float)(tot / (double)m);
+        s.cen[k] = (float)(tot / (double)ms);
         s.lo[k] = (int32_t)(l >> 32);
         s.hi[k] = (int32_t)(h >> 32);
         s.rep[2 * k] = (uint32_t)l;
@@ -160,26 +164,36 @@ hipError_t launch_harvest(const GridView& g, const CoreOut& c, const CellSummary
 // One wave per sample: z [B x 2] for features X [B x 16] (FP16).
 __global__ __launch_bounds__(kBlock) void mlp_forward_kernel(const __half* __restrict__ X, int64_t B,
                                                              const __half* __restrict__ params, float* __restrict__ Z) {
-    __shared__ MlpLds W;
-    __shared__ float hbuf[kWavesPerBlock][kWave];
-    mlp_load(W, params);
+    __shared__ MlpMfma W;
+    __shared__ MlpMfmaScratch S[kWavesPerBlock];
+    mlp_mfma_load(W, params);
     __syncthreads();
-    const int w = wave_id();
-    for (int64_t r = (int64_t)blockIdx.x * kWavesPerBlock + w; r < B; r += (int64_t)gridDim.x * kWavesPerBlock) {
-        float f[kFeat];
+    const int w = wave_id(), l = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock * 16;
+    for (int64_t r0 = ((int64_t)blockIdx.x * kWavesPerBlock + w) * 16; r0 < B; r0 += stride) {
+        for (int i = l; i < 16 * kFeat; i += kWave) {
+            const int row = i / kFeat, k = i % kFeat;
+            S[w].feat[row][k] = r0 + row < B ? (_Float16)__half2float(X[(r0 + row) * kFeat + k]) : (_Float16)0.f;
+        }
+        wave_sync();
+        float z0[4], z1[4];
+        mlp_forward_mfma(W, S[w], z0, z1);
+        if ((l & 15) == 0) {
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) f[k] = __half2float(X[r * kFeat + k]);
-        const MlpTrace t = mlp_forward_wave(W, f, hbuf[w]);
-        if (lane_id() == 0) {
-            Z[r * 2 + 0] = t.z0;
-            Z[r * 2 + 1] = t.z1;
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = r0 + 4 * (l >> 4) + j;
+                if (row < B) {
+                    Z[row * 2 + 0] = z0[j];
+                    Z[row * 2 + 1] = z1[j];
+                }
+            }
         }
     }
 }
 
 hipError_t launch_mlp_forward(const __half* X, int64_t B, const __half* params, float* Z, hipStream_t st) {
     if (B <= 0) return hipSuccess;
-    int64_t blocks = (B + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t blocks = (B + 16 * kWavesPerBlock - 1) / (16 * kWavesPerBlock);
     if (blocks > 2048) blocks = 2048;
     mlp_forward_kernel<<<dim3((unsigned)blocks), dim3(kBlock), 0, st>>>(X, B, params, Z);
     return hipGetLastError();

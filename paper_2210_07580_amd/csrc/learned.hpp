@@ -83,6 +83,93 @@ __device__ inline void mlp_load(MlpLds& m, const __half* __restrict__ p) {
     if (threadIdx.x < kOut) m.b3[threadIdx.x] = __half2float(p[oB3 + threadIdx.x]);
 }
 
+// The scorer on the matrix cores: 16 pairs at a time as three small GEMMs
+// with v_mfma_f32_16x16x16_f16 (FP16 operands, FP32 accumulation), the same
+// arithmetic as mlp_forward_wave (hidden activations rounded to FP16).
+// Operand layout of the 16x16x16 instruction, lane l = 0..63, element j:
+//   A (rows x k):  A[l % 16][4 (l / 16) + j]
+//   B (k x cols):  B[4 (l / 16) + j][l % 16]
+//   D (rows x cols): D[4 (l / 16) + j][l % 16]
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+struct MlpMfma {
+    _Float16 w1[kHid][kFeat];  // W1 as stored: row = hidden unit, column = feature
+    _Float16 w2[kHid][kHid];   // W2: row = output unit, column = input unit
+    float b1[kHid], b2[kHid];
+    float w3[kOut][kHid];
+    float b3[kOut];
+};
+
+__device__ inline void mlp_mfma_load(MlpMfma& m, const __half* __restrict__ p) {
+    for (int i = threadIdx.x; i < kHid * kFeat; i += blockDim.x)
+        (&m.w1[0][0])[i] = (_Float16)__half2float(p[oW1 + i]);
+    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x)
+        (&m.w2[0][0])[i] = (_Float16)__half2float(p[oW2 + i]);
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        m.b1[i] = __half2float(p[oB1 + i]);
+        m.b2[i] = __half2float(p[oB2 + i]);
+        m.w3[0][i] = __half2float(p[oW3 + i]);
+        m.w3[1][i] = __half2float(p[oW3 + kHid + i]);
+    }
+    if (threadIdx.x < kOut) m.b3[threadIdx.x] = __half2float(p[oB3 + threadIdx.x]);
+}
+
+// Scratch of one wave: the 16 feature rows and the first hidden layer.
+struct MlpMfmaScratch {
+    _Float16 feat[16][kFeat];
+    _Float16 h1[16][kHid];
+};
+
+// Scores of the 16 feature rows in s.feat (all lanes call it).  On return
+// lane l holds z[o][r] for rows r = 4 (l / 16) + j in z0[j], z1[j].
+__device__ inline void mlp_forward_mfma(const MlpMfma& m, MlpMfmaScratch& s, float (&z0)[4], float (&z1)[4]) {
+    const int l = lane_id();
+    const int r = l & 15, g = l >> 4;
+    const float4_t zero = {0.f, 0.f, 0.f, 0.f};
+    // layer 1: [16 x 16] . [16 x 64]
+    const half4_t a1 = *reinterpret_cast<const half4_t*>(&s.feat[r][4 * g]);
+#pragma unroll
+    for (int nb = 0; nb < kHid / 16; ++nb) {
+        const half4_t b = *reinterpret_cast<const half4_t*>(&m.w1[nb * 16 + r][4 * g]);
+        const float4_t d = __builtin_amdgcn_mfma_f32_16x16x16f16(a1, b, zero, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s.h1[4 * g + j][nb * 16 + r] = (_Float16)fmaxf(d[j] + m.b1[nb * 16 + r], 0.f);
+    }
+    wave_sync();
+    // layer 2: [16 x 64] . [64 x 64], then layer 3 on the result
+    float p0[4] = {0.f, 0.f, 0.f, 0.f}, p1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int nb = 0; nb < kHid / 16; ++nb) {
+        float4_t acc = zero;
+#pragma unroll
+        for (int kb = 0; kb < kHid / 16; ++kb) {
+            const half4_t a = *reinterpret_cast<const half4_t*>(&s.h1[r][kb * 16 + 4 * g]);
+            const half4_t b = *reinterpret_cast<const half4_t*>(&m.w2[nb * 16 + r][kb * 16 + 4 * g]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+        }
+        const int col = nb * 16 + r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float h2 = (float)(_Float16)fmaxf(acc[j] + m.b2[col], 0.f);
+            p0[j] += m.w3[0][col] * h2;
+            p1[j] += m.w3[1][col] * h2;
+        }
+    }
+    // sum over the 16 columns each lane group holds
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            p0[j] += __shfl_xor(p0[j], o);
+            p1[j] += __shfl_xor(p1[j], o);
+        }
+        z0[j] = p0[j] + m.b3[0];
+        z1[j] = p1[j] + m.b3[1];
+    }
+    wave_sync();  // s.h1 may be rewritten by the next call
+}
+
 // Forward pass for one pair on a whole wave: lane u owns hidden unit u.
 // `f` is uniform across the wave (the features already rounded to FP16);
 // `hbuf` is 64 floats of the wave's own LDS.  Hidden activations are

@@ -133,11 +133,13 @@ __global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut 
                                                            uint32_t words, uint32_t* parent, MergeStats* stats,
                                                            Proposal prop) {
     extern __shared__ uint64_t smem[];
-    using Weights = typename std::conditional<kLearned, MlpLds, float>::type;
+    using Weights = typename std::conditional<kLearned, MlpMfma, float>::type;
+    using Scratch = typename std::conditional<kLearned, MlpMfmaScratch, float>::type;
     __shared__ Weights W[1];
-    __shared__ float hbuf[kLearned ? kWavesPerBlock : 1][kWave];
+    __shared__ Scratch S[kLearned ? kWavesPerBlock : 1];
+    __shared__ float2 zb[kLearned ? kWavesPerBlock : 1][kLearned ? kWave : 1];
     if constexpr (kLearned) {
-        mlp_load(W[0], prop.weights);
+        mlp_mfma_load(W[0], prop.weights);
         __syncthreads();
     }
     const int lane = lane_id();
@@ -181,21 +183,36 @@ __global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut 
         float my_z0 = 0.f, my_z1 = 0.f;
         uint32_t my_ra = 0, my_rb = 0;
         if constexpr (kLearned) {
-            for (uint64_t todo = pend; todo; todo &= todo - 1ull) {
-                const int l = ffs64(todo);
-                const uint32_t j = readlane(cj, l);
-                if (readlane(mj, l) > 64u * words) continue;
-                float f[kFeat];
-                uint32_t ra, rb;
-                pair_setup<D>(gv, co, prop.sum, ci, j, eps, f, ra, rb);
-                const MlpTrace tr = mlp_forward_wave(W[0], f, hbuf[w]);
-                if (lane == l) {
-                    my_z0 = tr.z0;
-                    my_z1 = tr.z1;
-                    my_ra = ra;
-                    my_rb = rb;
+            // score every pending pair: features per lane, the scorer on the
+            // matrix cores 16 pairs at a time
+            const bool pl = ((pend >> lane) & 1ull) && mj <= 64u * words;
+            const uint64_t pm = ballot(pl);
+            const uint32_t rk = (uint32_t)popc64(pm & lanemask_lt());
+            const int np = popc64(pm);
+            float f[kFeat];
+            uint32_t ra = 0, rb = 0;
+            if (pl) pair_setup<D>(gv, co, prop.sum, ci, cj, eps, f, ra, rb);
+            my_ra = ra;
+            my_rb = rb;
+            for (int b0 = 0; b0 < np; b0 += 16) {
+                if (pl && rk >= (uint32_t)b0 && rk < (uint32_t)b0 + 16u) {
+#pragma unroll
+                    for (int k = 0; k < kFeat; ++k) S[w].feat[rk - b0][k] = (_Float16)f[k];
                 }
+                wave_sync();
+                float z0[4], z1[4];
+                mlp_forward_mfma(W[0], S[w], z0, z1);
+                if ((lane & 15) == 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) zb[w][b0 + 4 * (lane >> 4) + j] = make_float2(z0[j], z1[j]);
+                }
+                wave_sync();
             }
+            if (pl) {
+                my_z0 = zb[w][rk].x;
+                my_z1 = zb[w][rk].y;
+            }
+            wave_sync();
         }
         while (pend) {
             int l;
@@ -278,7 +295,8 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     const unsigned blocks = (unsigned)((ncc - b0 + wpb - 1) / wpb);
     // the scorer's weights take static LDS beside the bitmaps; if both do not
     // fit, run without the proposal (the answers are the same)
-    const bool learned = prop.weights && lds + sizeof(MlpLds) + sizeof(float) * kWavesPerBlock * kWave <= 65536;
+    const bool learned = prop.weights && lds + sizeof(MlpMfma) + kWavesPerBlock * (sizeof(MlpMfmaScratch) +
+                                                                                 sizeof(float2) * kWave) <= 65536;
     if (learned) {
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, words, parent, stats, prop)));
