@@ -146,6 +146,14 @@ def bench_batched(G, steps, warmup, max_instances):
     ctx.set_option(G.GD_OPT_GRAPH, 0)
     t_batch_eager = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
     log(f"bench: batched without graph {1e3 * t_batch_eager:.2f} ms")
+    ctx.set_option(G.GD_OPT_TIMING, 1)
+    ctx.dbscan_batched(probs, outs=outs)
+    batch_phases = {k: round(v, 4) for k, v in ctx.phase_times().items()}
+    ctx.set_option(G.GD_OPT_TIMING, 0)
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    ctx.dbscan_batched(probs, outs=outs)
+    bst = ctx.stats()
+    ctx.set_option(G.GD_OPT_STATS, 0)
 
     def each():
         for (t, e, m), (lab, core) in zip(probs, outs):
@@ -163,7 +171,9 @@ def bench_batched(G, steps, warmup, max_instances):
         "autotuned": tuned, "autotune_trials_ms": {f"{r['tile_points']}x{r['merge_waves']}": round(r["ms"], 3)
                                                    for r in trials},
         "graph_replay": replayed, "no_graph_value": round(total / t_batch_eager, 1),
-        "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3),
+        "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3), "phases_ms": batch_phases,
+        "work": {k: bst[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids", "merge_tests",
+                                     "merge_distances", "core_distances", "key_bits")},
     }
 
 

@@ -78,7 +78,7 @@ __device__ __forceinline__ void load_point(const PointSet& s, uint32_t pos, int3
     load_row<D>(s.rows, (int64_t)s.base + pos, x);
 }
 
-constexpr uint32_t kUnroll = 4;  // words of a set whose loads are issued together
+constexpr uint32_t kUnroll = 2;  // words of a set whose loads are issued together
 
 // Loads the point of this lane in word w (position clamped into the set so
 // the address is always valid; callers ignore lanes whose bit is clear).

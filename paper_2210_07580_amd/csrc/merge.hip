@@ -125,8 +125,11 @@ __device__ __forceinline__ uint32_t orderable(float z) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// The kernel is bound by the latency of union-find and FastMerging steps:
+// six waves per SIMD (at most 85 registers) hide more of it than wider
+// unrolling inside a wave.
 template <int D, bool kLearned>
-__global__ __launch_bounds__(kBlock) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+__global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
                                                            const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,

@@ -1,5 +1,5 @@
-// Device-wide exclusive prefix sum (reduce, scan of block totals, scan):
-// three launches, no inter-workgroup waiting.  The input is a functor
+// Device-wide exclusive prefix sum: a reduce pass and a scan pass, no
+// inter-workgroup waiting.  The input is a functor
 // f(i) -> T so that flags can be formed on the fly from other arrays.
 #pragma once
 
@@ -32,22 +32,6 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(F f, int64_t n, T* 
     }
 }
 
-// One workgroup: exclusive scan of the block totals in place; grand total out.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void scan_partials_kernel(T* partial, int64_t nb, T* total) {
-    __shared__ T wsum[kWavesPerBlock];
-    T carry = 0;
-    for (int64_t base = 0; base < nb; base += kBlock) {
-        const int64_t i = base + threadIdx.x;
-        T v = i < nb ? partial[i] : T(0);
-        T tot;
-        T ex = block_excl_scan(v, wsum, tot);
-        if (i < nb) partial[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total) *total = carry;
-}
-
 // Output of a scan: store the exclusive prefix (or hand it to a functor).
 template <typename T>
 struct StoreOut {
@@ -55,11 +39,22 @@ struct StoreOut {
     __device__ void operator()(int64_t i, T ex) const { out[i] = ex; }
 };
 
+// Each workgroup sums the totals of the tiles before it (a few thousand
+// values at most, from L2) instead of waiting for a separate pass to scan
+// them; the last workgroup writes the grand total.
 template <typename T, typename F, typename O>
-__global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const T* partial, O o) {
+__global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const T* partial, O o, T* total) {
     __shared__ T wsum[kWavesPerBlock];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    T carry = partial[blockIdx.x];
+    T carry = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) carry += partial[b];
+    carry = wave_sum(carry);
+    if (lane_id() == 0) wsum[wave_id()] = carry;
+    __syncthreads();
+    carry = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) carry += wsum[w];
+    __syncthreads();
     for (int r = 0; r < kScanItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
         if (base + (int64_t)r * kBlock >= n) break;  // uniform across the block
@@ -69,6 +64,7 @@ __global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const
         if (i < n) o(i, carry + ex);
         carry += tot;
     }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = carry;
 }
 
 // Short scans (up to kSingleScanMax elements) run in one workgroup of 1024
@@ -127,8 +123,7 @@ hipError_t scan_apply(F f, int64_t n, O o, T* total, T* partial, hipStream_t st)
         return hipGetLastError();
     }
     scan_reduce_kernel<T, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
-    scan_partials_kernel<T><<<1, kBlock, 0, st>>>(partial, nb, total);
-    scan_down_kernel<T, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o);
+    scan_down_kernel<T, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o, total);
     return hipGetLastError();
 }
 
