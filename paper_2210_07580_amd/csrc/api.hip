@@ -216,6 +216,7 @@ struct Layout {
     uint32_t* core_cnt;
     uint32_t* core_begin;
     uint32_t* side_off;
+    uint32_t* count_part;
     uint32_t* cell_min_core;
     uint32_t* list;
     uint32_t* rank;
@@ -253,6 +254,7 @@ Layout carve(char* base, int64_t n, int D) {
     L.core_cnt = c.take<uint32_t>(n);
     L.core_begin = c.take<uint32_t>(n);
     L.side_off = c.take<uint32_t>(n + 1);
+    L.count_part = c.take<uint32_t>(5 * (n / kBlock + 2));
     L.cell_min_core = c.take<uint32_t>(n);
     L.list = c.take<uint32_t>(n);
     L.rank = c.take<uint32_t>(n);
@@ -419,6 +421,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     co.ccrd = L.crd;
     co.corig = const_cast<uint32_t*>(sidx);
     co.side_off = L.side_off;
+    co.count_part = L.count_part;
     co.cell_min_core = L.cell_min_core;
     co.counts = Hd->counts;
     ctx->mark(P_CORE_COMPACT, 0);
@@ -464,7 +467,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(launch_summaries(g, co, sum, st));
         ctx->last_summaries = true;
     }
-    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, (ctx->ldf && !plan) ? (int64_t)H->counts[4] : -1,
+    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, !ctx->ldf ? -1 : plan ? -2 : (int64_t)H->counts[4],
                         max_core, ctx->merge_waves, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                         ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
     ctx->mark(P_MERGE, 1);

@@ -113,7 +113,9 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
     if (c >= (int64_t)*gv.ncell_dev) return;
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
-    const int32_t val = co.core_cnt[c] == k ? cell_label[c] : kDeferred;
+    // only all-core grids go in: a missing identifier reads as deferred
+    if (co.core_cnt[c] != k) return;
+    const int32_t val = cell_label[c];
     const K key = skeys[st];
     if (key == ~K(0)) {
         tab[1ull << bits].val = val;

@@ -147,8 +147,12 @@ struct SideRows {
 };
 
 // One thread per grid: where its core set starts, the smallest input index
-// of its core points (grids without side rows), and the header counts.
-__global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut co) {
+// of its core points (grids without side rows), and the header counts.  The
+// counts are reduced per workgroup and written to part[] (five words per
+// workgroup), then summed by core_counts_kernel: atomics from every wave to
+// five addresses serialise on grids by the million.
+__global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut co, uint32_t* part) {
+    __shared__ uint32_t red[5][kWavesPerBlock];
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool v = c < (int64_t)*gv.ncell_dev;
     uint32_t cnt = 0, size = 0, minpts = 0;
@@ -161,17 +165,50 @@ __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut
         co.core_begin[c] = side ? (uint32_t)gv.n + co.side_off[c] : st;
         if (!side) co.cell_min_core[c] = cnt ? gv.sidx[st] : kNone;
     }
-    const uint64_t has = ballot(v && cnt > 0);
-    const uint64_t dense = ballot(v && size >= minpts);
-    const uint64_t tiny = ballot(v && cnt > 0 && cnt <= kTinyCore);
+    const uint32_t has = (uint32_t)popc64(ballot(v && cnt > 0));
+    const uint32_t dense = (uint32_t)popc64(ballot(v && size >= minpts));
+    const uint32_t tiny = (uint32_t)popc64(ballot(v && cnt > 0 && cnt <= kTinyCore));
     const uint32_t mx = wave_max_u32(cnt);
     const uint32_t tot = wave_sum(cnt);
+    const int w = wave_id();
     if (lane_id() == 0) {
-        if (tot) atomicAdd(&co.counts[0], tot);
-        if (has) atomicAdd(&co.counts[1], (uint32_t)popc64(has));
-        if (dense) atomicAdd(&co.counts[3], (uint32_t)popc64(dense));
-        if (tiny) atomicAdd(&co.counts[4], (uint32_t)popc64(tiny));
-        if (mx) atomicMax(&co.counts[2], mx);
+        red[0][w] = tot;
+        red[1][w] = has;
+        red[2][w] = mx;
+        red[3][w] = dense;
+        red[4][w] = tiny;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        uint32_t a = 0;
+        for (int ww = 0; ww < kWavesPerBlock; ++ww)
+            a = threadIdx.x == 2 ? max(a, red[2][ww]) : a + red[threadIdx.x][ww];
+        part[(int64_t)blockIdx.x * 5 + threadIdx.x] = a;
+    }
+}
+
+// One workgroup: counts[0..4] from the per-workgroup words.
+__global__ __launch_bounds__(1024) void core_counts_kernel(const uint32_t* part, int64_t blocks, uint32_t* counts) {
+    __shared__ uint32_t red[5][1024 / kWave];
+    uint32_t a[5] = {0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < blocks; b += 1024) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const uint32_t x = part[b * 5 + k];
+            a[k] = k == 2 ? max(a[k], x) : a[k] + x;
+        }
+    }
+    const int w = wave_id();
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const uint32_t r = k == 2 ? wave_max_u32(a[k]) : wave_sum(a[k]);
+        if (lane_id() == 0) red[k][w] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        uint32_t r = 0;
+        for (int ww = 0; ww < 1024 / kWave; ++ww) r = threadIdx.x == 2 ? max(r, red[2][ww]) : r + red[threadIdx.x][ww];
+        counts[threadIdx.x] = r;
     }
 }
 
@@ -208,13 +245,14 @@ __global__ __launch_bounds__(kBlock) void side_copy_kernel(GridView gv, CoreOut 
 }
 
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st) {
-    hipError_t e = fill<uint32_t>(c.counts, 5, 0u, st);
-    if (e != hipSuccess) return e;
-    if (g.ncell == 0) return hipSuccess;
+    if (g.ncell == 0) return fill<uint32_t>(c.counts, 5, 0u, st);
+    hipError_t e;
     e = scan_exclusive<uint32_t>(SideRows{c.core_cnt, g.cell_start, g.ncell_dev}, g.ncell + 1, c.side_off,
                                  (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
-    core_cells_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c);
+    const unsigned nb = grid_for(g.ncell);
+    core_cells_kernel<<<dim3(nb), dim3(kBlock), 0, st>>>(g, c, c.count_part);
+    core_counts_kernel<<<1, 1024, 0, st>>>(c.count_part, nb, c.counts);
     GD_DISPATCH_D(g.D, (side_copy_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(g, c)));
     return hipGetLastError();
 }

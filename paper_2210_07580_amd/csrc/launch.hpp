@@ -159,6 +159,7 @@ struct CoreOut {
     uint32_t* side_off;         // ncell + 1: exclusive scan of the side rows of each grid
     uint32_t* cell_min_core;    // ncell: smallest input index of a core point (kNone if none)
     uint32_t* counts;           // header counts
+    uint32_t* count_part;       // 5 words per workgroup of core_cells_kernel (ncell / 256 + 1 workgroups)
 };
 constexpr uint32_t kTinyCore = 8;  // core sets decided by one lane in the merge step
 // Work counters of core marking (one copy per stat slot).
@@ -190,7 +191,8 @@ struct MergeStats {
 constexpr int64_t kMaxCoreBits = 262144;
 struct CellSummary;
 // waves: waves per workgroup of the FastMerging kernel (1, 2 or 4; fewer
-// if the LDS bitmaps do not fit).
+// if the LDS bitmaps do not fit).  n_small: tiny core grids leading the
+// visiting order (-2: as many as the device count says, -1: not ordered).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
                         int64_t max_core, int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,

@@ -42,10 +42,11 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
                                                              const uint32_t* __restrict__ nei,
                                                              const uint32_t* __restrict__ ldf,
                                                              const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
-                                                             uint32_t* parent, MergeStats* stats) {
+                                                             const uint32_t* split, uint32_t* parent,
+                                                             MergeStats* stats) {
     const int lane = lane_id();
     const int64_t r = r0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
-    if (r >= r1 || r >= (int64_t)co.counts[1]) return;
+    if (r >= r1 || r >= (int64_t)co.counts[1] || (split && r >= (int64_t)*split)) return;
     const uint32_t ci = ldf[r];
     const uint32_t T = cell_inst(gv, ci).T;
     const uint32_t bi = co.core_begin[ci];
@@ -133,8 +134,8 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
                                                            const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
-                                                           uint32_t words, uint32_t* parent, MergeStats* stats,
-                                                           Proposal prop) {
+                                                           const uint32_t* split, uint32_t words, uint32_t* parent,
+                                                           MergeStats* stats, Proposal prop) {
     extern __shared__ uint64_t smem[];
     using Weights = typename std::conditional<kLearned, MlpMfma, float>::type;
     using Scratch = typename std::conditional<kLearned, MlpMfmaScratch, float>::type;
@@ -148,7 +149,8 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
     const int lane = lane_id();
     const int wpb = (int)(blockDim.x / kWave);
     const int w = wave_id();
-    const int64_t r = r0 + (int64_t)blockIdx.x * wpb + w;
+    // with a device split the big core sets start right after the tiny ones
+    const int64_t r = (split ? (int64_t)*split : r0) + (int64_t)blockIdx.x * wpb + w;
     if (r >= r1 || r >= (int64_t)co.counts[1]) return;
     const uint32_t ci = ldf[r];
     const Inst& I = cell_inst(gv, ci);
@@ -281,13 +283,17 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
     // n_small >= 0: the visiting order puts the n_small tiny core grids first
-    // (ascending core count); otherwise every wave checks its grid's size.
+    // (ascending core count).  n_small == -2: the same order, but the count
+    // is only known on the device (split); both kernels get grids for all
+    // ncc ranks and leave the other kernel's ranks alone.  n_small == -1: no
+    // such order; every wave checks its grid's size.
+    const uint32_t* split = n_small == -2 ? &c.counts[4] : nullptr;
     const int64_t s1 = n_small >= 0 ? n_small : ncc;
     const int64_t b0 = n_small >= 0 ? n_small : 0;
     if (s1 > 0) {
         const unsigned blocks = (unsigned)((s1 + kWavesPerBlock - 1) / kWavesPerBlock);
         GD_DISPATCH_D(g.D, (merge_small_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, 0, s1, parent, stats)));
+                               g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
     const uint32_t words = (uint32_t)((max_core + kWave - 1) / kWave);
@@ -302,10 +308,10 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                                                                                  sizeof(float2) * kWave) <= 65536;
     if (learned) {
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, words, parent, stats, prop)));
+                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, parent, stats, prop)));
     } else {
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, words, parent, stats, prop)));
+                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, parent, stats, prop)));
     }
     return hipGetLastError();
 }
@@ -365,12 +371,23 @@ hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* row
     return hipGetLastError();
 }
 
+// The smallest core index per union-find root.  Neighbouring grids mostly
+// share a root, so the lanes holding the first lane's root reduce first and
+// add one atomic; the rest add their own.
 __global__ __launch_bounds__(kBlock) void root_min_kernel(const uint32_t* ncell, const uint32_t* core_cnt,
                                                           const uint32_t* cell_min_core, uint32_t* parent,
                                                           uint32_t* root_min) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)*ncell || core_cnt[c] == 0) return;
-    atomicMin(&root_min[uf_find(parent, (uint32_t)c)], cell_min_core[c]);
+    const bool v = c < (int64_t)*ncell && core_cnt[c] != 0;
+    const uint32_t r = v ? uf_find(parent, (uint32_t)c) : kNone;
+    const uint32_t m = v ? cell_min_core[c] : kNone;
+    const uint64_t valid = ballot(v);
+    if (!valid) return;
+    const uint32_t r0 = readlane(r, ffs64(valid));
+    const bool same = v && r == r0;
+    const uint32_t m0 = (uint32_t)wave_min_u64(same ? (uint64_t)m : ~0ull);
+    if (lane_id() == ffs64(valid)) atomicMin(&root_min[r0], m0);
+    if (v && !same) atomicMin(&root_min[r], m);
 }
 
 __global__ __launch_bounds__(kBlock) void cell_label_kernel(const uint32_t* ncell, const uint32_t* core_cnt,
