@@ -39,8 +39,10 @@ template <int D, bool kStats>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
+    constexpr int S = row_stride(D);
     __shared__ uint32_t s_start[kWavesPerBlock][kWave];
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
+    __shared__ __align__(16) int32_t s_q[kWavesPerBlock][kWave * S];  // the query rows of the batch
     const int w = wave_id(), lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
     if (c >= (int64_t)*gv.ncell_dev) return;
@@ -61,8 +63,11 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     for (uint32_t qb = 0; qb < k; qb += kWave) {
         const uint32_t nq = min((uint32_t)kWave, k - qb);
         uint64_t active = nq == (uint32_t)kWave ? ~0ull : ((1ull << nq) - 1ull);
-        int32_t qx[D];
-        load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
+        {
+            int32_t qx[D];
+            load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
+            store_row<D>(s_q[w], lane, qx);
+        }
         uint32_t mycnt = 0;  // lane i: hits of query i
         for (uint64_t e = e0; e < e1 && active; e += kWave) {
             const uint64_t idx = e + lane;
@@ -86,20 +91,28 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                 int32_t y[D];
                 load_row<D>(gv.crd, tv ? q : st, y);
                 const uint64_t tvm = ballot(tv);
-                uint64_t act = uniform64(active), closed = 0;
-                while (act) {
-                    const int qi = ffs64(act);
+                // every open query against the 64 candidates, two queries per
+                // round so their LDS reads overlap: the query row comes from
+                // LDS (one broadcast read), lane qi keeps query qi's hits;
+                // counts and closings are folded in once per step
+                const uint64_t act0 = uniform64(active);
+                uint32_t step_hits = 0;
+                for (uint64_t act = act0; act;) {
+                    const int qa = ffs64(act);
                     act &= act - 1ull;
-                    int32_t p[D];
-#pragma unroll
-                    for (int jj = 0; jj < D; ++jj) p[jj] = readlane(qx[jj], qi);
-                    const uint32_t hits = (uint32_t)popc64(ballot(sqdist_nb<D>(y, p) <= T) & tvm);
-                    const uint32_t cnt = readlane(mycnt, qi) + hits;
-                    mycnt = lane == qi ? cnt : mycnt;
-                    if (cnt >= need) closed |= 1ull << qi;
-                    if constexpr (kStats) ndist += min(tot - t0, (uint32_t)kWave);
+                    const int qb2 = act ? ffs64(act) : qa;
+                    act &= act - 1ull;
+                    int32_t pa[D], pb[D];
+                    load_row<D>(s_q[w], qa, pa);
+                    load_row<D>(s_q[w], qb2, pb);
+                    const uint32_t ha = (uint32_t)popc64(ballot(sqdist_nb<D>(y, pa) <= T) & tvm);
+                    const uint32_t hb = (uint32_t)popc64(ballot(sqdist_nb<D>(y, pb) <= T) & tvm);
+                    step_hits = lane == qa ? ha : step_hits;
+                    step_hits = lane == qb2 ? hb : step_hits;
+                    if constexpr (kStats) ndist += (qb2 != qa ? 2u : 1u) * min(tot - t0, (uint32_t)kWave);
                 }
-                active &= ~closed;
+                mycnt += step_hits;
+                active = act0 & ~ballot(((act0 >> lane) & 1ull) && mycnt >= need);
                 if constexpr (kStats) npts += min(tot - t0, (uint32_t)kWave);
             }
             if constexpr (kStats) ncells += (unsigned long long)min(e1 - e, (uint64_t)kWave);
