@@ -219,7 +219,7 @@ struct Layout {
     uint32_t* count_part;
     uint32_t* cell_min_core;
     uint32_t* list;
-    uint32_t* rank;
+    uint4* rank;
     uint32_t* parent;
     uint32_t* root_min;
     int32_t* cell_label;
@@ -257,7 +257,7 @@ Layout carve(char* base, int64_t n, int D) {
     L.count_part = c.take<uint32_t>(5 * (n / kBlock + 2));
     L.cell_min_core = c.take<uint32_t>(n);
     L.list = c.take<uint32_t>(n);
-    L.rank = c.take<uint32_t>(n);
+    L.rank = c.take<uint4>(n);
     L.parent = c.take<uint32_t>(n);
     L.root_min = c.take<uint32_t>(n);
     L.cell_label = c.take<int32_t>(n);

@@ -278,24 +278,29 @@ struct CoreCellFlag {
 
 __global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell_dev, const uint32_t* core_cnt,
                                                            const uint32_t* excl, uint32_t* list, uint32_t* keys,
-                                                           uint32_t* rank) {
+                                                           uint4* rec) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= (int64_t)*ncell_dev) return;
     const uint32_t cnt = core_cnt[c];
-    rank[c] = kNone;
+    rec[c] = make_uint4(kNone, 0u, 0u, 0u);
     if (cnt) {
         list[excl[c]] = (uint32_t)c;
         keys[excl[c]] = cnt;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, const uint32_t* m, uint32_t* rank) {
+// The merge step's record of each core grid: rank in the visiting order,
+// first row and size of its core set (one load instead of three).
+__global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, const uint32_t* m, CoreOut co,
+                                                      uint4* rec) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < (int64_t)*m) rank[sorted[r]] = (uint32_t)r;
+    if (r >= (int64_t)*m) return;
+    const uint32_t c = sorted[r];
+    rec[c] = make_uint4((uint32_t)r, co.core_begin[c], co.core_cnt[c], 0u);
 }
 
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b,
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* keys_a, uint32_t* keys_b,
                             uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
                             uint32_t** sorted_list, hipStream_t st) {
     *sorted_list = list;
@@ -315,7 +320,7 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
         if (e != hipSuccess) return e;
         *sorted_list = res.vals;
     }
-    if (ncc > 0) rank_kernel<<<dim3(grid_for(ncc)), dim3(kBlock), 0, st>>>(*sorted_list, &c.counts[1], rank);
+    if (ncc > 0) rank_kernel<<<dim3(grid_for(ncc)), dim3(kBlock), 0, st>>>(*sorted_list, &c.counts[1], c, rank);
     return hipGetLastError();
 }
 

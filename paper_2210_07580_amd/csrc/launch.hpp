@@ -173,12 +173,13 @@ hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const ui
                             uint32_t* core_cnt, CoreStats* stats, hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
-// index); rank[g] = position (kNone for non-core grids).  ncc: number of
+// index); rank[g] = (position (kNone for non-core grids), core_begin,
+// core_cnt, 0).  ncc: number of
 // core grids, or an upper bound (then pad_tail: the slots past the device
 // count sort last, under the key 2^count_bits - 1); count_bits: bits of the
 // sort keys.
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint32_t* rank, uint32_t* keys_a, uint32_t* keys_b,
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* keys_a, uint32_t* keys_b,
                             uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
                             uint32_t** sorted_list, hipStream_t st);
 
@@ -194,7 +195,7 @@ struct CellSummary;
 // if the LDS bitmaps do not fit).  n_small: tiny core grids leading the
 // visiting order (-2: as many as the device count says, -1: not ordered).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                        const uint32_t* ldf_list, const uint32_t* rank, int64_t n_core_cells, int64_t n_small,
+                        const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
                         int64_t max_core, int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
                         const CellSummary* sum, hipStream_t st);
 // pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).

@@ -41,7 +41,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
                                                              const uint32_t* __restrict__ ldf,
-                                                             const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
+                                                             const uint4* __restrict__ rank, int64_t r0, int64_t r1,
                                                              const uint32_t* split, uint32_t* parent,
                                                              MergeStats* stats) {
     const int lane = lane_id();
@@ -68,10 +68,11 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
         uint32_t cj = 0, bj = 0, mj = 0;
         if (idx < e1) {
             cj = nei[idx];
-            const uint32_t rj = rank[cj];
+            const uint4 rc = rank[cj];
+            const uint32_t rj = rc.x;
             if (rj != kNone && rj > (uint32_t)r) {
-                bj = co.core_begin[cj];
-                mj = co.core_cnt[cj];
+                bj = rc.y;
+                mj = rc.z;
                 cand = mj <= kSmallSet;
             }
         }
@@ -133,7 +134,7 @@ template <int D, bool kLearned>
 __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
-                                                           const uint32_t* __restrict__ rank, int64_t r0, int64_t r1,
+                                                           const uint4* __restrict__ rank, int64_t r0, int64_t r1,
                                                            const uint32_t* split, uint32_t words, uint32_t* parent,
                                                            MergeStats* stats, Proposal prop) {
     extern __shared__ uint64_t smem[];
@@ -173,10 +174,11 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
         bool cand = false;
         if (idx < e1) {
             cj = nei[idx];
-            const uint32_t rj = rank[cj];
+            const uint4 rc = rank[cj];
+            const uint32_t rj = rc.x;
             if (rj != kNone) {
-                bj = co.core_begin[cj];
-                mj = co.core_cnt[cj];
+                bj = rc.y;
+                mj = rc.z;
                 cand = mj <= kSmallSet || rj > (uint32_t)r;
             }
         }
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
 }
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                        const uint32_t* ldf_list, const uint32_t* rank, int64_t ncc, int64_t n_small, int64_t max_core,
+                        const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
                         int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
                         const CellSummary* sum, hipStream_t st) {
     const Proposal prop{proposal, sum};
