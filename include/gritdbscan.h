@@ -118,6 +118,15 @@ void gd_destroy(gd_ctx *ctx);
  * The call is synchronous: it returns after the results are written.  The
  * caller owns points, labels and core_flags; the context owns its
  * workspace, which grows on demand and is kept for later calls.
+ *
+ * Errors (outputs unspecified, message in gd_last_error): GD_EINVAL for
+ * bad sizes, a non-integer or non-positive eps, minpts < 1 or NULL
+ * pointers; GD_ERANGE for a coordinate that is not a finite integer of
+ * magnitude <= 2^24, or for grid identifiers that would need more than 64
+ * bits (eps too small for the data's extent); GD_EUNSUPPORTED if one grid
+ * holds more than 262144 core points (the merge step keeps each core set
+ * as a bitmap in LDS); GD_ENOMEM if the workspace cannot be allocated or
+ * exceeds GD_OPT_WORKSPACE_LIMIT; GD_EDEVICE for a failed HIP call.
  */
 int dbscan(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps,
            int32_t minpts, int32_t *labels, uint8_t *core_flags, void *stream);
