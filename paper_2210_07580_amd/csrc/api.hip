@@ -187,10 +187,10 @@ struct Plan {
     int64_t max_core;  // largest core set
 };
 
-// Output hash table: 2^bits slots for ncell grids (load <= 1/2).
+// Output hash table: 2^bits slots for ncell grids (load <= 1/4).
 int table_bits(int64_t ncell) {
     int b = 10;
-    while (((int64_t)1 << b) < 2 * ncell) ++b;
+    while (((int64_t)1 << b) < 4 * ncell) ++b;
     return b;
 }
 
@@ -218,6 +218,7 @@ struct Layout {
     uint32_t* side_off;
     uint32_t* count_part;
     uint32_t* cell_min_core;
+    int32_t* tile_mm;
     uint32_t* list;
     uint4* rank;
     uint32_t* parent;
@@ -226,7 +227,7 @@ struct Layout {
     size_t bytes;
 };
 
-Layout carve(char* base, int64_t n, int D) {
+Layout carve(char* base, int64_t n, int D, uint32_t tiles) {
     Layout L{};
     Carve c{base};
     L.keys_a = c.take<uint64_t>(n);  // identifiers in input order (kept for the output pass)
@@ -238,7 +239,7 @@ Layout carve(char* base, int64_t n, int D) {
     L.vals_b = c.take<uint32_t>(2 * n);
     const int64_t big_scan = std::max<int64_t>(n + 1, (int64_t)radix_max_bins<uint32_t>() * radix_tiles(n));
     L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
-    L.partial = c.take<uint64_t>(scan_blocks(big_scan) + 4);
+    L.partial = c.take<uint64_t>(scan_partial_cap(big_scan) + 4);
     L.crd = c.take<int32_t>((int64_t)row_stride(D) * 2 * n);  // sorted rows, then the side area
     L.excl = c.take<uint32_t>(n + 1);
     L.cell_start = c.take<uint32_t>(n + 1);
@@ -256,6 +257,7 @@ Layout carve(char* base, int64_t n, int D) {
     L.side_off = c.take<uint32_t>(n + 1);
     L.count_part = c.take<uint32_t>(5 * (n / kBlock + 2));
     L.cell_min_core = c.take<uint32_t>(n);
+    L.tile_mm = c.take<int32_t>((int64_t)2 * kMaxD * tiles);
     L.list = c.take<uint32_t>(n);
     L.rank = c.take<uint4>(n);
     L.parent = c.take<uint32_t>(n);
@@ -307,10 +309,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     if (n == 0) return GD_OK;
 
     // ---- workspace
-    Layout L = carve(nullptr, n, D);
+    Layout L = carve(nullptr, n, D, tiles);
     int rc = plan ? GD_OK : grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
     if (rc) return rc;
-    L = carve((char*)ctx->arena.p, n, D);
+    L = carve((char*)ctx->arena.p, n, D, tiles);
     Header* Hd = ctx->hdr_dev;
     Header* H = ctx->hdr_host;
 
@@ -338,7 +340,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(fill<unsigned long long>(&ctx->stats_dev->merge[0].pairs,
                                         (int64_t)(sizeof(StatBlock) / sizeof(unsigned long long)), 0ull, st));
     ctx->mark(P_MINMAX, 0);
-    GD_TRY(launch_minmax(b, st));
+    GD_TRY(launch_minmax(b, L.tile_mm, st));
     GD_TRY(launch_layout(b, plan ? plan->key_bits : 64, st));
     ctx->mark(P_MINMAX, 1);
     if (!plan && (rc = readback(ctx, st))) return rc;

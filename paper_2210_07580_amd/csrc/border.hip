@@ -40,12 +40,15 @@ struct alignas(16) HashSlot<uint64_t> {
     int32_t pad;
 };
 
-// Buckets of 64 bytes (8 slots of u32 identifiers, 4 of u64): a lookup
-// reads one bucket with four 16-byte loads and almost always ends there.
+// Buckets of 16 bytes (2 slots of u32 identifiers, 1 of u64) at load <= 1/4:
+// a lookup reads one bucket with a single 16-byte load and almost always ends
+// there.  The table is hit at random addresses, one per lane, so the cost of
+// a lookup is set by the cache lines each load instruction touches, not by
+// the bytes: one load per lookup rather than a wider bucket.
 template <typename K>
-constexpr int kBucketSlots = 64 / (int)sizeof(HashSlot<K>);
+constexpr int kBucketSlots = 16 / (int)sizeof(HashSlot<K>);
 template <typename K>
-constexpr int kBucketShift = sizeof(K) == 4 ? 3 : 2;
+constexpr int kBucketShift = sizeof(K) == 4 ? 1 : 0;
 
 template <typename K>
 __device__ __forceinline__ uint64_t hash_bucket(K key, int bbits) {
@@ -59,40 +62,31 @@ __device__ __forceinline__ uint64_t cas_key(uint64_t* p, uint64_t cmp, uint64_t 
 }
 
 // Look `key` up in one loaded bucket: 1 found (val set), 0 absent (the
-// bucket has an empty slot), -1 look in the next bucket.
-__device__ __forceinline__ int bucket_match(const uint4 (&q)[4], uint32_t key, int32_t& val) {
-    const uint32_t w[16] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x, q[1].y, q[1].z, q[1].w,
-                            q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
-    int r = -1;
-#pragma unroll
-    for (int j = 7; j >= 0; --j) {
-        if (w[2 * j] == ~0u) r = r == 1 ? 1 : 0;
-        if (w[2 * j] == key) {
-            r = 1;
-            val = (int32_t)w[2 * j + 1];
-        }
+// bucket has an empty slot: slots fill in order and are never freed), -1
+// look in the next bucket.
+__device__ __forceinline__ int bucket_match(const uint4& q, uint32_t key, int32_t& val) {
+    if (q.x == key) {
+        val = (int32_t)q.y;
+        return 1;
     }
-    return r;
+    if (q.z == key) {
+        val = (int32_t)q.w;
+        return 1;
+    }
+    return (q.x == ~0u || q.z == ~0u) ? 0 : -1;
 }
-__device__ __forceinline__ int bucket_match(const uint4 (&q)[4], uint64_t key, int32_t& val) {
-    int r = -1;
-#pragma unroll
-    for (int j = 3; j >= 0; --j) {
-        const uint64_t kj = (uint64_t)q[j].x | ((uint64_t)q[j].y << 32);
-        if (kj == ~0ull) r = r == 1 ? 1 : 0;
-        if (kj == key) {
-            r = 1;
-            val = (int32_t)q[j].z;
-        }
+__device__ __forceinline__ int bucket_match(const uint4& q, uint64_t key, int32_t& val) {
+    const uint64_t k = (uint64_t)q.x | ((uint64_t)q.y << 32);
+    if (k == key) {
+        val = (int32_t)q.z;
+        return 1;
     }
-    return r;
+    return k == ~0ull ? 0 : -1;
 }
 
 template <typename K>
-__device__ __forceinline__ void load_bucket(const HashSlot<K>* tab, uint64_t b, uint4 (&q)[4]) {
-    const uint4* p = reinterpret_cast<const uint4*>(tab + (b << kBucketShift<K>));
-#pragma unroll
-    for (int j = 0; j < 4; ++j) q[j] = p[j];
+__device__ __forceinline__ uint4 load_bucket(const HashSlot<K>* tab, uint64_t b) {
+    return *reinterpret_cast<const uint4*>(tab + (b << kBucketShift<K>));
 }
 
 // The all-ones identifier marks an empty slot; a grid with that identifier
@@ -123,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
     }
     const int bbits = bits - kBucketShift<K>;
     const uint64_t bmask = (1ull << bbits) - 1ull;
-    // load <= 1/2, so a free slot is always found
+    // load <= 1/4, so a free slot is always found
     for (uint64_t b = hash_bucket(key, bbits);; b = (b + 1) & bmask) {
         HashSlot<K>* bucket = tab + (b << kBucketShift<K>);
         for (int j = 0; j < kBucketSlots<K>; ++j) {
@@ -140,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
 template <typename K>
 __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
                                                                const HashSlot<K>* __restrict__ tab, int bits) {
-    constexpr int U = 4;
+    constexpr int U = 8;
     if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
@@ -155,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
     for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kBlock) {
         K key[U];
         uint64_t bk[U];
-        uint4 q[U][4];
+        uint4 q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + (int64_t)u * kBlock;
@@ -164,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             bk[u] = hash_bucket(key[u], bbits);
-            if (key[u] != ~K(0)) load_bucket(tab, bk[u], q[u]);
+            if (key[u] != ~K(0)) q[u] = load_bucket(tab, bk[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -178,8 +172,7 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
                 // every identifier of the batch is in the table; the bound only guards the loop
                 for (uint64_t probes = 0; r < 0 && probes < bmask; ++probes) {
                     bk[u] = (bk[u] + 1) & bmask;
-                    load_bucket(tab, bk[u], q[u]);
-                    r = bucket_match(q[u], key[u], val);
+                    r = bucket_match(load_bucket(tab, bk[u]), key[u], val);
                 }
                 if (r != 1) val = kDeferred;
             }

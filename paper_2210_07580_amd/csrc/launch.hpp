@@ -114,7 +114,8 @@ struct GridView {
 __device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) { return g.b.inst[g.ck[c]]; }
 
 // ---- partition.hip
-hipError_t launch_minmax(const Batch& b, hipStream_t st);
+// part: scratch of 2 * kMaxD int32 per point tile.
+hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st);
 // plan_bits: identifier bits a sync-free run sorts (64 otherwise); more raise kErrPlan.
 hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st);
 // Sync-free runs: compare the device counts with the capacities the run was

@@ -2,8 +2,9 @@
 // Algorithm 2) on gfx950, for a batch of instances.
 //
 //   minmax  : mn_j = min over each instance's points (Eq. (1)) and the input
-//             check (finite integers, |x| <= 2^24); one workgroup per tile of
-//             4096 points, LDS + device atomics
+//             check (finite integers, |x| <= 2^24); one workgroup per point
+//             tile leaves a record per tile, one workgroup per instance
+//             folds them
 //   layout  : per instance, the bit width of each identifier field; the
 //             instance id goes above the widest instance's fields
 //   keys    : identifiers of Eq. (1), exact (see grid_coord), packed into one
@@ -92,23 +93,22 @@ __device__ __forceinline__ void minmax_tile(Inst& I, int64_t lo, int64_t hi, int
             c = max(c, __shfl_xor(c, o));
         }
         if (lane_id() == 0) {
-            atomicMin(&smn[j], a);
-            atomicMax(&smx[j], c);
+            smn[wave_id() * kMaxD + j] = a;
+            smx[wave_id() * kMaxD + j] = c;
         }
     }
     if (ballot(bad) && lane_id() == 0) atomicOr(&I.err, kErrNotInteger);
 }
 
-__global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
-    __shared__ int smn[kMaxD], smx[kMaxD];
+// Each workgroup leaves its tile's minima and maxima in part (one 64-byte
+// record per tile, plain stores: a few thousand workgroups updating the same
+// two words with device atomics serialise on them).
+__global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b, int32_t* __restrict__ part) {
+    constexpr int kWaves = kBlock / kWave;
+    __shared__ int smn[kWaves * kMaxD], smx[kWaves * kMaxD];
     const int k = tile_instance(b, blockIdx.x);
     Inst& I = const_cast<Inst&>(b.inst[k]);
     const int d = I.d;
-    if (threadIdx.x < kMaxD) {
-        smn[threadIdx.x] = INT_MAX;
-        smx[threadIdx.x] = INT_MIN;
-    }
-    __syncthreads();
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
     const int64_t hi = min(I.n, lo + b.tile_pts);
     switch (d) {
@@ -123,14 +123,88 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b) {
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)d) {
-        atomicMin(&I.mn[threadIdx.x], smn[threadIdx.x]);
-        atomicMax(&I.mx[threadIdx.x], smx[threadIdx.x]);
+        const int j = threadIdx.x;
+        int a = smn[j], c = smx[j];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            a = min(a, smn[w * kMaxD + j]);
+            c = max(c, smx[w * kMaxD + j]);
+        }
+        int32_t* rec = part + (int64_t)blockIdx.x * 2 * kMaxD;
+        rec[j] = a;
+        rec[kMaxD + j] = c;
     }
 }
 
-hipError_t launch_minmax(const Batch& b, hipStream_t st) {
+// One workgroup per instance folds its tiles' records into mn and mx.
+__global__ __launch_bounds__(kBlock) void minmax_finish_kernel(Batch b, const int32_t* __restrict__ part) {
+    constexpr int kWaves = kBlock / kWave;
+    __shared__ int smn[kWaves * kMaxD], smx[kWaves * kMaxD];
+    Inst& I = const_cast<Inst&>(b.inst[blockIdx.x]);
+    const int d = I.d;
+    const uint32_t nt = (uint32_t)((I.n + b.tile_pts - 1) / b.tile_pts);
+    // thread t reads quarter q = t % 4 of records t / 4, t / 4 + 64, ...
+    // (quarters 0-1: minima, 2-3: maxima), eight records in flight
+    const int q = threadIdx.x & 3;
+    const bool is_min = q < 2;
+    int4 acc = is_min ? make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX) : make_int4(INT_MIN, INT_MIN, INT_MIN, INT_MIN);
+    const int4* rec = reinterpret_cast<const int4*>(part + (int64_t)I.tile0 * 2 * kMaxD) + q;
+    constexpr uint32_t kStep = kBlock / 4;
+    for (uint32_t t0 = threadIdx.x >> 2; t0 < nt; t0 += 8 * kStep) {
+        int4 r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t t = t0 + u * kStep;
+            r[u] = t < nt ? rec[(int64_t)t * 4] : acc;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (is_min) {
+                acc.x = min(acc.x, r[u].x); acc.y = min(acc.y, r[u].y);
+                acc.z = min(acc.z, r[u].z); acc.w = min(acc.w, r[u].w);
+            } else {
+                acc.x = max(acc.x, r[u].x); acc.y = max(acc.y, r[u].y);
+                acc.z = max(acc.z, r[u].z); acc.w = max(acc.w, r[u].w);
+            }
+        }
+    }
+    // lanes with the same quarter: xor over 4, 8, 16, 32 keeps q
+#pragma unroll
+    for (int o = 4; o < kWave; o <<= 1) {
+        const int4 b = make_int4(__shfl_xor(acc.x, o), __shfl_xor(acc.y, o), __shfl_xor(acc.z, o), __shfl_xor(acc.w, o));
+        if (is_min) {
+            acc.x = min(acc.x, b.x); acc.y = min(acc.y, b.y); acc.z = min(acc.z, b.z); acc.w = min(acc.w, b.w);
+        } else {
+            acc.x = max(acc.x, b.x); acc.y = max(acc.y, b.y); acc.z = max(acc.z, b.z); acc.w = max(acc.w, b.w);
+        }
+    }
+    if (lane_id() < 4) {
+        int* dst = (is_min ? smn : smx) + wave_id() * kMaxD + (q & 1) * 4;
+        dst[0] = acc.x;
+        dst[1] = acc.y;
+        dst[2] = acc.z;
+        dst[3] = acc.w;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)d) {
+        const int j = threadIdx.x;
+        int a = smn[j], c = smx[j];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            a = min(a, smn[w * kMaxD + j]);
+            c = max(c, smx[w * kMaxD + j]);
+        }
+        I.mn[j] = a;
+        I.mx[j] = c;
+    }
+}
+
+hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st) {
     if (b.tiles == 0) return hipSuccess;
-    minmax_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b);
+    minmax_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, part);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    minmax_finish_kernel<<<dim3(b.count), dim3(kBlock), 0, st>>>(b, part);
     return hipGetLastError();
 }
 
@@ -331,8 +405,12 @@ hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hip
 template <typename K>
 struct KeyChange {
     const K* k;
-    int64_t n;
-    __device__ uint32_t operator()(int64_t i) const { return i < n && (i == 0 || k[i] != k[i - 1]); }
+    // called for i < n only; both loads unconditional (no branch per element)
+    __device__ uint32_t operator()(int64_t i) const {
+        const K a = k[i];
+        const K b = k[i > 0 ? i - 1 : 0];
+        return (uint32_t)((i == 0) | (a != b));
+    }
 };
 
 // Runs of equal identifiers, written from the scan of "identifier changes
@@ -344,11 +422,10 @@ struct CellWriter {
     uint32_t* cell_start;
     int32_t* ck;
     int64_t ck_stride;
-    __device__ void operator()(int64_t s, uint32_t ex) const {
-        const K key = skeys[s];
-        const bool first = s == 0 || skeys[s - 1] != key;
-        const uint32_t c = ex + (first ? 1u : 0u) - 1u;
+    __device__ void operator()(int64_t s, uint32_t ex, uint32_t first) const {
+        const uint32_t c = ex + first - 1u;
         if (first) {
+            const K key = skeys[s];
             cell_start[c] = (uint32_t)s;
             const int ishift = b.hdr->inst_shift;
             int k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
@@ -375,7 +452,7 @@ template <typename K>
 hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st) {
     (void)excl;
-    return scan_apply<uint32_t>(KeyChange<K>{skeys, b.n}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
+    return scan_apply<uint32_t>(KeyChange<K>{skeys}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
                                 &b.hdr->ncell, partial, st);
 }
 template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,

@@ -36,7 +36,7 @@ inline int64_t radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile
 inline int64_t radix_scratch_words(int64_t n) {
     const int64_t t = radix_tiles(n);
     constexpr int64_t bins = 1 << 8;
-    return 2 * bins * t + scan_blocks(bins * t) + 4;
+    return 2 * bins * t + scan_partial_cap(bins * t) + 4;
 }
 
 template <typename K>
@@ -50,13 +50,18 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     const int w = wave_id();
     const uint32_t mask = (uint32_t)bins - 1u;
-#pragma unroll 4
+    // all loads of the tile in flight before the first count
+    K k[kRadixItems];
+    const bool full = base + kRadixTile <= n;
+#pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (i < n) {
-            const uint32_t dg = (uint32_t)(keys[i] >> shift) & mask;
-            atomicAdd(&h[w][dg], 1u);
-        }
+        k[r] = (full || i < n) ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        if (full || i < n) atomicAdd(&h[w][(uint32_t)(k[r] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < bins; t += kBlock) {
@@ -108,12 +113,20 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
         const int li = w * kPerWave + it * kWave + lane;
         const bool valid = li < tile_n;
         const uint32_t dg = (uint32_t)(k[it] >> shift) & mask;
-        uint64_t peers = ballot(valid);
-        for (int b = 0; b < rbits; ++b) {
-            const bool bit = (dg >> b) & 1u;
-            const uint64_t m = ballot(bit);
-            peers &= bit ? m : ~m;
+        // lanes with the same digit: one ballot per digit bit; the digit bits
+        // above rbits are 0 in every lane and leave the mask unchanged.  The
+        // halves are kept as 32-bit words and combined as p & ~(m ^ x), which
+        // gfx950 evaluates with three-input bit operations.
+        const uint64_t vm = ballot(valid);
+        uint32_t plo = (uint32_t)vm, phi = (uint32_t)(vm >> 32);
+#pragma unroll
+        for (int b = 0; b < radix_max_bits<K>(); ++b) {
+            const uint32_t x = (uint32_t)(((int32_t)(dg << (31 - b))) >> 31);  // all ones where bit b is set
+            const uint64_t m = ballot(x != 0u);
+            plo &= ~((uint32_t)m ^ x);
+            phi &= ~((uint32_t)(m >> 32) ^ x);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = valid ? wcnt[w][dg] : 0u;
         wave_sync();
         const uint32_t rank = before + (uint32_t)popc64(peers & lt);

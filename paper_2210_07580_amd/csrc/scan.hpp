@@ -7,64 +7,125 @@
 
 namespace gd {
 
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;  // 4096 elements per workgroup
+// Scans of more than kScanMid elements take 16 elements per thread (4096 per
+// workgroup); shorter ones 4 (1024 per workgroup), so that a scan over the
+// grids still spreads over enough workgroups to hide the load latency.
+constexpr int kScanItemsBig = 16;
+constexpr int kScanItemsMid = 4;
+constexpr int64_t kScanMid = 1 << 21;
 
-inline int64_t scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+inline int scan_items(int64_t n) { return n > kScanMid ? kScanItemsBig : kScanItemsMid; }
+inline int64_t scan_blocks(int64_t n) {
+    const int64_t tile = (int64_t)kBlock * scan_items(n);
+    return (n + tile - 1) / tile;
+}
+// Partials needed by any scan of at most n elements.
+inline int64_t scan_partial_cap(int64_t n) {
+    const int64_t mid = n < kScanMid ? n : kScanMid;
+    return (mid + kBlock * kScanItemsMid - 1) / (kBlock * kScanItemsMid) + scan_blocks(n);
+}
 
-template <typename T, typename F>
+// f over the workgroup's tile, element base + r * kBlock + threadIdx.x in
+// v[r] (0 past n): every load of the tile is issued before the first use.
+template <int kItems, typename T, typename F>
+__device__ __forceinline__ void scan_load(F& f, int64_t n, int64_t base, T (&v)[kItems]) {
+    if (base + (int64_t)kBlock * kItems <= n) {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) v[r] = f(base + (int64_t)r * kBlock + threadIdx.x);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+            v[r] = i < n ? f(i) : T(0);
+        }
+    }
+}
+
+template <typename T, int kItems, typename F>
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(F f, int64_t n, T* partial) {
     __shared__ T wsum[kWavesPerBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T v[kItems];
+    scan_load<kItems>(f, n, (int64_t)blockIdx.x * kBlock * kItems, v);
     T s = 0;
-#pragma unroll 4
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (i < n) s += f(i);
-    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) s += v[r];
     s = wave_sum(s);
     if (lane_id() == 0) wsum[wave_id()] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         T t = 0;
+#pragma unroll
         for (int w = 0; w < kWavesPerBlock; ++w) t += wsum[w];
         partial[blockIdx.x] = t;
     }
 }
 
-// Output of a scan: store the exclusive prefix (or hand it to a functor).
+// Output of a scan: store the exclusive prefix (or hand it to a functor,
+// which also gets the element's own value v = f(i)).
 template <typename T>
 struct StoreOut {
     T* out;
-    __device__ void operator()(int64_t i, T ex) const { out[i] = ex; }
+    __device__ void operator()(int64_t i, T ex, T) const { out[i] = ex; }
 };
 
 // Each workgroup sums the totals of the tiles before it (a few thousand
 // values at most, from L2) instead of waiting for a separate pass to scan
-// them; the last workgroup writes the grand total.
-template <typename T, typename F, typename O>
+// them; the last workgroup writes the grand total.  The tile is read with
+// coalesced loads, transposed through LDS so that each thread scans kItems
+// consecutive elements (one workgroup scan per tile), and transposed back
+// for coalesced output.  LDS rows are kItems + 1 long so that neither
+// direction conflicts on banks.
+template <typename T, int kItems, typename F, typename O>
 __global__ __launch_bounds__(kBlock) void scan_down_kernel(F f, int64_t n, const T* partial, O o, T* total) {
+    constexpr int kRow = kItems + 1;
+    __shared__ T tile[kBlock * kRow];
     __shared__ T wsum[kWavesPerBlock];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kItems;
+    T v[kItems];
+    scan_load<kItems>(f, n, base, v);
+    T acc[8] = {};
+    for (int64_t b0 = t; b0 < (int64_t)blockIdx.x; b0 += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t b = b0 + (int64_t)u * kBlock;
+            if (b < (int64_t)blockIdx.x) acc[u] += partial[b];
+        }
+    }
     T carry = 0;
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) carry += partial[b];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) carry += acc[u];
     carry = wave_sum(carry);
     if (lane_id() == 0) wsum[wave_id()] = carry;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int p = r * kBlock + t;
+        tile[(p / kItems) * kRow + p % kItems] = v[r];
+    }
     __syncthreads();
     carry = 0;
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) carry += wsum[w];
-    __syncthreads();
-    for (int r = 0; r < kScanItems; ++r) {
-        const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (base + (int64_t)r * kBlock >= n) break;  // uniform across the block
-        T v = i < n ? f(i) : T(0);
-        T tot;
-        T ex = block_excl_scan(v, wsum, tot);
-        if (i < n) o(i, carry + ex);
-        carry += tot;
+    T loc[kItems];
+    T run = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        loc[k] = run;
+        run += tile[t * kRow + k];
     }
-    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = carry;
+    __syncthreads();  // wsum is reused by the workgroup scan
+    T tot;
+    const T ex = carry + block_excl_scan(run, wsum, tot);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) tile[t * kRow + k] = ex + loc[k];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const int p = r * kBlock + t;
+        const int64_t i = base + p;
+        if (i < n) o(i, tile[(p / kItems) * kRow + p % kItems], v[r]);
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && t == 0) *total = carry + tot;
 }
 
 // Short scans (up to kSingleScanMax elements) run in one workgroup of 1024
@@ -102,7 +163,7 @@ __global__ __launch_bounds__(kSingleScanThreads) void scan_single_kernel(F f, in
         T acc = carry + off + incl - run;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (i0 + k < n) o(i0 + k, acc);
+            if (i0 + k < n) o(i0 + k, acc, v[k]);
             acc += v[k];
         }
         carry += tot;
@@ -111,7 +172,7 @@ __global__ __launch_bounds__(kSingleScanThreads) void scan_single_kernel(F f, in
 }
 
 // o(i, sum_{k < i} f(k)) for 0 <= i < n; *total = sum of all (device).
-// `partial` needs scan_blocks(n) elements.
+// `partial` needs scan_blocks(n) elements (scan_partial_cap(m) covers every n <= m).
 template <typename T, typename F, typename O>
 hipError_t scan_apply(F f, int64_t n, O o, T* total, T* partial, hipStream_t st) {
     const int64_t nb = scan_blocks(n);
@@ -122,8 +183,13 @@ hipError_t scan_apply(F f, int64_t n, O o, T* total, T* partial, hipStream_t st)
         scan_single_kernel<T, F, O><<<1, kSingleScanThreads, 0, st>>>(f, n, o, total);
         return hipGetLastError();
     }
-    scan_reduce_kernel<T, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
-    scan_down_kernel<T, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o, total);
+    if (scan_items(n) == kScanItemsBig) {
+        scan_reduce_kernel<T, kScanItemsBig, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
+        scan_down_kernel<T, kScanItemsBig, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o, total);
+    } else {
+        scan_reduce_kernel<T, kScanItemsMid, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
+        scan_down_kernel<T, kScanItemsMid, F, O><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, o, total);
+    }
     return hipGetLastError();
 }
 
