@@ -1,8 +1,8 @@
 // Non-empty neighbouring grids query (Section 4.2.2, Algorithm 3, Eq. (2)).
 //
-// One thread per grid g walks the grid tree level by level (after the
-// exact match of g's instance at level 0).  At level l it
-// visits the children whose key k satisfies |k - g_l| <= w, accumulating
+// Each grid g walks the grid tree level by level (after the exact match of
+// g's instance at level 0), its first levels split over lanes.  At level l
+// it visits the children whose key k satisfies |k - g_l| <= w, accumulating
 //   offset += max(|k - g_l| - 1, 0)^2                       (Eq. (2))
 // and drops a node once offset >= d.  The paper scans the fixed window
 // +-ceil(sqrt(d)) and prunes afterwards; here the window shrinks with the
@@ -47,16 +47,60 @@ __device__ __forceinline__ void walk(const TreeView& t, const int32_t (&g)[D + 1
     }
 }
 
-// Full query: find the instance node at level 0, then walk levels 1..D.
-template <int D, typename Emit>
-__device__ __forceinline__ void query(const TreeView& t, const int32_t (&g)[D + 1], int dk, Emit& emit) {
-    const int32_t* key0 = t.key[0];
-    uint32_t a = 0, b = t.level_count[0];
-    while (a < b) {
-        const uint32_t m = (a + b) >> 1;
-        if (key0[m] < g[0]) a = m + 1; else b = m;
+// With few grids, each grid's walk is split over kSplit = 8 consecutive
+// lanes: lane p takes the level-1 children whose key is g_1 + p - 3.  The
+// level-1 window is 1 + isqrt(d - 1) <= 3 for d <= 8, so offsets -3..+3
+// cover it (lane 7 has nothing to do).  The tree walk is a chain of
+// dependent loads, and one thread per grid leaves most of the chip idle when
+// the grids number in the tens of thousands; with millions of grids one
+// thread per grid is already enough and the split would only add the extra
+// counting walk of the fill pass.  (Splitting the next level too repeats the
+// upper searches in every lane and costs more than it saves.)  Lanes follow
+// the tree order, so the lists come out as one walk would emit them.
+constexpr int kSplit = 8;
+constexpr int64_t kSplitMaxGrids = 1 << 20;
+
+inline int nei_lanes(int64_t ncell) { return ncell <= kSplitMaxGrids ? kSplit : 1; }
+
+__device__ __forceinline__ int level_window(int budget) {
+    int w = 0;
+    while ((w + 1) * (w + 1) <= budget - 1) ++w;
+    return w + 1;
+}
+
+// First index in [lo, hi) whose key is >= want.
+__device__ __forceinline__ uint32_t lower_key(const int32_t* __restrict__ key, uint32_t lo, uint32_t hi, int32_t want) {
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (key[m] < want) lo = m + 1; else hi = m;
     }
-    walk<D, 1>(t, g, dk, t.child[0][a], t.child[0][a + 1], 0, emit);
+    return lo;
+}
+
+// The neighbours below the level-1 children with key g_1 + delta,
+// delta in [d_lo, d_hi].
+template <int D, typename Emit>
+__device__ __forceinline__ void query_part(const TreeView& t, const int32_t (&g)[D + 1], int dk, int d_lo, int d_hi,
+                                           Emit& emit) {
+    const int w1 = level_window(dk);
+    d_lo = d_lo < -w1 ? -w1 : d_lo;
+    d_hi = d_hi > w1 ? w1 : d_hi;
+    if (d_lo > d_hi) return;
+    const uint32_t a0 = lower_key(t.key[0], 0, t.level_count[0], g[0]);
+    const uint32_t hi1 = t.child[0][a0 + 1];
+    const int32_t* __restrict__ key1 = t.key[1];
+    for (uint32_t a = lower_key(key1, t.child[0][a0], hi1, g[1] + d_lo); a < hi1; ++a) {
+        const int d1 = key1[a] - g[1];
+        if (d1 > d_hi) break;
+        const int gap = (d1 < 0 ? -d1 : d1) - 1;
+        const int o = gap > 0 ? gap * gap : 0;
+        if (o >= dk) continue;
+        if constexpr (D == 1) {
+            emit(a, o);
+        } else {
+            walk<D, 2>(t, g, dk, t.child[1][a], t.child[1][a + 1], o, emit);
+        }
+    }
 }
 
 template <int D>
@@ -65,25 +109,45 @@ __device__ __forceinline__ void load_grid(const GridView& gv, int64_t c, int32_t
     for (int j = 0; j <= D; ++j) g[j] = gv.ck[(int64_t)j * gv.ck_stride + c];
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts) {
-    __shared__ uint32_t sc[D][kBlock];
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)*gv.ncell_dev) return;
-#pragma unroll
-    for (int o = 0; o < D; ++o) sc[o][threadIdx.x] = 0;
+// This lane's part of grid c's neighbours, counted per offset value into
+// cnt[o][threadIdx.x] (LDS).
+template <int D, int P>
+__device__ __forceinline__ void count_part(const GridView& gv, const TreeView& t, int64_t c, int p,
+                                           uint32_t (*cnt)[kBlock]) {
     int32_t g[D + 1];
     load_grid<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
     auto emit = [&](uint32_t a, int o) {
-        if (a != (uint32_t)c) sc[o][threadIdx.x] += 1;
+        if (a != (uint32_t)c) cnt[o][threadIdx.x] += 1;
     };
-    query<D>(t, g, dk, emit);
-#pragma unroll
-    for (int o = 0; o < D; ++o) off_counts[c * D + o] = sc[o][threadIdx.x];
+    query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
 }
 
-template <int D>
+template <int D, int P>
+__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts) {
+    __shared__ uint32_t sc[D][kBlock];
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t c = gt / P;
+    const int p = (int)(gt % P);
+    const bool valid = c < (int64_t)*gv.ncell_dev;
+    if (P == 1 && !valid) return;
+#pragma unroll
+    for (int o = 0; o < D; ++o) sc[o][threadIdx.x] = 0;
+    if (valid) count_part<D, P>(gv, t, c, p, sc);
+#pragma unroll
+    for (int o = 0; o < D; ++o) {
+        uint32_t v = sc[o][threadIdx.x];
+        // sum over the grid's lanes (every lane takes part in the shuffles)
+#pragma unroll
+        for (int s = 1; s < P; s <<= 1) v += __shfl_xor(v, s);
+        if (valid && p == 0) off_counts[c * D + o] = v;
+    }
+}
+
+// The list of grid c holds its offset-0 neighbours, then offset 1, ...; within
+// one offset value the lanes' parts follow each other in lane order.  With a
+// split, each lane first counts its part again to find where its entries go.
+template <int D, int P>
 __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView t, const uint32_t* __restrict__ off_counts,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
                                                           uint64_t capacity) {
@@ -93,14 +157,34 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&gv.b.hdr->err, kErrNeiOverflow);
         return;
     }
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= ncell) return;
-    uint32_t acc = 0;
+    const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t c = gt / P;
+    const int p = (int)(gt % P);
+    const bool valid = c < ncell;
+    if (P == 1 && !valid) return;
+    if constexpr (P > 1) {
+#pragma unroll
+        for (int o = 0; o < D; ++o) pos[o][threadIdx.x] = 0;
+        if (valid) count_part<D, P>(gv, t, c, p, pos);
+    }
+    uint32_t run = 0;
 #pragma unroll
     for (int o = 0; o < D; ++o) {
-        pos[o][threadIdx.x] = acc;
-        acc += off_counts[c * D + o];
+        uint32_t mine = 0, incl = 0;
+        if constexpr (P > 1) {
+            // inclusive sum over the grid's lanes up to this one
+            mine = pos[o][threadIdx.x];
+            incl = mine;
+#pragma unroll
+            for (int s = 1; s < P; s <<= 1) {
+                const uint32_t v = __shfl_up(incl, s, P);
+                if (p >= s) incl += v;
+            }
+        }
+        pos[o][threadIdx.x] = run + (incl - mine);
+        run += valid ? off_counts[c * D + o] : 0u;
     }
+    if (!valid) return;
     const uint64_t base = nei_off[c];
     int32_t g[D + 1];
     load_grid<D>(gv, c, g);
@@ -112,12 +196,17 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
             nei[base + k] = a;
         }
     };
-    query<D>(t, g, dk, emit);
+    query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
 }
 
 hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    GD_DISPATCH_D(g.D, (nei_count_kernel<D><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, t, off_counts)));
+    if (nei_lanes(g.ncell) > 1) {
+        GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
+                               g, t, off_counts)));
+    } else {
+        GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, t, off_counts)));
+    }
     return hipGetLastError();
 }
 
@@ -150,8 +239,13 @@ hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uin
 hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint64_t* nei_off,
                            uint32_t* nei, uint64_t capacity, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    GD_DISPATCH_D(g.D, (nei_fill_kernel<D><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, t, off_counts,
-                                                                                               nei_off, nei, capacity)));
+    if (nei_lanes(g.ncell) > 1) {
+        GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
+                               g, t, off_counts, nei_off, nei, capacity)));
+    } else {
+        GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                               g, t, off_counts, nei_off, nei, capacity)));
+    }
     return hipGetLastError();
 }
 
