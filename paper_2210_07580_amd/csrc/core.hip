@@ -35,10 +35,50 @@ __device__ __forceinline__ uint32_t sqdist_nb(const int32_t (&a)[D], const int32
     return (uint32_t)dd;
 }
 
-template <int D, bool kStats>
+// Packed form for small eps: points of neighbouring grids differ by less
+// than (2 + sqrt(d - 1)) eps / sqrt(d) <= 2.13 eps per coordinate (the key
+// offsets of Eq. (2) bound |k_j - k'_j| by 1 + sqrt(d - 1)), so for
+// eps <= kPackedEpsMax every difference fits a signed 16-bit half and the
+// squared distance (at most d (2.13 eps)^2 < 2^32) is exact in 32 bits.  Two
+// coordinates share a word (low 16 bits of each; a 16-bit difference of the
+// low halves is the exact difference when that is below 2^15), one packed
+// subtraction and one two-term dot product handle both; an odd last
+// coordinate stays a full word.
+constexpr int64_t kPackedEpsMax = 10000;
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+template <int D>
+constexpr int packed_words() { return (D + 1) / 2; }
+
+template <int D>
+__device__ __forceinline__ void pack_row(const int32_t (&x)[D], int32_t (&p)[packed_words<D>()]) {
+#pragma unroll
+    for (int w = 0; w < D / 2; ++w) p[w] = (int32_t)(((uint32_t)x[2 * w] & 0xFFFFu) | ((uint32_t)x[2 * w + 1] << 16));
+    if constexpr (D & 1) p[D / 2] = x[D - 1];
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t sqdist_pk(const int32_t (&a)[packed_words<D>()],
+                                              const int32_t (&b)[packed_words<D>()]) {
+    int32_t acc = 0;
+#pragma unroll
+    for (int w = 0; w < D / 2; ++w) {
+        const short2_t t = __builtin_bit_cast(short2_t, a[w]) - __builtin_bit_cast(short2_t, b[w]);
+        acc = __builtin_amdgcn_sdot2(t, t, acc, false);
+    }
+    if constexpr (D & 1) {
+        const int32_t t = a[D / 2] - b[D / 2];
+        acc = __mul24(t, t) + acc;
+    }
+    return (uint32_t)acc;
+}
+
+template <int D, bool kStats, bool kPacked>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
+    constexpr int PW = packed_words<D>();
     constexpr int S = row_stride(D);
     __shared__ uint32_t s_start[kWavesPerBlock][kWave];
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
@@ -46,18 +86,20 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     const int w = wave_id(), lane = lane_id();
     const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
     if (c >= (int64_t)*gv.ncell_dev) return;
+    // every load that depends on c alone is issued before the first use
     const Inst& I = cell_inst(gv, c);
     const uint32_t st = gv.cell_start[c];
-    const uint32_t k = gv.cell_start[c + 1] - st;
+    const uint32_t en = gv.cell_start[c + 1];
+    const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     const uint32_t minpts = (uint32_t)I.minpts;
+    const uint32_t T = I.T;
+    const uint32_t k = en - st;
     if (k >= minpts) {
         for (uint32_t i = lane; i < k; i += kWave) core[st + i] = 1;
         if (lane == 0) core_cnt[c] = k;
         return;
     }
     const uint32_t need = minpts - k;
-    const uint32_t T = I.T;
-    const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     unsigned long long ndist = 0, npts = 0, ncells = 0;
     uint32_t m = 0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
@@ -66,7 +108,13 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
         {
             int32_t qx[D];
             load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
-            store_row<D>(s_q[w], lane, qx);
+            if constexpr (kPacked) {
+                int32_t pq[PW];
+                pack_row<D>(qx, pq);
+                store_row<PW>(s_q[w], lane, pq);
+            } else {
+                store_row<D>(s_q[w], lane, qx);
+            }
         }
         uint32_t mycnt = 0;  // lane i: hits of query i
         for (uint64_t e = e0; e < e1 && active; e += kWave) {
@@ -80,16 +128,26 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
             s_start[w][lane] = cs;
             s_excl[w][lane] = incl - cn;
             wave_sync();
-            for (uint32_t t0 = 0; t0 < tot && active; t0 += kWave) {
-                const uint32_t t = t0 + lane;
-                const bool tv = t < tot;
+            // row of flat candidate t (t < tot): binary search over the
+            // chunk's 64 grids
+            auto cand_row = [&](uint32_t t) -> uint32_t {
                 int j = 0;
 #pragma unroll
                 for (int step = 32; step > 0; step >>= 1)
                     if (s_excl[w][j + step] <= t) j += step;
-                const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
-                int32_t y[D];
-                load_row<D>(gv.crd, tv ? q : st, y);
+                return s_start[w][j] + (t - s_excl[w][j]);
+            };
+            int32_t y[D];
+            load_row<D>(gv.crd, (uint32_t)lane < tot ? cand_row(lane) : st, y);
+            for (uint32_t t0 = 0; t0 < tot && active; t0 += kWave) {
+                const uint32_t t = t0 + lane;
+                const bool tv = t < tot;
+                // the next step's candidates load while this step is evaluated
+                // (the slowest grids take dozens of steps one after another)
+                int32_t yn[D];
+                load_row<D>(gv.crd, t + kWave < tot ? cand_row(t + kWave) : st, yn);
+                int32_t yp[PW];
+                if constexpr (kPacked) pack_row<D>(y, yp);
                 const uint64_t tvm = ballot(tv);
                 // every open query against the 64 candidates, two queries per
                 // round so their LDS reads overlap: the query row comes from
@@ -102,11 +160,22 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                     act &= act - 1ull;
                     const int qb2 = act ? ffs64(act) : qa;
                     act &= act - 1ull;
-                    int32_t pa[D], pb[D];
-                    load_row<D>(s_q[w], qa, pa);
-                    load_row<D>(s_q[w], qb2, pb);
-                    const uint32_t ha = (uint32_t)popc64(ballot(sqdist_nb<D>(y, pa) <= T) & tvm);
-                    const uint32_t hb = (uint32_t)popc64(ballot(sqdist_nb<D>(y, pb) <= T) & tvm);
+                    uint32_t da, db;
+                    if constexpr (kPacked) {
+                        int32_t pa[PW], pb[PW];
+                        load_row<PW>(s_q[w], qa, pa);
+                        load_row<PW>(s_q[w], qb2, pb);
+                        da = sqdist_pk<D>(yp, pa);
+                        db = sqdist_pk<D>(yp, pb);
+                    } else {
+                        int32_t pa[D], pb[D];
+                        load_row<D>(s_q[w], qa, pa);
+                        load_row<D>(s_q[w], qb2, pb);
+                        da = sqdist_nb<D>(y, pa);
+                        db = sqdist_nb<D>(y, pb);
+                    }
+                    const uint32_t ha = (uint32_t)popc64(ballot(da <= T) & tvm);
+                    const uint32_t hb = (uint32_t)popc64(ballot(db <= T) & tvm);
                     step_hits = lane == qa ? ha : step_hits;
                     step_hits = lane == qb2 ? hb : step_hits;
                     if constexpr (kStats) ndist += (qb2 != qa ? 2u : 1u) * min(tot - t0, (uint32_t)kWave);
@@ -114,6 +183,8 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                 mycnt += step_hits;
                 active = act0 & ~ballot(((act0 >> lane) & 1ull) && mycnt >= need);
                 if constexpr (kStats) npts += min(tot - t0, (uint32_t)kWave);
+#pragma unroll
+                for (int j = 0; j < D; ++j) y[j] = yn[j];
             }
             if constexpr (kStats) ncells += (unsigned long long)min(e1 - e, (uint64_t)kWave);
             wave_sync();
@@ -134,15 +205,19 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
 }
 
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, hipStream_t st) {
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
+    const bool packed = max_eps <= kPackedEpsMax;
     if (stats) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core,
-                                                                                            core_cnt, stats)));
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
+    } else if (packed) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
     } else {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, nei_off, nei, core,
-                                                                                             core_cnt, stats)));
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
     }
     return hipGetLastError();
 }

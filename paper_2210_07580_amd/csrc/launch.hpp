@@ -111,7 +111,10 @@ struct GridView {
     int64_t ck_stride;
 };
 
-__device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) { return g.b.inst[g.ck[c]]; }
+// The instance of grid c (a single-instance call skips the identifier load).
+__device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) {
+    return g.b.inst[g.b.count == 1 ? 0 : g.ck[c]];
+}
 
 // ---- partition.hip
 // part: scratch of 2 * kMaxD int32 per point tile.
@@ -169,9 +172,10 @@ struct CoreStats {
     unsigned long long points;  // candidate points streamed (once per batch of 64 queries)
     unsigned long long grids;   // neighbour grids opened
 };
-// Core flags (sorted order) and m_i per grid.
+// Core flags (sorted order) and m_i per grid.  max_eps: the largest eps in
+// the batch (small ones allow packed 16-bit coordinate differences).
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, hipStream_t st);
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = (position (kNone for non-core grids), core_begin,

@@ -48,9 +48,12 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     const int64_t r = r0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (r >= r1 || r >= (int64_t)co.counts[1] || (split && r >= (int64_t)*split)) return;
     const uint32_t ci = ldf[r];
+    // every load that depends on ci alone is issued before the first use
     const uint32_t T = cell_inst(gv, ci).T;
-    const uint32_t bi = co.core_begin[ci];
-    const uint32_t mi = co.core_cnt[ci];
+    const uint4 own = rank[ci];
+    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    const uint32_t bi = own.y;
+    const uint32_t mi = own.z;
     if (mi > kSmallSet) return;
     int32_t pi[kSmallSet][D];
 #pragma unroll
@@ -61,7 +64,6 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
         for (int k = 0; k < D; ++k) pi[a][k] = uniform((uint32_t)a < mi ? t[k] : 0);
     }
     unsigned long long n_pairs = 0, n_yes = 0, n_dist = 0, n_pts = 0;
-    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
         bool cand = false;
@@ -154,10 +156,13 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
     const int64_t r = (split ? (int64_t)*split : r0) + (int64_t)blockIdx.x * wpb + w;
     if (r >= r1 || r >= (int64_t)co.counts[1]) return;
     const uint32_t ci = ldf[r];
+    // every load that depends on ci alone is issued before the first use
     const Inst& I = cell_inst(gv, ci);
+    const uint4 own = rank[ci];
+    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     const uint32_t T = I.T;
     const double eps = (double)I.eps;
-    PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
+    PointSet si{co.ccrd, own.y, own.z, smem + (int64_t)w * 2 * words, 0};
     if (si.m <= kSmallSet) return;
     if (si.m > 64u * words) {  // larger than the LDS bitmaps this launch was given
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
@@ -166,7 +171,6 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
     si.words = (si.m + kWave - 1) / kWave;
     PointSet sj{co.ccrd, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
-    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     uint32_t ri = uf_find(parent, ci);
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;

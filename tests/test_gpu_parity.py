@@ -77,6 +77,19 @@ def test_random_small_vs_brute(ctx, seed):
     assert_same(gpu_dbscan(ctx, x, eps, minpts), oracle.dbscan_brute(x, eps, minpts), f"seed {seed}")
 
 
+@pytest.mark.parametrize("eps,d", [(10000, 2), (10000, 3), (10000, 5), (10001, 3), (15000, 5), (21845, 2)])
+def test_eps_around_packed_limit(ctx, eps, d):
+    # core marking takes 16-bit coordinate differences up to eps = 10000 and
+    # full words above; clusters of width 2 eps put neighbour-grid
+    # differences near their bound of about 2.13 eps
+    rng = np.random.default_rng(eps * 10 + d)
+    n = 1500
+    centres = rng.integers(0, 6 * eps, size=(8, d))
+    x = (centres[rng.integers(0, 8, size=n)] + rng.integers(-eps, eps + 1, size=(n, d))).astype(np.int32)
+    print(f"case eps={eps} d={d}", flush=True)
+    assert_same(gpu_dbscan(ctx, x, eps, 6), oracle.dbscan_brute(x, eps, 6), f"eps {eps} d {d}")
+
+
 def test_cfg0_full(ctx):
     w = W.WORKLOADS["cfg0"]
     x = W.make_points(w)
