@@ -194,13 +194,13 @@ def bench_learned(G, steps, warmup):
     ref = None
     for name, blob in (("plain", None), ("learned", P.load_blob())):
         ctx.set_proposal(blob)
+        t = time_calls(lambda: ctx.dbscan(pts, w.eps, w.minpts, lab, core), steps, warmup)
+        # the merge phase alone, from calls with phase events
         ctx.set_option(G.GD_OPT_TIMING, 1)
         merge_ms = []
-
-        def call():
+        for _ in range(steps):
             ctx.dbscan(pts, w.eps, w.minpts, lab, core)
             merge_ms.append(ctx.phase_times()["merge"])
-        t = time_calls(call, steps, warmup)
         ctx.set_option(G.GD_OPT_TIMING, 0)
         ctx.set_option(G.GD_OPT_STATS, 1)
         ctx.dbscan(pts, w.eps, w.minpts, lab, core)
@@ -212,7 +212,7 @@ def bench_learned(G, steps, warmup):
         elif not (torch.equal(ref[0], out[0]) and torch.equal(ref[1], out[1])):
             raise RuntimeError("learned proposal changed the labels")
         res[name] = {"value": round(n / t, 1), "ms_per_step": round(1e3 * t, 3),
-                     "merge_ms": round(float(np.mean(merge_ms[warmup:] or merge_ms)), 4),
+                     "merge_ms": round(float(np.mean(merge_ms)), 4),
                      "merge_tests": st["merge_tests"], "merge_distances": st["merge_distances"],
                      "merge_iterations": st["merge_iterations"]}
         log(f"bench: {name} {res[name]}")
@@ -262,24 +262,35 @@ def main():
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     core = torch.empty(n, dtype=torch.uint8, device=dev)
     ctx = G.Context(0)
-    ctx.set_option(G.GD_OPT_TIMING, 1)
     for i in range(args.warmup):
         ctx.dbscan(pts, w.eps, w.minpts, labels, core)
         log(f"bench: warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    phase_sum = {}
     step_ms = []
     t0 = time.perf_counter()
     for i in range(args.steps):
         ts = time.perf_counter()
         ctx.dbscan(pts, w.eps, w.minpts, labels, core)  # returns after the stream has drained
         step_ms.append(1e3 * (time.perf_counter() - ts))
-        for k, v in ctx.phase_times().items():
-            phase_sum[k] = phase_sum.get(k, 0.0) + v
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"bench: {args.steps} timed steps done")
+    # Phase durations: the same K steps again with a pair of HIP events
+    # around every phase on the launch stream.  The events hold the stream
+    # at each phase boundary (about 0.1 ms per call in all), so the steps
+    # above run without them.
+    ctx.set_option(G.GD_OPT_TIMING, 1)
+    phase_sum = {}
+    ti0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.dbscan(pts, w.eps, w.minpts, labels, core)
+        for k, v in ctx.phase_times().items():
+            phase_sum[k] = phase_sum.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    t_instr = (time.perf_counter() - ti0) / args.steps
+    ctx.set_option(G.GD_OPT_TIMING, 0)
+    log(f"bench: {args.steps} steps with phase events done")
     # Work counters come from one more, untimed call with the device counters
     # on (the union order, hence the number of merge tests, varies slightly
     # from call to call).
@@ -288,7 +299,6 @@ def main():
     st = ctx.stats()
     ctx.set_option(G.GD_OPT_STATS, 0)
     # the same step replayed from a captured HIP graph (no host synchronisation between phases)
-    ctx.set_option(G.GD_OPT_TIMING, 0)
     ctx.set_option(G.GD_OPT_GRAPH, 2)
     t_graph = time_calls(lambda: ctx.dbscan(pts, w.eps, w.minpts, labels, core), args.steps, args.warmup)
     graph_ok = ctx.stats()["graph_replays"] == 1
@@ -340,6 +350,7 @@ def main():
         "graph_replay": {"value": round(n / t_graph, 1), "ms_per_step": round(1e3 * t_graph, 3),
                          "replayed": graph_ok},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "ms_per_step_with_phase_events": round(1e3 * t_instr, 3),
         "work": {k: st[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids",
                                     "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
                                     "merge_max_iterations", "merge_distances", "merge_set_points", "core_distances",
