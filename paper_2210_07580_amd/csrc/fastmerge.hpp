@@ -64,6 +64,24 @@ __device__ __forceinline__ void uf_union(uint32_t* parent, uint32_t a, uint32_t 
     }
 }
 
+// Union given ra and rb, nodes on the root paths of the two elements (their
+// roots as last seen).  The common case is one compare-and-swap: the larger
+// of the two is still a root and goes under the smaller, which keeps every
+// root the smallest index of its component.  Otherwise both are resolved
+// again.  Returns the root the sets were joined under (as it stood then);
+// callers use it as a hint: a later find() that returns it proves the
+// connection, a stale hint only costs an extra exact test.
+__device__ __forceinline__ uint32_t uf_union_from(uint32_t* parent, uint32_t ra, uint32_t rb) {
+    for (;;) {
+        if (ra == rb) return ra;
+        const uint32_t a = ra < rb ? ra : rb;
+        const uint32_t b = ra < rb ? rb : ra;
+        if (atomicCAS(&parent[b], b, a) == b) return a;
+        ra = uf_find(parent, a);
+        rb = uf_find(parent, b);
+    }
+}
+
 // A run of point rows (row_stride(D) int32 each): position i is row base + i.
 struct PointSet {
     const int32_t* rows;

@@ -186,7 +186,9 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
                 cand = mj <= kSmallSet || rj > (uint32_t)r;
             }
         }
-        const bool pend_l = cand && uf_find(parent, cj) != ri;
+        // root of each candidate's set, kept as the hint for a union
+        uint32_t root_j = cand ? uf_find(parent, cj) : 0u;
+        const bool pend_l = cand && root_j != ri;
         const uint64_t cands = ballot(cand);
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
@@ -239,7 +241,6 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
                 l = ffs64(pend);
             }
             pend &= ~(1ull << l);
-            const uint32_t j = readlane(cj, l);
             sj.base = readlane(bj, l);
             sj.m = readlane(mj, l);
             sj.words = (sj.m + kWave - 1) / kWave;
@@ -267,11 +268,15 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
             }
             if (yes) {
                 ++n_yes;
-                if (lane == 0) uf_union(parent, ci, j);
-                ri = uf_find(parent, ci);
+                const uint32_t rl = readlane(root_j, l);
+                uint32_t root = 0;
+                if (lane == 0) root = uf_union_from(parent, ri, rl);
+                ri = readlane(root, 0);
                 if (pend) {
                     // the union may have joined g_i to other pending grids' sets
-                    const bool still = ((pend >> lane) & 1ull) && uf_find(parent, cj) != ri;
+                    const bool pl = (pend >> lane) & 1ull;
+                    if (pl) root_j = uf_find(parent, root_j);
+                    const bool still = pl && root_j != ri;
                     const uint64_t np = ballot(still);
                     n_skip += (unsigned long long)(popc64(pend) - popc64(np));
                     pend = np;
