@@ -17,28 +17,27 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
     if (c >= (int64_t)*gv.ncell_dev || c >= gv.ncell) return;  // out[] holds gv.ncell summaries
     const uint32_t b = co.core_begin[c], m = co.core_cnt[c];
     if (m == 0) return;
-    double sum[D];
-    uint64_t lo[D], hi[D];
+    // coordinates are below 2^25 (minus the instance minimum, |x| <= 2^24),
+    // so value << 6 | position fits 32 bits and 64 of them sum exactly
+    uint32_t sum[D], lo[D], hi[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        sum[k] = 0.0;
-        lo[k] = ~0ull;
-        hi[k] = 0ull;
+        sum[k] = 0u;
+        lo[k] = ~0u;
+        hi[k] = 0u;
     }
     // the first (at most) 64 core points: in input order within the grid, a
     // uniform sample of its core set
     const uint32_t ms = min(m, (uint32_t)kWave);
-    for (uint32_t i = lane; i < ms; i += kWave) {
+    if ((uint32_t)lane < ms) {
         int32_t p[D];
-        load_row<D>(co.ccrd, b + i, p);
+        load_row<D>(co.ccrd, b + lane, p);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const uint32_t v = (uint32_t)p[k];
-            sum[k] += (double)v;
-            const uint64_t key_lo = ((uint64_t)v << 32) | i;                 // smallest value, lowest position
-            const uint64_t key_hi = ((uint64_t)v << 32) | (0xFFFFFFFFu - i); // largest value, lowest position
-            lo[k] = key_lo < lo[k] ? key_lo : lo[k];
-            hi[k] = key_hi > hi[k] ? key_hi : hi[k];
+            sum[k] = v;
+            lo[k] = (v << 6) | (uint32_t)lane;          // smallest value, lowest position
+            hi[k] = (v << 6) | (uint32_t)(63 - lane);   // largest value, lowest position
         }
     }
     CellSummary s;
@@ -50,14 +49,14 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const double tot = wave_sum(sum[k]);
-        const uint64_t l = wave_min_u64(lo[k]);
-        const uint64_t h = ~wave_min_u64(~hi[k]);
-        s.cen[k] = (float)(tot / (double)ms);
-        s.lo[k] = (int32_t)(l >> 32);
-        s.hi[k] = (int32_t)(h >> 32);
-        s.rep[2 * k] = (uint32_t)l;
-        s.rep[2 * k + 1] = 0xFFFFFFFFu - (uint32_t)h;
+        const uint32_t tot = wave_sum(sum[k]);
+        const uint32_t l = ~wave_max_u32(~lo[k]);
+        const uint32_t h = wave_max_u32(hi[k]);
+        s.cen[k] = (float)((double)tot / (double)ms);
+        s.lo[k] = (int32_t)(l >> 6);
+        s.hi[k] = (int32_t)(h >> 6);
+        s.rep[2 * k] = l & 63u;
+        s.rep[2 * k + 1] = 63u - (h & 63u);
     }
     if (lane == 0) out[c] = s;
 }
