@@ -35,8 +35,9 @@ __device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsign
 // core grid g_i; every lane takes one neighbouring tiny core grid g_j that
 // comes later in the visiting order and decides the pair by evaluating its
 // |s_i| x |s_j| distances directly: the answer FastMerging gives (Theorem
-// 2), without its wave-level iteration.  Only pairs that answer yes touch the
-// union-find.  s_i lives in scalar registers.
+// 2), without its wave-level iteration.  Each lane first resolves its
+// candidate's root and skips the pair when both grids are already in one
+// set; a yes joins the two roots.  s_i lives in scalar registers.
 template <int D>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
@@ -63,7 +64,8 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
 #pragma unroll
         for (int k = 0; k < D; ++k) pi[a][k] = uniform((uint32_t)a < mi ? t[k] : 0);
     }
-    unsigned long long n_pairs = 0, n_yes = 0, n_dist = 0, n_pts = 0;
+    unsigned long long n_pairs = 0, n_skip = 0, n_yes = 0, n_dist = 0, n_pts = 0;
+    uint32_t ri = uf_find(parent, ci);  // root hint of g_i's set
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
         bool cand = false;
@@ -78,35 +80,51 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
                 cand = mj <= kSmallSet;
             }
         }
+        // pairs already in one set are skipped; the root found is the hint
+        // for the union
+        uint32_t root_j = cand ? uf_find(parent, cj) : 0u;
+        const bool test = cand && root_j != ri;
         bool yes = false;
-        if (cand) {
-            for (uint32_t b = 0; b < mj && !yes; ++b) {
-                int32_t y[D];
-                load_row<D>(co.ccrd, bj + b, y);
+        if (test) {
+            // four rows of s_j per round, loaded together (a repeated last
+            // row only repeats a distance)
+            for (uint32_t b0 = 0; b0 < mj && !yes; b0 += 4) {
+                int32_t y[4][D];
 #pragma unroll
-                for (int a = 0; a < (int)kSmallSet; ++a) {
-                    if ((uint32_t)a < mi) {
-                        uint32_t dd = 0;
+                for (int u = 0; u < 4; ++u) load_row<D>(co.ccrd, bj + min(b0 + u, mj - 1), y[u]);
 #pragma unroll
-                        for (int k = 0; k < D; ++k) dd += sq24(y[k], pi[a][k]);
-                        yes |= dd <= T;
+                for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                    for (int a = 0; a < (int)kSmallSet; ++a) {
+                        if ((uint32_t)a < mi) {
+                            uint32_t dd = 0;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) dd += sq24(y[u][k], pi[a][k]);
+                            yes |= dd <= T;
+                        }
                     }
                 }
             }
-            if (yes && uf_find(parent, ci) != uf_find(parent, cj)) uf_union(parent, ci, cj);
+            if (yes) uf_union_from(parent, ri, root_j);
         }
+        // the unions may have put g_i's set under a smaller root
+        if (ballot(yes)) ri = uf_find(parent, ri);
         if (stats) {
             const unsigned long long np = (unsigned long long)popc64(ballot(cand));
-            const unsigned long long sj = (unsigned long long)wave_sum(cand ? mj : 0u);
+            const unsigned long long nt = (unsigned long long)popc64(ballot(test));
+            const unsigned long long sj = (unsigned long long)wave_sum(test ? mj : 0u);
             n_pairs += np;
+            n_skip += np - nt;
             n_yes += (unsigned long long)popc64(ballot(yes));
             n_dist += (unsigned long long)mi * sj;
-            n_pts += np * mi + sj;
+            n_pts += nt * mi + sj;
         }
     }
     // each one-lane test counts as one FastMerging iteration
-    if (stats && lane == 0)
-        flush_stats(stats, r, n_pairs, 0, n_pairs, n_yes, n_pairs, n_pairs ? 1 : 0, n_dist, n_pts);
+    if (stats && lane == 0) {
+        const unsigned long long nt = n_pairs - n_skip;
+        flush_stats(stats, r, n_pairs, n_skip, nt, n_yes, nt, nt ? 1 : 0, n_dist, n_pts);
+    }
 }
 
 // Every other pair: one wave per core grid g_i with more than kSmallSet core
