@@ -205,6 +205,31 @@ inline hipError_t fill(T* p, int64_t n, T v, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Workgroups are handed to the 8 XCDs of the chip round robin by index, and
+// each XCD has its own L2.  xcd_order(b, count) is the work item that
+// workgroup b takes so that every XCD walks one contiguous range of items in
+// order (a bijection of [0, count); only the speed depends on it).  Kernels
+// whose neighbouring items share data (neighbouring grids read largely the
+// same neighbour rows and tree nodes) then find it in their own L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t count) {
+    const int64_t q = count / kXcds, r = count % kXcds;
+    const int64_t x = b % kXcds, j = b / kXcds;
+    return x * q + (x < r ? x : r) + j;
+}
+
+// The same in runs of kRun items: XCD x takes runs x, x + 8, x + 16, ...
+// (locality within a run, every XCD spread over the whole range so that
+// uneven work is shared); the items past the last full group of 8 runs keep
+// their own index.
+template <int kRun>
+__device__ __forceinline__ int64_t xcd_runs(int64_t b, int64_t count) {
+    constexpr int64_t kGroup = (int64_t)kXcds * kRun;
+    if (b >= count / kGroup * kGroup) return b;
+    const int64_t x = b % kXcds, j = b / kXcds;
+    return (j / kRun) * kGroup + x * kRun + j % kRun;
+}
+
 #define GD_DISPATCH_D(d, CALL)                         \
     switch (d) {                                       \
         case 1: { constexpr int D = 1; CALL; } break;  \

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     __shared__ __align__(16) int32_t s_q[kWavesPerBlock][kWave * S];  // the query rows of the batch
     const int w = wave_id(), lane = lane_id();
-    const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t c = xcd_runs<16>(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
     if (c >= (int64_t)*gv.ncell_dev) return;
     // every load that depends on c alone is issued before the first use
     const Inst& I = cell_inst(gv, c);

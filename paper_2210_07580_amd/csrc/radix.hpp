@@ -39,20 +39,11 @@ inline int64_t radix_scratch_words(int64_t n) {
     return 2 * bins * t + scan_partial_cap(bins * t) + 4;
 }
 
-// Workgroups are handed to the 8 XCDs of the chip round robin by index, and
-// each XCD has its own L2.  Neighbouring tiles write neighbouring addresses
-// (their counts in the digit-major histogram table, their runs of one digit
-// in the scatter), so workgroup b takes tile xcd_tile(b), which gives every
-// XCD one contiguous range of tiles: a line is then written from one L2
-// instead of being merged from partial copies in several.  (A bijection of
-// [0, tiles); only the speed depends on it.)
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t tiles) {
-    const int64_t q = tiles / kXcds, r = tiles % kXcds;
-    const int64_t x = b % kXcds, j = b / kXcds;
-    return x * q + (x < r ? x : r) + j;
-}
-
+// Neighbouring tiles write neighbouring addresses (their counts in the
+// digit-major histogram table, their runs of one digit in the scatter), so
+// workgroup b takes tile xcd_order(b): every XCD then writes one contiguous
+// range, and a line is written from one L2 instead of being merged from
+// partial copies in several.
 template <typename K>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift, int rbits,
                                                             uint32_t* __restrict__ hist, int64_t tiles) {
@@ -61,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     const int bins = 1 << rbits;
     for (int i = threadIdx.x; i < kWavesPerBlock * kMaxBins; i += kBlock) (&h[0][0])[i] = 0;
     __syncthreads();
-    const int64_t tile = xcd_tile(blockIdx.x, tiles);
+    const int64_t tile = xcd_order(blockIdx.x, tiles);
     const int64_t base = tile * kRadixTile;
     const int w = wave_id();
     const uint32_t mask = (uint32_t)bins - 1u;
@@ -108,9 +99,9 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     const uint32_t mask = (uint32_t)bins - 1u;
     for (int i = t; i < kWavesPerBlock * kMaxBins; i += kBlock) (&wcnt[0][0])[i] = 0;
     __syncthreads();
-    // neighbouring tiles on one XCD (see xcd_tile): their runs of a digit are
+    // neighbouring tiles on one XCD (see xcd_order): their runs of a digit are
     // neighbours in the output
-    const int64_t tile = xcd_tile(blockIdx.x, tiles);
+    const int64_t tile = xcd_order(blockIdx.x, tiles);
     const int64_t base = tile * kRadixTile;
     const int tile_n = (int)min((int64_t)kRadixTile, n - base);
     const uint64_t lt = lanemask_lt();
