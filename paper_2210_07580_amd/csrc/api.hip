@@ -187,10 +187,12 @@ struct Plan {
     int64_t max_core;  // largest core set
 };
 
-// Output hash table: 2^bits slots for ncell grids (load <= 1/4).
+// Output hash table: 2^bits slots for ncell grids, load <= 1/8 up to 2^20
+// grids (fewer second probes), <= 1/4 above (the table stays modest).
 int table_bits(int64_t ncell) {
+    const int64_t slots = ncell <= (1 << 20) ? 8 * ncell : 4 * ncell;
     int b = 10;
-    while (((int64_t)1 << b) < 4 * ncell) ++b;
+    while (((int64_t)1 << b) < slots) ++b;
     return b;
 }
 

@@ -136,20 +136,22 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b, int32_t* __rest
     }
 }
 
-// One workgroup per instance folds its tiles' records into mn and mx.
-__global__ __launch_bounds__(kBlock) void minmax_finish_kernel(Batch b, const int32_t* __restrict__ part) {
-    constexpr int kWaves = kBlock / kWave;
+// One workgroup of 1024 threads per instance folds its tiles' records into mn
+// and mx (a few thousand records: more threads, fewer dependent rounds).
+constexpr int kFinishThreads = 1024;
+__global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, const int32_t* __restrict__ part) {
+    constexpr int kWaves = kFinishThreads / kWave;
     __shared__ int smn[kWaves * kMaxD], smx[kWaves * kMaxD];
     Inst& I = const_cast<Inst&>(b.inst[blockIdx.x]);
     const int d = I.d;
     const uint32_t nt = (uint32_t)((I.n + b.tile_pts - 1) / b.tile_pts);
-    // thread t reads quarter q = t % 4 of records t / 4, t / 4 + 64, ...
+    // thread t reads quarter q = t % 4 of records t / 4, t / 4 + 256, ...
     // (quarters 0-1: minima, 2-3: maxima), eight records in flight
     const int q = threadIdx.x & 3;
     const bool is_min = q < 2;
     int4 acc = is_min ? make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX) : make_int4(INT_MIN, INT_MIN, INT_MIN, INT_MIN);
     const int4* rec = reinterpret_cast<const int4*>(part + (int64_t)I.tile0 * 2 * kMaxD) + q;
-    constexpr uint32_t kStep = kBlock / 4;
+    constexpr uint32_t kStep = kFinishThreads / 4;
     for (uint32_t t0 = threadIdx.x >> 2; t0 < nt; t0 += 8 * kStep) {
         int4 r[8];
 #pragma unroll
@@ -204,7 +206,7 @@ hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st) {
     minmax_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, part);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    minmax_finish_kernel<<<dim3(b.count), dim3(kBlock), 0, st>>>(b, part);
+    minmax_finish_kernel<<<dim3(b.count), dim3(kFinishThreads), 0, st>>>(b, part);
     return hipGetLastError();
 }
 
