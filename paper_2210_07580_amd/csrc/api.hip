@@ -206,7 +206,6 @@ struct Layout {
     uint32_t* radix_scratch;
     uint64_t* partial;
     int32_t* crd;
-    uint32_t* excl;
     uint32_t* cell_start;
     int32_t* ck;
     uint32_t* level_excl;
@@ -243,7 +242,6 @@ Layout carve(char* base, int64_t n, int D, uint32_t tiles) {
     L.radix_scratch = c.take<uint32_t>(radix_scratch_words(n));
     L.partial = c.take<uint64_t>(scan_partial_cap(big_scan) + 4);
     L.crd = c.take<int32_t>((int64_t)row_stride(D) * 2 * n);  // sorted rows, then the side area
-    L.excl = c.take<uint32_t>(n + 1);
     L.cell_start = c.take<uint32_t>(n + 1);
     L.ck = c.take<int32_t>((int64_t)(D + 1) * n);
     L.level_excl = c.take<uint32_t>((int64_t)D * (n + 1));
@@ -292,7 +290,7 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
     GD_TRY(launch_gather(b, res.vals, L.crd, st));
     ctx->mark(P_GATHER, 1);
     ctx->mark(P_CELLS, 0);
-    GD_TRY(launch_cells<K>(b, res.keys, L.excl, (uint32_t*)L.partial, L.cell_start, L.ck, b.n, st));
+    GD_TRY(launch_cells<K>(b, res.keys, (uint32_t*)L.partial, L.cell_start, L.ck, b.n, st));
     ctx->mark(P_CELLS, 1);
     *sidx_out = res.vals;
     *skeys_out = res.keys;
@@ -455,10 +453,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         ctx->mark(P_LDF, 0);
         // a planned run sorts ncc slots, the unused ones last under an all-ones key
         const int count_bits = bit_length((uint64_t)max_core) + (plan ? 1 : 0);
-        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, ka, kb, vb,
-                                L.radix_scratch, L.excl, (uint32_t*)L.partial, &ldf, st));
-        GD_TRY((iota_kernel<uint32_t><<<dim3(grid_for(ncell)), dim3(kBlock), 0, st>>>(L.parent, ncell),
-                hipGetLastError()));
+        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, L.parent, ka, kb,
+                                vb, L.radix_scratch, (uint32_t*)L.partial, &ldf, st));
         ctx->mark(P_LDF, 1);
     }
     CellSummary* sum = nullptr;

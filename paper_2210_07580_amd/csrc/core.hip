@@ -351,18 +351,26 @@ struct CoreCellFlag {
     __device__ uint32_t operator()(int64_t c) const { return c < (int64_t)*ncell && core_cnt[c] > 0; }
 };
 
-__global__ __launch_bounds__(kBlock) void core_list_kernel(const uint32_t* ncell_dev, const uint32_t* core_cnt,
-                                                           const uint32_t* excl, uint32_t* list, uint32_t* keys,
-                                                           uint4* rec) {
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= (int64_t)*ncell_dev) return;
-    const uint32_t cnt = core_cnt[c];
-    rec[c] = make_uint4(kNone, 0u, 0u, 0u);
-    if (cnt) {
-        list[excl[c]] = (uint32_t)c;
-        keys[excl[c]] = cnt;
+// Output of the core-grid scan: the list of core grids (and their counts as
+// sort keys) in grid order, the merge record reset, and every grid its own
+// union-find root.
+struct CoreListWriter {
+    const uint32_t* ncell;
+    const uint32_t* core_cnt;
+    uint32_t* list;
+    uint32_t* keys;
+    uint4* rec;
+    uint32_t* parent;
+    __device__ void operator()(int64_t c, uint32_t ex, uint32_t is_core) const {
+        if (c >= (int64_t)*ncell) return;
+        rec[c] = make_uint4(kNone, 0u, 0u, 0u);
+        parent[c] = (uint32_t)c;
+        if (is_core) {
+            list[ex] = (uint32_t)c;
+            keys[ex] = core_cnt[c];
+        }
     }
-}
+};
 
 // The merge step's record of each core grid: rank in the visiting order,
 // first row and size of its core set (one load instead of three).
@@ -375,8 +383,8 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, co
 }
 
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* keys_a, uint32_t* keys_b,
-                            uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* keys_a,
+                            uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* partial,
                             uint32_t** sorted_list, hipStream_t st) {
     *sorted_list = list;
     if (g.ncell == 0) return hipSuccess;
@@ -384,11 +392,10 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
         hipError_t e = fill<uint32_t>(keys_a, ncc, (uint32_t)((1ull << count_bits) - 1ull), st);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = scan_exclusive<uint32_t>(CoreCellFlag{c.core_cnt, g.ncell_dev}, g.ncell, excl,
-                                            (uint32_t*)nullptr, partial, st);
+    hipError_t e = scan_apply<uint32_t>(CoreCellFlag{c.core_cnt, g.ncell_dev}, g.ncell,
+                                        CoreListWriter{g.ncell_dev, c.core_cnt, list, keys_a, rank, parent},
+                                        (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
-    core_list_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, excl, list, keys_a,
-                                                                      rank);
     if (by_count && ncc > 1) {
         RadixResult<uint32_t> res;
         e = radix_sort_pairs<uint32_t>(keys_a, list, keys_b, vals_b, ncc, count_bits, false, radix_scratch, st, &res);

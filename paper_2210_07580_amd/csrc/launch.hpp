@@ -132,7 +132,7 @@ hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st);
 hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st);
 // Runs of equal keys: cell_start[0..ncell], identifiers; header ncell written.
 template <typename K>
-hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
+hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st);
 // Grid tree levels over the sorted grids.  level_excl: D x (ncell+1) scratch.
 hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partial, int32_t* const* tkey,
@@ -182,10 +182,10 @@ hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* pa
 // core_cnt, 0).  ncc: number of
 // core grids, or an upper bound (then pad_tail: the slots past the device
 // count sort last, under the key 2^count_bits - 1); count_bits: bits of the
-// sort keys.
+// sort keys.  Also sets parent[g] = g for every grid (union-find roots).
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* keys_a, uint32_t* keys_b,
-                            uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* excl, uint32_t* partial,
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* keys_a,
+                            uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* partial,
                             uint32_t** sorted_list, hipStream_t st);
 
 // ---- merge.hip (Algorithms 4-5, union-find)

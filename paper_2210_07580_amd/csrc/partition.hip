@@ -451,15 +451,14 @@ struct CellWriter {
 };
 
 template <typename K>
-hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* excl, uint32_t* partial, uint32_t* cell_start,
+hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st) {
-    (void)excl;
     return scan_apply<uint32_t>(KeyChange<K>{skeys}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
                                 &b.hdr->ncell, partial, st);
 }
-template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,
+template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, int32_t*,
                                            int64_t, hipStream_t);
-template hipError_t launch_cells<uint64_t>(const Batch&, const uint64_t*, uint32_t*, uint32_t*, uint32_t*, int32_t*,
+template hipError_t launch_cells<uint64_t>(const Batch&, const uint64_t*, uint32_t*, uint32_t*, int32_t*,
                                            int64_t, hipStream_t);
 
 // A grid starts a new node at level l iff it differs from the previous grid
