@@ -134,7 +134,8 @@ hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hip
 template <typename K>
 hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st);
-// Grid tree levels over the sorted grids.  level_excl: D x (ncell+1) scratch.
+// Grid tree levels over the sorted grids.  level_excl: D x (ncell+1) scratch;
+// partial: scan scratch of 64-bit words (passed as the u32 view).
 hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partial, int32_t* const* tkey,
                        uint32_t* const* tchild, hipStream_t st);
 

@@ -17,6 +17,7 @@
 //   tree    : level 0 = instances, level l = distinct prefixes of length l,
 //             each level in sorted order, so every node's children are
 //             contiguous and their keys ascend
+#include <algorithm>
 #include <climits>
 
 #include "launch.hpp"
@@ -463,17 +464,42 @@ template hipError_t launch_cells<uint64_t>(const Batch&, const uint64_t*, uint32
 
 // A grid starts a new node at level l iff it differs from the previous grid
 // in one of the identifier rows 0..l (grids are in lexicographic order).
-struct LevelFlag {
+// Node-start flags of levels l0 .. l0 + nl - 1 for grid c, packed `bits`
+// apart so one scan counts several levels: a grid starts a new node at level
+// l iff it differs from the previous grid in one of the identifier rows
+// 0..l (grids are in lexicographic order).
+struct LevelFlags {
     const int32_t* ck;
     int64_t stride;
     const uint32_t* ncell;
-    int l;
-    __device__ uint32_t operator()(int64_t c) const {
+    int l0, nl, bits;
+    __device__ uint64_t operator()(int64_t c) const {
         if (c >= (int64_t)*ncell) return 0;
-        if (c == 0) return 1;
-        for (int j = 0; j <= l; ++j)
-            if (ck[(int64_t)j * stride + c] != ck[(int64_t)j * stride + c - 1]) return 1;
-        return 0;
+        bool diff = c == 0;
+        uint64_t v = 0;
+        for (int j = 0; j < l0 + nl; ++j) {
+            if (!diff) diff = ck[(int64_t)j * stride + c] != ck[(int64_t)j * stride + c - 1];
+            if (j >= l0 && diff) v |= 1ull << ((j - l0) * bits);
+        }
+        return v;
+    }
+};
+
+// Unpacks the scan: per level, the nodes before grid c; at c = ncell that is
+// the level's node count.
+struct LevelExcl {
+    uint32_t* excl[kMaxLevels];
+    uint32_t* count;
+    const uint32_t* ncell;
+    int l0, nl, bits;
+    __device__ void operator()(int64_t c, uint64_t ex, uint64_t) const {
+        const uint64_t mask = (1ull << bits) - 1ull;
+        const bool last = c == (int64_t)*ncell;
+        for (int k = 0; k < nl; ++k) {
+            const uint32_t v = (uint32_t)((ex >> (k * bits)) & mask);
+            excl[k][c] = v;
+            if (last) count[l0 + k] = v;
+        }
     }
 };
 
@@ -489,8 +515,7 @@ __global__ __launch_bounds__(kBlock) void tree_kernel(const int32_t* __restrict_
     const int64_t ncell = *ncell_dev;
     if (c > ncell) return;
     for (int l = 0; l + 1 < levels; ++l) {
-        LevelFlag f{ck, stride, ncell_dev, l};
-        if (c == ncell || f(c)) {
+        if (c == ncell || tb.excl[l][c + 1] != tb.excl[l][c]) {
             const uint32_t a = tb.excl[l][c];
             if (c < ncell) tb.key[l][a] = ck[(int64_t)l * stride + c];
             // children: the level-(l+1) node that starts at grid c; the last level's nodes are the grids
@@ -509,13 +534,26 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
     // the last level's nodes are the grids
     copy_u32_kernel<<<1, 1, 0, st>>>(g.ncell_dev, level_count + (levels - 1));
     for (int l = 0; l + 1 < levels; ++l) {
-        uint32_t* ex = level_excl + (int64_t)l * (g.ncell + 1);
-        hipError_t e = scan_exclusive<uint32_t>(LevelFlag{g.ck, g.ck_stride, g.ncell_dev, l}, g.ncell + 1, ex,
-                                                level_count + l, partial, st);
-        if (e != hipSuccess) return e;
         tb.key[l] = tkey[l];
         tb.child[l] = tchild[l];
-        tb.excl[l] = ex;
+        tb.excl[l] = level_excl + (int64_t)l * (g.ncell + 1);
+    }
+    // several levels per scan: counts are at most ncell + 1
+    int bits = 1;
+    while (((uint64_t)g.ncell + 1) >> bits) ++bits;
+    const int per = 64 / bits;
+    for (int l0 = 0; l0 + 1 < levels; l0 += per) {
+        const int nl = std::min(per, levels - 1 - l0);
+        LevelExcl out{};
+        for (int k = 0; k < nl; ++k) out.excl[k] = level_excl + (int64_t)(l0 + k) * (g.ncell + 1);
+        out.count = level_count;
+        out.ncell = g.ncell_dev;
+        out.l0 = l0;
+        out.nl = nl;
+        out.bits = bits;
+        hipError_t e = scan_apply<uint64_t>(LevelFlags{g.ck, g.ck_stride, g.ncell_dev, l0, nl, bits}, g.ncell + 1,
+                                            out, (uint64_t*)nullptr, reinterpret_cast<uint64_t*>(partial), st);
+        if (e != hipSuccess) return e;
     }
     if (g.ncell == 0) return hipGetLastError();
     tree_kernel<<<dim3(grid_for(g.ncell + 1)), dim3(kBlock), 0, st>>>(g.ck, g.ck_stride, g.ncell_dev, levels, tb);
