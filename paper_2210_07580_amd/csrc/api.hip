@@ -453,8 +453,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         ctx->mark(P_LDF, 0);
         // a planned run sorts ncc slots, the unused ones last under an all-ones key
         const int count_bits = bit_length((uint64_t)max_core) + (plan ? 1 : 0);
-        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, L.parent, ka, kb,
-                                vb, L.radix_scratch, (uint32_t*)L.partial, &ldf, st));
+        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, L.parent,
+                                L.root_min, ka, kb, vb, L.radix_scratch, (uint32_t*)L.partial, &ldf, st));
         ctx->mark(P_LDF, 1);
     }
     CellSummary* sum = nullptr;

@@ -352,8 +352,8 @@ struct CoreCellFlag {
 };
 
 // Output of the core-grid scan: the list of core grids (and their counts as
-// sort keys) in grid order, the merge record reset, and every grid its own
-// union-find root.
+// sort keys) in grid order, the merge record reset, every grid its own
+// union-find root, and the per-root minima of the labelling step cleared.
 struct CoreListWriter {
     const uint32_t* ncell;
     const uint32_t* core_cnt;
@@ -361,10 +361,12 @@ struct CoreListWriter {
     uint32_t* keys;
     uint4* rec;
     uint32_t* parent;
+    uint32_t* root_min;
     __device__ void operator()(int64_t c, uint32_t ex, uint32_t is_core) const {
         if (c >= (int64_t)*ncell) return;
         rec[c] = make_uint4(kNone, 0u, 0u, 0u);
         parent[c] = (uint32_t)c;
+        root_min[c] = kNone;
         if (is_core) {
             list[ex] = (uint32_t)c;
             keys[ex] = core_cnt[c];
@@ -383,9 +385,9 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(const uint32_t* sorted, co
 }
 
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* keys_a,
-                            uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* partial,
-                            uint32_t** sorted_list, hipStream_t st) {
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* root_min,
+                            uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch,
+                            uint32_t* partial, uint32_t** sorted_list, hipStream_t st) {
     *sorted_list = list;
     if (g.ncell == 0) return hipSuccess;
     if (by_count && pad_tail && ncc > 0) {
@@ -393,7 +395,7 @@ hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, 
         if (e != hipSuccess) return e;
     }
     hipError_t e = scan_apply<uint32_t>(CoreCellFlag{c.core_cnt, g.ncell_dev}, g.ncell,
-                                        CoreListWriter{g.ncell_dev, c.core_cnt, list, keys_a, rank, parent},
+                                        CoreListWriter{g.ncell_dev, c.core_cnt, list, keys_a, rank, parent, root_min},
                                         (uint32_t*)nullptr, partial, st);
     if (e != hipSuccess) return e;
     if (by_count && ncc > 1) {

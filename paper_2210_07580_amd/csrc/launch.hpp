@@ -183,11 +183,12 @@ hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* pa
 // core_cnt, 0).  ncc: number of
 // core grids, or an upper bound (then pad_tail: the slots past the device
 // count sort last, under the key 2^count_bits - 1); count_bits: bits of the
-// sort keys.  Also sets parent[g] = g for every grid (union-find roots).
+// sort keys.  Also sets parent[g] = g (union-find roots) and root_min[g] =
+// kNone for every grid (the labelling step's minima).
 hipError_t launch_ldf_order(const GridView& g, const CoreOut& c, bool by_count, int64_t ncc, int count_bits,
-                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* keys_a,
-                            uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch, uint32_t* partial,
-                            uint32_t** sorted_list, hipStream_t st);
+                            bool pad_tail, uint32_t* list, uint4* rank, uint32_t* parent, uint32_t* root_min,
+                            uint32_t* keys_a, uint32_t* keys_b, uint32_t* vals_b, uint32_t* radix_scratch,
+                            uint32_t* partial, uint32_t** sorted_list, hipStream_t st);
 
 // ---- merge.hip (Algorithms 4-5, union-find)
 constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats)
@@ -208,6 +209,7 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
                               int64_t npairs, int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
                               hipStream_t st);
+// root_min must hold kNone for every grid (launch_ldf_order clears it).
 hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, uint32_t* root_min,
                          int32_t* cell_label, hipStream_t st);
 

@@ -430,8 +430,7 @@ __global__ __launch_bounds__(kBlock) void cell_label_kernel(const uint32_t* ncel
 hipError_t launch_labels(const GridView& g, const CoreOut& c, uint32_t* parent, uint32_t* root_min,
                          int32_t* cell_label, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    hipError_t e = fill<uint32_t>(root_min, g.ncell, kNone, st);
-    if (e != hipSuccess) return e;
+    // root_min was cleared to kNone with the core-grid list (launch_ldf_order)
     root_min_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, c.cell_min_core,
                                                                       parent, root_min);
     cell_label_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, parent, root_min,

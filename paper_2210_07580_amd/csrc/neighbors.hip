@@ -222,18 +222,23 @@ struct CellTotal {
     }
 };
 
-__global__ void nei_total_kernel(const uint64_t* nei_off, const uint32_t* ncell, uint64_t* total) {
-    *total = nei_off[*ncell];
-}
+// nei_off[c] = ex; at c = ncell that is the total, kept in the header.
+struct NeiOffWriter {
+    uint64_t* nei_off;
+    const uint32_t* ncell;
+    uint64_t* total;
+    __device__ void operator()(int64_t c, uint64_t ex, uint64_t) const {
+        nei_off[c] = ex;
+        if (c == (int64_t)*ncell) *total = ex;
+    }
+};
 
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st) {
     // nei_off[c] for c in [0, ncell]; entries beyond the true ncell repeat the total
-    hipError_t e = scan_exclusive<uint64_t>(CellTotal{off_counts, g.ncell_dev, g.D}, g.ncell + 1, nei_off,
-                                            (uint64_t*)nullptr, partial, st);
-    if (e != hipSuccess) return e;
-    nei_total_kernel<<<1, 1, 0, st>>>(nei_off, g.ncell_dev, &g.b.hdr->nei_total);
-    return hipGetLastError();
+    return scan_apply<uint64_t>(CellTotal{off_counts, g.ncell_dev, g.D}, g.ncell + 1,
+                                NeiOffWriter{nei_off, g.ncell_dev, &g.b.hdr->nei_total}, (uint64_t*)nullptr, partial,
+                                st);
 }
 
 hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint64_t* nei_off,

@@ -491,7 +491,7 @@ struct LevelExcl {
     uint32_t* excl[kMaxLevels];
     uint32_t* count;
     const uint32_t* ncell;
-    int l0, nl, bits;
+    int l0, nl, bits, levels;
     __device__ void operator()(int64_t c, uint64_t ex, uint64_t) const {
         const uint64_t mask = (1ull << bits) - 1ull;
         const bool last = c == (int64_t)*ncell;
@@ -500,6 +500,7 @@ struct LevelExcl {
             excl[k][c] = v;
             if (last) count[l0 + k] = v;
         }
+        if (last && l0 == 0) count[levels - 1] = (uint32_t)c;  // the last level's nodes are the grids
     }
 };
 
@@ -524,15 +525,11 @@ __global__ __launch_bounds__(kBlock) void tree_kernel(const int32_t* __restrict_
     }
 }
 
-__global__ void copy_u32_kernel(const uint32_t* src, uint32_t* dst) { *dst = *src; }
-
 hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partial, int32_t* const* tkey,
                        uint32_t* const* tchild, hipStream_t st) {
     const int levels = g.D + 1;
     uint32_t* level_count = g.b.hdr->level_count;
     TreeBuild tb{};
-    // the last level's nodes are the grids
-    copy_u32_kernel<<<1, 1, 0, st>>>(g.ncell_dev, level_count + (levels - 1));
     for (int l = 0; l + 1 < levels; ++l) {
         tb.key[l] = tkey[l];
         tb.child[l] = tchild[l];
@@ -551,6 +548,7 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
         out.l0 = l0;
         out.nl = nl;
         out.bits = bits;
+        out.levels = levels;
         hipError_t e = scan_apply<uint64_t>(LevelFlags{g.ck, g.ck_stride, g.ncell_dev, l0, nl, bits}, g.ncell + 1,
                                             out, (uint64_t*)nullptr, reinterpret_cast<uint64_t*>(partial), st);
         if (e != hipSuccess) return e;
