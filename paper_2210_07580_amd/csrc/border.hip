@@ -204,23 +204,17 @@ size_t output_table_bytes(int bits, int key_bytes) {
     return (size_t)((1ll << bits) + 1) * (key_bytes == 4 ? 8 : 16);
 }
 
+// Border and noise points of grid c (rows [st, st + k)), one wave.
 template <int D>
-__global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
-                                                        const uint32_t* __restrict__ nei,
-                                                        const int32_t* __restrict__ cell_label) {
-    __shared__ uint32_t s_start[kWavesPerBlock][kWave];
-    __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
-    __shared__ int32_t s_lab[kWavesPerBlock][kWave];
-    const int w = wave_id(), lane = lane_id();
-    const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + w;
-    if (c >= (int64_t)*gv.ncell_dev) return;
+__device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& co, const uint64_t* __restrict__ nei_off,
+                                            const uint32_t* __restrict__ nei, const int32_t* __restrict__ cell_label,
+                                            int64_t c, uint32_t st, uint32_t k, uint32_t* s_start, uint32_t* s_excl,
+                                            int32_t* s_lab) {
+    const int lane = lane_id();
     const Inst& I = cell_inst(gv, c);
     const uint32_t off = (uint32_t)I.off;  // cluster ids and output slots are local to the instance
     int32_t* __restrict__ labels = I.labels;
     uint8_t* __restrict__ core_flags = I.core;
-    const uint32_t st = gv.cell_start[c];
-    const uint32_t k = gv.cell_start[c + 1] - st;
-    if (co.core_cnt[c] == k) return;  // written in input order by output_direct_kernel
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
     const uint32_t T = I.T;
@@ -259,9 +253,9 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
             const uint32_t incl = wave_incl_scan(cn);
             const uint32_t tot = __shfl(incl, kWave - 1);
             if (tot == 0) continue;
-            s_start[w][lane] = cs;
-            s_excl[w][lane] = incl - cn;
-            s_lab[w][lane] = lab;
+            s_start[lane] = cs;
+            s_excl[lane] = incl - cn;
+            s_lab[lane] = lab;
             wave_sync();
             for (uint32_t t0 = 0; t0 < tot; t0 += kWave) {
                 const uint32_t t = t0 + lane;
@@ -269,11 +263,11 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
                 int j = 0;
 #pragma unroll
                 for (int step = 32; step > 0; step >>= 1)
-                    if (s_excl[w][j + step] <= t) j += step;
-                const uint32_t q = s_start[w][j] + (t - s_excl[w][j]);
+                    if (s_excl[j + step] <= t) j += step;
+                const uint32_t q = s_start[j] + (t - s_excl[j]);
                 int32_t y[D];
                 load_row<D>(co.ccrd, tv ? q : 0u, y);
-                const uint64_t cand = tv ? (((uint64_t)co.corig[q] << 32) | (uint32_t)s_lab[w][j]) : ~0ull;
+                const uint64_t cand = tv ? (((uint64_t)co.corig[q] << 32) | (uint32_t)s_lab[j]) : ~0ull;
                 uint64_t act = open;
                 while (act) {
                     const int qi = ffs64(act);
@@ -298,11 +292,49 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
     }
 }
 
+// Each wave checks G grids at once (one lane each) and serves only those
+// holding a non-core point (the all-core grids were written in input order
+// by output_direct_kernel).  With millions of grids G = 64: a wave per grid
+// would spend the kernel dispatching waves that exit at once.  With fewer
+// grids G = 1: the grids with non-core points sit together at cluster
+// borders, and one wave serving several of them one after another would
+// be the kernel's tail.
+constexpr int64_t kBorderGroupMinGrids = 1 << 20;
+
+template <int D, int G>
+__global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+                                                        const uint32_t* __restrict__ nei,
+                                                        const int32_t* __restrict__ cell_label) {
+    __shared__ uint32_t s_start[kWavesPerBlock][kWave];
+    __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
+    __shared__ int32_t s_lab[kWavesPerBlock][kWave];
+    const int w = wave_id(), lane = lane_id();
+    const int64_t c0 = ((int64_t)blockIdx.x * kWavesPerBlock + w) * G;
+    const int64_t ncell = *gv.ncell_dev;
+    uint32_t st_l = 0, k_l = 0;
+    bool need = false;
+    if (lane < G && c0 + lane < ncell) {
+        st_l = gv.cell_start[c0 + lane];
+        k_l = gv.cell_start[c0 + lane + 1] - st_l;
+        need = co.core_cnt[c0 + lane] != k_l;
+    }
+    for (uint64_t todo = ballot(need); todo; todo &= todo - 1ull) {
+        const int g = ffs64(todo);
+        border_grid<D>(gv, co, nei_off, nei, cell_label, c0 + g, readlane(st_l, g), readlane(k_l, g), s_start[w],
+                       s_excl[w], s_lab[w]);
+    }
+}
+
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                          const int32_t* cell_label, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    GD_DISPATCH_D(g.D, (output_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, c, nei_off, nei, cell_label)));
+    if (g.ncell >= kBorderGroupMinGrids) {
+        GD_DISPATCH_D(g.D, (output_kernel<D, kWave><<<dim3(grid_for(g.ncell, kWavesPerBlock * kWave)), dim3(kBlock), 0,
+                                                     st>>>(g, c, nei_off, nei, cell_label)));
+    } else {
+        GD_DISPATCH_D(g.D, (output_kernel<D, 1><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(
+                               g, c, nei_off, nei, cell_label)));
+    }
     return hipGetLastError();
 }
 

@@ -304,32 +304,45 @@ __global__ __launch_bounds__(1024) void core_counts_kernel(const uint32_t* part,
 // rows, in sorted order, to the side area.
 template <int D>
 __global__ __launch_bounds__(kBlock) void side_copy_kernel(GridView gv, CoreOut co) {
+    // each wave checks 64 grids at once (one lane each) and copies only the
+    // mixed ones: most grids need nothing, and a wave launched per grid would
+    // spend the kernel on dispatching waves that exit at once
     const int lane = lane_id();
-    const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
-    if (c >= (int64_t)*gv.ncell_dev) return;
-    const uint32_t st = gv.cell_start[c];
-    const uint32_t k = gv.cell_start[c + 1] - st;
-    const uint32_t m = co.core_cnt[c];
-    if (m == 0 || m == k) return;
-    const uint32_t base = (uint32_t)gv.n + co.side_off[c];
-    uint32_t done = 0, first = kNone;
-    for (uint32_t qb = 0; qb < k; qb += kWave) {
-        const bool v = qb + lane < k;
-        const bool f = v && co.core[st + qb + lane];
-        const uint32_t orig = v ? gv.sidx[st + qb + lane] : 0u;
-        const uint64_t bal = ballot(f);
-        if (f) {
-            const uint32_t r = base + done + (uint32_t)popc64(bal & lanemask_lt());
-            int32_t y[D];
-            load_row<D>(gv.crd, st + qb + lane, y);
-            store_row<D>(co.ccrd, r, y);
-            co.corig[r] = orig;
-        }
-        // sorted order within a grid is input order: the first core point has the smallest index
-        if (first == kNone && bal) first = readlane(orig, ffs64(bal));
-        done += (uint32_t)popc64(bal);
+    const int64_t c0 = ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * kWave;
+    const int64_t ncell = *gv.ncell_dev;
+    const int64_t cl = c0 + lane;
+    uint32_t st_l = 0, k_l = 0, m_l = 0;
+    if (cl < ncell) {
+        st_l = gv.cell_start[cl];
+        k_l = gv.cell_start[cl + 1] - st_l;
+        m_l = co.core_cnt[cl];
     }
-    if (lane == 0) co.cell_min_core[c] = first;
+    uint64_t todo = ballot(cl < ncell && m_l != 0 && m_l != k_l);
+    while (todo) {
+        const int g = ffs64(todo);
+        todo &= todo - 1ull;
+        const int64_t c = c0 + g;
+        const uint32_t st = readlane(st_l, g), k = readlane(k_l, g);
+        const uint32_t base = (uint32_t)gv.n + co.side_off[c];
+        uint32_t done = 0, first = kNone;
+        for (uint32_t qb = 0; qb < k; qb += kWave) {
+            const bool v = qb + lane < k;
+            const bool f = v && co.core[st + qb + lane];
+            const uint32_t orig = v ? gv.sidx[st + qb + lane] : 0u;
+            const uint64_t bal = ballot(f);
+            if (f) {
+                const uint32_t r = base + done + (uint32_t)popc64(bal & lanemask_lt());
+                int32_t y[D];
+                load_row<D>(gv.crd, st + qb + lane, y);
+                store_row<D>(co.ccrd, r, y);
+                co.corig[r] = orig;
+            }
+            // sorted order within a grid is input order: the first core point has the smallest index
+            if (first == kNone && bal) first = readlane(orig, ffs64(bal));
+            done += (uint32_t)popc64(bal);
+        }
+        if (lane == 0) co.cell_min_core[c] = first;
+    }
 }
 
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st) {
@@ -341,7 +354,8 @@ hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* pa
     const unsigned nb = grid_for(g.ncell);
     core_cells_kernel<<<dim3(nb), dim3(kBlock), 0, st>>>(g, c, c.count_part);
     core_counts_kernel<<<1, 1024, 0, st>>>(c.count_part, nb, c.counts);
-    GD_DISPATCH_D(g.D, (side_copy_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(g, c)));
+    GD_DISPATCH_D(g.D, (side_copy_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock * kWave)), dim3(kBlock), 0, st>>>(
+                           g, c)));
     return hipGetLastError();
 }
 
