@@ -32,6 +32,20 @@ WORKLOAD_DESC = {
 }
 
 
+# The kernels each timed phase launches (a phase is the run of launches
+# between two events; the kernel traces under profiles/ list them one by one).
+PHASE_KERNELS = {
+    "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel"],
+    "keys": ["keys_kernel"],
+    "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel"],
+    "gather": ["gather_kernel"],
+    "core_mark": ["core_mark_kernel"],
+    "merge": ["merge_small_kernel", "merge_big_kernel"],
+    "output": ["hash_clear_kernel", "hash_build_kernel", "output_direct_kernel", "output_kernel"],
+    "nei_fill": ["nei_fill_kernel"],
+}
+
+
 def algorithmic_bytes(phase, n, d, st, key_bytes, passes):
     """Bytes the phase must move at least (the method's own traffic), per call."""
     B = 4 * d  # coordinates per point
@@ -325,6 +339,8 @@ def main():
                          "traffic": int(t["fetch_bytes"] + t["write_bytes"]) if t else None,
                          "avg_ms": round(ms, 4), "algorithmic_bytes": int(b)}
     dominant = max(rooflines, key=lambda k: rooflines[k]["avg_ms"])
+    for ph in rooflines:
+        rooflines[ph]["kernels"] = PHASE_KERNELS.get(ph, [])
     roofline = dict(kernel=dominant, **rooflines[dominant])
 
     out = {
