@@ -6,6 +6,9 @@ hot path: identifiers, radix sort, grids, grid tree, neighbour lists, core
 marking, FastMerging + union-find, labels, border assignment, output), with
 the points already resident in device memory.  Prints one JSON line.
 
+The K timed steps run the plain call; per-phase durations (for the
+rooflines) come from K more steps with HIP events around every phase.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload H]
 """
 import argparse
