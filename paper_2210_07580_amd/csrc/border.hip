@@ -40,11 +40,12 @@ struct alignas(16) HashSlot<uint64_t> {
     int32_t pad;
 };
 
-// Buckets of 16 bytes (2 slots of u32 identifiers, 1 of u64) at load <= 1/4:
-// a lookup reads one bucket with a single 16-byte load and almost always ends
-// there.  The table is hit at random addresses, one per lane, so the cost of
-// a lookup is set by the cache lines each load instruction touches, not by
-// the bytes: one load per lookup rather than a wider bucket.
+// Buckets of 16 bytes (2 slots of u32 identifiers, 1 of u64) at load <= 1/4
+// (<= 1/8 up to 2^20 grids): a lookup reads one bucket with a single 16-byte
+// load and almost always ends there.  The table is hit at random addresses,
+// one per lane, so the cost of a lookup is set by the cache lines each load
+// instruction touches, not by the bytes: one load per lookup rather than a
+// wider bucket.
 template <typename K>
 constexpr int kBucketSlots = 16 / (int)sizeof(HashSlot<K>);
 template <typename K>
