@@ -414,10 +414,13 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
-    int64_t max_eps = 0;
-    for (int k = 0; k < count; ++k) max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
+    int64_t max_eps = 0, min_minpts = INT64_MAX;
+    for (int k = 0; k < count; ++k) {
+        max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
+        min_minpts = std::min<int64_t>(min_minpts, ctx->inst_host[k].minpts);
+    }
     GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, max_eps,
-                            st));
+                            min_minpts, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;

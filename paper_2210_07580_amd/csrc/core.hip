@@ -74,7 +74,12 @@ __device__ __forceinline__ uint32_t sqdist_pk(const int32_t (&a)[packed_words<D>
     return (uint32_t)acc;
 }
 
-template <int D, bool kStats, bool kPacked>
+// R: candidate rows per lane per step.  The slowest grids stream dozens of
+// steps one after another, each a chain of dependent rounds, so with a large
+// MinPts (a query needs more hits than one 64-candidate step can give) a
+// step takes two rows; with a small MinPts most queries close within the
+// first 64 candidates and a second row would only add distance tests.
+template <int D, bool kStats, bool kPacked, int R>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
@@ -137,22 +142,33 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                     if (s_excl[w][j + step] <= t) j += step;
                 return s_start[w][j] + (t - s_excl[w][j]);
             };
-            int32_t y[D];
-            load_row<D>(gv.crd, (uint32_t)lane < tot ? cand_row(lane) : st, y);
-            for (uint32_t t0 = 0; t0 < tot && active; t0 += kWave) {
-                const uint32_t t = t0 + lane;
-                const bool tv = t < tot;
-                // the next step's candidates load while this step is evaluated
-                // (the slowest grids take dozens of steps one after another)
-                int32_t yn[D];
-                load_row<D>(gv.crd, t + kWave < tot ? cand_row(t + kWave) : st, yn);
-                int32_t yp[PW];
-                if constexpr (kPacked) pack_row<D>(y, yp);
-                const uint64_t tvm = ballot(tv);
-                // every open query against the 64 candidates, two queries per
-                // round so their LDS reads overlap: the query row comes from
-                // LDS (one broadcast read), lane qi keeps query qi's hits;
-                // counts and closings are folded in once per step
+            // R candidates per lane per step (64 R per step), and the next
+            // step's candidates load while this one is evaluated
+            int32_t y[R][D];
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const uint32_t t = (uint32_t)(u * kWave + lane);
+                load_row<D>(gv.crd, t < tot ? cand_row(t) : st, y[u]);
+            }
+            for (uint32_t t0 = 0; t0 < tot && active; t0 += R * kWave) {
+                uint64_t tvm[R];
+#pragma unroll
+                for (int u = 0; u < R; ++u) tvm[u] = ballot(t0 + u * kWave + lane < tot);
+                int32_t yn[R][D];
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    const uint32_t tn = t0 + (R + u) * kWave + lane;
+                    load_row<D>(gv.crd, tn < tot ? cand_row(tn) : st, yn[u]);
+                }
+                int32_t yp[R][PW];
+                if constexpr (kPacked) {
+#pragma unroll
+                    for (int u = 0; u < R; ++u) pack_row<D>(y[u], yp[u]);
+                }
+                // every open query against the step's candidates, two queries
+                // per round so their LDS reads overlap: the query row comes
+                // from LDS (one broadcast read), lane qi keeps query qi's
+                // hits; counts and closings are folded in once per step
                 const uint64_t act0 = uniform64(active);
                 uint32_t step_hits = 0;
                 for (uint64_t act = act0; act;) {
@@ -160,31 +176,37 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                     act &= act - 1ull;
                     const int qb2 = act ? ffs64(act) : qa;
                     act &= act - 1ull;
-                    uint32_t da, db;
+                    uint32_t ha = 0, hb = 0;
                     if constexpr (kPacked) {
                         int32_t pa[PW], pb[PW];
                         load_row<PW>(s_q[w], qa, pa);
                         load_row<PW>(s_q[w], qb2, pb);
-                        da = sqdist_pk<D>(yp, pa);
-                        db = sqdist_pk<D>(yp, pb);
+#pragma unroll
+                        for (int u = 0; u < R; ++u) {
+                            ha += (uint32_t)popc64(ballot(sqdist_pk<D>(yp[u], pa) <= T) & tvm[u]);
+                            hb += (uint32_t)popc64(ballot(sqdist_pk<D>(yp[u], pb) <= T) & tvm[u]);
+                        }
                     } else {
                         int32_t pa[D], pb[D];
                         load_row<D>(s_q[w], qa, pa);
                         load_row<D>(s_q[w], qb2, pb);
-                        da = sqdist_nb<D>(y, pa);
-                        db = sqdist_nb<D>(y, pb);
+#pragma unroll
+                        for (int u = 0; u < R; ++u) {
+                            ha += (uint32_t)popc64(ballot(sqdist_nb<D>(y[u], pa) <= T) & tvm[u]);
+                            hb += (uint32_t)popc64(ballot(sqdist_nb<D>(y[u], pb) <= T) & tvm[u]);
+                        }
                     }
-                    const uint32_t ha = (uint32_t)popc64(ballot(da <= T) & tvm);
-                    const uint32_t hb = (uint32_t)popc64(ballot(db <= T) & tvm);
                     step_hits = lane == qa ? ha : step_hits;
                     step_hits = lane == qb2 ? hb : step_hits;
-                    if constexpr (kStats) ndist += (qb2 != qa ? 2u : 1u) * min(tot - t0, (uint32_t)kWave);
+                    if constexpr (kStats) ndist += (qb2 != qa ? 2u : 1u) * min(tot - t0, (uint32_t)(R * kWave));
                 }
                 mycnt += step_hits;
                 active = act0 & ~ballot(((act0 >> lane) & 1ull) && mycnt >= need);
-                if constexpr (kStats) npts += min(tot - t0, (uint32_t)kWave);
+                if constexpr (kStats) npts += min(tot - t0, (uint32_t)(R * kWave));
 #pragma unroll
-                for (int j = 0; j < D; ++j) y[j] = yn[j];
+                for (int u = 0; u < R; ++u)
+#pragma unroll
+                    for (int j = 0; j < D; ++j) y[u][j] = yn[u][j];
             }
             if constexpr (kStats) ncells += (unsigned long long)min(e1 - e, (uint64_t)kWave);
             wave_sync();
@@ -205,18 +227,30 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
 }
 
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, hipStream_t st) {
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts,
+                            hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
     const bool packed = max_eps <= kPackedEpsMax;
-    if (stats) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+    const bool two = min_minpts > kWave / 2;
+    // the counting variant takes the same steps as the timed one
+    if (stats && two) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
+    } else if (stats) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
+    } else if (packed && two) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else if (packed) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
+    } else if (two) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     }
     return hipGetLastError();

@@ -174,9 +174,12 @@ struct CoreStats {
     unsigned long long grids;   // neighbour grids opened
 };
 // Core flags (sorted order) and m_i per grid.  max_eps: the largest eps in
-// the batch (small ones allow packed 16-bit coordinate differences).
+// the batch (small ones allow packed 16-bit coordinate differences);
+// min_minpts: the smallest MinPts in the batch (large ones take two
+// candidate rows per lane per step).
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, hipStream_t st);
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts,
+                            hipStream_t st);
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = (position (kNone for non-core grids), core_begin,
