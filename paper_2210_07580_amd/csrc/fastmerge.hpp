@@ -40,14 +40,23 @@
 
 namespace gd {
 
-__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x) {
+// Root of x's set, given p, a value parent[x] has held (a caller may load it
+// early, beside other loads).  Links only ever point closer to a root, so a
+// stale p still leads to the current root.  Path halving on the way; a
+// parent found to be its own parent is returned without loading it again.
+__device__ __forceinline__ uint32_t uf_find_at(uint32_t* parent, uint32_t x, uint32_t p) {
     for (;;) {
-        const uint32_t p = load_acq(&parent[x]);
         if (p == x) return x;
         const uint32_t gp = load_acq(&parent[p]);
-        if (gp != p) store_rel(&parent[x], gp);
+        if (gp == p) return p;
+        store_rel(&parent[x], gp);
         x = gp;
+        p = load_acq(&parent[x]);
     }
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t* parent, uint32_t x) {
+    return uf_find_at(parent, x, load_acq(&parent[x]));
 }
 
 __device__ __forceinline__ void uf_union(uint32_t* parent, uint32_t a, uint32_t b) {

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     const uint32_t T = cell_inst(gv, ci).T;
     const uint4 own = rank[ci];
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    const uint32_t pci = load_acq(&parent[ci]);
     const uint32_t bi = own.y;
     const uint32_t mi = own.z;
     if (mi > kSmallSet) return;
@@ -65,13 +66,15 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
         for (int k = 0; k < D; ++k) pi[a][k] = uniform((uint32_t)a < mi ? t[k] : 0);
     }
     unsigned long long n_pairs = 0, n_skip = 0, n_yes = 0, n_dist = 0, n_pts = 0;
-    uint32_t ri = uf_find(parent, ci);  // root hint of g_i's set
+    uint32_t ri = uf_find_at(parent, ci, pci);  // root hint of g_i's set
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
         bool cand = false;
-        uint32_t cj = 0, bj = 0, mj = 0;
+        uint32_t cj = 0, bj = 0, mj = 0, pj = 0;
         if (idx < e1) {
             cj = nei[idx];
+            // the parent link loads beside the record (every grid has one)
+            pj = load_acq(&parent[cj]);
             const uint4 rc = rank[cj];
             const uint32_t rj = rc.x;
             if (rj != kNone && rj > (uint32_t)r) {
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
         }
         // pairs already in one set are skipped; the root found is the hint
         // for the union
-        uint32_t root_j = cand ? uf_find(parent, cj) : 0u;
+        uint32_t root_j = cand ? uf_find_at(parent, cj, pj) : 0u;
         const bool test = cand && root_j != ri;
         bool yes = false;
         if (test) {
@@ -149,9 +152,10 @@ __device__ __forceinline__ uint32_t orderable(float z) {
 
 // The kernel is bound by the latency of union-find and FastMerging steps:
 // six waves per SIMD (at most 85 registers) hide more of it than wider
-// unrolling inside a wave.
+// unrolling inside a wave.  The scorer's fragments do not fit in that
+// budget (they would spill to scratch), so the learned variant runs four.
 template <int D, bool kLearned>
-__global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+__global__ __launch_bounds__(kBlock, kLearned ? 4 : 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
                                                            const uint4* __restrict__ rank, int64_t r0, int64_t r1,
@@ -178,6 +182,7 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
     const Inst& I = cell_inst(gv, ci);
     const uint4 own = rank[ci];
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    const uint32_t pci = load_acq(&parent[ci]);
     const uint32_t T = I.T;
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, own.y, own.z, smem + (int64_t)w * 2 * words, 0};
@@ -189,13 +194,15 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
     si.words = (si.m + kWave - 1) / kWave;
     PointSet sj{co.ccrd, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
-    uint32_t ri = uf_find(parent, ci);
+    uint32_t ri = uf_find_at(parent, ci, pci);
     for (uint64_t e = e0; e < e1; e += kWave) {
         const uint64_t idx = e + lane;
-        uint32_t cj = 0, bj = 0, mj = 0;
+        uint32_t cj = 0, bj = 0, mj = 0, pj = 0;
         bool cand = false;
         if (idx < e1) {
             cj = nei[idx];
+            // the parent link loads beside the record (every grid has one)
+            pj = load_acq(&parent[cj]);
             const uint4 rc = rank[cj];
             const uint32_t rj = rc.x;
             if (rj != kNone) {
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(kBlock, 6) void merge_big_kernel(GridView gv, CoreO
             }
         }
         // root of each candidate's set, kept as the hint for a union
-        uint32_t root_j = cand ? uf_find(parent, cj) : 0u;
+        uint32_t root_j = cand ? uf_find_at(parent, cj, pj) : 0u;
         const bool pend_l = cand && root_j != ri;
         const uint64_t cands = ballot(cand);
         uint64_t pend = ballot(pend_l);

@@ -18,6 +18,7 @@
 //             each level in sorted order, so every node's children are
 //             contiguous and their keys ascend
 #include <algorithm>
+#include <type_traits>
 #include <climits>
 
 #include "launch.hpp"
@@ -104,6 +105,21 @@ __device__ __forceinline__ void minmax_tile(Inst& I, int64_t lo, int64_t hi, int
 // Each workgroup leaves its tile's minima and maxima in part (one 64-byte
 // record per tile, plain stores: a few thousand workgroups updating the same
 // two words with device atomics serialise on them).
+// Calls f(std::integral_constant<int, d>) for 1 <= d <= DB, the batch's
+// largest dimension: a kernel compiled for DB holds registers for d <= DB
+// only (one compiled for every d would size them all for d = 8).
+template <int DB, int D = 1, typename F>
+__device__ __forceinline__ void with_d(int d, F&& f) {
+    if constexpr (D < DB) {
+        if (d != D) {
+            with_d<DB, D + 1>(d, f);
+            return;
+        }
+    }
+    f(std::integral_constant<int, D>{});
+}
+
+template <int DB>
 __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b, int32_t* __restrict__ part) {
     constexpr int kWaves = kBlock / kWave;
     __shared__ int smn[kWaves * kMaxD], smx[kWaves * kMaxD];
@@ -112,16 +128,7 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b, int32_t* __rest
     const int d = I.d;
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
     const int64_t hi = min(I.n, lo + b.tile_pts);
-    switch (d) {
-        case 1: minmax_tile<1>(I, lo, hi, smn, smx); break;
-        case 2: minmax_tile<2>(I, lo, hi, smn, smx); break;
-        case 3: minmax_tile<3>(I, lo, hi, smn, smx); break;
-        case 4: minmax_tile<4>(I, lo, hi, smn, smx); break;
-        case 5: minmax_tile<5>(I, lo, hi, smn, smx); break;
-        case 6: minmax_tile<6>(I, lo, hi, smn, smx); break;
-        case 7: minmax_tile<7>(I, lo, hi, smn, smx); break;
-        default: minmax_tile<8>(I, lo, hi, smn, smx); break;
-    }
+    with_d<DB>(d, [&](auto dc) { minmax_tile<decltype(dc)::value>(I, lo, hi, smn, smx); });
     __syncthreads();
     if (threadIdx.x < (unsigned)d) {
         const int j = threadIdx.x;
@@ -204,7 +211,7 @@ __global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, 
 
 hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st) {
     if (b.tiles == 0) return hipSuccess;
-    minmax_kernel<<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, part);
+    GD_DISPATCH_D(b.D, (minmax_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, part)));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     minmax_finish_kernel<<<dim3(b.count), dim3(kFinishThreads), 0, st>>>(b, part);
@@ -303,7 +310,7 @@ __device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi,
     });
 }
 
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys) {
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
@@ -320,22 +327,13 @@ __global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ k
     const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
     const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
     const int64_t hi = min(I.n, lo + b.tile_pts);
-    switch (I.d) {
-        case 1: keys_tile<1, K>(I, lo, hi, top, keys); break;
-        case 2: keys_tile<2, K>(I, lo, hi, top, keys); break;
-        case 3: keys_tile<3, K>(I, lo, hi, top, keys); break;
-        case 4: keys_tile<4, K>(I, lo, hi, top, keys); break;
-        case 5: keys_tile<5, K>(I, lo, hi, top, keys); break;
-        case 6: keys_tile<6, K>(I, lo, hi, top, keys); break;
-        case 7: keys_tile<7, K>(I, lo, hi, top, keys); break;
-        default: keys_tile<8, K>(I, lo, hi, top, keys); break;
-    }
+    with_d<DB>(I.d, [&](auto dc) { keys_tile<decltype(dc)::value, K>(I, lo, hi, top, keys); });
 }
 
 template <typename K>
 hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st) {
     if (b.tiles == 0) return hipSuccess;
-    keys_kernel<K><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, keys);
+    GD_DISPATCH_D(b.D, (keys_kernel<K, D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, keys)));
     return hipGetLastError();
 }
 template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, hipStream_t);

@@ -64,10 +64,30 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
         k[r] = (full || i < n) ? keys[i] : K(0);
     }
+    // Lanes hold neighbouring keys, and after the first passes a run of
+    // neighbouring keys often shares the digit (a whole grid's points do in
+    // the last pass); same-address LDS atomics of one instruction serialise.
+    // So the keys that share the digit of the first lane still to count are
+    // counted by one atomic, as long as such groups have eight keys or more
+    // (at most eight groups); the rest count one by one (on random digits:
+    // one check per round).
+    const int lane = lane_id();
 #pragma unroll
     for (int r = 0; r < kRadixItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
-        if (full || i < n) atomicAdd(&h[w][(uint32_t)(k[r] >> shift) & mask], 1u);
+        const bool v = full || i < n;
+        const uint32_t dg = (uint32_t)(k[r] >> shift) & mask;
+        uint64_t rem = ballot(v);
+        while (rem) {
+            const int l0 = ffs64(rem);
+            const uint32_t d0 = readlane(dg, l0);
+            const uint64_t m = ballot(dg == d0) & rem;
+            const uint32_t c = (uint32_t)popc64(m);
+            if (c < 8u) break;
+            if (lane == l0) atomicAdd(&h[w][d0], c);
+            rem &= ~m;
+        }
+        if ((rem >> lane) & 1ull) atomicAdd(&h[w][dg], 1u);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < bins; t += kBlock) {
