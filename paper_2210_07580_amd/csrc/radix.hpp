@@ -1,16 +1,17 @@
 // Stable LSD radix sort of (key, u32 value) pairs for the grid identifiers
-// of Section 4.1 (Algorithm 1 line 2 sorts the points by identifier with a
-// radix sort).  A sort of B bits takes ceil(B / 8) passes of equal digits
+// of Section 4.1 (Algorithm 1 orders the points by identifier with a radix
+// sort).  A sort of B bits takes ceil(B / 8) passes of equal digits
 // of at most 8 bits (wider digits cost more per pass than the pass they
 // save: a 4x larger offset table to scan, more ranking ballots and less
 // occupancy).
 //
 // Each pass is reduce-then-scan: (1) every workgroup builds the digit
-// histogram of its 4096-key tile in LDS (one sub-histogram per wave to cut
-// atomic contention); (2) a device-wide exclusive scan over the
+// histogram of its tile (4096 keys, 1024 in sorts of at most 2^21 keys) in
+// LDS (one sub-histogram per wave to cut atomic contention); (2) a
+// device-wide exclusive scan over the
 // digit-major [bins][tiles] table gives every (digit, tile) its output base;
-// (3) every workgroup re-reads its tile; each wave takes a run of 1024
-// consecutive keys and ranks them among equal digits with wave64 ballots
+// (3) every workgroup re-reads its tile; each wave takes a run of a quarter
+// of it (consecutive keys) and ranks them among equal digits with wave64 ballots
 // (one ballot per digit bit gives the lanes holding the same digit; the rank
 // is the popcount below the lane plus the wave's running count of that
 // digit, kept in LDS), one scan over (digit, wave) turns the counts into
@@ -19,24 +20,38 @@
 // follow input order, so every pass is stable.
 #pragma once
 
+#include <algorithm>
+
 #include "scan.hpp"
 
 namespace gd {
 
-constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kBlock * kRadixItems;
+// Keys per thread of a tile: 16 (4096-key tiles), or 4 (1024-key tiles) for
+// sorts of at most kRadixSmallMax keys, which would otherwise have fewer
+// tiles than the GPU has compute units, each ranked by one long chain of
+// wave steps.
+constexpr int kRadixItemsBig = 16;
+constexpr int kRadixItemsSmall = 4;
+constexpr int64_t kRadixSmallMax = 1 << 21;
 
 template <typename K>
 constexpr int radix_max_bits() { return 8; }
 template <typename K>
 constexpr int radix_max_bins() { return 1 << radix_max_bits<K>(); }
 
-inline int64_t radix_tiles(int64_t n) { return (n + kRadixTile - 1) / kRadixTile; }
-// u32 entries of scratch needed for a sort of n keys (any key type)
-inline int64_t radix_scratch_words(int64_t n) {
+inline int radix_items(int64_t n) { return n <= kRadixSmallMax ? kRadixItemsSmall : kRadixItemsBig; }
+inline int64_t radix_tiles(int64_t n) {
+    const int64_t tile = (int64_t)kBlock * radix_items(n);
+    return (n + tile - 1) / tile;
+}
+inline int64_t radix_scratch_words_for(int64_t n) {
     const int64_t t = radix_tiles(n);
     constexpr int64_t bins = 1 << 8;
     return 2 * bins * t + scan_partial_cap(bins * t) + 4;
+}
+// u32 entries of scratch enough for a sort of any m <= n keys (any key type)
+inline int64_t radix_scratch_words(int64_t n) {
+    return std::max(radix_scratch_words_for(n), radix_scratch_words_for(std::min(n, kRadixSmallMax)));
 }
 
 // Neighbouring tiles write neighbouring addresses (their counts in the
@@ -44,7 +59,7 @@ inline int64_t radix_scratch_words(int64_t n) {
 // workgroup b takes tile xcd_order(b): every XCD then writes one contiguous
 // range, and a line is written from one L2 instead of being merged from
 // partial copies in several.
-template <typename K>
+template <typename K, int kItems>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift, int rbits,
                                                             uint32_t* __restrict__ hist, int64_t tiles) {
     constexpr int kMaxBins = radix_max_bins<K>();
@@ -52,15 +67,16 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     const int bins = 1 << rbits;
     for (int i = threadIdx.x; i < kWavesPerBlock * kMaxBins; i += kBlock) (&h[0][0])[i] = 0;
     __syncthreads();
+    constexpr int kTile = kBlock * kItems;
     const int64_t tile = xcd_order(blockIdx.x, tiles);
-    const int64_t base = tile * kRadixTile;
+    const int64_t base = tile * kTile;
     const int w = wave_id();
     const uint32_t mask = (uint32_t)bins - 1u;
     // all loads of the tile in flight before the first count
-    K k[kRadixItems];
-    const bool full = base + kRadixTile <= n;
+    K k[kItems];
+    const bool full = base + kTile <= n;
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
         k[r] = (full || i < n) ? keys[i] : K(0);
     }
@@ -73,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     // one check per round).
     const int lane = lane_id();
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < kItems; ++r) {
         const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
         const bool v = full || i < n;
         const uint32_t dg = (uint32_t)(k[r] >> shift) & mask;
@@ -98,17 +114,18 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     }
 }
 
-template <typename K, bool kIota>
+template <typename K, bool kIota, int kItems>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                                K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
                                                                int64_t n, int shift, int rbits,
                                                                const uint32_t* __restrict__ offs, int64_t tiles) {
     constexpr int kMaxBins = radix_max_bins<K>();
     constexpr int kDigitsPerThread = kMaxBins / kBlock;  // 4 or 2
-    constexpr int kPerWave = kRadixTile / kWavesPerBlock;  // 1024 consecutive keys per wave
-    constexpr int kIters = kPerWave / kWave;               // 16
-    __shared__ K skey[kRadixTile];                          // the tile, ordered by digit (stable)
-    __shared__ uint32_t sval[kRadixTile];
+    constexpr int kTile = kBlock * kItems;
+    constexpr int kPerWave = kTile / kWavesPerBlock;       // 64 kItems consecutive keys per wave
+    constexpr int kIters = kPerWave / kWave;               // kItems
+    __shared__ K skey[kTile];                               // the tile, ordered by digit (stable)
+    __shared__ uint32_t sval[kTile];
     __shared__ uint32_t wcnt[kWavesPerBlock][kMaxBins];     // keys per (wave, digit), then first local slot
     __shared__ uint32_t gbase[kMaxBins];                    // global slot of a digit's first key, minus its local start
     __shared__ uint32_t wsum[kWavesPerBlock];
@@ -122,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     // neighbouring tiles on one XCD (see xcd_order): their runs of a digit are
     // neighbours in the output
     const int64_t tile = xcd_order(blockIdx.x, tiles);
-    const int64_t base = tile * kRadixTile;
-    const int tile_n = (int)min((int64_t)kRadixTile, n - base);
+    const int64_t base = tile * kTile;
+    const int tile_n = (int)min((int64_t)kTile, n - base);
     const uint64_t lt = lanemask_lt();
     // 1. each wave ranks its own run of keys among equal digits, in order,
     //    with wave-private counters (no workgroup barrier)
@@ -250,19 +267,30 @@ hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals
     bool iota = vals_iota;
     const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
     const int rbits = passes ? (bits + passes - 1) / passes : 0;
+    const bool small = radix_items(n) == kRadixItemsSmall;
     for (int p = 0, shift = 0; p < passes; ++p, shift += rbits) {
         if (n == 0) break;
         const int64_t bins = (int64_t)1 << rbits;
-        radix_hist_kernel<K><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, n, shift, rbits, hist, tiles);
+        const dim3 grid((unsigned)tiles), block(kBlock);
+        if (small)
+            radix_hist_kernel<K, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, n, shift, rbits, hist, tiles);
+        else
+            radix_hist_kernel<K, kRadixItemsBig><<<grid, block, 0, st>>>(kin, n, shift, rbits, hist, tiles);
         hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, bins * tiles, offs, (uint32_t*)nullptr,
                                                 partial, st);
         if (e != hipSuccess) return e;
-        if (iota)
-            radix_scatter_kernel<K, true><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                        rbits, offs, tiles);
+        if (small && iota)
+            radix_scatter_kernel<K, true, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
+                                                                                   rbits, offs, tiles);
+        else if (small)
+            radix_scatter_kernel<K, false, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
+                                                                                    rbits, offs, tiles);
+        else if (iota)
+            radix_scatter_kernel<K, true, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
+                                                                                 rbits, offs, tiles);
         else
-            radix_scatter_kernel<K, false><<<dim3((unsigned)tiles), dim3(kBlock), 0, st>>>(kin, vin, kout, vout, n,
-                                                                                         shift, rbits, offs, tiles);
+            radix_scatter_kernel<K, false, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
+                                                                                  rbits, offs, tiles);
         iota = false;
         K* tk = kin; kin = kout; kout = (first && keys_spare) ? keys_spare : tk;
         first = false;
