@@ -414,8 +414,9 @@ struct KeyChange {
     }
 };
 
-// Runs of equal identifiers, written from the scan of "identifier changes
-// here": the grid of sorted point s is (changes up to s) - 1.
+// Runs of equal identifiers, from the flag scan of "identifier changes
+// here": the change at sorted position s starts grid c (its rank among the
+// changes); end() closes the last run.
 template <typename K>
 struct CellWriter {
     Batch b;
@@ -423,37 +424,38 @@ struct CellWriter {
     uint32_t* cell_start;
     int32_t* ck;
     int64_t ck_stride;
-    __device__ void operator()(int64_t s, uint32_t ex, uint32_t first) const {
-        const uint32_t c = ex + first - 1u;
-        if (first) {
-            const K key = skeys[s];
-            cell_start[c] = (uint32_t)s;
+    // s: first sorted position of grid c
+    __device__ void operator()(int64_t s, uint32_t c) const {
+        const K key = skeys[s];
+        cell_start[c] = (uint32_t)s;
+        int k = 0;
+        if (b.count > 1) {
             const int ishift = b.hdr->inst_shift;
-            int k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
+            k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
             if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
-            const Inst& I = b.inst[k];
-            ck[c] = k;
+        }
+        const Inst& I = b.inst[k];
+        ck[c] = k;
 #pragma unroll
-            for (int j = 0; j < kMaxD; ++j) {
-                if (j < b.D) {
-                    int32_t v = 0;
-                    if (j < I.d) {
-                        const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
-                        v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
-                    }
-                    ck[(int64_t)(j + 1) * ck_stride + c] = v;
+        for (int j = 0; j < kMaxD; ++j) {
+            if (j < b.D) {
+                int32_t v = 0;
+                if (j < I.d) {
+                    const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
+                    v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
                 }
+                ck[(int64_t)(j + 1) * ck_stride + c] = v;
             }
         }
-        if (s == b.n - 1) cell_start[c + 1] = (uint32_t)b.n;
     }
+    __device__ void end(uint32_t ncell) const { cell_start[ncell] = (uint32_t)b.n; }
 };
 
 template <typename K>
 hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* partial, uint32_t* cell_start,
                         int32_t* ck, int64_t ck_stride, hipStream_t st) {
-    return scan_apply<uint32_t>(KeyChange<K>{skeys}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
-                                &b.hdr->ncell, partial, st);
+    return scan_flags_apply(KeyChange<K>{skeys}, b.n, CellWriter<K>{b, skeys, cell_start, ck, ck_stride},
+                            &b.hdr->ncell, partial, st);
 }
 template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32_t*, uint32_t*, int32_t*,
                                            int64_t, hipStream_t);

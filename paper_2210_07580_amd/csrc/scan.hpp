@@ -193,6 +193,103 @@ hipError_t scan_apply(F f, int64_t n, O o, T* total, T* partial, hipStream_t st)
     return hipGetLastError();
 }
 
+// Scans of 0/1 flags whose output only concerns the set flags: w(i, r) for
+// every i with f(i) = 1, r = its rank among the set flags, then w.end(total)
+// once.  The scan pass needs no LDS transpose and no workgroup scan: wave w
+// of the workgroup takes the w-th quarter of the reduce pass's tile, 64
+// consecutive elements per round, and one ballot per round ranks the lanes.
+// The set flags of the wave are listed in LDS and handed out one per lane,
+// so the writer's loads for different flags are in flight together (called
+// in place, each set flag would wait for the previous one's stores).
+template <int kItems, typename F, typename W>
+__global__ __launch_bounds__(kBlock) void flag_down_kernel(F f, int64_t n, const uint32_t* partial, W wr,
+                                                           uint32_t* total) {
+    constexpr int kPerWave = kWave * kItems;
+    __shared__ uint32_t wcnt[kWavesPerBlock], wcarry[kWavesPerBlock];
+    __shared__ uint16_t list[kWavesPerBlock][kPerWave];
+    const int t = threadIdx.x, w = wave_id(), lane = lane_id();
+    const int64_t tile0 = (int64_t)blockIdx.x * kBlock * kItems;
+    const int64_t base = tile0 + (int64_t)w * kPerWave + lane;
+    uint32_t v[kItems];
+    if (tile0 + (int64_t)kBlock * kItems <= n) {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) v[r] = f(base + (int64_t)r * kWave);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+            const int64_t i = base + (int64_t)r * kWave;
+            v[r] = i < n ? f(i) : 0u;
+        }
+    }
+    uint32_t acc[8] = {};
+    for (int64_t b0 = t; b0 < (int64_t)blockIdx.x; b0 += 8 * kBlock) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t b = b0 + (int64_t)u * kBlock;
+            if (b < (int64_t)blockIdx.x) acc[u] += partial[b];
+        }
+    }
+    uint32_t carry = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) carry += acc[u];
+    carry = wave_sum(carry);
+    // rank within the wave's run; the run's set flags listed in order
+    const uint64_t lt = lanemask_lt();
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        const uint64_t m = ballot(v[r] != 0u);
+        if (v[r]) list[w][cnt + (uint32_t)popc64(m & lt)] = (uint16_t)(r * kWave + lane);
+        cnt += (uint32_t)popc64(m);
+    }
+    if (lane == 0) {
+        wcnt[w] = cnt;
+        wcarry[w] = carry;
+    }
+    __syncthreads();
+    uint32_t c = 0, before = 0, all = 0;
+#pragma unroll
+    for (int ww = 0; ww < kWavesPerBlock; ++ww) {
+        c += wcarry[ww];
+        before += ww < w ? wcnt[ww] : 0u;
+        all += wcnt[ww];
+    }
+    const int64_t run0 = tile0 + (int64_t)w * kPerWave;
+    for (uint32_t j = (uint32_t)lane; j < cnt; j += kWave) wr(run0 + list[w][j], c + before + j);
+    if (blockIdx.x == gridDim.x - 1 && t == 0) {
+        if (total) *total = c + all;
+        wr.end(c + all);
+    }
+}
+
+// The same writer on the general scan (short inputs): w for each set flag,
+// w.end after the last element.
+template <typename W>
+struct FlagOut {
+    W wr;
+    int64_t n;
+    __device__ void operator()(int64_t i, uint32_t ex, uint32_t v) const {
+        if (v) wr(i, ex);
+        if (i == n - 1) wr.end(ex + v);
+    }
+};
+
+// Flag scan with a writer of the set flags (see flag_down_kernel); with
+// n = 0 the writer is not called.
+template <typename F, typename W>
+hipError_t scan_flags_apply(F f, int64_t n, W wr, uint32_t* total, uint32_t* partial, hipStream_t st) {
+    const int64_t nb = scan_blocks(n);
+    if (nb == 0 || n <= kSingleScanMax) return scan_apply<uint32_t>(f, n, FlagOut<W>{wr, n}, total, partial, st);
+    if (scan_items(n) == kScanItemsBig) {
+        scan_reduce_kernel<uint32_t, kScanItemsBig, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
+        flag_down_kernel<kScanItemsBig, F, W><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, wr, total);
+    } else {
+        scan_reduce_kernel<uint32_t, kScanItemsMid, F><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial);
+        flag_down_kernel<kScanItemsMid, F, W><<<dim3((unsigned)nb), dim3(kBlock), 0, st>>>(f, n, partial, wr, total);
+    }
+    return hipGetLastError();
+}
+
 // out[i] = sum_{k < i} f(k) for 0 <= i < n; *total = sum of all (device).
 template <typename T, typename F>
 hipError_t scan_exclusive(F f, int64_t n, T* out, T* total, T* partial, hipStream_t st) {
