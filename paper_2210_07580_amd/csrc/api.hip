@@ -340,8 +340,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(fill<unsigned long long>(&ctx->stats_dev->merge[0].pairs,
                                         (int64_t)(sizeof(StatBlock) / sizeof(unsigned long long)), 0ull, st));
     ctx->mark(P_MINMAX, 0);
-    GD_TRY(launch_minmax(b, L.tile_mm, st));
-    GD_TRY(launch_layout(b, plan ? plan->key_bits : 64, st));
+    GD_TRY(launch_minmax(b, L.tile_mm, plan ? plan->key_bits : 64, st));
     ctx->mark(P_MINMAX, 1);
     if (!plan && (rc = readback(ctx, st))) return rc;
     if (!plan && (H->err & kErrNotInteger)) {

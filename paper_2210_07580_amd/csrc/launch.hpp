@@ -117,10 +117,10 @@ __device__ __forceinline__ const Inst& cell_inst(const GridView& g, int64_t c) {
 }
 
 // ---- partition.hip
-// part: scratch of 2 * kMaxD int32 per point tile.
-hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st);
-// plan_bits: identifier bits a sync-free run sorts (64 otherwise); more raise kErrPlan.
-hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st);
+// Minima and maxima of every instance, then the identifier layout.  part:
+// scratch of 2 * kMaxD int32 per point tile; plan_bits: identifier bits a
+// sync-free run sorts (64 otherwise); more raise kErrPlan.
+hipError_t launch_minmax(const Batch& b, int32_t* part, int plan_bits, hipStream_t st);
 // Sync-free runs: compare the device counts with the capacities the run was
 // planned with (stage 0: grids; 1: neighbour entries; 2: core grids and the
 // largest core set).  On overflow, or after an input error, kErrPlan goes up

@@ -144,10 +144,51 @@ __global__ __launch_bounds__(kBlock) void minmax_kernel(Batch b, int32_t* __rest
     }
 }
 
+__device__ __forceinline__ int bit_length_u64(uint64_t v) { return v == 0 ? 0 : 64 - __clzll((long long)v); }
+
+__device__ __forceinline__ uint64_t isqrt_u64(uint64_t y) {
+    uint64_t r = (uint64_t)sqrt((double)y);
+    while (r * r > y) --r;
+    while ((r + 1) * (r + 1) <= y) ++r;
+    return r;
+}
+
+// Field widths and shifts of instance I's identifiers from its minima and
+// maxima; returns the identifier's bit count.
+__device__ int inst_layout(Inst& I, const int* mn, const int* mx) {
+    int total = 0;
+    for (int j = 0; j < I.d; ++j) {
+        const uint64_t u = I.n > 0 ? (uint64_t)((int64_t)mx[j] - mn[j]) : 0;
+        const uint64_t kmax = isqrt_u64((uint64_t)I.d * u * u) / (uint64_t)I.eps;
+        I.bits[j] = bit_length_u64(kmax);
+        total += I.bits[j];
+    }
+    for (int j = I.d - 1, sh = 0; j >= 0; --j) {
+        I.shift[j] = sh;
+        sh += I.bits[j];
+    }
+    I.key_bits = total;
+    return total;
+}
+
+// Batch-wide layout: instance ids above the widest identifier.
+__device__ void batch_layout(const Batch& b, int max_bits, uint32_t err, int plan_bits) {
+    const int inst_bits = bit_length_u64((uint64_t)(b.count - 1));
+    b.hdr->inst_shift = max_bits;
+    b.hdr->total_bits = max_bits + inst_bits;
+    if (max_bits + inst_bits > 64) err |= kErrKeyBits;
+    if (max_bits + inst_bits > plan_bits) err |= kErrPlan;
+    b.hdr->err = err;
+}
+
 // One workgroup of 1024 threads per instance folds its tiles' records into mn
 // and mx (a few thousand records: more threads, fewer dependent rounds).
+// With kLayout (a batch of one instance) the same workgroup then lays out
+// the identifiers, which saves the layout launch.
 constexpr int kFinishThreads = 1024;
-__global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, const int32_t* __restrict__ part) {
+template <bool kLayout>
+__global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, const int32_t* __restrict__ part,
+                                                                       int plan_bits) {
     constexpr int kWaves = kFinishThreads / kWave;
     __shared__ int smn[kWaves * kMaxD], smx[kWaves * kMaxD];
     Inst& I = const_cast<Inst&>(b.inst[blockIdx.x]);
@@ -196,6 +237,7 @@ __global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, 
         dst[3] = acc.w;
     }
     __syncthreads();
+    __shared__ int fmn[kMaxD], fmx[kMaxD];
     if (threadIdx.x < (unsigned)d) {
         const int j = threadIdx.x;
         int a = smn[j], c = smx[j];
@@ -206,25 +248,30 @@ __global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, 
         }
         I.mn[j] = a;
         I.mx[j] = c;
+        fmn[j] = a;
+        fmx[j] = c;
+    }
+    if constexpr (kLayout) {
+        __syncthreads();
+        if (threadIdx.x == 0) batch_layout(b, inst_layout(I, fmn, fmx), I.err, plan_bits);
     }
 }
 
-hipError_t launch_minmax(const Batch& b, int32_t* part, hipStream_t st) {
-    if (b.tiles == 0) return hipSuccess;
+hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st);
+
+hipError_t launch_minmax(const Batch& b, int32_t* part, int plan_bits, hipStream_t st) {
+    if (b.tiles == 0) return launch_layout(b, plan_bits, st);
     GD_DISPATCH_D(b.D, (minmax_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, part)));
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    minmax_finish_kernel<<<dim3(b.count), dim3(kFinishThreads), 0, st>>>(b, part);
-    return hipGetLastError();
-}
-
-__device__ __forceinline__ int bit_length_u64(uint64_t v) { return v == 0 ? 0 : 64 - __clzll((long long)v); }
-
-__device__ __forceinline__ uint64_t isqrt_u64(uint64_t y) {
-    uint64_t r = (uint64_t)sqrt((double)y);
-    while (r * r > y) --r;
-    while ((r + 1) * (r + 1) <= y) ++r;
-    return r;
+    if (b.count == 1) {
+        minmax_finish_kernel<true><<<dim3(1), dim3(kFinishThreads), 0, st>>>(b, part, plan_bits);
+        return hipGetLastError();
+    }
+    minmax_finish_kernel<false><<<dim3(b.count), dim3(kFinishThreads), 0, st>>>(b, part, plan_bits);
+    const hipError_t e2 = hipGetLastError();
+    if (e2 != hipSuccess) return e2;
+    return launch_layout(b, plan_bits, st);
 }
 
 // One workgroup: per-instance field widths, then the batch-wide layout.
@@ -238,31 +285,11 @@ __global__ __launch_bounds__(kBlock) void layout_kernel(Batch b, int plan_bits) 
     __syncthreads();
     for (int k = threadIdx.x; k < b.count; k += kBlock) {
         Inst& I = const_cast<Inst&>(b.inst[k]);
-        int total = 0;
-        for (int j = 0; j < I.d; ++j) {
-            const uint64_t u = I.n > 0 ? (uint64_t)((int64_t)I.mx[j] - I.mn[j]) : 0;
-            const uint64_t kmax = isqrt_u64((uint64_t)I.d * u * u) / (uint64_t)I.eps;
-            I.bits[j] = bit_length_u64(kmax);
-            total += I.bits[j];
-        }
-        for (int j = I.d - 1, s = 0; j >= 0; --j) {
-            I.shift[j] = s;
-            s += I.bits[j];
-        }
-        I.key_bits = total;
-        atomicMax(&s_max, total);
+        atomicMax(&s_max, inst_layout(I, I.mn, I.mx));
         if (I.err) atomicOr(&s_err, I.err);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int inst_bits = bit_length_u64((uint64_t)(b.count - 1));
-        b.hdr->inst_shift = s_max;
-        b.hdr->total_bits = s_max + inst_bits;
-        uint32_t e = s_err;
-        if (s_max + inst_bits > 64) e |= kErrKeyBits;
-        if (s_max + inst_bits > plan_bits) e |= kErrPlan;
-        b.hdr->err = e;
-    }
+    if (threadIdx.x == 0) batch_layout(b, s_max, s_err, plan_bits);
 }
 
 hipError_t launch_layout(const Batch& b, int plan_bits, hipStream_t st) {
