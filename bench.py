@@ -38,7 +38,7 @@ WORKLOAD_DESC = {
 # The kernels each timed phase launches (a phase is the run of launches
 # between two events; the kernel traces under profiles/ list them one by one).
 PHASE_KERNELS = {
-    "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel"],
+    "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel (batches of several instances)"],
     "keys": ["keys_kernel"],
     "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel"],
     "gather": ["gather_kernel"],
