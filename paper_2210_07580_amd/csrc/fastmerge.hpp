@@ -116,11 +116,17 @@ __device__ __forceinline__ void load_lane_point(const PointSet& s, uint32_t w, i
     load_point<D>(s, pos, x);
 }
 
-// argmin over live y of D(p, y): returns (D << 32 | position)
+// argmin over live y of D(p, y): returns (D << 32 | position), and the
+// winning point's row in `row` (from the winning lane's registers: no second
+// load of it).  s must hold a live point.
 template <int D>
-__device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p)[D], unsigned long long& ndist) {
+__device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p)[D], unsigned long long& ndist,
+                                            int32_t (&row)[D]) {
     const int lane = lane_id();
     uint64_t best = ~0ull;
+    int32_t br[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) br[k] = 0;
     for (uint32_t w0 = 0; w0 < s.words; w0 += kUnroll) {
         uint64_t mk[kUnroll];
         int32_t y[kUnroll][D];
@@ -138,11 +144,20 @@ __device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p
 #pragma unroll
                 for (int k = 0; k < D; ++k) dd += sq24(y[u][k], p[k]);
                 const uint64_t cand = ((uint64_t)dd << 32) | ((w0 + u) * kWave + lane);
-                best = cand < best ? cand : best;
+                if (cand < best) {
+                    best = cand;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) br[k] = y[u][k];
+                }
             }
         }
     }
-    return wave_min_u64(best);
+    const uint64_t m = wave_min_u64(best);
+    // position % 64 is the lane that found it
+    const int wl = __builtin_amdgcn_readfirstlane((int)((uint32_t)m & (uint32_t)(kWave - 1)));
+#pragma unroll
+    for (int k = 0; k < D; ++k) row[k] = readlane(br[k], wl);
+    return m;
 }
 
 __device__ __forceinline__ float wave_min_f32(float v) {
@@ -280,23 +295,19 @@ __device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T
     init_alive<D>(si);
     init_alive<D>(sj);
     wave_sync();
-    uint32_t p = start;
     const uint32_t bound = si.m + sj.m + 2;
+    // P: the current point of si (first the start point), Q: its nearest in sj
+    int32_t P[D], Q[D];
+    load_point<D>(si, start, P);
     for (iters = 1;; ++iters) {
         if (iters > bound) return -1;
-        int32_t P[D];
-        load_point<D>(si, p, P);
-        const uint64_t bq = nearest<D>(sj, P, ndist);
-        const uint32_t dq = (uint32_t)(bq >> 32), q = (uint32_t)bq;
+        const uint64_t bq = nearest<D>(sj, P, ndist, Q);
+        const uint32_t dq = (uint32_t)(bq >> 32);
         if (dq <= T) return 1;
-        int32_t Q[D];
-        load_point<D>(sj, q, Q);
         if (!pruning<D>(si, sj, P, Q, dq, T, eps, ndist)) return 0;
-        const uint64_t bp = nearest<D>(si, Q, ndist);
+        const uint64_t bp = nearest<D>(si, Q, ndist, P);
         const uint32_t dp = (uint32_t)(bp >> 32);
-        p = (uint32_t)bp;
         if (dp <= T) return 1;
-        load_point<D>(si, p, P);
         if (!pruning<D>(sj, si, Q, P, dp, T, eps, ndist)) return 0;
     }
 }
