@@ -147,11 +147,23 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
 // The list of grid c holds its offset-0 neighbours, then offset 1, ...; within
 // one offset value the lanes' parts follow each other in lane order.  With a
 // split, each lane first counts its part again to find where its entries go.
+// With one lane per grid (long lists per lane), found neighbours are staged
+// in LDS and stored kFillStage at a time: gfx9 counts outstanding vector
+// loads and stores with one in-order counter, so a store issued between two
+// loads of the tree walk would make the second wait for it; in bursts, the
+// walk waits once per kFillStage entries (cfg2-like data: 59 -> 52 ms; 4
+// entries gave 56 ms, 16 cost occupancy and gave 68 ms).  A split walk
+// emits a few entries per lane, and staging them only costs.
+constexpr int kFillStage = 8;
+
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView t, const uint32_t* __restrict__ off_counts,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
                                                           uint64_t capacity) {
     __shared__ uint32_t pos[D][kBlock];
+    constexpr int kStage = P == 1 ? kFillStage : 1;
+    __shared__ uint32_t stage_a[kStage][kBlock];
+    __shared__ uint8_t stage_o[kStage][kBlock];
     const int64_t ncell = *gv.ncell_dev;
     if (nei_off[ncell] > capacity) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&gv.b.hdr->err, kErrNeiOverflow);
@@ -189,14 +201,31 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     int32_t g[D + 1];
     load_grid<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
+    int staged = 0;
+    auto flush = [&]() {
+        for (int j = 0; j < staged; ++j) {
+            const uint32_t a = stage_a[j][threadIdx.x];
+            const int o = stage_o[j][threadIdx.x];
+            const uint32_t k = pos[o][threadIdx.x];
+            pos[o][threadIdx.x] = k + 1;
+            nei[base + k] = a;
+        }
+        staged = 0;
+    };
     auto emit = [&](uint32_t a, int o) {
-        if (a != (uint32_t)c) {
+        if (a == (uint32_t)c) return;
+        if constexpr (P == 1) {
+            stage_a[staged][threadIdx.x] = a;
+            stage_o[staged][threadIdx.x] = (uint8_t)o;
+            if (++staged == kStage) flush();
+        } else {
             const uint32_t k = pos[o][threadIdx.x];
             pos[o][threadIdx.x] = k + 1;
             nei[base + k] = a;
         }
     };
     query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
+    flush();
 }
 
 hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, hipStream_t st) {
