@@ -288,17 +288,20 @@ __device__ __forceinline__ void init_alive(const PointSet& s) {
     }
 }
 
-// Algorithm 5.  Returns 1 (yes), 0 (no) or -1 (iteration bound exceeded).
+// Algorithm 5 from P0, the start point of si (its row, which a caller
+// testing several pairs from one si loads once).  Returns 1 (yes), 0 (no)
+// or -1 (iteration bound exceeded).
 template <int D>
-__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T, double eps,
-                            unsigned long long& ndist, uint32_t& iters) {
+__device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D], uint32_t T, double eps,
+                                 unsigned long long& ndist, uint32_t& iters) {
     init_alive<D>(si);
     init_alive<D>(sj);
     wave_sync();
     const uint32_t bound = si.m + sj.m + 2;
     // P: the current point of si (first the start point), Q: its nearest in sj
     int32_t P[D], Q[D];
-    load_point<D>(si, start, P);
+#pragma unroll
+    for (int k = 0; k < D; ++k) P[k] = P0[k];
     for (iters = 1;; ++iters) {
         if (iters > bound) return -1;
         const uint64_t bq = nearest<D>(sj, P, ndist, Q);
@@ -310,6 +313,15 @@ __device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T
         if (dp <= T) return 1;
         if (!pruning<D>(sj, si, Q, P, dp, T, eps, ndist)) return 0;
     }
+}
+
+// Algorithm 5 from position `start` of si.
+template <int D>
+__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T, double eps,
+                            unsigned long long& ndist, uint32_t& iters) {
+    int32_t P0[D];
+    load_point<D>(si, start, P0);
+    return fast_merging_from<D>(si, sj, P0, T, eps, ndist, iters);
 }
 
 }  // namespace gd

@@ -192,6 +192,9 @@ __global__ __launch_bounds__(kBlock, kLearned ? 4 : 6) void merge_big_kernel(Gri
         return;
     }
     si.words = (si.m + kWave - 1) / kWave;
+    // the plain tests all start from s_i's first point: loaded once
+    int32_t p0[D];
+    load_point<D>(si, 0u, p0);
     PointSet sj{co.ccrd, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
     unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
     uint32_t ri = uf_find_at(parent, ci, pci);
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(kBlock, kLearned ? 4 : 6) void merge_big_kernel(Gri
                 else
                     yes = fast_merging<D>(si, sj, readlane(my_ra, l), T, eps, n_dist, it);
             } else {
-                yes = fast_merging<D>(si, sj, 0u, T, eps, n_dist, it);
+                yes = fast_merging_from<D>(si, sj, p0, T, eps, n_dist, it);
             }
             ++n_test;
             n_pts += si.m + sj.m;

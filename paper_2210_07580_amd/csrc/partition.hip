@@ -195,21 +195,23 @@ __global__ __launch_bounds__(kFinishThreads) void minmax_finish_kernel(Batch b, 
     const int d = I.d;
     const uint32_t nt = (uint32_t)((I.n + b.tile_pts - 1) / b.tile_pts);
     // thread t reads quarter q = t % 4 of records t / 4, t / 4 + 256, ...
-    // (quarters 0-1: minima, 2-3: maxima), eight records in flight
+    // (quarters 0-1: minima, 2-3: maxima), twelve records in flight: up to
+    // 3072 tiles (12.5M points at 4096 per tile) in one round of loads
     const int q = threadIdx.x & 3;
     const bool is_min = q < 2;
     int4 acc = is_min ? make_int4(INT_MAX, INT_MAX, INT_MAX, INT_MAX) : make_int4(INT_MIN, INT_MIN, INT_MIN, INT_MIN);
     const int4* rec = reinterpret_cast<const int4*>(part + (int64_t)I.tile0 * 2 * kMaxD) + q;
     constexpr uint32_t kStep = kFinishThreads / 4;
-    for (uint32_t t0 = threadIdx.x >> 2; t0 < nt; t0 += 8 * kStep) {
-        int4 r[8];
+    constexpr int kInFlight = 12;
+    for (uint32_t t0 = threadIdx.x >> 2; t0 < nt; t0 += kInFlight * kStep) {
+        int4 r[kInFlight];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kInFlight; ++u) {
             const uint32_t t = t0 + u * kStep;
             r[u] = t < nt ? rec[(int64_t)t * 4] : acc;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kInFlight; ++u) {
             if (is_min) {
                 acc.x = min(acc.x, r[u].x); acc.y = min(acc.y, r[u].y);
                 acc.z = min(acc.z, r[u].z); acc.w = min(acc.w, r[u].w);
