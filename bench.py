@@ -254,8 +254,8 @@ def main():
                     help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is a design note, not built", file=sys.stderr)
+        print(f"bench.py: the library clusters on one GPU (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

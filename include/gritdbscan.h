@@ -56,7 +56,7 @@ typedef enum {
     GD_ENOMEM = -3,       /* device workspace could not be allocated (or the
                              context's workspace limit would be exceeded)     */
     GD_EDEVICE = -4,      /* a HIP runtime call failed                        */
-    GD_EUNSUPPORTED = -5  /* valid input outside what this build handles     */
+    GD_EUNSUPPORTED = -5  /* valid input outside what the library handles    */
 } gd_status;
 
 typedef struct gd_ctx gd_ctx;
