@@ -154,18 +154,36 @@ __device__ __forceinline__ uint64_t isqrt_u64(uint64_t y) {
 }
 
 // Field widths and shifts of instance I's identifiers from its minima and
-// maxima; returns the identifier's bit count.
+// maxima; returns the identifier's bit count.  Everything is computed in
+// registers and stored once at the end: reading a field back from memory
+// would wait for the store before it.
 __device__ int inst_layout(Inst& I, const int* mn, const int* mx) {
+    const int d = I.d;
+    const int64_t n = I.n;
+    const uint64_t eps = (uint64_t)I.eps;
+    int bits[kMaxD], shift[kMaxD];
     int total = 0;
-    for (int j = 0; j < I.d; ++j) {
-        const uint64_t u = I.n > 0 ? (uint64_t)((int64_t)mx[j] - mn[j]) : 0;
-        const uint64_t kmax = isqrt_u64((uint64_t)I.d * u * u) / (uint64_t)I.eps;
-        I.bits[j] = bit_length_u64(kmax);
-        total += I.bits[j];
+#pragma unroll
+    for (int j = 0; j < kMaxD; ++j) {
+        bits[j] = 0;
+        if (j < d) {
+            const uint64_t u = n > 0 ? (uint64_t)((int64_t)mx[j] - mn[j]) : 0;
+            bits[j] = bit_length_u64(isqrt_u64((uint64_t)d * u * u) / eps);
+            total += bits[j];
+        }
     }
-    for (int j = I.d - 1, sh = 0; j >= 0; --j) {
-        I.shift[j] = sh;
-        sh += I.bits[j];
+    int sh = 0;
+#pragma unroll
+    for (int j = kMaxD - 1; j >= 0; --j) {
+        shift[j] = sh;
+        if (j < d) sh += bits[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxD; ++j) {
+        if (j < d) {
+            I.bits[j] = bits[j];
+            I.shift[j] = shift[j];
+        }
     }
     I.key_bits = total;
     return total;
@@ -454,9 +472,10 @@ struct CellWriter {
     int32_t* ck;
     int64_t ck_stride;
     // s: first sorted position of grid c
+    // Every load comes before the first store: a load issued after a store
+    // would wait for it.
     __device__ void operator()(int64_t s, uint32_t c) const {
         const K key = skeys[s];
-        cell_start[c] = (uint32_t)s;
         int k = 0;
         if (b.count > 1) {
             const int ishift = b.hdr->inst_shift;
@@ -464,18 +483,22 @@ struct CellWriter {
             if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
         }
         const Inst& I = b.inst[k];
-        ck[c] = k;
+        const int d = I.d;
+        int32_t v[kMaxD];
 #pragma unroll
         for (int j = 0; j < kMaxD; ++j) {
-            if (j < b.D) {
-                int32_t v = 0;
-                if (j < I.d) {
-                    const uint64_t mask = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
-                    v = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
-                }
-                ck[(int64_t)(j + 1) * ck_stride + c] = v;
+            v[j] = 0;
+            if (j < b.D && j < d) {
+                const int bits = I.bits[j];
+                const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+                v[j] = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
             }
         }
+        cell_start[c] = (uint32_t)s;
+        ck[c] = k;
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j)
+            if (j < b.D) ck[(int64_t)(j + 1) * ck_stride + c] = v[j];
     }
     __device__ void end(uint32_t ncell) const { cell_start[ncell] = (uint32_t)b.n; }
 };
