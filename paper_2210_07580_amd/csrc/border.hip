@@ -144,8 +144,8 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
     const int bbits = bits - kBucketShift<K>;
     const uint64_t bmask = (1ull << bbits) - 1ull;
     const int32_t off = (int32_t)I.off;
-    int32_t* __restrict__ labels = I.labels;
-    uint8_t* __restrict__ flags = I.core;
+    int32_t GD_GLOBAL* __restrict__ labels = as_global(I.labels);
+    uint8_t GD_GLOBAL* __restrict__ flags = as_global(I.core);
     const int32_t special = tab[1ull << bits].val;
     for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kBlock) {
         K key[U];
@@ -214,8 +214,8 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
     const int lane = lane_id();
     const Inst& I = cell_inst(gv, c);
     const uint32_t off = (uint32_t)I.off;  // cluster ids and output slots are local to the instance
-    int32_t* __restrict__ labels = I.labels;
-    uint8_t* __restrict__ core_flags = I.core;
+    int32_t GD_GLOBAL* __restrict__ labels = as_global(I.labels);
+    uint8_t GD_GLOBAL* __restrict__ core_flags = as_global(I.core);
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
     const uint32_t T = I.T;

@@ -22,6 +22,16 @@ __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
 // index of the lowest set bit (m != 0)
 __device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
 
+// Pointers read from device-side tables (an instance's input and output
+// arrays) are generic to the compiler, which then emits flat instructions
+// (they also wait on the LDS counter); those arrays always live in global
+// memory, so the point kernels say so.
+#define GD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T GD_GLOBAL* as_global(T* p) {
+    return (T GD_GLOBAL*)p;
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }

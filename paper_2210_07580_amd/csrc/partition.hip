@@ -33,17 +33,18 @@ namespace gd {
 // its d coordinates.
 template <int D, typename F>
 __device__ __forceinline__ void for_points(const Inst& I, int64_t lo, int64_t hi, F&& f) {
-    const float* __restrict__ x = I.x;
+    const float GD_GLOBAL* __restrict__ x = as_global(I.x);
     int64_t rest = lo;
-    if ((reinterpret_cast<uintptr_t>(x) & 15u) == 0) {
+    if ((reinterpret_cast<uintptr_t>(I.x) & 15u) == 0) {
         const int64_t groups = (hi - lo) >> 2;
-        const float4* __restrict__ xv = reinterpret_cast<const float4*>(x + lo * D);
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 GD_GLOBAL* __restrict__ xv = reinterpret_cast<const f4 GD_GLOBAL*>(x + lo * D);
 #pragma unroll 2
         for (int64_t gi = threadIdx.x; gi < groups; gi += kBlock) {
             float v[4 * D];
 #pragma unroll
             for (int q = 0; q < D; ++q) {
-                const float4 t = xv[gi * D + q];
+                const f4 t = xv[gi * D + q];
                 v[4 * q + 0] = t.x;
                 v[4 * q + 1] = t.y;
                 v[4 * q + 2] = t.z;
@@ -406,9 +407,9 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t*
     int32_t mn[DB];
 #pragma unroll
     for (int j = 0; j < DB; ++j) mn[j] = j < d ? I.mn[j] : 0;
-    const float* __restrict__ x = I.x;
+    const float GD_GLOBAL* __restrict__ x = as_global(I.x);
     if (d == DB) {
-        const FRow<DB>* __restrict__ xr = reinterpret_cast<const FRow<DB>*>(x);
+        const FRow<DB> GD_GLOBAL* __restrict__ xr = reinterpret_cast<const FRow<DB> GD_GLOBAL*>(x);
         for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * kBlock) {
             uint32_t o[U];
 #pragma unroll
@@ -420,7 +421,10 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(Batch b, const uint32_t*
             FRow<DB> r[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (i0 + (int64_t)u * kBlock < hi) r[u] = xr[o[u]];
+                if (i0 + (int64_t)u * kBlock < hi) {
+#pragma unroll
+                    for (int j = 0; j < DB; ++j) r[u].v[j] = xr[o[u]].v[j];
+                }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t i = i0 + (int64_t)u * kBlock;
