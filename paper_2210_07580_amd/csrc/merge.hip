@@ -152,10 +152,11 @@ __device__ __forceinline__ uint32_t orderable(float z) {
 
 // The kernel is bound by the latency of union-find and FastMerging steps:
 // six waves per SIMD (at most 85 registers) hide more of it than wider
-// unrolling inside a wave.  The scorer's fragments do not fit in that
-// budget (they would spill to scratch), so the learned variant runs four.
+// unrolling inside a wave.  The scorer's fragments, and rows of d >= 5, do
+// not fit in that budget (they would spill to scratch), so those variants
+// run four.
 template <int D, bool kLearned>
-__global__ __launch_bounds__(kBlock, kLearned ? 4 : 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+__global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
                                                            const uint4* __restrict__ rank, int64_t r0, int64_t r1,
