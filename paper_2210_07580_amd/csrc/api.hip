@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -278,17 +279,43 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
                   hipStream_t st) {
     K* ka = (K*)L.keys_a;
     K* kb = (K*)L.keys_b;
-    ctx->mark(P_KEYS, 0);
-    GD_TRY(launch_keys<K>(b, ka, st));
-    ctx->mark(P_KEYS, 1);
+    // With 32-bit identifiers and every instance's grid side small enough,
+    // the sort carries each point's low coordinate bits and the sorted rows
+    // are rebuilt in sorted order (no random gather).  The value buffers
+    // hold 2n u32 each, so n u64 values fit.
+    bool pack = std::is_same<K, uint32_t>::value;
+    for (int k = 0; k < b.count && pack; ++k) pack = pack_fits(ctx->inst_host[k].d, ctx->inst_host[k].eps);
     RadixResult<K> res;
-    ctx->mark(P_SORT, 0);
-    GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, b.n, key_bits, true, L.radix_scratch, st, &res,
-                               (K*)L.keys_c));
-    ctx->mark(P_SORT, 1);
-    ctx->mark(P_GATHER, 0);
-    GD_TRY(launch_gather(b, res.vals, L.crd, st));
-    ctx->mark(P_GATHER, 1);
+    if (pack) {
+        uint64_t* va = reinterpret_cast<uint64_t*>(L.vals_a);
+        uint64_t* vb = reinterpret_cast<uint64_t*>(L.vals_b);
+        ctx->mark(P_KEYS, 0);
+        GD_TRY(launch_keys<K>(b, ka, va, st));
+        ctx->mark(P_KEYS, 1);
+        RadixResult<K, uint64_t> r64;
+        ctx->mark(P_SORT, 0);
+        GD_TRY((radix_sort_pairs<K, uint64_t>(ka, va, kb, vb, b.n, key_bits, false, L.radix_scratch, st, &r64,
+                                              (K*)L.keys_c)));
+        ctx->mark(P_SORT, 1);
+        // sidx goes to the value buffer the sorted values are not in
+        uint32_t* sidx = r64.vals == va ? L.vals_b : L.vals_a;
+        ctx->mark(P_GATHER, 0);
+        GD_TRY(launch_unpack(b, reinterpret_cast<const uint32_t*>(r64.keys), r64.vals, sidx, L.crd, st));
+        ctx->mark(P_GATHER, 1);
+        res.keys = r64.keys;
+        res.vals = sidx;
+    } else {
+        ctx->mark(P_KEYS, 0);
+        GD_TRY(launch_keys<K>(b, ka, nullptr, st));
+        ctx->mark(P_KEYS, 1);
+        ctx->mark(P_SORT, 0);
+        GD_TRY(radix_sort_pairs<K>(ka, L.vals_a, kb, L.vals_b, b.n, key_bits, true, L.radix_scratch, st, &res,
+                                   (K*)L.keys_c));
+        ctx->mark(P_SORT, 1);
+        ctx->mark(P_GATHER, 0);
+        GD_TRY(launch_gather(b, res.vals, L.crd, st));
+        ctx->mark(P_GATHER, 1);
+    }
     ctx->mark(P_CELLS, 0);
     GD_TRY(launch_cells<K>(b, res.keys, (uint32_t*)L.partial, L.cell_start, L.ck, b.n, st));
     ctx->mark(P_CELLS, 1);

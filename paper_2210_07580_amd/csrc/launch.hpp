@@ -126,10 +126,24 @@ hipError_t launch_minmax(const Batch& b, int32_t* part, int plan_bits, hipStream
 // largest core set).  On overflow, or after an input error, kErrPlan goes up
 // and the grid count drops to zero, so every later kernel finds no work.
 hipError_t launch_plan_check(Header* hdr, int stage, int64_t cap_a, int64_t cap_b, hipStream_t st);
+// Packed rows: each coordinate's low pack_bits(d) bits ride through the sort
+// in the high half of a 64-bit value (the point's index in the low half).
+// The grid's centre recovers the rest when it lies within 2^(bits-1) of
+// every coordinate of the grid: eps / sqrt(d) + 4 < 2^bits (with margin).
+__host__ __device__ constexpr int pack_bits(int d) { return 32 / d; }
+__host__ __device__ inline bool pack_fits(int d, int64_t eps) {
+    return d >= 1 && d <= kMaxD && (double)eps / sqrt((double)d) + 4.0 < (double)(1ull << pack_bits(d));
+}
+// Grid identifiers in input order; with vals (n entries), also the packed
+// sort values (index | low coordinate bits << 32).
 template <typename K>
-hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st);
+hipError_t launch_keys(const Batch& b, K* keys, uint64_t* vals, hipStream_t st);
 // Sorted point rows: crd row s = point sidx[s] (see GridView::crd).
 hipError_t launch_gather(const Batch& b, const uint32_t* sidx, int32_t* crd, hipStream_t st);
+// The same rows, and sidx, from the sorted identifiers and packed values
+// (32-bit identifiers; every instance pack_fits).
+hipError_t launch_unpack(const Batch& b, const uint32_t* skeys, const uint64_t* vals, uint32_t* sidx, int32_t* crd,
+                         hipStream_t st);
 // Runs of equal keys: cell_start[0..ncell], identifiers; header ncell written.
 template <typename K>
 hipError_t launch_cells(const Batch& b, const K* skeys, uint32_t* partial, uint32_t* cell_start,

@@ -339,8 +339,12 @@ hipError_t launch_plan_check(Header* hdr, int stage, int64_t cap_a, int64_t cap_
     return hipGetLastError();
 }
 
+// With `vals`, each point also gets the value that the sort carries for it:
+// its index (low half) and the low pack_bits(d) bits of each coordinate
+// (high half), from which unpack_kernel rebuilds the sorted rows.
 template <int D, typename K>
-__device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi, K top, K* __restrict__ keys) {
+__device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi, K top, K* __restrict__ keys,
+                                          uint64_t* __restrict__ vals) {
     int32_t mn[D], sh[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -349,43 +353,114 @@ __device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi,
     }
     const uint32_t eps = (uint32_t)I.eps;
     const float scale = (float)(sqrt((double)D) / (double)I.eps);
+    constexpr int B = pack_bits(D);
+    constexpr uint64_t kLow = B >= 32 ? 0xFFFFFFFFull : ((1ull << B) - 1ull);
     K* __restrict__ out = keys + I.off;
     for_points<D>(I, lo, hi, [&](int64_t i, const float (&row)[D]) {
         K key = top;
+        uint64_t packed = 0;
 #pragma unroll
-        for (int j = 0; j < D; ++j) key |= (K)grid_coord((uint32_t)((int)row[j] - mn[j]), D, eps, scale) << sh[j];
+        for (int j = 0; j < D; ++j) {
+            const uint32_t u = (uint32_t)((int)row[j] - mn[j]);
+            key |= (K)grid_coord(u, D, eps, scale) << sh[j];
+            packed |= ((uint64_t)u & kLow) << (j * B);
+        }
         out[i] = key;
+        if (vals) vals[I.off + i] = (packed << 32) | (uint64_t)(uint32_t)(I.off + i);
     });
 }
 
 template <typename K, int DB>
-__global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys) {
+__global__ __launch_bounds__(kBlock) void keys_kernel(Batch b, K* __restrict__ keys, uint64_t* __restrict__ vals) {
     const int k = tile_instance(b, blockIdx.x);
     const Inst& I = b.inst[k];
-    if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) {
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
+    // a sync-free run whose instance table no longer allows packed rows (a
+    // larger eps on replay) is discarded like one that outgrew its plan
+    const bool bad_pack = vals && !pack_fits(I.d, I.eps);
+    if (bad_pack && threadIdx.x == 0) atomicOr(&b.hdr->err, kErrPlan);
+    if (bad_pack || (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan))) {
         // a sync-free run on input it cannot handle (its result is discarded):
         // the instance id alone keeps every instance's points in its own
         // range through the sort, so later kernels stay within bounds
-        const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
-        const int64_t hi = min(I.n, lo + b.tile_pts);
-        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) keys[I.off + i] = (K)k;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+            keys[I.off + i] = (K)k;
+            if (vals) vals[I.off + i] = (uint64_t)(uint32_t)(I.off + i);
+        }
         return;
     }
     const int ishift = b.hdr->inst_shift;
     const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)k << ishift;
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
-    const int64_t hi = min(I.n, lo + b.tile_pts);
-    with_d<DB>(I.d, [&](auto dc) { keys_tile<decltype(dc)::value, K>(I, lo, hi, top, keys); });
+    with_d<DB>(I.d, [&](auto dc) { keys_tile<decltype(dc)::value, K>(I, lo, hi, top, keys, vals); });
 }
 
 template <typename K>
-hipError_t launch_keys(const Batch& b, K* keys, hipStream_t st) {
+hipError_t launch_keys(const Batch& b, K* keys, uint64_t* vals, hipStream_t st) {
     if (b.tiles == 0) return hipSuccess;
-    GD_DISPATCH_D(b.D, (keys_kernel<K, D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, keys)));
+    GD_DISPATCH_D(b.D, (keys_kernel<K, D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, keys, vals)));
     return hipGetLastError();
 }
-template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, hipStream_t);
-template hipError_t launch_keys<uint64_t>(const Batch&, uint64_t*, hipStream_t);
+template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, uint64_t*, hipStream_t);
+template hipError_t launch_keys<uint64_t>(const Batch&, uint64_t*, uint64_t*, hipStream_t);
+
+// Sorted rows without the random gather: the sort carried each point's
+// index and the low B = pack_bits(d) bits of its coordinates u_j = x_j -
+// mn_j.  The point's grid (from its sorted identifier) puts u_j in
+// [g_j s, (g_j + 1) s) with s = eps / sqrt(d), so the grid's centre a_j is
+// within s / 2 + 1 < 2^(B-1) of u_j (pack_fits), and u_j is the one value
+// within 2^(B-1) of a_j with those low bits.  Reads and writes in sorted
+// order only; tiles as the gather's.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void unpack_kernel(Batch b, const uint32_t* __restrict__ skeys,
+                                                        const uint64_t* __restrict__ vals,
+                                                        uint32_t* __restrict__ sidx, int32_t* __restrict__ crd) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
+    with_d<DB>(I.d, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        constexpr int B = pack_bits(D);
+        constexpr uint64_t kLow = B >= 32 ? 0xFFFFFFFFull : ((1ull << B) - 1ull);
+        constexpr int64_t kHalf = (int64_t)1 << (B - 1);
+        int sh[D];
+        uint32_t fm[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            sh[j] = I.shift[j];
+            fm[j] = I.bits[j] >= 32 ? 0xFFFFFFFFu : ((1u << I.bits[j]) - 1u);
+        }
+        const double side = (double)I.eps / sqrt((double)D);
+#pragma unroll 4
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+            const int64_t s = I.off + i;
+            const uint64_t v = vals[s];
+            const uint32_t key = skeys[s];
+            const uint64_t packed = v >> 32;
+            int32_t y[DB];
+#pragma unroll
+            for (int j = 0; j < DB; ++j) y[j] = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const uint32_t g = (key >> sh[j]) & fm[j];
+                const int64_t a = (int64_t)floor(((double)g + 0.5) * side);
+                const uint64_t low = (packed >> (j * B)) & kLow;
+                const uint64_t t = ((uint64_t)((int64_t)low - a + kHalf)) & kLow;
+                y[j] = (int32_t)(a + (int64_t)t - kHalf);
+            }
+            store_row<DB>(crd, s, y);
+            sidx[s] = (uint32_t)v;
+        }
+    });
+}
+
+hipError_t launch_unpack(const Batch& b, const uint32_t* skeys, const uint64_t* vals, uint32_t* sidx, int32_t* crd,
+                         hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    GD_DISPATCH_D(b.D, (unpack_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, skeys, vals, sidx, crd)));
+    return hipGetLastError();
+}
 
 template <int D>
 struct FRow {

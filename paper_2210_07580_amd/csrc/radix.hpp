@@ -29,8 +29,11 @@ namespace gd {
 // Keys per thread of a tile: 16 (4096-key tiles), or 4 (1024-key tiles) for
 // sorts of at most kRadixSmallMax keys, which would otherwise have fewer
 // tiles than the GPU has compute units, each ranked by one long chain of
-// wave steps.
+// wave steps.  Sorts with 64-bit values take 8 (2048-key tiles): a 4096-key
+// tile of them would stage 48 KB of keys and values in LDS and leave room
+// for two workgroups per compute unit.
 constexpr int kRadixItemsBig = 16;
+constexpr int kRadixItemsWide = 8;
 constexpr int kRadixItemsSmall = 4;
 constexpr int64_t kRadixSmallMax = 1 << 21;
 
@@ -39,19 +42,24 @@ constexpr int radix_max_bits() { return 8; }
 template <typename K>
 constexpr int radix_max_bins() { return 1 << radix_max_bits<K>(); }
 
-inline int radix_items(int64_t n) { return n <= kRadixSmallMax ? kRadixItemsSmall : kRadixItemsBig; }
-inline int64_t radix_tiles(int64_t n) {
-    const int64_t tile = (int64_t)kBlock * radix_items(n);
+inline int radix_items(int64_t n, int value_bytes = 4) {
+    return n <= kRadixSmallMax ? kRadixItemsSmall : value_bytes > 4 ? kRadixItemsWide : kRadixItemsBig;
+}
+inline int64_t radix_tiles(int64_t n, int value_bytes = 4) {
+    const int64_t tile = (int64_t)kBlock * radix_items(n, value_bytes);
     return (n + tile - 1) / tile;
 }
-inline int64_t radix_scratch_words_for(int64_t n) {
-    const int64_t t = radix_tiles(n);
+inline int64_t radix_scratch_words_for(int64_t n, int value_bytes) {
+    const int64_t t = radix_tiles(n, value_bytes);
     constexpr int64_t bins = 1 << 8;
     return 2 * bins * t + scan_partial_cap(bins * t) + 4;
 }
-// u32 entries of scratch enough for a sort of any m <= n keys (any key type)
+// u32 entries of scratch enough for a sort of any m <= n keys (any key and
+// value type)
 inline int64_t radix_scratch_words(int64_t n) {
-    return std::max(radix_scratch_words_for(n), radix_scratch_words_for(std::min(n, kRadixSmallMax)));
+    const int64_t small = std::min(n, kRadixSmallMax);
+    return std::max(std::max(radix_scratch_words_for(n, 4), radix_scratch_words_for(n, 8)),
+                    radix_scratch_words_for(small, 4));
 }
 
 // Neighbouring tiles write neighbouring addresses (their counts in the
@@ -114,9 +122,9 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     }
 }
 
-template <typename K, bool kIota, int kItems>
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                                               K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+template <typename K, typename V, bool kIota, int kItems>
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const V* __restrict__ vals,
+                                                               K* __restrict__ keys_out, V* __restrict__ vals_out,
                                                                int64_t n, int shift, int rbits,
                                                                const uint32_t* __restrict__ offs, int64_t tiles) {
     constexpr int kMaxBins = radix_max_bins<K>();
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     constexpr int kPerWave = kTile / kWavesPerBlock;       // 64 kItems consecutive keys per wave
     constexpr int kIters = kPerWave / kWave;               // kItems
     __shared__ K skey[kTile];                               // the tile, ordered by digit (stable)
-    __shared__ uint32_t sval[kTile];
+    __shared__ V sval[kTile];
     __shared__ uint32_t wcnt[kWavesPerBlock][kMaxBins];     // keys per (wave, digit), then first local slot
     __shared__ uint32_t gbase[kMaxBins];                    // global slot of a digit's first key, minus its local start
     __shared__ uint32_t wsum[kWavesPerBlock];
@@ -145,14 +153,14 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     // 1. each wave ranks its own run of keys among equal digits, in order,
     //    with wave-private counters (no workgroup barrier)
     K k[kIters];
-    uint32_t v[kIters];
+    V v[kIters];
     uint32_t dr[kIters];  // digit << 16 | rank within the wave
 #pragma unroll
     for (int it = 0; it < kIters; ++it) {
         const int li = w * kPerWave + it * kWave + lane;
         const bool valid = li < tile_n;
         k[it] = valid ? keys[base + li] : K(0);
-        v[it] = valid ? (kIota ? (uint32_t)(base + li) : vals[base + li]) : 0u;
+        v[it] = valid ? (kIota ? (V)(base + li) : vals[base + li]) : V(0);
     }
 #pragma unroll
     for (int it = 0; it < kIters; ++it) {
@@ -239,10 +247,10 @@ __global__ __launch_bounds__(kBlock) void iota_kernel(T* v, int64_t n) {
     if (i < n) v[i] = (T)i;
 }
 
-template <typename K>
+template <typename K, typename V = uint32_t>
 struct RadixResult {
     K* keys;
-    uint32_t* vals;
+    V* vals;
 };
 
 // Sorts keys[0..n) (and vals) on their low `bits` bits.  keys/vals and
@@ -251,53 +259,65 @@ struct RadixResult {
 // and keys_spare, so keys[] keeps the input order.
 // If vals_iota, vals[] is not read and the values start as 0..n-1.
 // `scratch` needs radix_scratch_words(n) u32.
-template <typename K>
-hipError_t radix_sort_pairs(K* keys, uint32_t* vals, K* keys_alt, uint32_t* vals_alt, int64_t n, int bits,
-                            bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K>* out,
+template <typename K, typename V = uint32_t>
+hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t n, int bits,
+                            bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K, V>* out,
                             K* keys_spare = nullptr) {
     K* kin = keys;
-    uint32_t* vin = vals;
+    V* vin = vals;
     K* kout = keys_alt;
-    uint32_t* vout = vals_alt;
+    V* vout = vals_alt;
     bool first = true;
-    const int64_t tiles = radix_tiles(n);
+    const int64_t tiles = radix_tiles(n, (int)sizeof(V));
     uint32_t* hist = scratch;
     uint32_t* offs = scratch + (int64_t)radix_max_bins<uint32_t>() * tiles;
     uint32_t* partial = offs + (int64_t)radix_max_bins<uint32_t>() * tiles;
     bool iota = vals_iota;
     const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
     const int rbits = passes ? (bits + passes - 1) / passes : 0;
-    const bool small = radix_items(n) == kRadixItemsSmall;
+    const int items = radix_items(n, (int)sizeof(V));
     for (int p = 0, shift = 0; p < passes; ++p, shift += rbits) {
         if (n == 0) break;
         const int64_t bins = (int64_t)1 << rbits;
         const dim3 grid((unsigned)tiles), block(kBlock);
-        if (small)
+        if (items == kRadixItemsSmall)
             radix_hist_kernel<K, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, n, shift, rbits, hist, tiles);
+        else if (items == kRadixItemsWide)
+            radix_hist_kernel<K, kRadixItemsWide><<<grid, block, 0, st>>>(kin, n, shift, rbits, hist, tiles);
         else
             radix_hist_kernel<K, kRadixItemsBig><<<grid, block, 0, st>>>(kin, n, shift, rbits, hist, tiles);
         hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, bins * tiles, offs, (uint32_t*)nullptr,
                                                 partial, st);
         if (e != hipSuccess) return e;
-        if (small && iota)
-            radix_scatter_kernel<K, true, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                   rbits, offs, tiles);
-        else if (small)
-            radix_scatter_kernel<K, false, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                    rbits, offs, tiles);
-        else if (iota)
-            radix_scatter_kernel<K, true, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                 rbits, offs, tiles);
-        else
-            radix_scatter_kernel<K, false, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n, shift,
-                                                                                  rbits, offs, tiles);
+        if (items == kRadixItemsSmall) {
+            if (iota)
+                radix_scatter_kernel<K, V, true, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                          shift, rbits, offs, tiles);
+            else
+                radix_scatter_kernel<K, V, false, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                           shift, rbits, offs, tiles);
+        } else if (items == kRadixItemsWide) {
+            if (iota)
+                radix_scatter_kernel<K, V, true, kRadixItemsWide><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                         shift, rbits, offs, tiles);
+            else
+                radix_scatter_kernel<K, V, false, kRadixItemsWide><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                          shift, rbits, offs, tiles);
+        } else {
+            if (iota)
+                radix_scatter_kernel<K, V, true, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                        shift, rbits, offs, tiles);
+            else
+                radix_scatter_kernel<K, V, false, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
+                                                                                         shift, rbits, offs, tiles);
+        }
         iota = false;
         K* tk = kin; kin = kout; kout = (first && keys_spare) ? keys_spare : tk;
         first = false;
-        uint32_t* tv = vin; vin = vout; vout = tv;
+        V* tv = vin; vin = vout; vout = tv;
     }
     if (iota && n > 0) {  // no pass ran: the values must still be 0..n-1
-        iota_kernel<uint32_t><<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(vin, n);
+        iota_kernel<V><<<dim3(grid_for(n)), dim3(kBlock), 0, st>>>(vin, n);
     }
     out->keys = kin;
     out->vals = vin;
