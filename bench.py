@@ -14,6 +14,7 @@ rooflines) come from K more steps with HIP events around every phase.
 import argparse
 import json
 import os
+import math
 import sys
 import time
 
@@ -41,7 +42,7 @@ PHASE_KERNELS = {
     "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel (batches of several instances)"],
     "keys": ["keys_kernel"],
     "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel"],
-    "gather": ["gather_kernel"],
+    "gather": ["unpack_kernel (rows rebuilt in order; gather_kernel when the low bits do not fit)"],
     "core_mark": ["core_mark_kernel"],
     "merge": ["merge_small_kernel", "merge_big_kernel"],
     "output": ["hash_clear_kernel", "hash_build_kernel", "output_direct_kernel", "output_kernel"],
@@ -49,18 +50,27 @@ PHASE_KERNELS = {
 }
 
 
-def algorithmic_bytes(phase, n, d, st, key_bytes, passes):
+def packed_rows(d, eps, key_bits):
+    """Whether the library carries low coordinate bits through the sort and
+    rebuilds the sorted rows in order (the same rule as its pack_fits)."""
+    return key_bits <= 32 and eps / math.sqrt(d) + 4.0 < 2.0 ** (32 // d)
+
+
+def algorithmic_bytes(phase, n, d, st, key_bytes, passes, packed):
     """Bytes the phase must move at least (the method's own traffic), per call."""
     B = 4 * d  # coordinates per point
+    V = 8 if packed else 4  # sort value: index, with the packed low bits
     if phase == "minmax":
         return n * B
     if phase == "keys":
-        return n * (B + key_bytes)
+        return n * (B + key_bytes + (8 if packed else 0))
     if phase == "radix_sort":
-        # per pass: histogram read of the keys, then (key, index) read and written
-        return passes * n * (key_bytes + 2 * (key_bytes + 4))
+        # per pass: histogram read of the keys, then (key, value) read and written
+        return passes * n * (key_bytes + 2 * (key_bytes + V))
     if phase == "gather":
-        return n * (4 + 2 * B)
+        # packed: sorted keys and values in, index and rows out; else the
+        # index, one row in and one row out
+        return n * (key_bytes + 8 + 4 + B) if packed else n * (4 + 2 * B)
     if phase == "core_mark":
         # flags, plus every neighbour point streamed for a sparse grid (8 B per neighbour grid opened)
         return n + st["core_candidates"] * B + 8 * st["core_neighbor_grids"]
@@ -332,7 +342,7 @@ def main():
     traffic = measured_traffic(w.name)
     rooflines = {}
     for ph, ms in phases.items():
-        b = algorithmic_bytes(ph, n, d, st, key_bytes, passes)
+        b = algorithmic_bytes(ph, n, d, st, key_bytes, passes, packed_rows(d, w.eps, st["key_bits"]))
         if b is None or ms <= 0:
             continue
         achieved = b / (ms * 1e-3) / 1e9

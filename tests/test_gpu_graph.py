@@ -145,3 +145,28 @@ def test_single_call_graph_mode(G):
         assert ctx.stats()["graph_replays"] == (1 if rep else 0)
         assert np.array_equal(core.cpu().numpy(), rc) and np.array_equal(lab.cpu().numpy(), rl)
     ctx.close()
+
+
+def test_replay_with_eps_beyond_packed_rows(G):
+    # Captured where each coordinate's low bits ride through the sort (d = 3,
+    # eps 200: grid side 115 < 2^10); replayed with eps 2400 (side 1386), for
+    # which they do not: the replay must notice, be discarded, and rerun
+    # eagerly with the gather, giving the eager result.
+    w = W.WORKLOADS["cfg1"]
+    x = W.make_points(w, n=100_000)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    big = 2400
+    c0 = G.Context(0)
+    c0.set_option(G.GD_OPT_GRAPH, 0)
+    rl, rc = (v.cpu().numpy() for v in c0.dbscan(t, big, w.minpts))
+    c0.close()
+    ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_GRAPH, 2)
+    ctx.dbscan(t, w.eps, w.minpts)
+    ctx.dbscan(t, w.eps, w.minpts)
+    assert ctx.stats()["graph_replays"] == 1
+    print("case: replay with eps beyond the packed rows", flush=True)
+    lab, core = ctx.dbscan(t, big, w.minpts)
+    assert ctx.stats()["graph_replays"] == 0, "the replay must be discarded"
+    assert np.array_equal(core.cpu().numpy(), rc) and np.array_equal(lab.cpu().numpy(), rl)
+    ctx.close()

@@ -90,6 +90,20 @@ def test_eps_around_packed_limit(ctx, eps, d):
     assert_same(gpu_dbscan(ctx, x, eps, 6), oracle.dbscan_brute(x, eps, 6), f"eps {eps} d {d}")
 
 
+@pytest.mark.parametrize("eps,d", [(1766, 3), (1767, 3), (134, 5), (135, 5), (33, 8), (34, 8), (21845, 2)])
+def test_eps_around_packed_rows(ctx, eps, d):
+    # the sorted rows are rebuilt from each coordinate's low 32 // d bits and
+    # the grid while eps / sqrt(d) + 4 < 2^(32 // d), gathered above: each
+    # pair straddles that bound (d = 2 fits up to the largest eps accepted);
+    # points fill whole grids, edges included
+    rng = np.random.default_rng(eps * 10 + d)
+    n = 1500
+    x = rng.integers(-3 * eps, 5 * eps, size=(n, d)).astype(np.int32)
+    x[:40] = (x[:40] // eps) * eps  # on grid-aligned multiples of eps
+    print(f"case eps={eps} d={d}", flush=True)
+    assert_same(gpu_dbscan(ctx, x, eps, 4), oracle.dbscan_brute(x, eps, 4), f"eps {eps} d {d}")
+
+
 def test_cfg0_full(ctx):
     w = W.WORKLOADS["cfg0"]
     x = W.make_points(w)
