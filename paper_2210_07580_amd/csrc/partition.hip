@@ -31,6 +31,45 @@ namespace gd {
 // rows are 16-byte aligned (four rows of d floats span exactly d float4),
 // then the remainder one point at a time.  f(i, row) gets the point index and
 // its d coordinates.
+// for_point_groups: the same walk, but each aligned group of four goes to
+// fg(i0, rows) at once (so that its outputs can be stored as vectors) and
+// only the remainder to f(i, row).
+template <int D, typename FG, typename F>
+__device__ __forceinline__ void for_point_groups(const Inst& I, int64_t lo, int64_t hi, FG&& fg, F&& f) {
+    const float GD_GLOBAL* __restrict__ x = as_global(I.x);
+    int64_t rest = lo;
+    if ((reinterpret_cast<uintptr_t>(I.x) & 15u) == 0) {
+        const int64_t groups = (hi - lo) >> 2;
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 GD_GLOBAL* __restrict__ xv = reinterpret_cast<const f4 GD_GLOBAL*>(x + lo * D);
+#pragma unroll 2
+        for (int64_t gi = threadIdx.x; gi < groups; gi += kBlock) {
+            float v[4 * D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                const f4 t = xv[gi * D + q];
+                v[4 * q + 0] = t.x;
+                v[4 * q + 1] = t.y;
+                v[4 * q + 2] = t.z;
+                v[4 * q + 3] = t.w;
+            }
+            float rows[4][D];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int j = 0; j < D; ++j) rows[p][j] = v[p * D + j];
+            fg(lo + 4 * gi, rows);
+        }
+        rest = lo + 4 * groups;
+    }
+    for (int64_t i = rest + threadIdx.x; i < hi; i += kBlock) {
+        float row[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) row[j] = x[i * D + j];
+        f(i, row);
+    }
+}
+
 template <int D, typename F>
 __device__ __forceinline__ void for_points(const Inst& I, int64_t lo, int64_t hi, F&& f) {
     const float GD_GLOBAL* __restrict__ x = as_global(I.x);
@@ -356,8 +395,8 @@ __device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi,
     constexpr int B = pack_bits(D);
     constexpr uint64_t kLow = B >= 32 ? 0xFFFFFFFFull : ((1ull << B) - 1ull);
     K* __restrict__ out = keys + I.off;
-    for_points<D>(I, lo, hi, [&](int64_t i, const float (&row)[D]) {
-        K key = top;
+    auto point = [&](int64_t i, const float (&row)[D], K& key, uint64_t& val) {
+        key = top;
         uint64_t packed = 0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -365,9 +404,49 @@ __device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi,
             key |= (K)grid_coord(u, D, eps, scale) << sh[j];
             packed |= ((uint64_t)u & kLow) << (j * B);
         }
-        out[i] = key;
-        if (vals) vals[I.off + i] = (packed << 32) | (uint64_t)(uint32_t)(I.off + i);
-    });
+        val = (packed << 32) | (uint64_t)(uint32_t)(I.off + i);
+    };
+    // a group's four identifiers (and values) go out as 16-byte stores when
+    // the instance starts on a multiple of four points
+    const bool vec = (I.off & 3) == 0;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    for_point_groups<D>(
+        I, lo, hi,
+        [&](int64_t i0, const float (&rows)[4][D]) {
+            K kk[4];
+            uint64_t vv[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) point(i0 + p, rows[p], kk[p], vv[p]);
+            if (vec) {
+                u4* ko = reinterpret_cast<u4*>(out + i0);
+                if constexpr (sizeof(K) == 4) {
+                    ko[0] = u4{(uint32_t)kk[0], (uint32_t)kk[1], (uint32_t)kk[2], (uint32_t)kk[3]};
+                } else {
+                    ko[0] = u4{(uint32_t)kk[0], (uint32_t)((uint64_t)kk[0] >> 32), (uint32_t)kk[1],
+                               (uint32_t)((uint64_t)kk[1] >> 32)};
+                    ko[1] = u4{(uint32_t)kk[2], (uint32_t)((uint64_t)kk[2] >> 32), (uint32_t)kk[3],
+                               (uint32_t)((uint64_t)kk[3] >> 32)};
+                }
+                if (vals) {
+                    u4* vo = reinterpret_cast<u4*>(vals + I.off + i0);
+                    vo[0] = u4{(uint32_t)vv[0], (uint32_t)(vv[0] >> 32), (uint32_t)vv[1], (uint32_t)(vv[1] >> 32)};
+                    vo[1] = u4{(uint32_t)vv[2], (uint32_t)(vv[2] >> 32), (uint32_t)vv[3], (uint32_t)(vv[3] >> 32)};
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    out[i0 + p] = kk[p];
+                    if (vals) vals[I.off + i0 + p] = vv[p];
+                }
+            }
+        },
+        [&](int64_t i, const float (&row)[D]) {
+            K key;
+            uint64_t val;
+            point(i, row, key, val);
+            out[i] = key;
+            if (vals) vals[I.off + i] = val;
+        });
 }
 
 template <typename K, int DB>
