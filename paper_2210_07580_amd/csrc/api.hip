@@ -422,7 +422,15 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     t.key[D] = L.ck + (int64_t)D * n;
     t.level_count = Hd->level_count;
     ctx->mark(P_NEI_COUNT, 0);
-    GD_TRY(launch_nei_count(g, t, L.off_counts, st));
+    // the split walk's per-lane counts go to the sort buffer that does not
+    // hold the sorted identifiers (free until the LDF step), when they fit
+    uint32_t* lane_cnt = nullptr;
+    {
+        const int64_t words = nei_lane_count_words(ncell, D);
+        if (words > 0 && words <= 2 * n)
+            lane_cnt = (uint32_t*)(skeys == L.keys_b ? L.keys_c : L.keys_b);
+    }
+    GD_TRY(launch_nei_count(g, t, L.off_counts, lane_cnt, st));
     GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
     ctx->mark(P_NEI_COUNT, 1);
     if (plan)
@@ -435,7 +443,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         return rc;
     uint32_t* nei = (uint32_t*)ctx->nei.p;
     ctx->mark(P_NEI_FILL, 0);
-    GD_TRY(launch_nei_fill(g, t, L.off_counts, L.nei_off, nei, nei_total, st));
+    GD_TRY(launch_nei_fill(g, t, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, st));
     ctx->mark(P_NEI_FILL, 1);
 
     // ---- core points

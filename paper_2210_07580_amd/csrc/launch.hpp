@@ -155,14 +155,18 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
 
 // ---- neighbors.hip (Algorithm 3)
 // Pass 1: per-grid neighbour count per offset value (ncell x D, u32).
-hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, hipStream_t st);
+// lane_cnt (optional, nei_lane_count_words(ncell, D) u32; nullptr when that
+// is 0 or no room): the split walk's per-lane counts, kept for pass 2.
+int64_t nei_lane_count_words(int64_t ncell, int D);
+hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
+                            hipStream_t st);
 // Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1); total into the header.
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st);
 // Pass 2: write Nei(g) ordered by offset (skipped, with kErrNeiOverflow, if
 // the total exceeds `capacity` entries).
-hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint64_t* nei_off,
-                           uint32_t* nei, uint64_t capacity, hipStream_t st);
+hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
+                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, hipStream_t st);
 
 // ---- core.hip
 // Core sets s_i as runs of point rows.  A grid whose points are all core

@@ -123,8 +123,11 @@ __device__ __forceinline__ void count_part(const GridView& gv, const TreeView& t
     query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
 }
 
+// With lane_cnt (split walks only), each lane also keeps its own counts for
+// the fill pass, which then needs no second counting walk.
 template <int D, int P>
-__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts) {
+__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts,
+                                                           uint32_t* __restrict__ lane_cnt) {
     __shared__ uint32_t sc[D][kBlock];
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t c = gt / P;
@@ -137,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
 #pragma unroll
     for (int o = 0; o < D; ++o) {
         uint32_t v = sc[o][threadIdx.x];
+        if (P > 1 && lane_cnt && valid) lane_cnt[gt * D + o] = v;
         // sum over the grid's lanes (every lane takes part in the shuffles)
 #pragma unroll
         for (int s = 1; s < P; s <<= 1) v += __shfl_xor(v, s);
@@ -158,6 +162,7 @@ constexpr int kFillStage = 8;
 
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView t, const uint32_t* __restrict__ off_counts,
+                                                          const uint32_t* __restrict__ lane_cnt,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
                                                           uint64_t capacity) {
     __shared__ uint32_t pos[D][kBlock];
@@ -175,9 +180,14 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     const bool valid = c < ncell;
     if (P == 1 && !valid) return;
     if constexpr (P > 1) {
+        if (lane_cnt) {
 #pragma unroll
-        for (int o = 0; o < D; ++o) pos[o][threadIdx.x] = 0;
-        if (valid) count_part<D, P>(gv, t, c, p, pos);
+            for (int o = 0; o < D; ++o) pos[o][threadIdx.x] = valid ? lane_cnt[gt * D + o] : 0u;
+        } else {
+#pragma unroll
+            for (int o = 0; o < D; ++o) pos[o][threadIdx.x] = 0;
+            if (valid) count_part<D, P>(gv, t, c, p, pos);
+        }
     }
     uint32_t run = 0;
 #pragma unroll
@@ -228,13 +238,19 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     flush();
 }
 
-hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, hipStream_t st) {
+int64_t nei_lane_count_words(int64_t ncell, int D) {
+    return nei_lanes(ncell) > 1 ? ncell * kSplit * D : 0;
+}
+
+hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
+                            hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     if (nei_lanes(g.ncell) > 1) {
         GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts)));
+                               g, t, off_counts, lane_cnt)));
     } else {
-        GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, t, off_counts)));
+        GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                               g, t, off_counts, nullptr)));
     }
     return hipGetLastError();
 }
@@ -270,15 +286,15 @@ hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uin
                                 st);
 }
 
-hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint64_t* nei_off,
-                           uint32_t* nei, uint64_t capacity, hipStream_t st) {
+hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
+                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     if (nei_lanes(g.ncell) > 1) {
         GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nei_off, nei, capacity)));
+                               g, t, off_counts, lane_cnt, nei_off, nei, capacity)));
     } else {
         GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nei_off, nei, capacity)));
+                               g, t, off_counts, nullptr, nei_off, nei, capacity)));
     }
     return hipGetLastError();
 }
