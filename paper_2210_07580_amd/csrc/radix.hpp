@@ -1,6 +1,7 @@
-// Stable LSD radix sort of (key, u32 value) pairs for the grid identifiers
-// of Section 4.1 (Algorithm 1 orders the points by identifier with a radix
-// sort).  A sort of B bits takes ceil(B / 8) passes of equal digits
+// Stable LSD radix sort of (key, value) pairs (u32 or u64 values) for the
+// grid identifiers of Section 4.1 (Algorithm 1 orders the points by
+// identifier with a radix sort).  A sort of B bits takes ceil(B / 8) passes
+// of equal digits
 // of at most 8 bits (wider digits cost more per pass than the pass they
 // save: a 4x larger offset table to scan, more ranking ballots and less
 // occupancy).
