@@ -1,18 +1,17 @@
 // Stable LSD radix sort of (key, value) pairs (u32 or u64 values) for the
 // grid identifiers of Section 4.1 (Algorithm 1 orders the points by
 // identifier with a radix sort).  A sort of B bits takes ceil(B / 8) passes
-// of equal digits
-// of at most 8 bits (wider digits cost more per pass than the pass they
-// save: a 4x larger offset table to scan, more ranking ballots and less
-// occupancy).
+// of equal digits of at most 8 bits (wider digits cost more per pass than
+// the pass they save: a 4x larger offset table to scan, more ranking
+// ballots and less occupancy).
 //
 // Each pass is reduce-then-scan: (1) every workgroup builds the digit
-// histogram of its tile (4096 keys, 1024 in sorts of at most 2^21 keys) in
-// LDS (one sub-histogram per wave to cut atomic contention); (2) a
-// device-wide exclusive scan over the
-// digit-major [bins][tiles] table gives every (digit, tile) its output base;
-// (3) every workgroup re-reads its tile; each wave takes a run of a quarter
-// of it (consecutive keys) and ranks them among equal digits with wave64 ballots
+// histogram of its tile (4096 keys; 2048 with 64-bit values; 1024 in sorts
+// of at most 2^21 keys) in LDS (one sub-histogram per wave to cut atomic
+// contention); (2) a device-wide exclusive scan over the digit-major
+// [bins][tiles] table gives every (digit, tile) its output base; (3) every
+// workgroup re-reads its tile; each wave takes a run of a quarter of it
+// (consecutive keys) and ranks them among equal digits with wave64 ballots
 // (one ballot per digit bit gives the lanes holding the same digit; the rank
 // is the popcount below the lane plus the wave's running count of that
 // digit, kept in LDS), one scan over (digit, wave) turns the counts into
