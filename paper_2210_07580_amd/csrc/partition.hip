@@ -11,8 +11,10 @@
 //             integer with the instance in the top field and dimension 1
 //             highest below it, so integer order is the lexicographic order
 //             the paper's radix sort produces, instance by instance
-//   gather  : sorted points as padded int32 rows (one vector load per point
-//             in the later phases; instances with d < D padded with 0)
+//   rows    : sorted points as padded int32 rows (one vector load per point
+//             in the later phases; instances with d < D padded with 0),
+//             rebuilt in sorted order from the low coordinate bits the sort
+//             carried (unpack) or, when those do not fit, gathered
 //   cells   : runs of equal identifiers = the non-empty grids Gs
 //   tree    : level 0 = instances, level l = distinct prefixes of length l,
 //             each level in sorted order, so every node's children are
