@@ -271,7 +271,7 @@ struct SideRows {
 // One thread per grid: where its core set starts, the smallest input index
 // of its core points (grids without side rows), and the header counts.  The
 // counts are reduced per workgroup and written to part[] (five words per
-// workgroup), then summed by core_counts_kernel: atomics from every wave to
+// workgroup), then summed by core_counts_fold: atomics from every wave to
 // five addresses serialise on grids by the million.
 __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut co, uint32_t* part) {
     __shared__ uint32_t red[5][kWavesPerBlock];
@@ -309,11 +309,12 @@ __global__ __launch_bounds__(kBlock) void core_cells_kernel(GridView gv, CoreOut
     }
 }
 
-// One workgroup: counts[0..4] from the per-workgroup words.
-__global__ __launch_bounds__(1024) void core_counts_kernel(const uint32_t* part, int64_t blocks, uint32_t* counts) {
-    __shared__ uint32_t red[5][1024 / kWave];
+// counts[0..4] from the per-workgroup words of core_cells_kernel, by one
+// workgroup (the first of the side copy, which needs no extra launch).
+__device__ __forceinline__ void core_counts_fold(const uint32_t* part, int64_t blocks, uint32_t* counts) {
+    __shared__ uint32_t red[5][kWavesPerBlock];
     uint32_t a[5] = {0, 0, 0, 0, 0};
-    for (int64_t b = threadIdx.x; b < blocks; b += 1024) {
+    for (int64_t b = threadIdx.x; b < blocks; b += kBlock) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             const uint32_t x = part[b * 5 + k];
@@ -329,15 +330,19 @@ __global__ __launch_bounds__(1024) void core_counts_kernel(const uint32_t* part,
     __syncthreads();
     if (threadIdx.x < 5) {
         uint32_t r = 0;
-        for (int ww = 0; ww < 1024 / kWave; ++ww) r = threadIdx.x == 2 ? max(r, red[2][ww]) : r + red[threadIdx.x][ww];
+        for (int ww = 0; ww < kWavesPerBlock; ++ww)
+            r = threadIdx.x == 2 ? max(r, red[2][ww]) : r + red[threadIdx.x][ww];
         counts[threadIdx.x] = r;
     }
 }
 
 // One wave per grid holding both core and non-core points: copy its core
-// rows, in sorted order, to the side area.
+// rows, in sorted order, to the side area.  Workgroup 0 first folds the
+// header counts (part, blocks: see core_cells_kernel).
 template <int D>
-__global__ __launch_bounds__(kBlock) void side_copy_kernel(GridView gv, CoreOut co) {
+__global__ __launch_bounds__(kBlock) void side_copy_kernel(GridView gv, CoreOut co, const uint32_t* part,
+                                                           int64_t blocks) {
+    if (blockIdx.x == 0) core_counts_fold(part, blocks, co.counts);
     // each wave checks 64 grids at once (one lane each) and copies only the
     // mixed ones: most grids need nothing, and a wave launched per grid would
     // spend the kernel on dispatching waves that exit at once
@@ -387,9 +392,8 @@ hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* pa
     if (e != hipSuccess) return e;
     const unsigned nb = grid_for(g.ncell);
     core_cells_kernel<<<dim3(nb), dim3(kBlock), 0, st>>>(g, c, c.count_part);
-    core_counts_kernel<<<1, 1024, 0, st>>>(c.count_part, nb, c.counts);
     GD_DISPATCH_D(g.D, (side_copy_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock * kWave)), dim3(kBlock), 0, st>>>(
-                           g, c)));
+                           g, c, c.count_part, (int64_t)nb)));
     return hipGetLastError();
 }
 
