@@ -17,7 +17,9 @@ Loss of one sample with targets (y0, y1, w1):
 (binary cross-entropy with logits), averaged over the batch.
 
 Parity unpinned by the paper (this model is not in it); pinned here by
-central finite differences and by closed forms on hand-set weights.
+central finite differences, closed forms on hand-set weights, and closed
+forms of the Adam recursion (first step, constant gradient, a single
+gradient followed by zeros, scale invariance).
 """
 from __future__ import annotations
 
@@ -57,14 +59,26 @@ def init(seed: int = 0):
     return pack(p)
 
 
-def forward(theta, x):
-    """Logits z [B, 2] and the hidden activations."""
+def _to_half(a):
+    """Round to the nearest IEEE binary16 value (ties to even), kept in FP64."""
+    return np.asarray(a, dtype=np.float64).astype(np.float16).astype(np.float64)
+
+
+def forward(theta, x, hidden_fp16=False):
+    """Logits z [B, 2] and the hidden activations.
+
+    hidden_fp16: round each hidden activation h = relu(a) to binary16 before
+    the next layer uses it (the storage precision of the FP16 scorer, whose
+    kernels keep hidden activations as halves); everything else stays FP64.
+    The gradient then follows the rounded forward pass, with the rounding
+    itself treated as the identity (straight-through), as the kernels do."""
     p = unpack(theta)
     x = np.asarray(x, dtype=np.float64)
+    rnd = _to_half if hidden_fp16 else (lambda a: a)
     a1 = x @ p["W1"].T + p["b1"]
-    h1 = np.maximum(a1, 0.0)
+    h1 = rnd(np.maximum(a1, 0.0))
     a2 = h1 @ p["W2"].T + p["b2"]
-    h2 = np.maximum(a2, 0.0)
+    h2 = rnd(np.maximum(a2, 0.0))
     z = h2 @ p["W3"].T + p["b3"]
     return z, (x, a1, h1, a2, h2)
 
@@ -77,19 +91,19 @@ def sigmoid(z):
     return 0.5 * (1.0 + np.tanh(0.5 * z))
 
 
-def loss(theta, x, t):
+def loss(theta, x, t, hidden_fp16=False):
     """Mean loss over the batch; t [B, 3] = (y0, y1, w1)."""
-    z, _ = forward(theta, x)
+    z, _ = forward(theta, x, hidden_fp16)
     t = np.asarray(t, dtype=np.float64)
     l0 = softplus(z[:, 0]) - t[:, 0] * z[:, 0]
     l1 = softplus(z[:, 1]) - t[:, 1] * z[:, 1]
     return float(np.mean(l0 + LAMBDA * t[:, 2] * l1))
 
 
-def grad(theta, x, t):
+def grad(theta, x, t, hidden_fp16=False):
     """Gradient of loss() by back-propagation (chain rule, layer by layer)."""
     p = unpack(theta)
-    z, (x, a1, h1, a2, h2) = forward(theta, x)
+    z, (x, a1, h1, a2, h2) = forward(theta, x, hidden_fp16)
     t = np.asarray(t, dtype=np.float64)
     B = x.shape[0]
     dz = np.empty_like(z)
@@ -119,8 +133,20 @@ def numeric_grad(theta, x, t, idx, h=1e-6):
     return out
 
 
+def block_slices():
+    """Name and slice of each parameter block in the flat vector."""
+    out, o = [], 0
+    for name, shape in SHAPES:
+        k = int(np.prod(shape))
+        out.append((name, slice(o, o + k)))
+        o += k
+    return out
+
+
 def adam_step(theta, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam update (Kingma & Ba), step counted from 1."""
+    """One Adam update (Kingma & Ba 2015, Algorithm 1), step counted from 1:
+    first and second moment estimates, their bias corrections
+    1 - b1^step and 1 - b2^step, and the step lr * m_hat / (sqrt(v_hat) + eps)."""
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g
     mh = m / (1 - b1 ** step)
