@@ -229,25 +229,7 @@ class Context:
         (points float32 [n_k, d_k] on the device, eps_k, minpts_k).  Returns
         a list of (labels, core_flags) device tensors, one per instance
         (``outs``, when given, is such a list to write into)."""
-        import torch
-        descs = (Instance * max(len(problems), 1))()
-        given, outs, keep = outs, [], []
-        for k, (pts, eps, minpts) in enumerate(problems):
-            if pts.dtype != torch.float32 or pts.dim() != 2 or pts.device.type != "cuda":
-                raise ValueError(f"instance {k}: points must be a float32 [n, d] GPU tensor")
-            pts = pts.contiguous()
-            n, d = pts.shape
-            if given is not None:
-                lab, core = given[k]
-                if lab.numel() != n or core.numel() != n or lab.dtype != torch.int32 or core.dtype != torch.uint8:
-                    raise ValueError(f"instance {k}: output tensors must be int32 [n] and uint8 [n]")
-            else:
-                lab = torch.empty(n, dtype=torch.int32, device=pts.device)
-                core = torch.empty(n, dtype=torch.uint8, device=pts.device)
-            descs[k] = Instance(_ptr(pts) if n else None, int(n), int(d), int(minpts), float(eps),
-                                _ptr(lab) if n else None, _ptr(core) if n else None)
-            keep.append(pts)
-            outs.append((lab, core))
+        descs, outs, keep = self._descriptors(problems, outs)
         rc = load_library().dbscan_batched(self._h, descs, len(problems), _stream_handle(stream))
         self._check(rc)
         return outs

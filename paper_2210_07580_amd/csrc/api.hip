@@ -605,8 +605,19 @@ int check_params(gd_ctx* ctx, int k, int64_t n, int32_t d, double eps, int32_t m
     return GD_OK;
 }
 
+void drop_graph(gd_ctx* ctx) {
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+    ctx->gsig.clear();
+}
+
 int ensure_inst_capacity(gd_ctx* ctx, int count) {
     if (count <= ctx->inst_cap) return GD_OK;
+    // a captured graph reads the instance table through the old pointers
+    // (its copy node from the pinned host table, every kernel from the
+    // device table): it must never run again
+    drop_graph(ctx);
+    ++ctx->generation;
     if (ctx->inst_dev) (void)hipFree(ctx->inst_dev);
     if (ctx->inst_host) (void)hipHostFree(ctx->inst_host);
     ctx->inst_dev = nullptr;
@@ -659,13 +670,19 @@ void finish_table(gd_ctx* ctx, int count, int* D, int64_t* n, uint32_t* tiles) {
 }
 
 // Shape of the batch a graph is valid for: instance sizes and dimensions
-// plus the options that change the launch sequence.  Coordinates, eps,
-// MinPts and the caller's pointers live in the device instance table, which
-// the graph re-reads from pinned host memory on every replay.
+// plus the options and host-side choices that change the launch sequence.
+// Coordinates, eps, MinPts and the caller's pointers live in the device
+// instance table, which the graph re-reads from pinned host memory on every
+// replay; the one kernel variant chosen from eps (packed 16-bit coordinate
+// differences in core marking, exact only up to kPackedEpsMax) is part of
+// the shape, and that kernel also refuses a larger eps on the device.
 std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
     std::vector<int64_t> sig;
-    sig.reserve(2 * (size_t)count + 3);
+    sig.reserve(2 * (size_t)count + 7);
     sig.push_back(count);
+    int64_t max_eps = 0;
+    for (int k = 0; k < count; ++k) max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
+    sig.push_back(core_mark_packed(max_eps) ? 1 : 0);
     sig.push_back(ctx->ldf ? 1 : 0);
     sig.push_back(ctx->proposal_on ? 1 : 0);
     sig.push_back(ctx->tile_pts);
@@ -675,12 +692,6 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
         sig.push_back(ctx->inst_host[k].d);
     }
     return sig;
-}
-
-void drop_graph(gd_ctx* ctx) {
-    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
-    ctx->gexec = nullptr;
-    ctx->gsig.clear();
 }
 
 // Capture a planned run sized from the eager call that just finished.

@@ -22,29 +22,26 @@
 namespace gd {
 
 // Squared distance of two points of neighbouring grids: every coordinate
-// difference is below 2 eps < 2^23, so one signed 24-bit multiply-add per
-// coordinate is exact.
+// difference is below 2.13 eps < 2^16 in magnitude, so each square is an
+// exact unsigned 24-bit product, and the sum (below 9 eps^2 < 2^32 for
+// eps <= 21845) is exact in unsigned 32-bit arithmetic.
 template <int D>
 __device__ __forceinline__ uint32_t sqdist_nb(const int32_t (&a)[D], const int32_t (&b)[D]) {
-    int32_t dd = 0;
+    uint32_t dd = 0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        const int32_t t = a[j] - b[j];
-        dd = __mul24(t, t) + dd;
-    }
-    return (uint32_t)dd;
+    for (int j = 0; j < D; ++j) dd += sq24(a[j], b[j]);
+    return dd;
 }
 
 // Packed form for small eps: points of neighbouring grids differ by less
 // than (2 + sqrt(d - 1)) eps / sqrt(d) <= 2.13 eps per coordinate (the key
 // offsets of Eq. (2) bound |k_j - k'_j| by 1 + sqrt(d - 1)), so for
 // eps <= kPackedEpsMax every difference fits a signed 16-bit half and the
-// squared distance (at most d (2.13 eps)^2 < 2^32) is exact in 32 bits.  Two
+// squared distance (at most d (2.13 eps)^2 < 2^31) is exact in 32 bits.  Two
 // coordinates share a word (low 16 bits of each; a 16-bit difference of the
 // low halves is the exact difference when that is below 2^15), one packed
 // subtraction and one two-term dot product handle both; an odd last
 // coordinate stays a full word.
-constexpr int64_t kPackedEpsMax = 10000;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
@@ -99,6 +96,12 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     const uint32_t minpts = (uint32_t)I.minpts;
     const uint32_t T = I.T;
     const uint32_t k = en - st;
+    if (kPacked && I.eps > kPackedEpsMax) {
+        // a replayed graph met a larger eps than it was captured for: the
+        // packed differences could wrap, so the run is discarded
+        if (lane == 0) atomicOr(&gv.b.hdr->err, kErrPlan);
+        return;
+    }
     if (k >= minpts) {
         for (uint32_t i = lane; i < k; i += kWave) core[st + i] = 1;
         if (lane == 0) core_cnt[c] = k;
@@ -231,7 +234,7 @@ hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const ui
                             hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
-    const bool packed = max_eps <= kPackedEpsMax;
+    const bool packed = core_mark_packed(max_eps);
     const bool two = min_minpts > kWave / 2;
     // the counting variant takes the same steps as the timed one
     if (stats && two) {

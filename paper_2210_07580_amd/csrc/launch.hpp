@@ -198,6 +198,11 @@ struct CoreStats {
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
                             uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts,
                             hipStream_t st);
+// Whether core marking compares coordinates as packed 16-bit differences
+// for a batch whose largest eps is max_eps (exact for eps <= 10000: points
+// of neighbouring grids differ by less than 2.13 eps per coordinate).
+constexpr int64_t kPackedEpsMax = 10000;
+inline bool core_mark_packed(int64_t max_eps) { return max_eps <= kPackedEpsMax; }
 hipError_t launch_core_compact(const GridView& g, const CoreOut& c, uint32_t* partial, hipStream_t st);
 // LDF order (Section 5.2): core grids by ascending core count (ties by grid
 // index); rank[g] = (position (kNone for non-core grids), core_begin,

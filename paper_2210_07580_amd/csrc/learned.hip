@@ -263,34 +263,46 @@ __global__ __launch_bounds__(kBlock) void mlp_train_kernel(TrainArgs a) {
             for (int k = 0; k < kFeat; ++k) gW1[k] += da1 * f[k];
             wave_sync();
         }
+        // the waves add their rows in wave order (a fixed summation order,
+        // so the gradient of a batch is the same on every call); within a
+        // wave every lane owns its own addresses
+        for (int turn = 0; turn < kWavesPerBlock; ++turn) {
+            if (w == turn) {
 #pragma unroll
-        for (int k = 0; k < kFeat; ++k) atomicAdd(&G[oW1 + u * kFeat + k], gW1[k]);
-        atomicAdd(&G[oB1 + u], gb1);
+                for (int k = 0; k < kFeat; ++k) G[oW1 + u * kFeat + k] += gW1[k];
+                G[oB1 + u] += gb1;
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) atomicAdd(&G[oW2 + u * kHid + k], gW2[k]);
-        atomicAdd(&G[oB2 + u], gb2);
-        atomicAdd(&G[oW3 + u], gW30);
-        atomicAdd(&G[oW3 + kHid + u], gW31);
-        if (u == 0) {
-            atomicAdd(&G[oB3], gb30);
-            atomicAdd(&G[oB3 + 1], gb31);
-            atomicAdd(&s_loss, lsum);
+                for (int k = 0; k < kHid; ++k) G[oW2 + u * kHid + k] += gW2[k];
+                G[oB2 + u] += gb2;
+                G[oW3 + u] += gW30;
+                G[oW3 + kHid + u] += gW31;
+                if (u == 0) {
+                    G[oB3] += gb30;
+                    G[oB3 + 1] += gb31;
+                    s_loss += lsum;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         if (a.grad && step == 0)
             for (int i = tid; i < kParams; i += kBlock) a.grad[i] = G[i];
         if (a.loss && tid == 0) a.loss[step] = s_loss * inv_b;
         if (a.update) {
-            const float b1 = 0.9f, b2 = 0.999f;
+            // Adam (beta1 0.9, beta2 0.999, eps 1e-8).  The step's bias
+            // corrections 1 - beta^t are taken in double (in single precision
+            // 1 - 0.999^t loses five digits to cancellation), and 1 - beta
+            // is the single-precision value of the exact difference.
             const int t = a.adam_t0 + step + 1;
-            const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+            const double c1 = 1.0 - pow(0.9, (double)t), c2 = 1.0 - pow(0.999, (double)t);
+            const float inv_c1 = (float)(1.0 / c1), inv_sqrt_c2 = (float)(1.0 / sqrt(c2));
+            const float b1 = 0.9f, b2 = 0.999f, omb1 = 0.1f, omb2 = 0.001f;
             for (int i = tid; i < kParams; i += kBlock) {
                 const float g = G[i];
-                const float mm = b1 * a.m[i] + (1.f - b1) * g;
-                const float vv = b2 * a.v[i] + (1.f - b2) * g * g;
+                const float mm = b1 * a.m[i] + omb1 * g;
+                const float vv = b2 * a.v[i] + omb2 * (g * g);
                 a.m[i] = mm;
                 a.v[i] = vv;
-                a.params[i] -= a.lr * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+                a.params[i] -= a.lr * (mm * inv_c1) / (sqrtf(vv) * inv_sqrt_c2 + 1e-8f);
             }
         }
         __syncthreads();

@@ -6,6 +6,10 @@ generator is told apart from a wrong result), the digests of the oracle's
 int32 labels and uint8 core flags, and a few counts for diagnosis.
 
     python tests/golden/make_oracle_digests.py cfg1 H cfg4 cfg2 [--threads N]
+    python tests/golden/make_oracle_digests.py cfg3 [--threads N]
+
+``cfg3`` is the 256-instance batch workload: one record per instance, in
+instance order, under the key "cfg3".
 """
 import argparse
 import hashlib
@@ -54,6 +58,18 @@ def main():
             db = json.load(f)
     threads = args.threads or oracle.max_threads()
     for name in args.names:
+        if name == "cfg3":
+            recs = []
+            for k, w in enumerate(W.batch_workloads()):
+                x = W.make_points(w)
+                t0 = time.time()
+                labels, core = oracle.dbscan(x, w.eps, w.minpts, nthreads=threads)
+                recs.append(record(w, x, labels, core, time.time() - t0, threads))
+                print(f"cfg3 instance {k}: n={x.shape[0]} d={x.shape[1]} {recs[-1]['oracle_seconds']} s", flush=True)
+            db[name] = recs
+            with open(OUT, "w") as f:
+                json.dump(db, f, indent=1, sort_keys=True)
+            continue
         w = W.WORKLOADS[name]
         x = W.make_points(w)
         t0 = time.time()

@@ -170,3 +170,64 @@ def test_replay_with_eps_beyond_packed_rows(G):
     assert ctx.stats()["graph_replays"] == 0, "the replay must be discarded"
     assert np.array_equal(core.cpu().numpy(), rc) and np.array_equal(lab.cpu().numpy(), rl)
     ctx.close()
+
+
+def _wrap_trap():
+    """d = 2 points where a 16-bit coordinate difference wraps into the eps
+    ball: point 0 sits at x = 0, five points at x = 45000 lie two grids
+    away (grid side eps / sqrt(2) ~ 15447 for eps = 21845, so the grids are
+    neighbours by Eq. (2)), 45000 - 2^16 = -20536 would pass |dx| <= eps.
+    The true distance is 45000 > eps: point 0 is noise for MinPts 3."""
+    pts = [(0, 0)] + [(45000, k) for k in range(5)] + [(90000 + 7 * k, 3 * k) for k in range(6)]
+    return np.array(pts, dtype=np.int32)
+
+
+def test_replay_across_packed_difference_bound(G):
+    # captured at eps <= 10000 (core marking compares packed 16-bit
+    # differences), then the same shape at eps 21845, where those would wrap
+    x = _wrap_trap()
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    want_l, want_c = oracle.dbscan(x, 21845, 3)
+    assert want_c[0] == 0 and want_l[0] == -1
+    ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_GRAPH, 2)
+    for _ in range(2):
+        ctx.dbscan(t, 5000, 3)
+    assert ctx.stats()["graph_replays"] == 1
+    for rep, eps in enumerate((21845, 21100, 21845)):
+        print(f"case: same shape at eps {eps} after a capture at eps 5000 ({rep})", flush=True)
+        wl, wc = oracle.dbscan(x, eps, 3)
+        lab, core = ctx.dbscan(t, eps, 3)
+        assert np.array_equal(core.cpu().numpy(), wc) and np.array_equal(lab.cpu().numpy(), wl)
+    # and back below the bound: the small-eps graph is captured again
+    for _ in range(2):
+        lab, core = ctx.dbscan(t, 5000, 3)
+    wl, wc = oracle.dbscan(x, 5000, 3)
+    assert np.array_equal(core.cpu().numpy(), wc) and np.array_equal(lab.cpu().numpy(), wl)
+    ctx.close()
+
+
+def test_instance_table_growth_drops_graph(G):
+    # a graph captured for 8 instances reads the instance table through the
+    # pointers of that time; a later call with more instances than the table
+    # holds (one that does not capture: statistics on) reallocates it, and
+    # the next call of the first shape must not replay the stale graph
+    small = _problems(9191, count=8)
+    many = _problems(9292, count=20)
+    ctx = G.Context(0)
+    outs = ctx.dbscan_batched(_dev(small))  # eager + capture
+    outs = ctx.dbscan_batched(_dev(small))
+    assert ctx.stats()["graph_replays"] == 1
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    print("case: 20 instances with statistics on (instance table grows)", flush=True)
+    ctx.dbscan_batched(_dev(many))
+    ctx.set_option(G.GD_OPT_STATS, 0)
+    print("case: the 8-instance shape again", flush=True)
+    outs = ctx.dbscan_batched(_dev(small))
+    assert ctx.stats()["graph_replays"] == 0, "a graph over the old instance table must not replay"
+    for k, (lab, core) in enumerate(outs):
+        wl, wc = oracle.dbscan(*small[k])
+        assert np.array_equal(core.cpu().numpy(), wc) and np.array_equal(lab.cpu().numpy(), wl), f"instance {k}"
+    outs = ctx.dbscan_batched(_dev(small))
+    assert ctx.stats()["graph_replays"] == 1
+    ctx.close()
