@@ -131,6 +131,31 @@ void gd_destroy(gd_ctx *ctx);
 int dbscan(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps,
            int32_t minpts, int32_t *labels, uint8_t *core_flags, void *stream);
 
+/*
+ * dbscan_noalloc: dbscan() for callers that cannot allocate device memory
+ * (tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * result and errors as dbscan(); the call itself allocates and frees
+ * nothing: every workspace buffer is carved from one fixed array of
+ * GD_NOALLOC_SCRATCH_BYTES bytes per device, part of the library's device
+ * code and held until the process ends (its device address is looked up by
+ * gd_create).  The context must exist already.  Like dbscan() the call
+ * reads counts back to the host between phases, so it cannot itself be
+ * recorded into a HIP graph.
+ *
+ * Limits: the workspace of one call must fit the array (about 230 bytes per
+ * point at d = 3 plus 4 bytes per neighbour-list entry and the output hash
+ * table: roughly a million points of clustered 3-D data); a larger input
+ * returns GD_ENOMEM with the sizes in gd_last_error(), before any kernel
+ * runs, or once the neighbour-list total is known.  Every call on one
+ * device shares that device's array, and it keeps the last call's contents:
+ * calls that overlap on one device (several host threads, or several
+ * streams without ordering between them) race and must not be made.  The
+ * call never captures or replays a graph.
+ */
+#define GD_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int dbscan_noalloc(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+                   int32_t *labels, uint8_t *core_flags, void *stream);
+
 /* One instance of a batch (dbscan_batched).  Pointers are DEVICE pointers
  * with the same meaning as dbscan()'s arguments. */
 typedef struct {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
 GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES = 6, 7
+NOALLOC_SCRATCH_BYTES = 256 << 20
 PHASE_COUNT = 14
 EPS_MAX = 21845
 D_MAX = 8
@@ -56,7 +57,7 @@ class Instance(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ("gd_create", "gd_destroy", "dbscan", "dbscan_batched", "gd_set_option", "gd_get_stats",
+EXPORTS = ("gd_create", "gd_destroy", "dbscan", "dbscan_noalloc", "dbscan_batched", "gd_set_option", "gd_get_stats",
            "gd_debug_grids", "gd_debug_neighbors", "gd_debug_core", "gd_merge_test",
            "gd_get_phase_times", "gd_phase_name", "gd_set_proposal", "gd_proposal_harvest",
            "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string", "gd_autotune")
@@ -80,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.gd_destroy.restype = None
     lib.dbscan.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, vp]
     lib.dbscan.restype = ctypes.c_int
+    lib.dbscan_noalloc.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, vp]
+    lib.dbscan_noalloc.restype = ctypes.c_int
     lib.dbscan_batched.argtypes = [vp, ctypes.POINTER(Instance), i32, vp]
     lib.dbscan_batched.restype = ctypes.c_int
     lib.gd_set_option.argtypes = [vp, ctypes.c_int, i64]
@@ -172,6 +175,17 @@ class Context:
 
         Returns (labels int32 [n], core_flags uint8 [n]) as device tensors.
         """
+        return self._single(load_library().dbscan, points, eps, minpts, labels, core_flags, stream)
+
+    def dbscan_noalloc(self, points, eps, minpts: int, labels, core_flags, stream=None):
+        """dbscan() into caller-given output tensors, with every workspace
+        buffer taken from the library's fixed per-device scratch array (the
+        call allocates nothing)."""
+        if labels is None or core_flags is None:
+            raise ValueError("dbscan_noalloc writes into given labels and core_flags tensors")
+        return self._single(load_library().dbscan_noalloc, points, eps, minpts, labels, core_flags, stream)
+
+    def _single(self, fn, points, eps, minpts, labels, core_flags, stream):
         import torch
         if not isinstance(points, torch.Tensor) or points.dim() != 2:
             raise ValueError("points must be a 2-D torch tensor")
@@ -185,8 +199,11 @@ class Context:
             labels = torch.empty(n, dtype=torch.int32, device=pts.device)
         if core_flags is None:
             core_flags = torch.empty(n, dtype=torch.uint8, device=pts.device)
-        rc = load_library().dbscan(self._h, _ptr(pts), int(n), int(d), float(eps), int(minpts),
-                                   _ptr(labels), _ptr(core_flags), _stream_handle(stream))
+        if labels.numel() != n or core_flags.numel() != n or labels.dtype != torch.int32 \
+                or core_flags.dtype != torch.uint8:
+            raise ValueError("labels must be int32 [n] and core_flags uint8 [n]")
+        rc = fn(self._h, _ptr(pts), int(n), int(d), float(eps), int(minpts), _ptr(labels), _ptr(core_flags),
+                _stream_handle(stream))
         self._check(rc)
         return labels, core_flags
 

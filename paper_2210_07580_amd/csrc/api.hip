@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,14 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// The workspace buffers a call grows on demand.
+struct Bufs {
+    DevBuf arena;   // everything sized by the batch's points and dimension
+    DevBuf nei;     // the neighbour lists, sized by their total
+    DevBuf table;   // identifier -> label hash table of the output pass
+    DevBuf sumbuf;  // CellSummary per grid (learned proposal)
+};
+
 enum Phase {
     P_MINMAX, P_KEYS, P_SORT, P_GATHER, P_CELLS, P_TREE, P_NEI_COUNT, P_NEI_FILL,
     P_CORE_MARK, P_CORE_COMPACT, P_LDF, P_MERGE, P_LABELS, P_OUTPUT, P_COUNT
@@ -44,13 +53,43 @@ const char* const kPhaseNames[P_COUNT] = {
     "minmax", "keys", "radix_sort", "gather", "cells", "grid_tree", "nei_count", "nei_fill",
     "core_mark", "core_compact", "ldf_order", "merge", "labels", "output"};
 
+// Workspace of dbscan_noalloc: one fixed array per device, never
+// allocated or freed by a call.  Host code must not use this name as a
+// device address (in host code it names a host-side stand-in): gd_create
+// looks the device address up once per device and every call uses that.
+static __device__ __align__(256) unsigned char scratch[GD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (= `device`), looked up
+// on the first call for that device.  nullptr if the lookup failed.
+char* scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+            g_scratch_ptr[device] = (char*)ptr;
+        else
+            (void)hipGetLastError();
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 struct gd_ctx {
     int device = 0;
     std::string err;
-    DevBuf arena;  // everything sized by the batch's points and dimension
-    DevBuf nei;    // the neighbour lists, sized by their total
+    Bufs own;              // the context's workspace (hipMalloc'ed, grown on demand)
+    Bufs* cur = &own;      // the workspace of the running call
+    // dbscan_noalloc: buffers are carved in order from the device's fixed
+    // scratch array instead of being allocated
+    char* bump_base = nullptr;
+    size_t bump_cap = 0, bump_used = 0;
+    char* scratch = nullptr;  // this device's scratch array (hipGetSymbolAddress at gd_create)
     Header* hdr_dev = nullptr;
     Header* hdr_host = nullptr;  // pinned
     StatBlock* stats_dev = nullptr;
@@ -82,8 +121,6 @@ struct gd_ctx {
     // learned proposal
     __half* proposal_dev = nullptr;  // GD_MLP_PARAMS halves
     bool proposal_on = false;
-    DevBuf sumbuf;                   // CellSummary per grid
-    DevBuf table;                    // identifier -> label hash table of the output pass
     unsigned long long* counter_dev = nullptr;
     // sync-free runs captured into a HIP graph and replayed
     int graph_mode = 1;              // 0 never, 1 dbscan_batched, 2 every call
@@ -158,6 +195,19 @@ struct Carve {
 
 int grow(gd_ctx* ctx, DevBuf& b, size_t need, size_t other_held) {
     if (need <= b.cap) return GD_OK;
+    if (ctx->bump_base) {
+        // no allocation: the next slice of the fixed scratch array
+        const size_t off = align_up(ctx->bump_used);
+        if (off > ctx->bump_cap || need > ctx->bump_cap - off)
+            return ctx->fail(GD_ENOMEM,
+                             "dbscan_noalloc: the call needs more than the fixed %llu-byte scratch "
+                             "(%zu bytes already taken, %zu more asked)",
+                             (unsigned long long)ctx->bump_cap, off, need);
+        b.p = ctx->bump_base + off;
+        b.cap = need;
+        ctx->bump_used = off + need;
+        return GD_OK;
+    }
     if (ctx->ws_limit > 0 && (int64_t)(need + other_held) > ctx->ws_limit)
         return ctx->fail(GD_ENOMEM, "workspace of %zu bytes exceeds the context limit of %lld bytes", need + other_held,
                          (long long)ctx->ws_limit);
@@ -337,9 +387,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- workspace
     Layout L = carve(nullptr, n, D, tiles);
-    int rc = plan ? GD_OK : grow(ctx, ctx->arena, L.bytes, ctx->nei.cap);
+    int rc = plan ? GD_OK : grow(ctx, ctx->cur->arena, L.bytes, ctx->cur->nei.cap);
     if (rc) return rc;
-    L = carve((char*)ctx->arena.p, n, D, tiles);
+    L = carve((char*)ctx->cur->arena.p, n, D, tiles);
     Header* Hd = ctx->hdr_dev;
     Header* H = ctx->hdr_host;
 
@@ -438,10 +488,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     else if ((rc = readback(ctx, st)))
         return rc;
     const uint64_t nei_total = plan ? plan->nei : H->nei_total;
-    if (!plan && (rc = grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t),
-                            ctx->arena.cap)))
+    if (!plan && (rc = grow(ctx, ctx->cur->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t),
+                            ctx->cur->arena.cap)))
         return rc;
-    uint32_t* nei = (uint32_t*)ctx->nei.p;
+    uint32_t* nei = (uint32_t*)ctx->cur->nei.p;
     ctx->mark(P_NEI_FILL, 0);
     GD_TRY(launch_nei_fill(g, t, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, st));
     ctx->mark(P_NEI_FILL, 1);
@@ -497,10 +547,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     CellSummary* sum = nullptr;
     ctx->last_summaries = false;
     if (ctx->proposal_on) {
-        if (!plan && (rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(ncell, 1),
-                                ctx->arena.cap + ctx->nei.cap)))
+        if (!plan && (rc = grow(ctx, ctx->cur->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(ncell, 1),
+                                ctx->cur->arena.cap + ctx->cur->nei.cap)))
             return rc;
-        sum = (CellSummary*)ctx->sumbuf.p;
+        sum = (CellSummary*)ctx->cur->sumbuf.p;
     }
     ctx->mark(P_MERGE, 0);
     if (sum) {
@@ -517,16 +567,16 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- border / noise, output in input order
     const int hbits = table_bits(ncell);
-    if (!plan && (rc = grow(ctx, ctx->table, output_table_bytes(hbits, k32 ? 4 : 8),
-                            ctx->arena.cap + ctx->nei.cap + ctx->sumbuf.cap)))
+    if (!plan && (rc = grow(ctx, ctx->cur->table, output_table_bytes(hbits, k32 ? 4 : 8),
+                            ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap)))
         return rc;
     ctx->mark(P_OUTPUT, 0);
     if (k32)
         GD_TRY(launch_output_direct<uint32_t>(g, co, (const uint32_t*)L.keys_a, (const uint32_t*)skeys, L.cell_label,
-                                              ctx->table.p, hbits, st));
+                                              ctx->cur->table.p, hbits, st));
     else
         GD_TRY(launch_output_direct<uint64_t>(g, co, (const uint64_t*)L.keys_a, (const uint64_t*)skeys, L.cell_label,
-                                              ctx->table.p, hbits, st));
+                                              ctx->cur->table.p, hbits, st));
     GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
     ctx->mark(P_OUTPUT, 1);
     if (stats) GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
@@ -722,11 +772,11 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
             if (c->generation != g) c->have_last = false;
         }
     } inval{ctx, gen0};
-    if (grow(ctx, ctx->nei, (size_t)std::max<uint64_t>(p.nei, 1) * sizeof(uint32_t), ctx->arena.cap) ||
-        grow(ctx, ctx->table, output_table_bytes(table_bits(p.ncell), p.key_bits <= 32 ? 4 : 8),
-             ctx->arena.cap + ctx->nei.cap) ||
-        (ctx->proposal_on && grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(p.ncell, 1),
-                                  ctx->arena.cap + ctx->nei.cap + ctx->table.cap))) {
+    if (grow(ctx, ctx->cur->nei, (size_t)std::max<uint64_t>(p.nei, 1) * sizeof(uint32_t), ctx->cur->arena.cap) ||
+        grow(ctx, ctx->cur->table, output_table_bytes(table_bits(p.ncell), p.key_bits <= 32 ? 4 : 8),
+             ctx->cur->arena.cap + ctx->cur->nei.cap) ||
+        (ctx->proposal_on && grow(ctx, ctx->cur->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(p.ncell, 1),
+                                  ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->table.cap))) {
         ctx->err = saved_err;
         return;
     }
@@ -805,6 +855,8 @@ int gd_create(gd_ctx** out, int device) {
              hipMalloc(&ctx->proposal_dev, sizeof(__half) * kParams) == hipSuccess &&
              hipMalloc(&ctx->counter_dev, sizeof(unsigned long long)) == hipSuccess &&
              ensure_inst_capacity(ctx, 16) == GD_OK;
+        // with the device current: this device's copy of the scratch array
+        if (ok) ctx->scratch = scratch_address(device);
         if (ok) {
             ctx->events_ok = true;
             for (int p = 0; p < P_COUNT; ++p)
@@ -823,8 +875,8 @@ int gd_create(gd_ctx** out, int device) {
 void gd_destroy(gd_ctx* ctx) {
     if (!ctx) return;
     DeviceGuard guard(ctx->device);
-    if (ctx->arena.p) (void)hipFree(ctx->arena.p);
-    if (ctx->nei.p) (void)hipFree(ctx->nei.p);
+    if (ctx->own.arena.p) (void)hipFree(ctx->own.arena.p);
+    if (ctx->own.nei.p) (void)hipFree(ctx->own.nei.p);
     if (ctx->hdr_dev) (void)hipFree(ctx->hdr_dev);
     if (ctx->hdr_host) (void)hipHostFree(ctx->hdr_host);
     if (ctx->stats_dev) (void)hipFree(ctx->stats_dev);
@@ -833,8 +885,8 @@ void gd_destroy(gd_ctx* ctx) {
     if (ctx->inst_host) (void)hipHostFree(ctx->inst_host);
     if (ctx->proposal_dev) (void)hipFree(ctx->proposal_dev);
     if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
-    if (ctx->sumbuf.p) (void)hipFree(ctx->sumbuf.p);
-    if (ctx->table.p) (void)hipFree(ctx->table.p);
+    if (ctx->own.sumbuf.p) (void)hipFree(ctx->own.sumbuf.p);
+    if (ctx->own.table.p) (void)hipFree(ctx->own.table.p);
     drop_graph(ctx);
     if (ctx->gev) (void)hipEventDestroy(ctx->gev);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
@@ -858,6 +910,39 @@ int dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, i
     uint32_t tiles;
     finish_table(ctx, 1, &D, &total, &tiles);
     return run_call(ctx, 1, D, total, tiles, (hipStream_t)stream, false);
+}
+
+int dbscan_noalloc(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, int32_t minpts,
+                   int32_t* labels, uint8_t* core_flags, void* stream) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    int rc = check_params(ctx, 0, n, d, eps, minpts, points, labels, core_flags);
+    if (rc) return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    if (!ctx->scratch) return ctx->fail(GD_EDEVICE, "dbscan_noalloc: the scratch array's device address is unknown");
+    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags);
+    int D;
+    int64_t total;
+    uint32_t tiles;
+    finish_table(ctx, 1, &D, &total, &tiles);
+    const size_t need = carve(nullptr, total, D, tiles).bytes;
+    if (need > (size_t)GD_NOALLOC_SCRATCH_BYTES)
+        return ctx->fail(GD_ENOMEM,
+                         "dbscan_noalloc: n = %lld at d = %d needs %zu bytes of workspace before its neighbour "
+                         "lists; the fixed scratch holds %llu",
+                         (long long)n, d, need, (unsigned long long)GD_NOALLOC_SCRATCH_BYTES);
+    // every buffer of this call comes from the scratch array, in order;
+    // nothing is allocated and no graph is captured or replayed
+    Bufs view{};
+    ctx->cur = &view;
+    ctx->bump_base = ctx->scratch;
+    ctx->bump_cap = (size_t)GD_NOALLOC_SCRATCH_BYTES;
+    ctx->bump_used = 0;
+    rc = run_batch(ctx, 1, D, total, tiles, (hipStream_t)stream, nullptr);
+    ctx->cur = &ctx->own;
+    ctx->bump_base = nullptr;
+    return rc;
 }
 
 int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* stream) {
@@ -1084,10 +1169,10 @@ int gd_proposal_harvest(gd_ctx* ctx, uint32_t seed, uint32_t keep_mod, int64_t c
     hipStream_t st = (hipStream_t)stream;
     const GridView& g = ctx->last_g;
     int rc;
-    if ((rc = grow(ctx, ctx->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(g.ncell, 1),
-                   ctx->arena.cap + ctx->nei.cap)))
+    if ((rc = grow(ctx, ctx->cur->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(g.ncell, 1),
+                   ctx->cur->arena.cap + ctx->cur->nei.cap)))
         return rc;
-    CellSummary* sum = (CellSummary*)ctx->sumbuf.p;
+    CellSummary* sum = (CellSummary*)ctx->cur->sumbuf.p;
     GD_TRY(fill<unsigned long long>(ctx->counter_dev, 1, 0ull, st));
     GD_TRY(launch_summaries(g, ctx->last_co, sum, st));
     GD_TRY(launch_harvest(g, ctx->last_co, sum, ctx->last_nei_off, ctx->last_nei, seed, keep_mod, cap,
