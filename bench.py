@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the batched and learned comparisons")
     ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--neighbor-mode", type=int, default=0, choices=(0, 1, 2),
+                    help="GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists for every grid, 2 walks in the consumers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -289,6 +291,7 @@ def main():
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     core = torch.empty(n, dtype=torch.uint8, device=dev)
     ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_NEIGHBOR_MODE, args.neighbor_mode)
     for i in range(args.warmup):
         ctx.dbscan(pts, w.eps, w.minpts, labels, core)
         log(f"bench: warmup {i + 1}/{args.warmup} done")

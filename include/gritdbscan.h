@@ -90,6 +90,10 @@ typedef struct {
     int64_t core_candidates;   /* candidate points streamed while marking core
                                   points (once per batch of 64 queries) */
     int64_t core_neighbor_grids; /* neighbour grids opened while marking */
+    int64_t neighbor_walk;     /* 1 if the consumers walked the grid tree themselves
+                                  (GD_OPT_NEIGHBOR_MODE): neighbor_entries then
+                                  counts only the lists of grids with more than 8
+                                  core points */
 } gd_stats;
 
 /* Create a context bound to HIP device `device` (the caller's current device
@@ -208,8 +212,28 @@ typedef enum {
     GD_OPT_TILE_POINTS = 6,   /* points per workgroup of the point-indexed
                                  kernels: a multiple of 256 in [256, 65536]
                                  (default 4096)                               */
-    GD_OPT_MERGE_WAVES = 7    /* waves per workgroup of the FastMerging
+    GD_OPT_MERGE_WAVES = 7,   /* waves per workgroup of the FastMerging
                                  kernel: 1, 2 or 4 (default 4)                */
+    GD_OPT_NEIGHBOR_MODE = 8, /* how the consumers get Nei(g) (Algorithm 3):
+                                 1 lists written out for every grid first;
+                                 2 core marking, the merging of core sets of at
+                                 most 8 points and border assignment each walk
+                                 the grid tree for their own grid (lists only
+                                 for grids with more core points: far less
+                                 memory, slower); 0 (default) lists, or walks
+                                 when the lists would not fit the workspace
+                                 (GD_OPT_WORKSPACE_LIMIT, or the fixed array
+                                 of dbscan_noalloc).  The result is the same in
+                                 every mode.                                   */
+    GD_OPT_MERGE_ORDER = 9    /* order in which core grids are merged: 0 grid
+                                 (identifier) order with union-find; 1 (default)
+                                 ascending core count with union-find (the LDF
+                                 variant, Section 5.2); 2 the breadth-first
+                                 searches of Algorithm 6 (Section 4.4), run level
+                                 by level from many seeds, on the full lists and
+                                 without graph replay or the learned proposal.
+                                 GD_OPT_LDF_ORDER sets 1 or 0.  The result is
+                                 the same in every order (Theorem 4).         */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);
@@ -265,7 +289,10 @@ const char *gd_phase_name(int32_t i);
  * gd_debug_neighbors (Section 4.2.2, Algorithm 3):
  *   offsets         |Gs|+1 (uint64): Nei(g) of grid g is
  *   neighbors       neighbors[offsets[g] .. offsets[g+1]) (grid indices),
- *                   ordered by the offset of Eq. (2), g itself excluded
+ *                   g itself excluded, ordered by the offset of Eq. (2) for
+ *                   at most 2^20 grids (above, in the order of the tree walk)
+ *                   Needs the lists of every grid (GD_EUNSUPPORTED after a
+ *                   call that walked instead, see GD_OPT_NEIGHBOR_MODE).
  * gd_debug_core: core_flags_sorted (n, sorted order), grid_label (|Gs|:
  *   cluster id of a core grid, -1 otherwise).
  */

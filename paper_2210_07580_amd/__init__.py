@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
-GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES = 6, 7
+GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES, GD_OPT_NEIGHBOR_MODE, GD_OPT_MERGE_ORDER = 6, 7, 8, 9
 NOALLOC_SCRATCH_BYTES = 256 << 20
 PHASE_COUNT = 14
 EPS_MAX = 21845
@@ -39,7 +39,7 @@ class Stats(ctypes.Structure):
             "max_grid_points", "merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
             "merge_iterations", "merge_max_iterations", "merge_distances", "core_distances",
             "border_points", "noise_points", "clusters", "merge_set_points", "graph_replays",
-            "core_candidates", "core_neighbor_grids")]
+            "core_candidates", "core_neighbor_grids", "neighbor_walk")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

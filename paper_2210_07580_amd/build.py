@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgritdbscan.so")
-SOURCES = ["partition.hip", "neighbors.hip", "core.hip", "merge.hip", "border.hip", "learned.hip", "api.hip"]
+SOURCES = ["partition.hip", "neighbors.hip", "walk.hip", "core.hip", "merge.hip", "border.hip", "learned.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

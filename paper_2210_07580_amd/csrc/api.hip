@@ -99,7 +99,10 @@ struct gd_ctx {
     int inst_cap = 0;
     int64_t ws_limit = 0;
     bool stats = false;
-    bool ldf = true;
+    bool ldf = true;               // LDF order (merge_order 1) or identifier order (0)
+    bool bfs = false;              // the BFS order of Algorithm 6 (merge_order 2)
+    int nei_mode = 0;              // GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists, 2 walks
+    bool last_walk = false;        // the last eager call walked (no full lists)
     gd_stats last{};
     // what the last successful call left in the workspace (for gd_debug_*)
     bool have_last = false;
@@ -236,7 +239,12 @@ struct Plan {
     uint64_t nei;      // neighbour-list entries
     int64_t ncc;       // core grids
     int64_t max_core;  // largest core set
+    bool walk;         // consumers walk the grid tree (lists only for big core sets)
 };
+
+// build_lists: the full lists do not fit the workspace (limit or fixed
+// scratch) and the consumers may walk the grid tree instead.
+constexpr int kListsDoNotFit = 1;
 
 // Output hash table: 2^bits slots for ncell grids, load <= 1/8 up to 2^20
 // grids (fewer second probes), <= 1/4 above (the table stays modest).
@@ -374,6 +382,32 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
     return GD_OK;
 }
 
+// The merge in the BFS order of Algorithm 6: rounds of seeds, each
+// followed by breadth-first levels until the frontier is empty; every level
+// reads its frontier size back (an eager run only).
+int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* nei_off, const uint32_t* nei,
+            int64_t max_core, uint32_t* state, uint32_t* front, uint32_t* next, uint32_t* cnt, uint32_t* parent,
+            MergeStats* stats, hipStream_t st) {
+    GD_TRY(fill<uint32_t>(state, g.ncell, 0u, st));
+    uint32_t h[3];
+    for (;;) {
+        GD_TRY(fill<uint32_t>(cnt, 3, 0u, st));
+        GD_TRY(launch_bfs_seeds(g, co, nei_off, nei, state, front, cnt, st));
+        GD_TRY(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, st));
+        GD_TRY(hipStreamSynchronize(st));
+        if (h[0] == 0) return GD_OK;  // every core grid is classified
+        uint32_t nf = h[1];
+        while (nf > 0) {
+            GD_TRY(fill<uint32_t>(cnt + 2, 1, 0u, st));
+            GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, state, parent, stats, st));
+            GD_TRY(hipMemcpyAsync(h + 2, cnt + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            GD_TRY(hipStreamSynchronize(st));
+            nf = h[2];
+            std::swap(front, next);
+        }
+    }
+}
+
 // Validated batch in ctx->inst_host[0..count): run every phase.  With a
 // plan the run is sync-free (every buffer already grown, capacities from
 // the plan, no host readback until the end) so that it can be captured into
@@ -471,7 +505,11 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     }
     t.key[D] = L.ck + (int64_t)D * n;
     t.level_count = Hd->level_count;
-    ctx->mark(P_NEI_COUNT, 0);
+    // Lists for every grid, unless asked to walk (the BFS order expands
+    // every core grid over its full list) or, by default, when the lists do
+    // not fit the workspace: then the consumers walk the grid tree.
+    bool walk = plan ? plan->walk : (!ctx->bfs && ctx->nei_mode == 2);
+    const bool may_walk = !plan && !ctx->bfs && ctx->nei_mode == 0;
     // the split walk's per-lane counts go to the sort buffer that does not
     // hold the sorted identifiers (free until the LDF step), when they fit
     uint32_t* lane_cnt = nullptr;
@@ -480,21 +518,43 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if (words > 0 && words <= 2 * n)
             lane_cnt = (uint32_t*)(skeys == L.keys_b ? L.keys_c : L.keys_b);
     }
-    GD_TRY(launch_nei_count(g, t, L.off_counts, lane_cnt, st));
-    GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
-    ctx->mark(P_NEI_COUNT, 1);
-    if (plan)
-        GD_TRY(launch_plan_check(Hd, 1, (int64_t)plan->nei, 0, st));
-    else if ((rc = readback(ctx, st)))
-        return rc;
-    const uint64_t nei_total = plan ? plan->nei : H->nei_total;
-    if (!plan && (rc = grow(ctx, ctx->cur->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t),
-                            ctx->cur->arena.cap)))
-        return rc;
-    uint32_t* nei = (uint32_t*)ctx->cur->nei.p;
-    ctx->mark(P_NEI_FILL, 0);
-    GD_TRY(launch_nei_fill(g, t, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, st));
-    ctx->mark(P_NEI_FILL, 1);
+    uint64_t nei_total = 0;
+    uint32_t* nei = nullptr;
+    // Nei(g) of every grid, or (walk mode) of the grids with more than
+    // kTinyCore core points, known only after core marking
+    auto build_lists = [&](const uint32_t* only_big, bool fallback) -> int {
+        ctx->mark(P_NEI_COUNT, 0);
+        GD_TRY(launch_nei_count(g, t, L.off_counts, lane_cnt, only_big, st));
+        GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
+        ctx->mark(P_NEI_COUNT, 1);
+        int rc2;
+        if (plan)
+            GD_TRY(launch_plan_check(Hd, 1, (int64_t)plan->nei, 0, st));
+        else if ((rc2 = readback(ctx, st)))
+            return rc2;
+        nei_total = plan ? plan->nei : H->nei_total;
+        if (!plan && (rc2 = grow(ctx, ctx->cur->nei, (size_t)std::max<uint64_t>(nei_total, 1) * sizeof(uint32_t),
+                                 ctx->cur->arena.cap))) {
+            if (fallback && rc2 == GD_ENOMEM) {
+                ctx->err.clear();
+                return kListsDoNotFit;
+            }
+            return rc2;
+        }
+        nei = (uint32_t*)ctx->cur->nei.p;
+        ctx->mark(P_NEI_FILL, 0);
+        GD_TRY(launch_nei_fill(g, t, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, st));
+        ctx->mark(P_NEI_FILL, 1);
+        return GD_OK;
+    };
+    if (!walk) {
+        rc = build_lists(nullptr, may_walk);
+        if (rc == kListsDoNotFit)
+            walk = true;
+        else if (rc)
+            return rc;
+    }
+    ctx->last.neighbor_walk = walk ? 1 : 0;
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
@@ -503,8 +563,11 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
         min_minpts = std::min<int64_t>(min_minpts, ctx->inst_host[k].minpts);
     }
-    GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, max_eps,
-                            min_minpts, st));
+    if (walk)
+        GD_TRY(launch_core_walk(g, t, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, st));
+    else
+        GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr,
+                                max_eps, min_minpts, st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;
@@ -529,6 +592,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     if (max_core > kMaxCoreBits)
         return ctx->fail(GD_EUNSUPPORTED, "a grid holds %lld core points; the merge step handles at most %lld",
                          (long long)max_core, (long long)kMaxCoreBits);
+    if (walk && (rc = build_lists(L.core_cnt, false))) return rc;
 
     // ---- merging (Algorithm 5 + union-find, LDF order)
     uint32_t* ldf = nullptr;
@@ -540,9 +604,18 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         ctx->mark(P_LDF, 0);
         // a planned run sorts ncc slots, the unused ones last under an all-ones key
         const int count_bits = bit_length((uint64_t)max_core) + (plan ? 1 : 0);
-        GD_TRY(launch_ldf_order(g, co, ctx->ldf, ncc, count_bits, plan != nullptr, L.list, L.rank, L.parent,
-                                L.root_min, ka, kb, vb, L.radix_scratch, (uint32_t*)L.partial, &ldf, st));
+        GD_TRY(launch_ldf_order(g, co, ctx->ldf && !ctx->bfs, ncc, count_bits, plan != nullptr, L.list, L.rank,
+                                L.parent, L.root_min, ka, kb, vb, L.radix_scratch, (uint32_t*)L.partial, &ldf, st));
         ctx->mark(P_LDF, 1);
+        if (ctx->bfs && !plan) {
+            // Algorithm 6's order: the free sort buffers hold the grid states
+            // and the two frontiers, the radix scratch the counters
+            ctx->mark(P_MERGE, 0);
+            rc = run_bfs(ctx, g, co, L.nei_off, nei, max_core, ka, kb, vb, L.radix_scratch, L.parent,
+                         stats ? ctx->stats_dev->merge : nullptr, st);
+            if (rc) return rc;
+            ctx->mark(P_MERGE, 1);
+        }
     }
     CellSummary* sum = nullptr;
     ctx->last_summaries = false;
@@ -552,15 +625,20 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
             return rc;
         sum = (CellSummary*)ctx->cur->sumbuf.p;
     }
-    ctx->mark(P_MERGE, 0);
-    if (sum) {
-        GD_TRY(launch_summaries(g, co, sum, st));
-        ctx->last_summaries = true;
+    if (!ctx->bfs || plan) {
+        ctx->mark(P_MERGE, 0);
+        if (sum) {
+            GD_TRY(launch_summaries(g, co, sum, st));
+            ctx->last_summaries = true;
+        }
+        const int64_t n_small = !ctx->ldf ? -1 : plan ? -2 : (int64_t)H->counts[4];
+        if (walk)
+            GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
+        GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves, walk,
+                            L.parent, stats ? ctx->stats_dev->merge : nullptr,
+                            ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
+        ctx->mark(P_MERGE, 1);
     }
-    GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, !ctx->ldf ? -1 : plan ? -2 : (int64_t)H->counts[4],
-                        max_core, ctx->merge_waves, L.parent, stats ? ctx->stats_dev->merge : nullptr,
-                        ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
-    ctx->mark(P_MERGE, 1);
     ctx->mark(P_LABELS, 0);
     GD_TRY(launch_labels(g, co, L.parent, L.root_min, L.cell_label, st));
     ctx->mark(P_LABELS, 1);
@@ -577,7 +655,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     else
         GD_TRY(launch_output_direct<uint64_t>(g, co, (const uint64_t*)L.keys_a, (const uint64_t*)skeys, L.cell_label,
                                               ctx->cur->table.p, hbits, st));
-    GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
+    if (walk)
+        GD_TRY(launch_border_walk(g, co, t, L.cell_label, st));
+    else
+        GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
     ctx->mark(P_OUTPUT, 1);
     if (stats) GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
     if (plan) {
@@ -614,6 +695,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->last_co = co;
     ctx->last_max_core = max_core;
     ctx->last_key_bits = key_bits;
+    ctx->last_walk = walk;
 
     gd_stats& s = ctx->last;
     s.grids = ncell;
@@ -756,6 +838,7 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
     p.nei = (uint64_t)e.neighbor_entries + (uint64_t)e.neighbor_entries / 16 + 4096;
     p.ncc = std::min<int64_t>(p.ncell, e.core_grids + e.core_grids / 16 + 256);
     p.max_core = std::min<int64_t>(std::min<int64_t>(n, kMaxCoreBits), ctx->last_max_core + ctx->last_max_core / 16 + 64);
+    p.walk = ctx->last_walk;
     if (!ctx->gstream) {
         if (hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ctx->gev, hipEventDisableTiming) != hipSuccess) {
@@ -803,7 +886,7 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
 // eagerly (and capture for the next call).  A replay whose data outgrew the
 // plan, or that met bad input, is discarded and the call runs eagerly.
 int run_call(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream_t st, bool batched) {
-    const bool want = n > 0 && !ctx->stats && !ctx->timing &&
+    const bool want = n > 0 && !ctx->stats && !ctx->timing && !ctx->bfs &&
                       (ctx->graph_mode == 2 || (ctx->graph_mode == 1 && batched));
     if (!want) return run_batch(ctx, count, D, n, tiles, st, nullptr);
     std::vector<int64_t> sig = batch_signature(ctx, count);
@@ -825,6 +908,7 @@ int run_call(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream
             ctx->last.core_grids = H->counts[1];
             ctx->last.dense_grids = H->counts[3];
             ctx->last.graph_replays = 1;
+            ctx->last.neighbor_walk = ctx->last_walk ? 1 : 0;
             return GD_OK;
         }
         drop_graph(ctx);  // run eagerly below; the next call captures anew
@@ -1026,7 +1110,15 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
     if (!ctx) return GD_EINVAL;
     switch (option) {
         case GD_OPT_STATS: ctx->stats = value != 0; return GD_OK;
-        case GD_OPT_LDF_ORDER: ctx->ldf = value != 0; return GD_OK;
+        case GD_OPT_LDF_ORDER:
+            ctx->ldf = value != 0;
+            ctx->bfs = false;
+            return GD_OK;
+        case GD_OPT_MERGE_ORDER:
+            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "merge order must be 0, 1 or 2");
+            ctx->ldf = value == 1;
+            ctx->bfs = value == 2;
+            return GD_OK;
         case GD_OPT_TIMING: ctx->timing = value != 0; return GD_OK;
         case GD_OPT_TILE_POINTS:
             if (value < 256 || value > 65536 || value % 256)
@@ -1044,6 +1136,10 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
                 DeviceGuard guard(ctx->device);
                 drop_graph(ctx);
             }
+            return GD_OK;
+        case GD_OPT_NEIGHBOR_MODE:
+            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "neighbour mode must be 0, 1 or 2");
+            ctx->nei_mode = (int)value;
             return GD_OK;
         case GD_OPT_WORKSPACE_LIMIT:
             if (value < 0) return ctx->fail(GD_EINVAL, "workspace limit must be >= 0");
@@ -1091,6 +1187,9 @@ int gd_debug_grids(gd_ctx* ctx, int64_t* n_grids, uint32_t* sorted_index, uint32
 int gd_debug_neighbors(gd_ctx* ctx, uint64_t* offsets, uint32_t* neighbors) {
     if (!ctx) return GD_EINVAL;
     if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to inspect");
+    if (ctx->last_walk)
+        return ctx->fail(GD_EUNSUPPORTED, "the last call walked the grid tree instead of writing every list "
+                                          "(GD_OPT_NEIGHBOR_MODE = 1 keeps them)");
     DeviceGuard guard(ctx->device);
     int rc;
     if ((rc = copy_d2h(ctx, offsets, ctx->last_nei_off, sizeof(uint64_t) * (ctx->last_ncell + 1)))) return rc;
@@ -1163,6 +1262,9 @@ int gd_proposal_harvest(gd_ctx* ctx, uint32_t seed, uint32_t keep_mod, int64_t c
     if (!ctx) return GD_EINVAL;
     ctx->err.clear();
     if (!ctx->have_last) return ctx->fail(GD_EINVAL, "no successful dbscan() call to harvest from");
+    if (ctx->last_walk)
+        return ctx->fail(GD_EUNSUPPORTED, "harvesting needs the neighbour lists of every grid "
+                                          "(GD_OPT_NEIGHBOR_MODE = 1)");
     if (keep_mod < 1 || cap < 0 || (cap > 0 && (!features || !targets)) || !count)
         return ctx->fail(GD_EINVAL, "bad harvest arguments");
     DeviceGuard guard(ctx->device);

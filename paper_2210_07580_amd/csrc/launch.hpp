@@ -158,15 +158,18 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
 // lane_cnt (optional, nei_lane_count_words(ncell, D) u32; nullptr when that
 // is 0 or no room): the split walk's per-lane counts, kept for pass 2.
 int64_t nei_lane_count_words(int64_t ncell, int D);
+// only_big (optional): per-grid core counts; then only grids with more than
+// kTinyCore core points get a list, the others an empty one.
 hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
-                            hipStream_t st);
+                            const uint32_t* only_big, hipStream_t st);
 // Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1); total into the header.
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st);
 // Pass 2: write Nei(g) ordered by offset (skipped, with kErrNeiOverflow, if
 // the total exceeds `capacity` entries).
 hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
-                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, hipStream_t st);
+                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
+                           hipStream_t st);
 
 // ---- core.hip
 // Core sets s_i as runs of point rows.  A grid whose points are all core
@@ -227,10 +230,20 @@ struct CellSummary;
 // waves: waves per workgroup of the FastMerging kernel (1, 2 or 4; fewer
 // if the LDS bitmaps do not fit).  n_small: tiny core grids leading the
 // visiting order (-2: as many as the device count says, -1: not ordered).
+// tiny_done: the pairs of two tiny core sets were already merged (walk mode).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
-                        const CellSummary* sum, hipStream_t st);
+                        int64_t max_core, int waves, bool tiny_done, uint32_t* parent, MergeStats* stats,
+                        const __half* proposal, const CellSummary* sum, hipStream_t st);
+// The BFS order of Algorithm 6 (GD_OPT_MERGE_ORDER = 2), on the full lists.
+// state: ncell u32, cleared to 0 for every grid first.  cnt: 3 u32 (the
+// caller clears them): cnt[0] unclassified core grids seen by the seed pass,
+// cnt[1] seeds appended to front, cnt[2] grids appended to next by a level.
+hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                            uint32_t* state, uint32_t* front, uint32_t* cnt, hipStream_t st);
+hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                            const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
+                            uint32_t* state, uint32_t* parent, MergeStats* stats, hipStream_t st);
 // pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
                               int64_t npairs, int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,
@@ -247,6 +260,20 @@ hipError_t launch_harvest(const GridView& g, const CoreOut& c, const CellSummary
 hipError_t launch_mlp_forward(const __half* X, int64_t B, const __half* params, float* Z, hipStream_t st);
 struct TrainArgs;
 hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
+
+// ---- walk.hip (consumers that walk the grid tree themselves; no Nei lists)
+// Core flags and m_i per grid, each sparse grid's queries counting hits over
+// the neighbours its own tree walk finds, with early exit at MinPts.
+hipError_t launch_core_walk(const GridView& g, const TreeView& t, uint8_t* core, uint32_t* core_cnt, CoreStats* stats,
+                            hipStream_t st);
+// Pairs of tiny core sets (both at most kTinyCore points), each tested once
+// from its lower grid; n_small as for launch_merge.  Pairs involving a larger
+// core set are left to launch_merge (with lists for those grids only).
+hipError_t launch_merge_walk(const GridView& g, const CoreOut& c, const TreeView& t, const uint32_t* ldf_list,
+                             int64_t n_small, uint32_t* parent, MergeStats* stats, hipStream_t st);
+// Border and noise points of the grids holding a non-core point.
+hipError_t launch_border_walk(const GridView& g, const CoreOut& c, const TreeView& t, const int32_t* cell_label,
+                              hipStream_t st);
 
 // ---- border.hip
 // Grids with a non-core point: border search and output through the permutation.

@@ -32,12 +32,15 @@ __device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsign
 }
 
 // Pairs of tiny core sets (both at most kSmallSet points).  One wave per tiny
-// core grid g_i; every lane takes one neighbouring tiny core grid g_j that
-// comes later in the visiting order and decides the pair by evaluating its
-// |s_i| x |s_j| distances directly: the answer FastMerging gives (Theorem
-// 2), without its wave-level iteration.  Each lane first resolves its
-// candidate's root and skips the pair when both grids are already in one
-// set; a yes joins the two roots.  s_i lives in scalar registers.
+// core grid g_i; every lane takes one neighbouring tiny core grid g_j with a
+// larger grid index (each pair once, from its lower grid: the tiny core
+// grids are all visited by this one launch, so their order among themselves
+// is immaterial, and half of the list needs no load at all) and decides the
+// pair by evaluating its |s_i| x |s_j| distances directly: the answer
+// FastMerging gives (Theorem 2), without its wave-level iteration.  Each
+// lane first resolves its candidate's root and skips the pair when both
+// grids are already in one set; a yes joins the two roots.  s_i lives in
+// scalar registers.
 template <int D>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
@@ -67,61 +70,80 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     }
     unsigned long long n_pairs = 0, n_skip = 0, n_yes = 0, n_dist = 0, n_pts = 0;
     uint32_t ri = uf_find_at(parent, ci, pci);  // root hint of g_i's set
-    for (uint64_t e = e0; e < e1; e += kWave) {
-        const uint64_t idx = e + lane;
-        bool cand = false;
-        uint32_t cj = 0, bj = 0, mj = 0, pj = 0;
-        if (idx < e1) {
-            cj = nei[idx];
-            // the parent link loads beside the record (every grid has one)
-            pj = load_acq(&parent[cj]);
-            const uint4 rc = rank[cj];
-            const uint32_t rj = rc.x;
-            if (rj != kNone && rj > (uint32_t)r) {
-                bj = rc.y;
-                mj = rc.z;
-                cand = mj <= kSmallSet;
+    // each round takes two list entries per lane, whose loads are issued
+    // together: the rounds are chains of dependent loads, so half as many
+    // rounds cost about half the time
+    constexpr int U = 2;
+    for (uint64_t e = e0; e < e1; e += U * kWave) {
+        bool cand[U];
+        uint32_t cj[U], bj[U], mj[U], pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t idx = e + (uint64_t)u * kWave + lane;
+            cand[u] = false;
+            cj[u] = bj[u] = mj[u] = pj[u] = 0;
+            if (idx < e1) cj[u] = nei[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (cj[u] > ci) {
+                // the parent link loads beside the record (every grid has one)
+                pj[u] = load_acq(&parent[cj[u]]);
+                const uint4 rc = rank[cj[u]];
+                if (rc.x != kNone) {
+                    bj[u] = rc.y;
+                    mj[u] = rc.z;
+                    cand[u] = mj[u] <= kSmallSet;
+                }
             }
         }
         // pairs already in one set are skipped; the root found is the hint
         // for the union
-        uint32_t root_j = cand ? uf_find_at(parent, cj, pj) : 0u;
-        const bool test = cand && root_j != ri;
-        bool yes = false;
-        if (test) {
-            // four rows of s_j per round, loaded together (a repeated last
-            // row only repeats a distance)
-            for (uint32_t b0 = 0; b0 < mj && !yes; b0 += 4) {
-                int32_t y[4][D];
+        uint32_t root_j[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) load_row<D>(co.ccrd, bj + min(b0 + u, mj - 1), y[u]);
+        for (int u = 0; u < U; ++u) root_j[u] = cand[u] ? uf_find_at(parent, cj[u], pj[u]) : 0u;
+        bool any_yes = false;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
+            const bool test = cand[u] && root_j[u] != ri;
+            bool yes = false;
+            if (test) {
+                // four rows of s_j per round, loaded together (a repeated last
+                // row only repeats a distance)
+                for (uint32_t b0 = 0; b0 < mj[u] && !yes; b0 += 4) {
+                    int32_t y[4][D];
 #pragma unroll
-                    for (int a = 0; a < (int)kSmallSet; ++a) {
-                        if ((uint32_t)a < mi) {
-                            uint32_t dd = 0;
+                    for (int v = 0; v < 4; ++v) load_row<D>(co.ccrd, bj[u] + min(b0 + v, mj[u] - 1), y[v]);
 #pragma unroll
-                            for (int k = 0; k < D; ++k) dd += sq24(y[u][k], pi[a][k]);
-                            yes |= dd <= T;
+                    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                        for (int a = 0; a < (int)kSmallSet; ++a) {
+                            if ((uint32_t)a < mi) {
+                                uint32_t dd = 0;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) dd += sq24(y[v][k], pi[a][k]);
+                                yes |= dd <= T;
+                            }
                         }
                     }
                 }
+                // a stale root only costs this lane's union a second find
+                if (yes) uf_union_from(parent, ri, root_j[u]);
             }
-            if (yes) uf_union_from(parent, ri, root_j);
+            any_yes |= yes;
+            if (stats) {
+                const unsigned long long np = (unsigned long long)popc64(ballot(cand[u]));
+                const unsigned long long nt = (unsigned long long)popc64(ballot(test));
+                const unsigned long long sj = (unsigned long long)wave_sum(test ? mj[u] : 0u);
+                n_pairs += np;
+                n_skip += np - nt;
+                n_yes += (unsigned long long)popc64(ballot(yes));
+                n_dist += (unsigned long long)mi * sj;
+                n_pts += nt * mi + sj;
+            }
         }
         // the unions may have put g_i's set under a smaller root
-        if (ballot(yes)) ri = uf_find(parent, ri);
-        if (stats) {
-            const unsigned long long np = (unsigned long long)popc64(ballot(cand));
-            const unsigned long long nt = (unsigned long long)popc64(ballot(test));
-            const unsigned long long sj = (unsigned long long)wave_sum(test ? mj : 0u);
-            n_pairs += np;
-            n_skip += np - nt;
-            n_yes += (unsigned long long)popc64(ballot(yes));
-            n_dist += (unsigned long long)mi * sj;
-            n_pts += nt * mi + sj;
-        }
+        if (ballot(any_yes)) ri = uf_find(parent, ri);
     }
     // each one-lane test counts as one FastMerging iteration
     if (stats && lane == 0) {
@@ -318,7 +340,7 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
-                        int waves, uint32_t* parent, MergeStats* stats, const __half* proposal,
+                        int waves, bool tiny_done, uint32_t* parent, MergeStats* stats, const __half* proposal,
                         const CellSummary* sum, hipStream_t st) {
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
@@ -330,7 +352,7 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     const uint32_t* split = n_small == -2 ? &c.counts[4] : nullptr;
     const int64_t s1 = n_small >= 0 ? n_small : ncc;
     const int64_t b0 = n_small >= 0 ? n_small : 0;
-    if (s1 > 0) {
+    if (s1 > 0 && !tiny_done) {
         const unsigned blocks = (unsigned)((s1 + kWavesPerBlock - 1) / kWavesPerBlock);
         GD_DISPATCH_D(g.D, (merge_small_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
@@ -353,6 +375,166 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, parent, stats, prop)));
     }
+    return hipGetLastError();
+}
+
+// ---- The BFS merge order of Algorithm 6 (Section 4.4), for comparison with
+// LDF.  Algorithm 6 starts a breadth-first search at an unclassified core
+// grid, tests each expanded grid against its unclassified core neighbours
+// and claims those FastMerging joins; classified grids are not tested
+// again.  Here the searches run level by level, from many seeds at once:
+// the seeds of a round are the unclassified core grids with no unclassified
+// core neighbour of smaller index (the round's smallest unclassified grid
+// is always one, so rounds repeat until every core grid is classified).  A
+// neighbour already claimed by another seed's search is tested too when it
+// is not yet in the expanding grid's set, and unioned on yes, so searches
+// that meet inside one cluster join: the components are those of the
+// merge graph whatever the interleaving, as with every order (Theorem 4).
+
+enum : uint32_t { kBfsNew = 0u, kBfsClassified = 1u };
+
+// Seeds of a round: cnt[0] += unclassified core grids, cnt[1] += seeds
+// (appended to front).
+__global__ __launch_bounds__(kBlock) void bfs_seed_kernel(const uint32_t* ncell, const uint64_t* __restrict__ nei_off,
+                                                          const uint32_t* __restrict__ nei,
+                                                          const uint32_t* __restrict__ core_cnt,
+                                                          uint32_t* __restrict__ state, uint32_t* __restrict__ front,
+                                                          uint32_t* cnt) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool open = false, seed = false;
+    if (c < (int64_t)*ncell && core_cnt[c] != 0 && state[c] == kBfsNew) {
+        open = true;
+        seed = true;
+        for (uint64_t e = nei_off[c]; e < nei_off[c + 1] && seed; ++e) {
+            const uint32_t a = nei[e];
+            if (a < (uint32_t)c && core_cnt[a] != 0 && state[a] == kBfsNew) seed = false;
+        }
+    }
+    const uint64_t om = ballot(open), sm = ballot(seed);
+    uint32_t base = 0;
+    if (lane_id() == 0 && om) {
+        atomicAdd(&cnt[0], (uint32_t)popc64(om));
+        if (sm) base = atomicAdd(&cnt[1], (uint32_t)popc64(sm));
+    }
+    base = readlane(base, 0);
+    if (seed) {
+        front[base + popc64(sm & lanemask_lt())] = (uint32_t)c;
+        state[c] = kBfsClassified;
+    }
+}
+
+// One level: a wave per frontier grid tests its core neighbours that are
+// unclassified, or classified outside its set; claimed grids form the next
+// frontier (cnt[2]).
+template <int D>
+__global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
+                                                           const uint32_t* __restrict__ nei,
+                                                           const uint32_t* __restrict__ front, uint32_t nfront,
+                                                           uint32_t* __restrict__ next, uint32_t* cnt, uint32_t words,
+                                                           uint32_t* state, uint32_t* parent, MergeStats* stats) {
+    extern __shared__ uint64_t smem[];
+    const int lane = lane_id();
+    const int wpb = (int)(blockDim.x / kWave);
+    const int w = wave_id();
+    const int64_t f = (int64_t)blockIdx.x * wpb + w;
+    if (f >= (int64_t)nfront) return;
+    const uint32_t ci = front[f];
+    const Inst& I = cell_inst(gv, ci);
+    const uint32_t T = I.T;
+    const double eps = (double)I.eps;
+    PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
+    si.words = (si.m + kWave - 1) / kWave;
+    if (si.m > 64u * words) {
+        if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
+        return;
+    }
+    int32_t p0[D];
+    load_point<D>(si, 0u, p0);
+    PointSet sj{co.ccrd, 0, 0, smem + (int64_t)w * 2 * words + words, 0};
+    unsigned long long n_pairs = 0, n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
+    uint32_t ri = uf_find(parent, ci);
+    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    for (uint64_t e = e0; e < e1; e += kWave) {
+        const uint64_t idx = e + lane;
+        uint32_t cj = 0, mj = 0, sj_state = 0, root_j = 0;
+        bool cand = false;
+        if (idx < e1) {
+            cj = nei[idx];
+            mj = co.core_cnt[cj];
+            if (mj != 0) {
+                cand = true;
+                sj_state = load_acq(&state[cj]);
+                root_j = uf_find(parent, cj);
+            }
+        }
+        const bool pend_l = cand && (sj_state == kBfsNew || root_j != ri);
+        const uint64_t cands = ballot(cand);
+        uint64_t pend = ballot(pend_l);
+        n_pairs += (unsigned long long)popc64(cands);
+        n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
+        while (pend) {
+            const int l = ffs64(pend);
+            pend &= pend - 1ull;
+            const uint32_t cjl = readlane(cj, l);
+            sj.base = co.core_begin[cjl];
+            sj.m = readlane(mj, l);
+            sj.words = (sj.m + kWave - 1) / kWave;
+            if (sj.m > 64u * words) {
+                if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
+                continue;
+            }
+            // a union since this round's roots were read may have joined them
+            if (uf_find(parent, cjl) == uf_find(parent, ri) && load_acq(&state[cjl]) == kBfsClassified) {
+                ++n_skip;
+                continue;
+            }
+            uint32_t it = 0;
+            const int yes = fast_merging_from<D>(si, sj, p0, T, eps, n_dist, it);
+            ++n_test;
+            n_pts += si.m + sj.m;
+            n_iter += it;
+            max_it = it > max_it ? it : max_it;
+            if (yes < 0) {
+                if (lane == 0) atomicOr(&gv.b.hdr->err, kErrMergeRunaway);
+                continue;
+            }
+            if (yes) {
+                ++n_yes;
+                uint32_t root = 0;
+                if (lane == 0) {
+                    // claim an unclassified grid for this search; a grid
+                    // already classified (by any search) is only unioned
+                    if (atomicCAS(&state[cjl], kBfsNew, kBfsClassified) == kBfsNew)
+                        next[atomicAdd(&cnt[2], 1u)] = cjl;
+                    root = uf_union_from(parent, uf_find(parent, ri), uf_find(parent, cjl));
+                }
+                ri = readlane(root, 0);
+            }
+        }
+    }
+    if (stats && lane == 0) flush_stats(stats, f, n_pairs, n_skip, n_test, n_yes, n_iter, max_it, n_dist, n_pts);
+}
+
+hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                            uint32_t* state, uint32_t* front, uint32_t* cnt, hipStream_t st) {
+    if (g.ncell == 0) return hipSuccess;
+    bfs_seed_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, nei_off, nei, c.core_cnt, state,
+                                                                       front, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                            const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
+                            uint32_t* state, uint32_t* parent, MergeStats* stats, hipStream_t st) {
+    if (nfront == 0) return hipSuccess;
+    const uint32_t words = (uint32_t)((std::max<int64_t>(max_core, 1) + kWave - 1) / kWave);
+    int wpb = kWavesPerBlock;
+    while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
+    const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
+    if (lds > 65536) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((nfront + wpb - 1) / wpb);
+    GD_DISPATCH_D(g.D, (bfs_level_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                           g, c, nei_off, nei, front, nfront, next, cnt, words, state, parent, stats)));
     return hipGetLastError();
 }
 

@@ -1,51 +1,14 @@
-// Non-empty neighbouring grids query (Section 4.2.2, Algorithm 3, Eq. (2)).
+// Non-empty neighbouring grids query (Section 4.2.2, Algorithm 3, Eq. (2)),
+// written out as lists Nei(g).
 //
-// Each grid g walks the grid tree level by level (after the exact match of
-// g's instance at level 0), its first levels split over lanes.  At level l
-// it visits the children whose key k satisfies |k - g_l| <= w, accumulating
-//   offset += max(|k - g_l| - 1, 0)^2                       (Eq. (2))
-// and drops a node once offset >= d.  The paper scans the fixed window
-// +-ceil(sqrt(d)) and prunes afterwards; here the window shrinks with the
-// budget left (w = 1 + isqrt(d - 1 - offset)), which keeps exactly the same
-// nodes.  The first child in the window is found by binary search over the
-// node's contiguous, ascending children (the role the paper gives to its
-// hash table h for nodes with many children).  The result excludes g itself
-// and is ordered by offset (the paper's counting sort), nearest grids first.
+// Each grid g walks the grid tree level by level (walk.hpp), its first
+// level split over lanes.  The result excludes g itself and is ordered by
+// offset (the paper's counting sort), nearest grids first.
 #include "launch.hpp"
 #include "scan.hpp"
+#include "walk.hpp"
 
 namespace gd {
-
-// Levels 1..D of the walk (level 0, the instance, is matched exactly by the
-// caller).  `g` holds the query grid's identifiers at g[1..D]; `dk` is the
-// instance's own dimension (identifier rows beyond dk are 0 for all its grids).
-template <int D, int L, typename Emit>
-__device__ __forceinline__ void walk(const TreeView& t, const int32_t (&g)[D + 1], int dk, uint32_t lo, uint32_t hi,
-                                     int off, Emit& emit) {
-    const int R = dk - off;  // budget left, >= 1
-    int gmax = 0;
-    while ((gmax + 1) * (gmax + 1) <= R - 1) ++gmax;
-    const int win = gmax + 1;
-    const int32_t* __restrict__ key = t.key[L];
-    const int32_t lo_key = g[L] - win;
-    uint32_t a = lo, b = hi;
-    while (a < b) {
-        const uint32_t m = (a + b) >> 1;
-        if (key[m] < lo_key) a = m + 1; else b = m;
-    }
-    for (; a < hi; ++a) {
-        const int32_t dk_ = key[a] - g[L];
-        if (dk_ > win) break;
-        const int gap = (dk_ < 0 ? -dk_ : dk_) - 1;
-        const int o = off + (gap > 0 ? gap * gap : 0);
-        if (o >= dk) continue;
-        if constexpr (L == D) {
-            emit(a, o);
-        } else {
-            walk<D, L + 1>(t, g, dk, t.child[L][a], t.child[L][a + 1], o, emit);
-        }
-    }
-}
 
 // With few grids, each grid's walk is split over kSplit = 8 consecutive
 // lanes: lane p takes the level-1 children whose key is g_1 + p - 3.  The
@@ -62,34 +25,24 @@ constexpr int64_t kSplitMaxGrids = 1 << 20;
 
 inline int nei_lanes(int64_t ncell) { return ncell <= kSplitMaxGrids ? kSplit : 1; }
 
-__device__ __forceinline__ int level_window(int budget) {
-    int w = 0;
-    while ((w + 1) * (w + 1) <= budget - 1) ++w;
-    return w + 1;
-}
-
-// First index in [lo, hi) whose key is >= want.
-__device__ __forceinline__ uint32_t lower_key(const int32_t* __restrict__ key, uint32_t lo, uint32_t hi, int32_t want) {
-    while (lo < hi) {
-        const uint32_t m = (lo + hi) >> 1;
-        if (key[m] < want) lo = m + 1; else hi = m;
-    }
-    return lo;
-}
-
 // The neighbours below the level-1 children with key g_1 + delta,
-// delta in [d_lo, d_hi].
+// delta in [d_lo, d_hi], in tree order (emit(a, offset) for each; g itself
+// is emitted too and the callers skip it).
 template <int D, typename Emit>
 __device__ __forceinline__ void query_part(const TreeView& t, const int32_t (&g)[D + 1], int dk, int d_lo, int d_hi,
                                            Emit& emit) {
-    const int w1 = level_window(dk);
+    const int w1 = walk_window(dk);
     d_lo = d_lo < -w1 ? -w1 : d_lo;
     d_hi = d_hi > w1 ? w1 : d_hi;
     if (d_lo > d_hi) return;
-    const uint32_t a0 = lower_key(t.key[0], 0, t.level_count[0], g[0]);
+    auto visit = [&](uint32_t a, int o) -> bool {
+        emit(a, o);
+        return true;
+    };
+    const uint32_t a0 = walk_lower(t.key[0], 0, t.level_count[0], g[0]);
     const uint32_t hi1 = t.child[0][a0 + 1];
     const int32_t* __restrict__ key1 = t.key[1];
-    for (uint32_t a = lower_key(key1, t.child[0][a0], hi1, g[1] + d_lo); a < hi1; ++a) {
+    for (uint32_t a = walk_lower(key1, t.child[0][a0], hi1, g[1] + d_lo); a < hi1; ++a) {
         const int d1 = key1[a] - g[1];
         if (d1 > d_hi) break;
         const int gap = (d1 < 0 ? -d1 : d1) - 1;
@@ -98,15 +51,9 @@ __device__ __forceinline__ void query_part(const TreeView& t, const int32_t (&g)
         if constexpr (D == 1) {
             emit(a, o);
         } else {
-            walk<D, 2>(t, g, dk, t.child[1][a], t.child[1][a + 1], o, emit);
+            walk_levels<D, 2>(t, g, dk, t.child[1][a], t.child[1][a + 1], o, true, visit);
         }
     }
-}
-
-template <int D>
-__device__ __forceinline__ void load_grid(const GridView& gv, int64_t c, int32_t (&g)[D + 1]) {
-#pragma unroll
-    for (int j = 0; j <= D; ++j) g[j] = gv.ck[(int64_t)j * gv.ck_stride + c];
 }
 
 // This lane's part of grid c's neighbours, counted per offset value into
@@ -115,7 +62,7 @@ template <int D, int P>
 __device__ __forceinline__ void count_part(const GridView& gv, const TreeView& t, int64_t c, int p,
                                            uint32_t (*cnt)[kBlock]) {
     int32_t g[D + 1];
-    load_grid<D>(gv, c, g);
+    load_grid_key<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
     auto emit = [&](uint32_t a, int o) {
         if (a != (uint32_t)c) cnt[o][threadIdx.x] += 1;
@@ -125,9 +72,16 @@ __device__ __forceinline__ void count_part(const GridView& gv, const TreeView& t
 
 // With lane_cnt (split walks only), each lane also keeps its own counts for
 // the fill pass, which then needs no second counting walk.
+// only_big (optional): the core counts of the grids; then only grids with
+// more than kTinyCore core points get a list (the others count 0).
+__device__ __forceinline__ bool wants_list(const uint32_t* only_big, int64_t c) {
+    return !only_big || only_big[c] > kTinyCore;
+}
+
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts,
-                                                           uint32_t* __restrict__ lane_cnt) {
+                                                           uint32_t* __restrict__ lane_cnt,
+                                                           const uint32_t* __restrict__ only_big) {
     __shared__ uint32_t sc[D][kBlock];
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t c = gt / P;
@@ -136,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
     if (P == 1 && !valid) return;
 #pragma unroll
     for (int o = 0; o < D; ++o) sc[o][threadIdx.x] = 0;
-    if (valid) count_part<D, P>(gv, t, c, p, sc);
+    if (valid && wants_list(only_big, c)) count_part<D, P>(gv, t, c, p, sc);
 #pragma unroll
     for (int o = 0; o < D; ++o) {
         uint32_t v = sc[o][threadIdx.x];
@@ -148,27 +102,24 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
     }
 }
 
-// The list of grid c holds its offset-0 neighbours, then offset 1, ...; within
-// one offset value the lanes' parts follow each other in lane order.  With a
-// split, each lane first counts its part again to find where its entries go.
-// With one lane per grid (long lists per lane), found neighbours are staged
-// in LDS and stored kFillStage at a time: gfx9 counts outstanding vector
-// loads and stores with one in-order counter, so a store issued between two
-// loads of the tree walk would make the second wait for it; in bursts, the
-// walk waits once per kFillStage entries (cfg2-like data: 59 -> 52 ms; 4
-// entries gave 56 ms, 16 cost occupancy and gave 68 ms).  A split walk
-// emits a few entries per lane, and staging them only costs.
-constexpr int kFillStage = 8;
+// With a split (at most 2^20 grids), the list of grid c holds its offset-0
+// neighbours, then offset 1, ... (the paper's counting sort, for early exit
+// in core marking); within one offset value the lanes' parts follow each
+// other in lane order.  With more grids (one lane per grid, hundreds of
+// entries each), the list is kept in walk order instead: found neighbours
+// are staged in LDS and stored kFillStage consecutive entries at a time, so
+// that the stores fill whole cache lines rather than scattering single
+// words over the offset buckets (the stores dominated this pass).
+constexpr int kFillStage = 16;
 
 template <int D, int P>
 __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView t, const uint32_t* __restrict__ off_counts,
                                                           const uint32_t* __restrict__ lane_cnt,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
-                                                          uint64_t capacity) {
+                                                          uint64_t capacity, const uint32_t* __restrict__ only_big) {
     __shared__ uint32_t pos[D][kBlock];
     constexpr int kStage = P == 1 ? kFillStage : 1;
     __shared__ uint32_t stage_a[kStage][kBlock];
-    __shared__ uint8_t stage_o[kStage][kBlock];
     const int64_t ncell = *gv.ncell_dev;
     if (nei_off[ncell] > capacity) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&gv.b.hdr->err, kErrNeiOverflow);
@@ -177,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t c = gt / P;
     const int p = (int)(gt % P);
-    const bool valid = c < ncell;
+    const bool valid = c < ncell && wants_list(only_big, c);
     if (P == 1 && !valid) return;
     if constexpr (P > 1) {
         if (lane_cnt) {
@@ -209,33 +160,36 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     if (!valid) return;
     const uint64_t base = nei_off[c];
     int32_t g[D + 1];
-    load_grid<D>(gv, c, g);
+    load_grid_key<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
-    int staged = 0;
-    auto flush = [&]() {
-        for (int j = 0; j < staged; ++j) {
-            const uint32_t a = stage_a[j][threadIdx.x];
-            const int o = stage_o[j][threadIdx.x];
-            const uint32_t k = pos[o][threadIdx.x];
-            pos[o][threadIdx.x] = k + 1;
-            nei[base + k] = a;
-        }
-        staged = 0;
-    };
-    auto emit = [&](uint32_t a, int o) {
-        if (a == (uint32_t)c) return;
-        if constexpr (P == 1) {
+    if constexpr (P == 1) {
+        // millions of grids: the list in walk order (level 1 centre-out, so
+        // nearer slabs of grids still come first), staged and stored as
+        // runs of consecutive entries
+        uint32_t run_pos = 0;
+        int staged = 0;
+        auto flush = [&]() {
+            for (int j = 0; j < staged; ++j) nei[base + run_pos + j] = stage_a[j][threadIdx.x];
+            run_pos += (uint32_t)staged;
+            staged = 0;
+        };
+        auto visit = [&](uint32_t a, int) -> bool {
+            if (a == (uint32_t)c) return true;
             stage_a[staged][threadIdx.x] = a;
-            stage_o[staged][threadIdx.x] = (uint8_t)o;
             if (++staged == kStage) flush();
-        } else {
+            return true;
+        };
+        tree_walk<D>(t, g, dk, false, visit);
+        flush();
+    } else {
+        auto emit = [&](uint32_t a, int o) {
+            if (a == (uint32_t)c) return;
             const uint32_t k = pos[o][threadIdx.x];
             pos[o][threadIdx.x] = k + 1;
             nei[base + k] = a;
-        }
-    };
-    query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
-    flush();
+        };
+        query_part<D>(t, g, dk, p - 3, p - 3, emit);
+    }
 }
 
 int64_t nei_lane_count_words(int64_t ncell, int D) {
@@ -243,14 +197,14 @@ int64_t nei_lane_count_words(int64_t ncell, int D) {
 }
 
 hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
-                            hipStream_t st) {
+                            const uint32_t* only_big, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     if (nei_lanes(g.ncell) > 1) {
         GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, lane_cnt)));
+                               g, t, off_counts, lane_cnt, only_big)));
     } else {
         GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nullptr)));
+                               g, t, off_counts, nullptr, only_big)));
     }
     return hipGetLastError();
 }
@@ -287,14 +241,15 @@ hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uin
 }
 
 hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
-                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, hipStream_t st) {
+                           const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
+                           hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     if (nei_lanes(g.ncell) > 1) {
         GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, lane_cnt, nei_off, nei, capacity)));
+                               g, t, off_counts, lane_cnt, nei_off, nei, capacity, only_big)));
     } else {
         GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nullptr, nei_off, nei, capacity)));
+                               g, t, off_counts, nullptr, nei_off, nei, capacity, only_big)));
     }
     return hipGetLastError();
 }

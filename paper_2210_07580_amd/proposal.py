@@ -34,8 +34,14 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 
 def harvest_from(ctx: Context, points, eps, minpts, target: int, seed: int = 0):
-    """Cluster one workload and harvest about `target` pairs from it."""
-    ctx.dbscan(points, eps, minpts)
+    """Cluster one workload and harvest about `target` pairs from it (with
+    the neighbour lists of every grid written out, which harvesting reads)."""
+    from . import GD_OPT_NEIGHBOR_MODE
+    ctx.set_option(GD_OPT_NEIGHBOR_MODE, 1)
+    try:
+        ctx.dbscan(points, eps, minpts)
+    finally:
+        ctx.set_option(GD_OPT_NEIGHBOR_MODE, 0)
     st = ctx.stats()
     pairs = max(1, st["neighbor_entries"] // 2)
     keep_mod = max(1, pairs // max(target, 1))

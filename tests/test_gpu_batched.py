@@ -77,3 +77,37 @@ def test_batch_errors(ctx):
     assert ctx.dbscan_batched([]) == []
     outs = ctx.dbscan_batched([(good, 3, 2), (torch.zeros((0, 3), dtype=torch.float32, device="cuda"), 3, 2)])
     assert (outs[0][1].cpu().numpy() == 1).all() and outs[1][0].numel() == 0
+
+
+def test_full_batch_workload_matches_oracle_digests(ctx):
+    """All 256 instances of the batch workload at full size (sum of n about
+    34M), in one dbscan_batched() call as the benchmark makes it, against the
+    oracle's per-instance digests (tests/golden/make_oracle_digests.py cfg3),
+    then once more replayed from the captured graph."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
+    with open(path) as f:
+        recs = json.load(f).get("cfg3")
+    if recs is None:
+        pytest.skip("no stored oracle digests for the batch workload")
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+    ws = W.batch_workloads()
+    assert len(recs) == len(ws)
+    probs = []
+    for k, (w, rec) in enumerate(zip(ws, recs)):
+        x = W.make_points(w)
+        assert sha(x) == rec["points_sha256"], f"instance {k}: generator output changed"
+        probs.append((torch.from_numpy(x.astype(np.float32)).cuda(), w.eps, w.minpts))
+    print(f"case: full batch workload, {len(probs)} instances, "
+          f"{sum(int(p[0].shape[0]) for p in probs)} points", flush=True)
+    for rep in range(2):
+        outs = ctx.dbscan_batched(probs)
+        assert ctx.stats()["graph_replays"] == rep
+        for k, ((lab, core), rec) in enumerate(zip(outs, recs)):
+            assert sha(core.cpu().numpy().astype(np.uint8)) == rec["core_sha256"], f"instance {k}: core flags"
+            assert sha(lab.cpu().numpy().astype("<i4")) == rec["labels_sha256"], f"instance {k}: labels"

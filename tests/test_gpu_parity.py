@@ -40,6 +40,16 @@ def gpu_dbscan(ctx, x, eps, minpts):
     return lab.cpu().numpy(), core.cpu().numpy()
 
 
+@pytest.fixture()
+def list_ctx(G):
+    """A context that writes every grid's neighbour list out (the debug views
+    of Nei(g) need them; sparse data in d >= 4 would walk instead)."""
+    c = G.Context(0)
+    c.set_option(G.GD_OPT_NEIGHBOR_MODE, 1)
+    yield c
+    c.close()
+
+
 def assert_same(got, want, what=""):
     gl, gc = got
     wl, wc = want
@@ -142,7 +152,8 @@ def _grid_points(grids, side_units):
     return np.array([[k * side_units for k in g] for g in grids], np.int32)
 
 
-def test_paper_grid_example(ctx, golden_dir):
+def test_paper_grid_example(list_ctx, golden_dir):
+    ctx = list_ctx
     with open(os.path.join(golden_dir, "paper_grid_example.json")) as f:
         ex = json.load(f)
     # eps = 100, d = 2: side 70.71; coordinate 71 k lands in grid k for k < 244
@@ -156,7 +167,8 @@ def test_paper_grid_example(ctx, golden_dir):
 
 
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
-def test_neighbors_match_definition(ctx, d):
+def test_neighbors_match_definition(list_ctx, d):
+    ctx = list_ctx
     rng = np.random.default_rng(50 + d)
     n = 1500 if d < 5 else 800
     x = rng.integers(0, 1200, size=(n, d)).astype(np.int32)
