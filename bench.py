@@ -119,6 +119,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Model name and clock of the host cores (from /proc/cpuinfo)."""
+    model, mhz = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model is None:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("cpu MHz") and mhz is None:
+                    mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return {"model": model, "mhz": mhz, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(w, sample_n):
     import oracle
     x = W.make_points(w, n=sample_n)
@@ -126,6 +141,14 @@ def cpu_baseline(w, sample_n):
     t0 = time.perf_counter()
     oracle.dbscan(x, w.eps, w.minpts, nthreads=threads)
     dt = time.perf_counter() - t0
+    # the small blob workload whole, on all threads and on one
+    w0 = W.WORKLOADS["cfg0"]
+    x0 = W.make_points(w0)
+    single = {}
+    for th in (threads, 1):
+        t1 = time.perf_counter()
+        oracle.dbscan(x0, w0.eps, w0.minpts, nthreads=th)
+        single[th] = time.perf_counter() - t1
     return {
         "value": round(sample_n / dt, 1),
         "unit": "points/s",
@@ -133,7 +156,148 @@ def cpu_baseline(w, sample_n):
         "kind": "oracle",
         "sample": (f"the same generator ({w.name}) at n={sample_n:,}: same density recipe, full oracle "
                    f"clustering (eps-side cells, pointwise range queries, union-find), {dt:.1f} s"),
+        "host": host_cpu(),
+        "cfg0_whole": {"n": int(x0.shape[0]), "seconds_all_threads": round(single[threads], 4),
+                       "seconds_one_thread": round(single[1], 4),
+                       "one_thread_points_per_s": round(x0.shape[0] / single[1], 1)},
     }
+
+
+_POINTS = {}
+
+
+def points(name):
+    """Device tensor of a workload's points (generated once per run)."""
+    import torch
+    if name not in _POINTS:
+        w = W.WORKLOADS[name]
+        log(f"bench: generating {w.name} n={w.n:,} d={w.d}")
+        _POINTS[name] = torch.from_numpy(W.make_points(w).astype(np.float32)).cuda()
+    return _POINTS[name]
+
+
+def oracle_digest(name):
+    """Stored SHA-256 digests of the oracle's labels and core flags for a
+    workload (tests/golden/oracle_digests.json), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(name)
+    except OSError:
+        return None
+    return rec if isinstance(rec, dict) else None
+
+
+def matches_oracle(name, lab, core):
+    import hashlib
+    rec = oracle_digest(name)
+    if rec is None:
+        return None
+    sl = hashlib.sha256(np.ascontiguousarray(lab.cpu().numpy().astype("<i4")).tobytes()).hexdigest()
+    sc = hashlib.sha256(np.ascontiguousarray(core.cpu().numpy().astype(np.uint8)).tobytes()).hexdigest()
+    return sl == rec["labels_sha256"] and sc == rec["core_sha256"]
+
+
+def run_plain(G, name, steps, warmup, options=(), blob=None):
+    """One workload with the plain call (the learned proposal set when a blob
+    is given): wall time per call, phase times, work counters, and the labels."""
+    import torch
+    w = W.WORKLOADS[name]
+    pts = points(name)
+    n = int(pts.shape[0])
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    core = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx = G.Context(0)
+    for opt, val in options:
+        ctx.set_option(opt, val)
+    if blob is not None:
+        ctx.set_proposal(blob)
+    ms = []
+    for i in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+        if i >= warmup:
+            ms.append(1e3 * (time.perf_counter() - t0))
+    ctx.set_option(G.GD_OPT_TIMING, 1)
+    ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+    phases = {k: round(v, 4) for k, v in ctx.phase_times().items() if v > 0}
+    ctx.set_option(G.GD_OPT_TIMING, 0)
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+    st = ctx.stats()
+    ctx.close()
+    med = float(np.median(ms))
+    return {"n": n, "d": w.d, "eps": w.eps, "minpts": w.minpts, "value": round(n / (med * 1e-3), 1),
+            "ms_median": round(med, 3), "ms_min": round(min(ms), 3), "ms_max": round(max(ms), 3),
+            "phases_ms": phases, "labels": (lab, core), "stats": st}
+
+
+def bench_configs(G, steps, warmup):
+    """Plain points/s of the listed configurations beside the headline."""
+    out = {}
+    for name in ("cfg0", "cfg1", "cfg2"):
+        r = run_plain(G, name, steps, warmup)
+        lab, core = r.pop("labels")
+        st = r.pop("stats")
+        r["workload"] = WORKLOAD_DESC[name]
+        r["labels_equal_oracle_digest"] = matches_oracle(name, lab, core)
+        r["work"] = {k: st[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids", "merge_tests",
+                                        "merge_distances", "core_distances", "neighbor_walk")}
+        out[name] = r
+        log(f"bench: {name} {r['ms_median']} ms ({r['value']:.3g} points/s)")
+    return out
+
+
+def bench_merge_orders(G, steps, warmup):
+    """Merge-order ablation (grid order, LDF, the BFS searches of Algorithm 6,
+    LDF with the learned proposal): work and merge time at identical labels."""
+    import torch
+    from paper_2210_07580_amd import proposal as P
+    orders = {"grid": [(G.GD_OPT_MERGE_ORDER, 0)], "ldf": [(G.GD_OPT_MERGE_ORDER, 1)],
+              "bfs": [(G.GD_OPT_MERGE_ORDER, 2)], "learned": [(G.GD_OPT_MERGE_ORDER, 1), ("proposal", 1)]}
+    out = {}
+    for name in ("cfg1", "H", "cfg4"):
+        res, ref = {}, None
+        for oname, opts in orders.items():
+            plain = [o for o in opts if o[0] != "proposal"]
+            blob = P.load_blob() if any(o[0] == "proposal" for o in opts) else None
+            r = run_plain(G, name, steps, warmup, plain, blob)
+            lab, core = r.pop("labels")
+            st = r.pop("stats")
+            if ref is None:
+                ref = (lab.clone(), core.clone())
+            elif not (torch.equal(ref[0], lab) and torch.equal(ref[1], core)):
+                raise RuntimeError(f"merge order {oname} changed the labels on {name}")
+            res[oname] = {"ms_median": r["ms_median"], "merge_ms": r["phases_ms"].get("merge", 0.0),
+                          "ldf_order_ms": r["phases_ms"].get("ldf_order", 0.0),
+                          **{k: st[k] for k in ("merge_pairs", "merge_skipped", "merge_tests", "merge_yes",
+                                                "merge_iterations", "merge_distances")}}
+            log(f"bench: merge order {oname} on {name}: {res[oname]}")
+        out[name] = res
+    return out
+
+
+def bench_neighbor_modes(G, steps, warmup):
+    """Neighbour-query ablation: lists written for every grid versus the
+    consumers walking the grid tree themselves, at identical labels."""
+    import torch
+    out = {}
+    for name in ("cfg2", "H"):
+        res, ref = {}, None
+        for mname, mode in (("lists", 1), ("walks", 2)):
+            r = run_plain(G, name, steps, warmup, [(G.GD_OPT_NEIGHBOR_MODE, mode)])
+            lab, core = r.pop("labels")
+            st = r.pop("stats")
+            if ref is None:
+                ref = (lab.clone(), core.clone())
+            elif not (torch.equal(ref[0], lab) and torch.equal(ref[1], core)):
+                raise RuntimeError(f"neighbour mode {mname} changed the labels on {name}")
+            res[mname] = {"ms_median": r["ms_median"], "phases_ms": r["phases_ms"],
+                          "neighbor_entries": st["neighbor_entries"], "core_neighbor_grids": st["core_neighbor_grids"]}
+            log(f"bench: neighbour mode {mname} on {name}: {r['ms_median']} ms")
+        out[name] = res
+    return out
 
 
 def time_calls(fn, steps, warmup):
@@ -210,10 +374,8 @@ def bench_learned(G, steps, warmup):
     import torch
     from paper_2210_07580_amd import proposal as P
     w = W.WORKLOADS["cfg4"]
-    log(f"bench: generating {w.name} n={w.n:,}")
-    x = W.make_points(w)
-    pts = torch.from_numpy(x.astype(np.float32)).cuda()
-    n = x.shape[0]
+    pts = points("cfg4")
+    n = int(pts.shape[0])
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
     core = torch.empty(n, dtype=torch.uint8, device="cuda")
     ctx = G.Context(0)
@@ -395,6 +557,12 @@ def main():
         out["batched"] = bench_batched(G, max(2, args.steps // 2), 1, args.batch_instances)
         torch.cuda.empty_cache()
         out["learned"] = bench_learned(G, max(2, args.steps // 2), 1)
+        few = max(3, min(args.steps, 10) // 2)
+        out["configs"] = bench_configs(G, few, 1)
+        out["merge_orders"] = bench_merge_orders(G, 3, 1)
+        out["neighbor_modes"] = bench_neighbor_modes(G, 3, 1)
+        _POINTS.clear()
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle on a sample of n={args.cpu_sample:,}")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
