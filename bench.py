@@ -278,6 +278,31 @@ def bench_merge_orders(G, steps, warmup):
     return out
 
 
+def bench_approx(G, steps, warmup):
+    """Approximate FastMerging (a yes once a pair within eps + delta is met)
+    against the exact merge: time, iterations and how the clusters differ."""
+    import torch
+    out = {}
+    for name in ("H", "cfg4"):
+        w = W.WORKLOADS[name]
+        res, exact = {}, None
+        for delta in (0, w.eps // 10, w.eps // 2):
+            r = run_plain(G, name, steps, warmup, [(G.GD_OPT_APPROX_DELTA, delta)])
+            lab, core = r.pop("labels")
+            st = r.pop("stats")
+            clusters = int(torch.unique(lab[lab >= 0]).numel())
+            if exact is None:
+                exact = lab.clone()
+            res[f"delta_{delta}"] = {
+                "ms_median": r["ms_median"], "merge_ms": r["phases_ms"].get("merge", 0.0),
+                "merge_tests": st["merge_tests"], "merge_iterations": st["merge_iterations"],
+                "merge_max_iterations": st["merge_max_iterations"], "merge_distances": st["merge_distances"],
+                "clusters": clusters, "labels_equal_exact": bool(torch.equal(lab, exact))}
+            log(f"bench: approximate merge on {name}, delta {delta}: {res[f'delta_{delta}']}")
+        out[name] = res
+    return out
+
+
 def bench_neighbor_modes(G, steps, warmup):
     """Neighbour-query ablation: lists written for every grid versus the
     consumers walking the grid tree themselves, at identical labels."""
@@ -561,6 +586,7 @@ def main():
         out["configs"] = bench_configs(G, few, 1)
         out["merge_orders"] = bench_merge_orders(G, 3, 1)
         out["neighbor_modes"] = bench_neighbor_modes(G, 3, 1)
+        out["approximate"] = bench_approx(G, 3, 1)
         _POINTS.clear()
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

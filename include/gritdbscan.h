@@ -225,7 +225,7 @@ typedef enum {
                                  (GD_OPT_WORKSPACE_LIMIT, or the fixed array
                                  of dbscan_noalloc).  The result is the same in
                                  every mode.                                   */
-    GD_OPT_MERGE_ORDER = 9    /* order in which core grids are merged: 0 grid
+    GD_OPT_MERGE_ORDER = 9,   /* order in which core grids are merged: 0 grid
                                  (identifier) order with union-find; 1 (default)
                                  ascending core count with union-find (the LDF
                                  variant, Section 5.2); 2 the breadth-first
@@ -234,6 +234,21 @@ typedef enum {
                                  without graph replay or the learned proposal.
                                  GD_OPT_LDF_ORDER sets 1 or 0.  The result is
                                  the same in every order (Theorem 4).         */
+    GD_OPT_APPROX_DELTA = 10  /* approximate FastMerging (Section 4.3.3, the
+                                 remark on numerical error): an integer delta
+                                 in [0, 65535 - GD_EPS_MAX]; 0 (default) is
+                                 exact.  With delta > 0 FastMerging answers yes
+                                 as soon as it meets a pair within eps + delta
+                                 (Pruning keeps eps), so its iterations are
+                                 bounded independently of eps and d.  Core
+                                 flags and border rules are unchanged; core
+                                 grids whose core points come within eps are
+                                 always joined, and grids are only joined when
+                                 some pair of their core points is within
+                                 eps + delta: each cluster is a union of exact
+                                 clusters and lies inside one component of the
+                                 core points' (eps + delta)-graph.  Labels are
+                                 then NOT those of dbscan(): an opt-in mode.  */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);

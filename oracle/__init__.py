@@ -112,3 +112,37 @@ def neighbor_count_brute(points, eps, qidx, nthreads: int = 0):
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def core_components(points, core, radius):
+    """Canonical component labels of the core points under the graph with an
+    edge wherever two core points are within `radius` (exact integer squared
+    distances): each core point gets the smallest index of its component,
+    every other point -1.  With radius = eps this is DBSCAN's partition of
+    the core points (Definitions 2-5); with eps + delta it is the coarsest
+    partition the approximate merge of Section 4.3.3 (the remark on numerical
+    error) may produce.  Pairs come from scipy's k-d tree (a library
+    neighbour search, queried with a half-unit slack) and are kept only when
+    their exact squared distance is at most radius^2."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    x, r = _prep(points, radius)
+    core = np.asarray(core).astype(bool)
+    idx = np.nonzero(core)[0]
+    labels = np.full(x.shape[0], -1, np.int64)
+    if idx.size == 0:
+        return labels.astype(np.int32)
+    pts = x[idx].astype(np.int64)
+    pairs = cKDTree(pts).query_pairs(r + 0.5, output_type="ndarray")
+    if pairs.size:
+        d2 = ((pts[pairs[:, 0]] - pts[pairs[:, 1]]) ** 2).sum(axis=1)
+        pairs = pairs[d2 <= r * r]
+    m = idx.size
+    g = coo_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(m, m)) if len(pairs) else \
+        coo_matrix((m, m))
+    _, comp = connected_components(g, directed=False)
+    first = np.full(comp.max() + 1, np.iinfo(np.int64).max)
+    np.minimum.at(first, comp, idx)
+    labels[idx] = first[comp]
+    return labels.astype(np.int32)

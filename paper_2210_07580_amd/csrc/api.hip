@@ -102,6 +102,7 @@ struct gd_ctx {
     bool ldf = true;               // LDF order (merge_order 1) or identifier order (0)
     bool bfs = false;              // the BFS order of Algorithm 6 (merge_order 2)
     int nei_mode = 0;              // GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists, 2 walks
+    int64_t approx_delta = 0;      // GD_OPT_APPROX_DELTA (0: exact merging)
     bool last_walk = false;        // the last eager call walked (no full lists)
     gd_stats last{};
     // what the last successful call left in the workspace (for gd_debug_*)
@@ -241,6 +242,9 @@ struct Plan {
     int64_t max_core;  // largest core set
     bool walk;         // consumers walk the grid tree (lists only for big core sets)
 };
+
+// Largest delta of approximate merging: (eps + delta)^2 must fit 32 bits.
+constexpr int kApproxDeltaMax = 65535 - GD_EPS_MAX;
 
 // build_lists: the full lists do not fit the workspace (limit or fixed
 // scratch) and the consumers may walk the grid tree instead.
@@ -767,7 +771,7 @@ int ensure_inst_capacity(gd_ctx* ctx, int count) {
 
 // Fill an instance record from the caller's description.
 void set_inst(Inst& I, const float* x, int64_t n, int32_t d, double eps, int32_t minpts, int32_t* labels,
-              uint8_t* core) {
+              uint8_t* core, int64_t delta) {
     std::memset(&I, 0, sizeof(I));
     I.x = x;
     I.labels = labels;
@@ -776,6 +780,7 @@ void set_inst(Inst& I, const float* x, int64_t n, int32_t d, double eps, int32_t
     I.d = d;
     I.eps = (int64_t)eps;
     I.T = (uint32_t)(I.eps * I.eps);
+    I.Tm = (uint32_t)((I.eps + delta) * (I.eps + delta));  // eps + delta <= 65535
     I.minpts = minpts;
     for (int j = 0; j < kMaxD; ++j) {
         I.mn[j] = INT_MAX;
@@ -988,7 +993,7 @@ int dbscan(gd_ctx* ctx, const float* points, int64_t n, int32_t d, double eps, i
     if (rc) return rc;
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
-    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags);
+    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags, ctx->approx_delta);
     int D;
     int64_t total;
     uint32_t tiles;
@@ -1005,7 +1010,7 @@ int dbscan_noalloc(gd_ctx* ctx, const float* points, int64_t n, int32_t d, doubl
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return ctx->fail(GD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
     if (!ctx->scratch) return ctx->fail(GD_EDEVICE, "dbscan_noalloc: the scratch array's device address is unknown");
-    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags);
+    set_inst(ctx->inst_host[0], points, n, d, eps, minpts, labels, core_flags, ctx->approx_delta);
     int D;
     int64_t total;
     uint32_t tiles;
@@ -1049,7 +1054,7 @@ int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* st
     if (rc) return rc;
     for (int k = 0; k < count; ++k) {
         const gd_instance& q = inst[k];
-        set_inst(ctx->inst_host[k], q.points, q.n, q.d, q.eps, q.minpts, q.labels, q.core_flags);
+        set_inst(ctx->inst_host[k], q.points, q.n, q.d, q.eps, q.minpts, q.labels, q.core_flags, ctx->approx_delta);
     }
     int D;
     uint32_t tiles;
@@ -1136,6 +1141,11 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
                 DeviceGuard guard(ctx->device);
                 drop_graph(ctx);
             }
+            return GD_OK;
+        case GD_OPT_APPROX_DELTA:
+            if (value < 0 || value > kApproxDeltaMax)
+                return ctx->fail(GD_EINVAL, "approximation delta must be in [0, %d]", kApproxDeltaMax);
+            ctx->approx_delta = value;
             return GD_OK;
         case GD_OPT_NEIGHBOR_MODE:
             if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "neighbour mode must be 0, 1 or 2");

@@ -33,6 +33,10 @@
 //   The start point p is the first core point of s_i (the paper picks one at
 //   random; the choice does not change the answer).  If a Pruning call
 //   empties a set the answer is "no" at once.
+//   Approximate FastMerging (the remark on numerical error, Section 4.3.3):
+//   the two "yes" tests accept D(p, q) <= Tyes = (eps + delta)^2 while
+//   Pruning keeps eps; then every pair with MinDist <= eps still answers yes,
+//   and a yes implies MinDist <= eps + delta.  Tyes = eps^2 is the exact test.
 #pragma once
 
 #include "common.hpp"
@@ -292,8 +296,8 @@ __device__ __forceinline__ void init_alive(const PointSet& s) {
 // testing several pairs from one si loads once).  Returns 1 (yes), 0 (no)
 // or -1 (iteration bound exceeded).
 template <int D>
-__device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D], uint32_t T, double eps,
-                                 unsigned long long& ndist, uint32_t& iters) {
+__device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D], uint32_t T, uint32_t Tyes,
+                                 double eps, unsigned long long& ndist, uint32_t& iters) {
     init_alive<D>(si);
     init_alive<D>(sj);
     wave_sync();
@@ -306,22 +310,22 @@ __device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D
         if (iters > bound) return -1;
         const uint64_t bq = nearest<D>(sj, P, ndist, Q);
         const uint32_t dq = (uint32_t)(bq >> 32);
-        if (dq <= T) return 1;
+        if (dq <= Tyes) return 1;
         if (!pruning<D>(si, sj, P, Q, dq, T, eps, ndist)) return 0;
         const uint64_t bp = nearest<D>(si, Q, ndist, P);
         const uint32_t dp = (uint32_t)(bp >> 32);
-        if (dp <= T) return 1;
+        if (dp <= Tyes) return 1;
         if (!pruning<D>(sj, si, Q, P, dp, T, eps, ndist)) return 0;
     }
 }
 
 // Algorithm 5 from position `start` of si.
 template <int D>
-__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T, double eps,
+__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T, uint32_t Tyes, double eps,
                             unsigned long long& ndist, uint32_t& iters) {
     int32_t P0[D];
     load_point<D>(si, start, P0);
-    return fast_merging_from<D>(si, sj, P0, T, eps, ndist, iters);
+    return fast_merging_from<D>(si, sj, P0, T, Tyes, eps, ndist, iters);
 }
 
 }  // namespace gd

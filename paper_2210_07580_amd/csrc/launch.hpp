@@ -42,6 +42,7 @@ struct Inst {
     int32_t d;
     int32_t minpts;
     uint32_t T;        // eps^2
+    uint32_t Tm;       // (eps + delta)^2: FastMerging's "yes" bound (delta 0: exact)
     uint32_t tile0;    // first point tile of the instance (tiles never straddle instances)
     // filled on the device
     int32_t mn[kMaxD];

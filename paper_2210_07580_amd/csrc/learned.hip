@@ -125,9 +125,9 @@ __global__ __launch_bounds__(kBlock) void harvest_kernel(GridView gv, CoreOut co
             PointSet sb{co.ccrd, bb, mb, bits_b, (mb + kWave - 1) / kWave};
             unsigned long long c0 = 0, c1 = 0, c2 = 0;
             uint32_t it;
-            const int y = fast_merging<D>(sa, sb, 0u, I.T, eps, c0, it);
-            fast_merging<D>(sa, sb, ra, I.T, eps, c1, it);
-            fast_merging<D>(sb, sa, rb, I.T, eps, c2, it);
+            const int y = fast_merging<D>(sa, sb, 0u, I.T, I.T, eps, c0, it);
+            fast_merging<D>(sa, sb, ra, I.T, I.T, eps, c1, it);
+            fast_merging<D>(sb, sa, rb, I.T, I.T, eps, c2, it);
             if (lane < kFeat) {
                 float v = 0.f;
 #pragma unroll

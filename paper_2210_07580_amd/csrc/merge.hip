@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     if (r >= r1 || r >= (int64_t)co.counts[1] || (split && r >= (int64_t)*split)) return;
     const uint32_t ci = ldf[r];
     // every load that depends on ci alone is issued before the first use
-    const uint32_t T = cell_inst(gv, ci).T;
+    // the merge's "yes" bound: eps^2, or (eps + delta)^2 when approximate
+    const uint32_t T = cell_inst(gv, ci).Tm;
     const uint4 own = rank[ci];
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     const uint32_t pci = load_acq(&parent[ci]);
@@ -303,11 +304,11 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
             int yes;
             if constexpr (kLearned) {
                 if (__shfl(my_z1, l) > 0.f)
-                    yes = fast_merging<D>(sj, si, readlane(my_rb, l), T, eps, n_dist, it);
+                    yes = fast_merging<D>(sj, si, readlane(my_rb, l), T, I.Tm, eps, n_dist, it);
                 else
-                    yes = fast_merging<D>(si, sj, readlane(my_ra, l), T, eps, n_dist, it);
+                    yes = fast_merging<D>(si, sj, readlane(my_ra, l), T, I.Tm, eps, n_dist, it);
             } else {
-                yes = fast_merging_from<D>(si, sj, p0, T, eps, n_dist, it);
+                yes = fast_merging_from<D>(si, sj, p0, T, I.Tm, eps, n_dist, it);
             }
             ++n_test;
             n_pts += si.m + sj.m;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
                 continue;
             }
             uint32_t it = 0;
-            const int yes = fast_merging_from<D>(si, sj, p0, T, eps, n_dist, it);
+            const int yes = fast_merging_from<D>(si, sj, p0, T, I.Tm, eps, n_dist, it);
             ++n_test;
             n_pts += si.m + sj.m;
             n_iter += it;
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     b.words = (b.m + kWave - 1) / kWave;
     unsigned long long nd = 0;
     uint32_t it = 0;
-    const int yes = fast_merging<D>(a, b, 0u, T, eps, nd, it);
+    const int yes = fast_merging<D>(a, b, 0u, T, T, eps, nd, it);
     if (lane_id() == 0) {
         answers[r] = yes < 0 ? 2 : (uint8_t)yes;
         if (iterations) iterations[r] = it;

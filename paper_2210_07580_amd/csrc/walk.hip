@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void merge_walk_kernel(GridView gv, CoreOut
     if (mi == 0 || mi > kTinyCore) return;
     const uint32_t bi = co.core_begin[ci];
     const Inst& I = cell_inst(gv, ci);
-    const uint32_t T = I.T;
+    const uint32_t T = I.Tm;  // the merge's "yes" bound (eps^2 unless approximate)
     const int dk = I.d;
     int32_t pi[kTinyCore][D];
 #pragma unroll
