@@ -234,7 +234,7 @@ typedef enum {
                                  without graph replay or the learned proposal.
                                  GD_OPT_LDF_ORDER sets 1 or 0.  The result is
                                  the same in every order (Theorem 4).         */
-    GD_OPT_APPROX_DELTA = 10  /* approximate FastMerging (Section 4.3.3, the
+    GD_OPT_APPROX_DELTA = 10, /* approximate FastMerging (Section 4.3.3, the
                                  remark on numerical error): an integer delta
                                  in [0, 65535 - GD_EPS_MAX]; 0 (default) is
                                  exact.  With delta > 0 FastMerging answers yes
@@ -249,6 +249,17 @@ typedef enum {
                                  clusters and lies inside one component of the
                                  core points' (eps + delta)-graph.  Labels are
                                  then NOT those of dbscan(): an opt-in mode.  */
+    GD_OPT_NEIGHBOR_QUERY = 11 /* how the lists Nei(g) are found: 0 (default)
+                                 the grid tree of Algorithm 3, lists ordered by
+                                 offset (Eq. (2)) for at most 2^20 grids and in
+                                 walk order above; 1 the grid tree, lists in
+                                 walk order always (no offset order for core
+                                 marking's early exit); 2 direct hashing of
+                                 every candidate identifier with offset < d in
+                                 a table of the non-empty grids, lists ordered
+                                 by offset (the query the grid tree avoids;
+                                 candidates grow as (2 ceil(sqrt(d)) + 1)^d).
+                                 The result is the same for every query.      */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);

@@ -103,6 +103,7 @@ struct gd_ctx {
     bool bfs = false;              // the BFS order of Algorithm 6 (merge_order 2)
     int nei_mode = 0;              // GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists, 2 walks
     int64_t approx_delta = 0;      // GD_OPT_APPROX_DELTA (0: exact merging)
+    int nei_query = kNeiTree;      // GD_OPT_NEIGHBOR_QUERY
     bool last_walk = false;        // the last eager call walked (no full lists)
     gd_stats last{};
     // what the last successful call left in the workspace (for gd_debug_*)
@@ -516,19 +517,36 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     const bool may_walk = !plan && !ctx->bfs && ctx->nei_mode == 0;
     // the split walk's per-lane counts go to the sort buffer that does not
     // hold the sorted identifiers (free until the LDF step), when they fit
-    uint32_t* lane_cnt = nullptr;
-    {
-        const int64_t words = nei_lane_count_words(ncell, D);
-        if (words > 0 && words <= 2 * n)
-            lane_cnt = (uint32_t*)(skeys == L.keys_b ? L.keys_c : L.keys_b);
-    }
     uint64_t nei_total = 0;
     uint32_t* nei = nullptr;
     // Nei(g) of every grid, or (walk mode) of the grids with more than
     // kTinyCore core points, known only after core marking
     auto build_lists = [&](const uint32_t* only_big, bool fallback) -> int {
+        NeiQuery nq{};
+        nq.t = t;
+        nq.kind = only_big ? kNeiTree : ctx->nei_query;
+        nq.key_bytes = k32 ? 4 : 8;
+        nq.inst = b.inst;
+        nq.inst_shift = &Hd->inst_shift;
+        // the split query's per-lane counts go to the sort buffer that does
+        // not hold the sorted identifiers (free until the LDF step), when
+        // they fit
+        uint32_t* lane_cnt = nullptr;
+        const int64_t words = nei_lane_count_words(nq, ncell, D);
+        if (words > 0 && words <= 2 * n) lane_cnt = (uint32_t*)(skeys == L.keys_b ? L.keys_c : L.keys_b);
         ctx->mark(P_NEI_COUNT, 0);
-        GD_TRY(launch_nei_count(g, t, L.off_counts, lane_cnt, only_big, st));
+        if (nq.kind == kNeiHash) {
+            // the identifier -> grid table lives in the output pass's table
+            // buffer, which that pass clears and refills later
+            nq.bits = table_bits(ncell);
+            int rc2;
+            if (!plan && (rc2 = grow(ctx, ctx->cur->table, output_table_bytes(nq.bits, nq.key_bytes),
+                                     ctx->cur->arena.cap)))
+                return rc2;
+            nq.table = ctx->cur->table.p;
+            GD_TRY(launch_grid_table(g, skeys, nq.key_bytes, ctx->cur->table.p, nq.bits, st));
+        }
+        GD_TRY(launch_nei_count(g, nq, L.off_counts, lane_cnt, only_big, st));
         GD_TRY(launch_nei_offsets(g, L.off_counts, L.nei_off, L.partial, st));
         ctx->mark(P_NEI_COUNT, 1);
         int rc2;
@@ -547,7 +565,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         }
         nei = (uint32_t*)ctx->cur->nei.p;
         ctx->mark(P_NEI_FILL, 0);
-        GD_TRY(launch_nei_fill(g, t, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, st));
+        GD_TRY(launch_nei_fill(g, nq, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, st));
         ctx->mark(P_NEI_FILL, 1);
         return GD_OK;
     };
@@ -1141,6 +1159,10 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
                 DeviceGuard guard(ctx->device);
                 drop_graph(ctx);
             }
+            return GD_OK;
+        case GD_OPT_NEIGHBOR_QUERY:
+            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "neighbour query must be 0, 1 or 2");
+            ctx->nei_query = (int)value;
             return GD_OK;
         case GD_OPT_APPROX_DELTA:
             if (value < 0 || value > kApproxDeltaMax)

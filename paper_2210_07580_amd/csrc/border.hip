@@ -19,6 +19,7 @@
 // through the wave-per-grid kernel, which writes through the permutation.
 #include <algorithm>
 
+#include "hash.hpp"
 #include "launch.hpp"
 #include "scan.hpp"
 
@@ -26,79 +27,6 @@ namespace gd {
 
 constexpr int32_t kDeferred = -2;  // grid output written by the wave-per-grid kernel
 
-template <typename K>
-struct HashSlot;
-template <>
-struct alignas(8) HashSlot<uint32_t> {
-    uint32_t key;
-    int32_t val;
-};
-template <>
-struct alignas(16) HashSlot<uint64_t> {
-    uint64_t key;
-    int32_t val;
-    int32_t pad;
-};
-
-// Buckets of 16 bytes (2 slots of u32 identifiers, 1 of u64) at load <= 1/4
-// (<= 1/8 up to 2^20 grids): a lookup reads one bucket with a single 16-byte
-// load and almost always ends there.  The table is hit at random addresses,
-// one per lane, so the cost of a lookup is set by the cache lines each load
-// instruction touches, not by the bytes: one load per lookup rather than a
-// wider bucket.
-template <typename K>
-constexpr int kBucketSlots = 16 / (int)sizeof(HashSlot<K>);
-template <typename K>
-constexpr int kBucketShift = sizeof(K) == 4 ? 1 : 0;
-
-template <typename K>
-__device__ __forceinline__ uint64_t hash_bucket(K key, int bbits) {
-    return ((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - bbits);
-}
-
-__device__ __forceinline__ uint32_t cas_key(uint32_t* p, uint32_t cmp, uint32_t v) { return atomicCAS(p, cmp, v); }
-__device__ __forceinline__ uint64_t cas_key(uint64_t* p, uint64_t cmp, uint64_t v) {
-    return (uint64_t)atomicCAS(reinterpret_cast<unsigned long long*>(p), (unsigned long long)cmp,
-                               (unsigned long long)v);
-}
-
-// Look `key` up in one loaded bucket: 1 found (val set), 0 absent (the
-// bucket has an empty slot: slots fill in order and are never freed), -1
-// look in the next bucket.
-__device__ __forceinline__ int bucket_match(const uint4& q, uint32_t key, int32_t& val) {
-    if (q.x == key) {
-        val = (int32_t)q.y;
-        return 1;
-    }
-    if (q.z == key) {
-        val = (int32_t)q.w;
-        return 1;
-    }
-    return (q.x == ~0u || q.z == ~0u) ? 0 : -1;
-}
-__device__ __forceinline__ int bucket_match(const uint4& q, uint64_t key, int32_t& val) {
-    const uint64_t k = (uint64_t)q.x | ((uint64_t)q.y << 32);
-    if (k == key) {
-        val = (int32_t)q.z;
-        return 1;
-    }
-    return k == ~0ull ? 0 : -1;
-}
-
-template <typename K>
-__device__ __forceinline__ uint4 load_bucket(const HashSlot<K>* tab, uint64_t b) {
-    return *reinterpret_cast<const uint4*>(tab + (b << kBucketShift<K>));
-}
-
-// The all-ones identifier marks an empty slot; a grid with that identifier
-// keeps its label in the extra slot at index 2^bits.
-template <typename K>
-__global__ __launch_bounds__(kBlock) void hash_clear_kernel(HashSlot<K>* tab, int64_t slots) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kBlock) {
-        tab[i].key = ~K(0);
-        tab[i].val = kDeferred;
-    }
-}
 
 template <typename K>
 __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut co, const K* __restrict__ skeys,
@@ -110,24 +38,7 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
     const uint32_t k = gv.cell_start[c + 1] - st;
     // only all-core grids go in: a missing identifier reads as deferred
     if (co.core_cnt[c] != k) return;
-    const int32_t val = cell_label[c];
-    const K key = skeys[st];
-    if (key == ~K(0)) {
-        tab[1ull << bits].val = val;
-        return;
-    }
-    const int bbits = bits - kBucketShift<K>;
-    const uint64_t bmask = (1ull << bbits) - 1ull;
-    // load <= 1/4, so a free slot is always found
-    for (uint64_t b = hash_bucket(key, bbits);; b = (b + 1) & bmask) {
-        HashSlot<K>* bucket = tab + (b << kBucketShift<K>);
-        for (int j = 0; j < kBucketSlots<K>; ++j) {
-            if (cas_key(&bucket[j].key, ~K(0), key) == ~K(0)) {
-                bucket[j].val = val;
-                return;
-            }
-        }
-    }
+    grid_table_insert<K>(tab, bits, skeys[st], cell_label[c]);
 }
 
 // Points in input order, instance tiles as in the identifier pass; each
@@ -191,7 +102,8 @@ hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* ke
     if (g.ncell == 0) return hipSuccess;
     HashSlot<K>* tab = reinterpret_cast<HashSlot<K>*>(table);
     const int64_t slots = (1ll << bits) + 1;
-    hash_clear_kernel<K><<<dim3((unsigned)std::min<int64_t>(grid_for(slots), 4096)), dim3(kBlock), 0, st>>>(tab, slots);
+    hash_clear_kernel<K><<<dim3((unsigned)std::min<int64_t>(grid_for(slots), 4096)), dim3(kBlock), 0, st>>>(tab, slots,
+                                                                                                      kDeferred);
     hash_build_kernel<K><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, skeys, cell_label, tab, bits);
     output_direct_kernel<K><<<dim3(g.b.tiles), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits);
     return hipGetLastError();

@@ -155,22 +155,40 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
                        uint32_t* const* tchild, hipStream_t st);
 
 // ---- neighbors.hip (Algorithm 3)
+// The query that produces the lists: the grid tree with offset-ordered lists
+// (walk order above 2^20 grids), the grid tree in walk order always, or
+// direct hashing of every candidate identifier (offset-ordered).
+enum NeiQueryKind { kNeiTree = 0, kNeiTreeWalkOrder = 1, kNeiHash = 2 };
+struct NeiQuery {
+    TreeView t;
+    int kind;
+    // hashing only: the identifier -> grid table (launch_grid_table)
+    const void* table;
+    int bits;
+    int key_bytes;          // 4 or 8
+    const Inst* inst;       // device instance table
+    const int* inst_shift;  // device: Header::inst_shift
+};
 // Pass 1: per-grid neighbour count per offset value (ncell x D, u32).
-// lane_cnt (optional, nei_lane_count_words(ncell, D) u32; nullptr when that
-// is 0 or no room): the split walk's per-lane counts, kept for pass 2.
-int64_t nei_lane_count_words(int64_t ncell, int D);
+// lane_cnt (optional, nei_lane_count_words u32; nullptr when that is 0 or
+// no room): the split query's per-lane counts, kept for pass 2.
 // only_big (optional): per-grid core counts; then only grids with more than
 // kTinyCore core points get a list, the others an empty one.
-hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
+int64_t nei_lane_count_words(const NeiQuery& nq, int64_t ncell, int D);
+hipError_t launch_nei_count(const GridView& g, const NeiQuery& nq, uint32_t* off_counts, uint32_t* lane_cnt,
                             const uint32_t* only_big, hipStream_t st);
 // Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1); total into the header.
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st);
-// Pass 2: write Nei(g) ordered by offset (skipped, with kErrNeiOverflow, if
-// the total exceeds `capacity` entries).
-hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
+// Pass 2: write Nei(g) (skipped, with kErrNeiOverflow, if the total exceeds
+// `capacity` entries).
+hipError_t launch_nei_fill(const GridView& g, const NeiQuery& nq, const uint32_t* off_counts, const uint32_t* lane_cnt,
                            const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
                            hipStream_t st);
+// Identifier -> grid index table (2^bits + 1 slots of 8 or 16 bytes, as
+// output_table_bytes) for the hashing query; skeys: sorted identifiers.
+hipError_t launch_grid_table(const GridView& g, const void* skeys, int key_bytes, void* table, int bits,
+                             hipStream_t st);
 
 // ---- core.hip
 // Core sets s_i as runs of point rows.  A grid whose points are all core

@@ -1,85 +1,161 @@
 // Non-empty neighbouring grids query (Section 4.2.2, Algorithm 3, Eq. (2)),
 // written out as lists Nei(g).
 //
-// Each grid g walks the grid tree level by level (walk.hpp), its first
-// level split over lanes.  The result excludes g itself and is ordered by
-// offset (the paper's counting sort), nearest grids first.
+// Two queries produce the same sets:
+//   the grid tree (Algorithm 3): each grid walks the tree level by level
+//     (walk.hpp), its first level split over lanes;
+//   direct hashing, for comparison: every candidate identifier g' with
+//     sum_j max(|g'_j - g_j| - 1, 0)^2 < d (the same shrinking windows,
+//     enumerated over all integers rather than over existing tree nodes) is
+//     probed in a hash table of the non-empty grids.
+// The result excludes g itself.  It is ordered by offset (the paper's
+// counting sort, nearest grids first, for early exit in core marking) when
+// the query splits over lanes or hashes; a one-lane tree walk over millions
+// of grids, or on request, keeps walk order (level 1 centre-out).
+#include <algorithm>
+#include <type_traits>
+
+#include "hash.hpp"
 #include "launch.hpp"
 #include "scan.hpp"
 #include "walk.hpp"
 
 namespace gd {
 
-// With few grids, each grid's walk is split over kSplit = 8 consecutive
-// lanes: lane p takes the level-1 children whose key is g_1 + p - 3.  The
-// level-1 window is 1 + isqrt(d - 1) <= 3 for d <= 8, so offsets -3..+3
-// cover it (lane 7 has nothing to do).  The tree walk is a chain of
-// dependent loads, and one thread per grid leaves most of the chip idle when
-// the grids number in the tens of thousands; with millions of grids one
-// thread per grid is already enough and the split would only add the extra
-// counting walk of the fill pass.  (Splitting the next level too repeats the
-// upper searches in every lane and costs more than it saves.)  Lanes follow
-// the tree order, so the lists come out as one walk would emit them.
+// With few grids, each grid's query is split over kSplit = 8 consecutive
+// lanes: lane p takes the level-1 key g_1 + p - 3.  The level-1 window is
+// 1 + isqrt(d - 1) <= 3 for d <= 8, so offsets -3..+3 cover it (lane 7 has
+// nothing to do).  The tree walk is a chain of dependent loads, and one
+// thread per grid leaves most of the chip idle when the grids number in the
+// tens of thousands; with millions of grids one thread per grid is already
+// enough and the split would only add the extra counting walk of the fill
+// pass.  (Splitting the next level too repeats the upper searches in every
+// lane and costs more than it saves.)  Lanes follow the query order, so the
+// lists come out as one query would emit them.
 constexpr int kSplit = 8;
 constexpr int64_t kSplitMaxGrids = 1 << 20;
 
 inline int nei_lanes(int64_t ncell) { return ncell <= kSplitMaxGrids ? kSplit : 1; }
 
-// The neighbours below the level-1 children with key g_1 + delta,
-// delta in [d_lo, d_hi], in tree order (emit(a, offset) for each; g itself
-// is emitted too and the callers skip it).
-template <int D, typename Emit>
-__device__ __forceinline__ void query_part(const TreeView& t, const int32_t (&g)[D + 1], int dk, int d_lo, int d_hi,
-                                           Emit& emit) {
-    const int w1 = walk_window(dk);
-    d_lo = d_lo < -w1 ? -w1 : d_lo;
-    d_hi = d_hi > w1 ? w1 : d_hi;
-    if (d_lo > d_hi) return;
-    auto visit = [&](uint32_t a, int o) -> bool {
-        emit(a, o);
-        return true;
-    };
-    const uint32_t a0 = walk_lower(t.key[0], 0, t.level_count[0], g[0]);
-    const uint32_t hi1 = t.child[0][a0 + 1];
-    const int32_t* __restrict__ key1 = t.key[1];
-    for (uint32_t a = walk_lower(key1, t.child[0][a0], hi1, g[1] + d_lo); a < hi1; ++a) {
-        const int d1 = key1[a] - g[1];
-        if (d1 > d_hi) break;
-        const int gap = (d1 < 0 ? -d1 : d1) - 1;
-        const int o = gap > 0 ? gap * gap : 0;
-        if (o >= dk) continue;
-        if constexpr (D == 1) {
+// Algorithm 3 on the grid tree.
+struct TreeQuery {
+    TreeView t;
+    // The neighbours below the level-1 children with key g_1 + delta, delta
+    // in [d_lo, d_hi], in tree order (emit(a, offset) for each; g itself is
+    // emitted too and the callers skip it).
+    template <int D, typename Emit>
+    __device__ __forceinline__ void part(const int32_t (&g)[D + 1], int dk, int d_lo, int d_hi, Emit& emit) const {
+        const int w1 = walk_window(dk);
+        d_lo = d_lo < -w1 ? -w1 : d_lo;
+        d_hi = d_hi > w1 ? w1 : d_hi;
+        if (d_lo > d_hi) return;
+        auto visit = [&](uint32_t a, int o) -> bool {
             emit(a, o);
-        } else {
-            walk_levels<D, 2>(t, g, dk, t.child[1][a], t.child[1][a + 1], o, true, visit);
+            return true;
+        };
+        const uint32_t a0 = walk_lower(t.key[0], 0, t.level_count[0], g[0]);
+        const uint32_t hi1 = t.child[0][a0 + 1];
+        const int32_t* __restrict__ key1 = t.key[1];
+        for (uint32_t a = walk_lower(key1, t.child[0][a0], hi1, g[1] + d_lo); a < hi1; ++a) {
+            const int d1 = key1[a] - g[1];
+            if (d1 > d_hi) break;
+            const int gap = (d1 < 0 ? -d1 : d1) - 1;
+            const int o = gap > 0 ? gap * gap : 0;
+            if (o >= dk) continue;
+            if constexpr (D == 1) {
+                emit(a, o);
+            } else {
+                walk_levels<D, 2>(t, g, dk, t.child[1][a], t.child[1][a + 1], o, true, visit);
+            }
         }
     }
-}
+    // Every neighbour in walk order (level 1 centre-out).
+    template <int D, typename V>
+    __device__ __forceinline__ void walk(const int32_t (&g)[D + 1], int dk, V& visit) const {
+        tree_walk<D>(t, g, dk, false, visit);
+    }
+};
+
+// Direct hashing of every candidate identifier.  Identifiers are packed as
+// in the identifier pass: the instance above inst_shift, coordinate j of
+// the grid at shift[j] with bits[j] bits.
+template <typename K>
+struct HashQuery {
+    const HashSlot<K>* tab;
+    int bits;              // table of 2^bits slots (+1)
+    const Inst* inst;      // device instance table
+    const int* inst_shift; // device: position of the instance field
+
+    template <int D, int L, typename Emit>
+    __device__ __forceinline__ void probe(const Inst& I, const int32_t (&g)[D + 1], int dk, K key, int off,
+                                          Emit& emit) const {
+        const int win = walk_window(dk - off);
+        const int64_t hi = (int64_t)1 << I.bits[L - 1];
+        for (int32_t k = g[L] - win; k <= g[L] + win; ++k) {
+            if (k < 0 || k >= hi) continue;
+            const int dl = k - g[L];
+            const int gap = (dl < 0 ? -dl : dl) - 1;
+            const int o = off + (gap > 0 ? gap * gap : 0);
+            if (o >= dk) continue;
+            const K kk = key | ((K)(uint32_t)k << I.shift[L - 1]);
+            if constexpr (L == D) {
+                const int32_t a = grid_table_find<K>(tab, bits, kk);
+                if (a >= 0) emit((uint32_t)a, o);
+            } else {
+                probe<D, L + 1>(I, g, dk, kk, o, emit);
+            }
+        }
+    }
+
+    template <int D, typename Emit>
+    __device__ __forceinline__ void part(const int32_t (&g)[D + 1], int dk, int d_lo, int d_hi, Emit& emit) const {
+        const Inst& I = inst[g[0]];
+        const int ishift = *inst_shift;
+        const K top = ishift >= (int)(8 * sizeof(K)) ? K(0) : (K)(uint32_t)g[0] << ishift;
+        const int w1 = walk_window(dk);
+        d_lo = d_lo < -w1 ? -w1 : d_lo;
+        d_hi = d_hi > w1 ? w1 : d_hi;
+        const int64_t hi = (int64_t)1 << I.bits[0];
+        for (int d1 = d_lo; d1 <= d_hi; ++d1) {
+            const int32_t k = g[1] + d1;
+            if (k < 0 || k >= hi) continue;
+            const int gap = (d1 < 0 ? -d1 : d1) - 1;
+            const int o = gap > 0 ? gap * gap : 0;
+            if (o >= dk) continue;
+            const K kk = top | ((K)(uint32_t)k << I.shift[0]);
+            if constexpr (D == 1) {
+                const int32_t a = grid_table_find<K>(tab, bits, kk);
+                if (a >= 0) emit((uint32_t)a, o);
+            } else {
+                probe<D, 2>(I, g, dk, kk, o, emit);
+            }
+        }
+    }
+};
 
 // This lane's part of grid c's neighbours, counted per offset value into
 // cnt[o][threadIdx.x] (LDS).
-template <int D, int P>
-__device__ __forceinline__ void count_part(const GridView& gv, const TreeView& t, int64_t c, int p,
-                                           uint32_t (*cnt)[kBlock]) {
+template <int D, int P, typename Q>
+__device__ __forceinline__ void count_part(const GridView& gv, const Q& q, int64_t c, int p, uint32_t (*cnt)[kBlock]) {
     int32_t g[D + 1];
     load_grid_key<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
     auto emit = [&](uint32_t a, int o) {
         if (a != (uint32_t)c) cnt[o][threadIdx.x] += 1;
     };
-    query_part<D>(t, g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
+    q.template part<D>(g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
 }
 
-// With lane_cnt (split walks only), each lane also keeps its own counts for
-// the fill pass, which then needs no second counting walk.
 // only_big (optional): the core counts of the grids; then only grids with
 // more than kTinyCore core points get a list (the others count 0).
 __device__ __forceinline__ bool wants_list(const uint32_t* only_big, int64_t c) {
     return !only_big || only_big[c] > kTinyCore;
 }
 
-template <int D, int P>
-__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView t, uint32_t* __restrict__ off_counts,
+// With lane_cnt (split queries only), each lane also keeps its own counts
+// for the fill pass, which then needs no second counting query.
+template <int D, int P, typename Q>
+__global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, Q q, uint32_t* __restrict__ off_counts,
                                                            uint32_t* __restrict__ lane_cnt,
                                                            const uint32_t* __restrict__ only_big) {
     __shared__ uint32_t sc[D][kBlock];
@@ -90,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
     if (P == 1 && !valid) return;
 #pragma unroll
     for (int o = 0; o < D; ++o) sc[o][threadIdx.x] = 0;
-    if (valid && wants_list(only_big, c)) count_part<D, P>(gv, t, c, p, sc);
+    if (valid && wants_list(only_big, c)) count_part<D, P>(gv, q, c, p, sc);
 #pragma unroll
     for (int o = 0; o < D; ++o) {
         uint32_t v = sc[o][threadIdx.x];
@@ -102,23 +178,22 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, TreeView
     }
 }
 
-// With a split (at most 2^20 grids), the list of grid c holds its offset-0
-// neighbours, then offset 1, ... (the paper's counting sort, for early exit
-// in core marking); within one offset value the lanes' parts follow each
-// other in lane order.  With more grids (one lane per grid, hundreds of
-// entries each), the list is kept in walk order instead: found neighbours
-// are staged in LDS and stored kFillStage consecutive entries at a time, so
-// that the stores fill whole cache lines rather than scattering single
-// words over the offset buckets (the stores dominated this pass).
+// Ordered lists hold a grid's offset-0 neighbours, then offset 1, ...; within
+// one offset value the lanes' parts follow each other in lane order.  In
+// walk order (one lane per grid), found neighbours are staged in LDS and
+// stored kFillStage consecutive entries at a time, so that the stores fill
+// whole cache lines rather than scattering single words over offset buckets
+// (with millions of grids the stores dominated this pass).
 constexpr int kFillStage = 16;
 
-template <int D, int P>
-__global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView t, const uint32_t* __restrict__ off_counts,
+template <int D, int P, bool kOrdered, typename Q>
+__global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, Q q, const uint32_t* __restrict__ off_counts,
                                                           const uint32_t* __restrict__ lane_cnt,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
                                                           uint64_t capacity, const uint32_t* __restrict__ only_big) {
+    static_assert(kOrdered || P == 1, "walk order is written by one lane per grid");
     __shared__ uint32_t pos[D][kBlock];
-    constexpr int kStage = P == 1 ? kFillStage : 1;
+    constexpr int kStage = kOrdered ? 1 : kFillStage;
     __shared__ uint32_t stage_a[kStage][kBlock];
     const int64_t ncell = *gv.ncell_dev;
     if (nei_off[ncell] > capacity) {
@@ -137,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
         } else {
 #pragma unroll
             for (int o = 0; o < D; ++o) pos[o][threadIdx.x] = 0;
-            if (valid) count_part<D, P>(gv, t, c, p, pos);
+            if (valid) count_part<D, P>(gv, q, c, p, pos);
         }
     }
     uint32_t run = 0;
@@ -162,10 +237,15 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
     int32_t g[D + 1];
     load_grid_key<D>(gv, c, g);
     const int dk = gv.b.inst[g[0]].d;
-    if constexpr (P == 1) {
-        // millions of grids: the list in walk order (level 1 centre-out, so
-        // nearer slabs of grids still come first), staged and stored as
-        // runs of consecutive entries
+    if constexpr (kOrdered) {
+        auto emit = [&](uint32_t a, int o) {
+            if (a == (uint32_t)c) return;
+            const uint32_t k = pos[o][threadIdx.x];
+            pos[o][threadIdx.x] = k + 1;
+            nei[base + k] = a;
+        };
+        q.template part<D>(g, dk, P == 1 ? -3 : p - 3, P == 1 ? 3 : p - 3, emit);
+    } else {
         uint32_t run_pos = 0;
         int staged = 0;
         auto flush = [&]() {
@@ -179,34 +259,52 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, TreeView 
             if (++staged == kStage) flush();
             return true;
         };
-        tree_walk<D>(t, g, dk, false, visit);
+        q.template walk<D>(g, dk, visit);
         flush();
-    } else {
-        auto emit = [&](uint32_t a, int o) {
-            if (a == (uint32_t)c) return;
-            const uint32_t k = pos[o][threadIdx.x];
-            pos[o][threadIdx.x] = k + 1;
-            nei[base + k] = a;
-        };
-        query_part<D>(t, g, dk, p - 3, p - 3, emit);
     }
 }
 
-int64_t nei_lane_count_words(int64_t ncell, int D) {
-    return nei_lanes(ncell) > 1 ? ncell * kSplit * D : 0;
+// How the lists are produced (see the top of this file).
+struct NeiShape {
+    int P;         // lanes per grid
+    bool ordered;  // by offset
+};
+inline NeiShape nei_shape(const NeiQuery& nq, int64_t ncell) {
+    if (nq.kind == kNeiTreeWalkOrder) return {1, false};
+    const int P = nei_lanes(ncell);
+    return {P, nq.kind == kNeiHash || P > 1};
 }
 
-hipError_t launch_nei_count(const GridView& g, const TreeView& t, uint32_t* off_counts, uint32_t* lane_cnt,
+int64_t nei_lane_count_words(const NeiQuery& nq, int64_t ncell, int D) {
+    return nei_shape(nq, ncell).P > 1 ? ncell * kSplit * D : 0;
+}
+
+// Dispatch on the query (tree, or hash of 32- or 64-bit identifiers).
+template <typename F>
+hipError_t with_query(const NeiQuery& nq, F&& f) {
+    if (nq.kind != kNeiHash) return f(TreeQuery{nq.t});
+    if (nq.key_bytes == 4)
+        return f(HashQuery<uint32_t>{reinterpret_cast<const HashSlot<uint32_t>*>(nq.table), nq.bits, nq.inst,
+                                     nq.inst_shift});
+    return f(HashQuery<uint64_t>{reinterpret_cast<const HashSlot<uint64_t>*>(nq.table), nq.bits, nq.inst,
+                                 nq.inst_shift});
+}
+
+hipError_t launch_nei_count(const GridView& g, const NeiQuery& nq, uint32_t* off_counts, uint32_t* lane_cnt,
                             const uint32_t* only_big, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    if (nei_lanes(g.ncell) > 1) {
-        GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, lane_cnt, only_big)));
-    } else {
-        GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nullptr, only_big)));
-    }
-    return hipGetLastError();
+    const NeiShape sh = nei_shape(nq, g.ncell);
+    return with_query(nq, [&](auto q) -> hipError_t {
+        using Q = decltype(q);
+        if (sh.P > 1) {
+            GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit, Q><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0,
+                                                                 st>>>(g, q, off_counts, lane_cnt, only_big)));
+        } else {
+            GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                                   g, q, off_counts, nullptr, only_big)));
+        }
+        return hipGetLastError();
+    });
 }
 
 struct CellTotal {
@@ -240,16 +338,55 @@ hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uin
                                 st);
 }
 
-hipError_t launch_nei_fill(const GridView& g, const TreeView& t, const uint32_t* off_counts, const uint32_t* lane_cnt,
+hipError_t launch_nei_fill(const GridView& g, const NeiQuery& nq, const uint32_t* off_counts, const uint32_t* lane_cnt,
                            const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
                            hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    if (nei_lanes(g.ncell) > 1) {
-        GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, lane_cnt, nei_off, nei, capacity, only_big)));
+    const NeiShape sh = nei_shape(nq, g.ncell);
+    return with_query(nq, [&](auto q) -> hipError_t {
+        using Q = decltype(q);
+        if (sh.P > 1) {
+            GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit, true, Q><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock),
+                                                                      0, st>>>(g, q, off_counts, lane_cnt, nei_off, nei,
+                                                                               capacity, only_big)));
+        } else if (sh.ordered) {
+            GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1, true, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big)));
+        } else if constexpr (std::is_same<Q, TreeQuery>::value) {
+            GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1, false, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big)));
+        } else {
+            return hipErrorInvalidValue;  // hashing always writes ordered lists
+        }
+        return hipGetLastError();
+    });
+}
+
+// The grid table of the hashing query: identifier -> grid index.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void grid_table_build_kernel(const uint32_t* ncell, const uint32_t* cell_start,
+                                                                  const K* __restrict__ skeys, HashSlot<K>* tab,
+                                                                  int bits) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)*ncell) return;
+    grid_table_insert<K>(tab, bits, skeys[cell_start[c]], (int32_t)c);
+}
+
+hipError_t launch_grid_table(const GridView& g, const void* skeys, int key_bytes, void* table, int bits,
+                             hipStream_t st) {
+    if (g.ncell == 0) return hipSuccess;
+    const int64_t slots = ((int64_t)1 << bits) + 1;
+    const unsigned cb = (unsigned)std::min<int64_t>(grid_for(slots), 4096);
+    if (key_bytes == 4) {
+        auto* tab = reinterpret_cast<HashSlot<uint32_t>*>(table);
+        hash_clear_kernel<uint32_t><<<dim3(cb), dim3(kBlock), 0, st>>>(tab, slots, -1);
+        grid_table_build_kernel<uint32_t><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+            g.ncell_dev, g.cell_start, reinterpret_cast<const uint32_t*>(skeys), tab, bits);
     } else {
-        GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                               g, t, off_counts, nullptr, nei_off, nei, capacity, only_big)));
+        auto* tab = reinterpret_cast<HashSlot<uint64_t>*>(table);
+        hash_clear_kernel<uint64_t><<<dim3(cb), dim3(kBlock), 0, st>>>(tab, slots, -1);
+        grid_table_build_kernel<uint64_t><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+            g.ncell_dev, g.cell_start, reinterpret_cast<const uint64_t*>(skeys), tab, bits);
     }
     return hipGetLastError();
 }
