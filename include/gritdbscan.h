@@ -27,7 +27,8 @@
  * Input rules: coordinates are float32 holding integers with |x| <= 2^24;
  * eps is a positive integer (so eps^2 is exact) with eps <= GD_EPS_MAX;
  * 1 <= d <= GD_D_MAX; the packed grid identifier (sum over dimensions of
- * the bit length of the largest identifier) must fit 64 bits.
+ * the bit length of the largest identifier) must fit 128 bits (identifiers
+ * of up to 64 bits are one word, wider ones two).
  *
  * Every entry point returns a gd_status.  On failure the outputs are
  * unspecified and gd_last_error() describes the failure; the context stays
@@ -52,7 +53,7 @@ typedef enum {
     GD_EINVAL = -1,       /* bad argument: NULL pointer, n < 0, d out of range,
                              eps not a positive integer, minpts < 1          */
     GD_ERANGE = -2,       /* a coordinate is not an integer of magnitude <= 2^24,
-                             eps > GD_EPS_MAX, or identifiers need > 64 bits  */
+                             eps > GD_EPS_MAX, or identifiers need > 128 bits */
     GD_ENOMEM = -3,       /* device workspace could not be allocated (or the
                              context's workspace limit would be exceeded)     */
     GD_EDEVICE = -4,      /* a HIP runtime call failed                        */
@@ -126,7 +127,7 @@ void gd_destroy(gd_ctx *ctx);
  * Errors (outputs unspecified, message in gd_last_error): GD_EINVAL for
  * bad sizes, a non-integer or non-positive eps, minpts < 1 or NULL
  * pointers; GD_ERANGE for a coordinate that is not a finite integer of
- * magnitude <= 2^24, or for grid identifiers that would need more than 64
+ * magnitude <= 2^24, or for grid identifiers that would need more than 128
  * bits (eps too small for the data's extent); GD_EUNSUPPORTED if one grid
  * holds more than 262144 core points (the merge step keeps each core set
  * as a bitmap in LDS); GD_ENOMEM if the workspace cannot be allocated or

@@ -292,12 +292,16 @@ struct Layout {
     size_t bytes;
 };
 
-Layout carve(char* base, int64_t n, int D, uint32_t tiles) {
+// Bytes of a packed identifier of `bits` bits: one 32- or 64-bit word, or two.
+int key_bytes_of(int bits) { return bits <= 32 ? 4 : bits <= 64 ? 8 : 16; }
+
+Layout carve(char* base, int64_t n, int D, uint32_t tiles, int key_bytes = 8) {
     Layout L{};
     Carve c{base};
-    L.keys_a = c.take<uint64_t>(n);  // identifiers in input order (kept for the output pass)
-    L.keys_b = c.take<uint64_t>(n);
-    L.keys_c = c.take<uint64_t>(n);
+    const int64_t kw = std::max(key_bytes, 8) / 8;  // identifier buffers hold n 64-bit words, or 2n
+    L.keys_a = c.take<uint64_t>(kw * n);  // identifiers in input order (kept for the output pass)
+    L.keys_b = c.take<uint64_t>(kw * n);
+    L.keys_c = c.take<uint64_t>(kw * n);
     // the sorted index doubles as the row -> input index map of the core
     // sets, whose side area follows row n
     L.vals_a = c.take<uint32_t>(2 * n);
@@ -424,11 +428,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->last.d = D;
     if (n == 0) return GD_OK;
 
-    // ---- workspace
-    Layout L = carve(nullptr, n, D, tiles);
+    // ---- workspace (identifiers of one word; two once the layout needs them)
+    int kbytes = plan ? key_bytes_of(plan->key_bits) : 8;
+    Layout L = carve(nullptr, n, D, tiles, kbytes);
     int rc = plan ? GD_OK : grow(ctx, ctx->cur->arena, L.bytes, ctx->cur->nei.cap);
     if (rc) return rc;
-    L = carve((char*)ctx->cur->arena.p, n, D, tiles);
+    L = carve((char*)ctx->cur->arena.p, n, D, tiles, kbytes);
     Header* Hd = ctx->hdr_dev;
     Header* H = ctx->hdr_host;
 
@@ -456,7 +461,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(fill<unsigned long long>(&ctx->stats_dev->merge[0].pairs,
                                         (int64_t)(sizeof(StatBlock) / sizeof(unsigned long long)), 0ull, st));
     ctx->mark(P_MINMAX, 0);
-    GD_TRY(launch_minmax(b, L.tile_mm, plan ? plan->key_bits : 64, st));
+    GD_TRY(launch_minmax(b, L.tile_mm, plan ? plan->key_bits : kMaxKeyBits, st));
     ctx->mark(P_MINMAX, 1);
     if (!plan && (rc = readback(ctx, st))) return rc;
     if (!plan && (H->err & kErrNotInteger)) {
@@ -467,19 +472,30 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         return ctx->fail(GD_ERANGE, "instance %d: a coordinate is not a finite integer of magnitude <= 2^24", bad);
     }
     if (!plan && (H->err & kErrKeyBits))
-        return ctx->fail(GD_ERANGE, "grid identifiers need %d bits (> 64): eps too small for the data's extent",
-                         H->total_bits);
+        return ctx->fail(GD_ERANGE, "grid identifiers need %d bits (> %d): eps too small for the data's extent",
+                         H->total_bits, kMaxKeyBits);
     const int key_bits = plan ? plan->key_bits : H->total_bits;
     ctx->last.key_bits = key_bits;
+    if (key_bytes_of(key_bits) > kbytes) {
+        // two-word identifiers: the identifier buffers double (the min/max
+        // records, the only data so far, are folded into the instance table)
+        kbytes = key_bytes_of(key_bits);
+        if ((rc = grow(ctx, ctx->cur->arena, carve(nullptr, n, D, tiles, kbytes).bytes, ctx->cur->nei.cap))) return rc;
+        L = carve((char*)ctx->cur->arena.p, n, D, tiles, kbytes);
+    }
+    if (kbytes > 8 && ctx->nei_query == kNeiHash)
+        return ctx->fail(GD_EUNSUPPORTED, "the hashing neighbour query takes identifiers of at most 64 bits (%d here)",
+                         key_bits);
 
     // ---- Algorithm 1: identifiers, radix sort, grids
     const uint32_t* sidx = nullptr;
     void* skeys = nullptr;
-    const bool k32 = key_bits <= 32;
-    if (k32)
+    if (kbytes == 4)
         rc = run_partition<uint32_t>(ctx, b, key_bits, L, &sidx, &skeys, st);
-    else
+    else if (kbytes == 8)
         rc = run_partition<uint64_t>(ctx, b, key_bits, L, &sidx, &skeys, st);
+    else
+        rc = run_partition<Key128>(ctx, b, key_bits, L, &sidx, &skeys, st);
     if (rc) return rc;
     if (plan)
         GD_TRY(launch_plan_check(Hd, 0, plan->ncell, 0, st));
@@ -525,7 +541,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         NeiQuery nq{};
         nq.t = t;
         nq.kind = only_big ? kNeiTree : ctx->nei_query;
-        nq.key_bytes = k32 ? 4 : 8;
+        nq.key_bytes = kbytes;
         nq.inst = b.inst;
         nq.inst_shift = &Hd->inst_shift;
         // the split query's per-lane counts go to the sort buffer that does
@@ -667,16 +683,19 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
 
     // ---- border / noise, output in input order
     const int hbits = table_bits(ncell);
-    if (!plan && (rc = grow(ctx, ctx->cur->table, output_table_bytes(hbits, k32 ? 4 : 8),
-                            ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap)))
+    if (!plan && kbytes <= 8 &&
+        (rc = grow(ctx, ctx->cur->table, output_table_bytes(hbits, kbytes),
+                   ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap)))
         return rc;
     ctx->mark(P_OUTPUT, 0);
-    if (k32)
+    if (kbytes == 4)
         GD_TRY(launch_output_direct<uint32_t>(g, co, (const uint32_t*)L.keys_a, (const uint32_t*)skeys, L.cell_label,
                                               ctx->cur->table.p, hbits, st));
-    else
+    else if (kbytes == 8)
         GD_TRY(launch_output_direct<uint64_t>(g, co, (const uint64_t*)L.keys_a, (const uint64_t*)skeys, L.cell_label,
                                               ctx->cur->table.p, hbits, st));
+    else
+        GD_TRY(launch_output_allcore(g, co, L.cell_label, st));
     if (walk)
         GD_TRY(launch_border_walk(g, co, t, L.cell_label, st));
     else
@@ -856,7 +875,7 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
     const gd_stats& e = ctx->last;
     Plan p{};
     const int kb = std::max(ctx->last_key_bits, 1);
-    p.key_bits = std::min((kb + 7) / 8 * 8, kb <= 32 ? 32 : 64);
+    p.key_bits = std::min((kb + 7) / 8 * 8, kb <= 32 ? 32 : kb <= 64 ? 64 : kMaxKeyBits);
     p.ncell = std::min<int64_t>(n, e.grids + e.grids / 16 + 1024);
     p.nei = (uint64_t)e.neighbor_entries + (uint64_t)e.neighbor_entries / 16 + 4096;
     p.ncc = std::min<int64_t>(p.ncell, e.core_grids + e.core_grids / 16 + 256);
@@ -879,8 +898,8 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
         }
     } inval{ctx, gen0};
     if (grow(ctx, ctx->cur->nei, (size_t)std::max<uint64_t>(p.nei, 1) * sizeof(uint32_t), ctx->cur->arena.cap) ||
-        grow(ctx, ctx->cur->table, output_table_bytes(table_bits(p.ncell), p.key_bits <= 32 ? 4 : 8),
-             ctx->cur->arena.cap + ctx->cur->nei.cap) ||
+        (p.key_bits <= 64 && grow(ctx, ctx->cur->table, output_table_bytes(table_bits(p.ncell), key_bytes_of(p.key_bits)),
+                                  ctx->cur->arena.cap + ctx->cur->nei.cap)) ||
         (ctx->proposal_on && grow(ctx, ctx->cur->sumbuf, sizeof(CellSummary) * (size_t)std::max<int64_t>(p.ncell, 1),
                                   ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->table.cap))) {
         ctx->err = saved_err;

@@ -113,6 +113,33 @@ template hipError_t launch_output_direct<uint32_t>(const GridView&, const CoreOu
 template hipError_t launch_output_direct<uint64_t>(const GridView&, const CoreOut&, const uint64_t*, const uint64_t*,
                                                    const int32_t*, void*, int, hipStream_t);
 
+// All-core grids without the hash table (identifiers of two words): their
+// points' labels go out through the sort permutation, one thread per grid.
+__global__ __launch_bounds__(kBlock) void output_allcore_kernel(GridView gv, CoreOut co,
+                                                                const int32_t* __restrict__ cell_label) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= (int64_t)*gv.ncell_dev) return;
+    const uint32_t st = gv.cell_start[c];
+    const uint32_t k = gv.cell_start[c + 1] - st;
+    if (co.core_cnt[c] != k) return;  // grids with a non-core point: the border pass
+    const Inst& I = cell_inst(gv, c);
+    const uint32_t off = (uint32_t)I.off;
+    int32_t GD_GLOBAL* __restrict__ labels = as_global(I.labels);
+    uint8_t GD_GLOBAL* __restrict__ flags = as_global(I.core);
+    const int32_t lab = cell_label[c] - (int32_t)off;
+    for (uint32_t s = st; s < st + k; ++s) {
+        const uint32_t o = gv.sidx[s] - off;
+        labels[o] = lab;
+        flags[o] = 1;
+    }
+}
+
+hipError_t launch_output_allcore(const GridView& g, const CoreOut& c, const int32_t* cell_label, hipStream_t st) {
+    if (g.ncell == 0) return hipSuccess;
+    output_allcore_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, cell_label);
+    return hipGetLastError();
+}
+
 size_t output_table_bytes(int bits, int key_bytes) {
     return (size_t)((1ll << bits) + 1) * (key_bytes == 4 ? 8 : 16);
 }

@@ -32,6 +32,48 @@ __device__ __forceinline__ T GD_GLOBAL* as_global(T* p) {
     return (T GD_GLOBAL*)p;
 }
 
+// Packed grid identifiers wider than 64 bits (d dimensions of up to ~18
+// bits each): two words, with the few operators the identifier, sort and
+// grid-run code applies to its key type.
+struct Key128 {
+    uint64_t lo, hi;
+    Key128() = default;
+    __host__ __device__ constexpr Key128(uint64_t v) : lo(v), hi(0) {}
+    __host__ __device__ constexpr Key128(uint64_t l, uint64_t h) : lo(l), hi(h) {}
+    __host__ __device__ friend bool operator==(const Key128& a, const Key128& b) { return a.lo == b.lo && a.hi == b.hi; }
+    __host__ __device__ friend bool operator!=(const Key128& a, const Key128& b) { return !(a == b); }
+    __host__ __device__ Key128 operator~() const { return Key128(~lo, ~hi); }
+    __host__ __device__ Key128 operator|(const Key128& o) const { return Key128(lo | o.lo, hi | o.hi); }
+    __host__ __device__ Key128 operator&(const Key128& o) const { return Key128(lo & o.lo, hi & o.hi); }
+    __host__ __device__ Key128& operator|=(const Key128& o) {
+        lo |= o.lo;
+        hi |= o.hi;
+        return *this;
+    }
+    __host__ __device__ Key128 operator<<(int s) const {
+        if (s <= 0) return *this;
+        if (s >= 128) return Key128(0, 0);
+        if (s >= 64) return Key128(0, lo << (s - 64));
+        return Key128(lo << s, (hi << s) | (lo >> (64 - s)));
+    }
+    __host__ __device__ Key128 operator>>(int s) const {
+        if (s <= 0) return *this;
+        if (s >= 128) return Key128(0, 0);
+        if (s >= 64) return Key128(hi >> (s - 64), 0);
+        return Key128((lo >> s) | (hi << (64 - s)), hi >> s);
+    }
+    __host__ __device__ explicit operator uint32_t() const { return (uint32_t)lo; }
+    __host__ __device__ explicit operator uint64_t() const { return lo; }
+};
+
+// Field of `bits` bits at `shift` of a packed identifier (0 beyond its width).
+template <typename K>
+__host__ __device__ __forceinline__ uint64_t key_field(K key, int shift, int bits) {
+    if (shift >= (int)(8 * sizeof(K))) return 0;
+    const uint64_t v = (uint64_t)(key >> shift);
+    return bits >= 64 ? v : (v & ((1ull << bits) - 1ull));
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }

@@ -19,12 +19,13 @@ namespace gd {
 constexpr int kMaxD = 8;
 constexpr int kMaxLevels = kMaxD + 1;  // grid tree: instance level + one level per dimension
 constexpr int kPointTile = 4096;       // default points per workgroup in the point-indexed kernels
+constexpr int kMaxKeyBits = 128;       // packed grid identifiers: one word (<= 64 bits) or two
 
 // Error bits raised by kernels into the device error word.
 enum : uint32_t {
     kErrNotInteger = 1u,    // a coordinate is not a finite integer of magnitude <= 2^24
     kErrMergeRunaway = 2u,  // FastMerging exceeded its iteration bound (cannot happen; checked anyway)
-    kErrKeyBits = 4u,       // packed identifiers need more than 64 bits
+    kErrKeyBits = 4u,       // packed identifiers need more than kMaxKeyBits bits
     kErrNeiOverflow = 8u,   // neighbour lists exceed the buffer given to a sync-free run
     kErrCoreCap = 16u,      // a grid's core set exceeds the merge step's LDS bitmap
     kErrPlan = 32u,         // a sync-free run met more data than it was planned for (or bad input)
@@ -305,5 +306,8 @@ template <typename K>
 hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* keys_in, const K* skeys,
                                 const int32_t* cell_label, void* table, int bits, hipStream_t st);
 size_t output_table_bytes(int bits, int key_bytes);
+// All-core grids of identifiers wider than 64 bits: output through the
+// sort permutation (no hash table).
+hipError_t launch_output_allcore(const GridView& g, const CoreOut& c, const int32_t* cell_label, hipStream_t st);
 
 }  // namespace gd

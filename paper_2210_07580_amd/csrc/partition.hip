@@ -236,7 +236,7 @@ __device__ void batch_layout(const Batch& b, int max_bits, uint32_t err, int pla
     const int inst_bits = bit_length_u64((uint64_t)(b.count - 1));
     b.hdr->inst_shift = max_bits;
     b.hdr->total_bits = max_bits + inst_bits;
-    if (max_bits + inst_bits > 64) err |= kErrKeyBits;
+    if (max_bits + inst_bits > kMaxKeyBits) err |= kErrKeyBits;
     if (max_bits + inst_bits > plan_bits) err |= kErrPlan;
     b.hdr->err = err;
 }
@@ -423,11 +423,14 @@ __device__ __forceinline__ void keys_tile(const Inst& I, int64_t lo, int64_t hi,
                 u4* ko = reinterpret_cast<u4*>(out + i0);
                 if constexpr (sizeof(K) == 4) {
                     ko[0] = u4{(uint32_t)kk[0], (uint32_t)kk[1], (uint32_t)kk[2], (uint32_t)kk[3]};
-                } else {
+                } else if constexpr (sizeof(K) == 8) {
                     ko[0] = u4{(uint32_t)kk[0], (uint32_t)((uint64_t)kk[0] >> 32), (uint32_t)kk[1],
                                (uint32_t)((uint64_t)kk[1] >> 32)};
                     ko[1] = u4{(uint32_t)kk[2], (uint32_t)((uint64_t)kk[2] >> 32), (uint32_t)kk[3],
                                (uint32_t)((uint64_t)kk[3] >> 32)};
+                } else {
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) out[i0 + p] = kk[p];  // one 16-byte store each
                 }
                 if (vals) {
                     u4* vo = reinterpret_cast<u4*>(vals + I.off + i0);
@@ -484,6 +487,7 @@ hipError_t launch_keys(const Batch& b, K* keys, uint64_t* vals, hipStream_t st) 
 }
 template hipError_t launch_keys<uint32_t>(const Batch&, uint32_t*, uint64_t*, hipStream_t);
 template hipError_t launch_keys<uint64_t>(const Batch&, uint64_t*, uint64_t*, hipStream_t);
+template hipError_t launch_keys<Key128>(const Batch&, Key128*, uint64_t*, hipStream_t);
 
 // Sorted rows without the random gather: the sort carried each point's
 // index and the low B = pack_bits(d) bits of its coordinates u_j = x_j -
@@ -639,8 +643,8 @@ struct CellWriter {
         int k = 0;
         if (b.count > 1) {
             const int ishift = b.hdr->inst_shift;
-            k = ishift >= 64 ? 0 : (int)min((uint64_t)key >> ishift, (uint64_t)(b.count - 1));
-            if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min((uint64_t)key, (uint64_t)(b.count - 1));
+            k = (int)min(key_field(key, ishift, 64), (uint64_t)(b.count - 1));
+            if (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan)) k = (int)min(key_field(key, 0, 64), (uint64_t)(b.count - 1));
         }
         const Inst& I = b.inst[k];
         const int d = I.d;
@@ -648,11 +652,7 @@ struct CellWriter {
 #pragma unroll
         for (int j = 0; j < kMaxD; ++j) {
             v[j] = 0;
-            if (j < b.D && j < d) {
-                const int bits = I.bits[j];
-                const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
-                v[j] = (int32_t)(((uint64_t)key >> I.shift[j]) & mask);
-            }
+            if (j < b.D && j < d) v[j] = (int32_t)key_field(key, I.shift[j], I.bits[j]);
         }
         cell_start[c] = (uint32_t)s;
         ck[c] = k;
@@ -673,6 +673,8 @@ template hipError_t launch_cells<uint32_t>(const Batch&, const uint32_t*, uint32
                                            int64_t, hipStream_t);
 template hipError_t launch_cells<uint64_t>(const Batch&, const uint64_t*, uint32_t*, uint32_t*, int32_t*,
                                            int64_t, hipStream_t);
+template hipError_t launch_cells<Key128>(const Batch&, const Key128*, uint32_t*, uint32_t*, int32_t*, int64_t,
+                                         hipStream_t);
 
 // A grid starts a new node at level l iff it differs from the previous grid
 // in one of the identifier rows 0..l (grids are in lexicographic order).

@@ -42,8 +42,11 @@ constexpr int radix_max_bits() { return 8; }
 template <typename K>
 constexpr int radix_max_bins() { return 1 << radix_max_bits<K>(); }
 
-inline int radix_items(int64_t n, int value_bytes = 4) {
-    return n <= kRadixSmallMax ? kRadixItemsSmall : value_bytes > 4 ? kRadixItemsWide : kRadixItemsBig;
+// Two-word identifiers take the 2048-key tiles too (a 4096-key tile of them
+// with their values would not fit the LDS).
+inline int radix_items(int64_t n, int value_bytes = 4, int key_bytes = 4) {
+    return n <= kRadixSmallMax ? kRadixItemsSmall
+                               : (value_bytes > 4 || key_bytes > 8) ? kRadixItemsWide : kRadixItemsBig;
 }
 inline int64_t radix_tiles(int64_t n, int value_bytes = 4) {
     const int64_t tile = (int64_t)kBlock * radix_items(n, value_bytes);
@@ -268,14 +271,14 @@ hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t 
     K* kout = keys_alt;
     V* vout = vals_alt;
     bool first = true;
-    const int64_t tiles = radix_tiles(n, (int)sizeof(V));
+    const int items = radix_items(n, (int)sizeof(V), (int)sizeof(K));
+    const int64_t tiles = (n + (int64_t)kBlock * items - 1) / ((int64_t)kBlock * items);
     uint32_t* hist = scratch;
     uint32_t* offs = scratch + (int64_t)radix_max_bins<uint32_t>() * tiles;
     uint32_t* partial = offs + (int64_t)radix_max_bins<uint32_t>() * tiles;
     bool iota = vals_iota;
     const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
     const int rbits = passes ? (bits + passes - 1) / passes : 0;
-    const int items = radix_items(n, (int)sizeof(V));
     for (int p = 0, shift = 0; p < passes; ++p, shift += rbits) {
         if (n == 0) break;
         const int64_t bins = (int64_t)1 << rbits;

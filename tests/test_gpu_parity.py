@@ -80,8 +80,8 @@ def test_random_small_vs_brute(ctx, seed):
     if n > 6:
         x[: n // 5] = x[n // 5: 2 * (n // 5)]  # duplicates
     eps = int(rng.integers(1, max(2, domain // 4)))
-    while sum(int(v).bit_length() for v in steps.cell_ids(x, eps).max(axis=0)) > 64:
-        eps += 1  # packed identifiers must fit 64 bits
+    while sum(int(v).bit_length() for v in steps.cell_ids(x, eps).max(axis=0)) > 128:
+        eps += 1  # packed identifiers must fit two words
     minpts = int(rng.choice([1, 2, 3, 5, 9, 17, max(1, n // 3), n + 1]))
     print(f"case seed={seed} n={n} d={d} eps={eps} minpts={minpts}", flush=True)
     assert_same(gpu_dbscan(ctx, x, eps, minpts), oracle.dbscan_brute(x, eps, minpts), f"seed {seed}")
@@ -284,7 +284,7 @@ def test_error_paths(ctx, G):
     with pytest.raises(G.GDError) as e:
         ctx.dbscan(nan, 5, 2)
     assert e.value.status == G.GD_ERANGE
-    # identifiers wider than 64 bits: 8 dimensions spanning 2^25 with eps = 1
+    # identifiers wider than 128 bits: 8 dimensions spanning 2^25 with eps = 1 (about 216 bits)
     wide = torch.zeros((2, 8), dtype=torch.float32, device="cuda")
     wide[1] = float(1 << 24)
     wide[0] = -float(1 << 24)

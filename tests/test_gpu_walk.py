@@ -60,7 +60,7 @@ def test_random_small_vs_brute(walk_ctx, seed):
     if n > 6:
         x[: n // 5] = x[n // 5: 2 * (n // 5)]  # duplicates
     eps = int(rng.integers(1, max(2, domain // 4)))
-    while sum(int(v).bit_length() for v in steps.cell_ids(x, eps).max(axis=0)) > 64:
+    while sum(int(v).bit_length() for v in steps.cell_ids(x, eps).max(axis=0)) > 128:
         eps += 1
     minpts = int(rng.choice([1, 2, 3, 5, 9, 17, max(1, n // 3), n + 1]))
     print(f"case seed={seed} n={n} d={d} eps={eps} minpts={minpts}", flush=True)
