@@ -128,10 +128,13 @@ void gd_destroy(gd_ctx *ctx);
  * bad sizes, a non-integer or non-positive eps, minpts < 1 or NULL
  * pointers; GD_ERANGE for a coordinate that is not a finite integer of
  * magnitude <= 2^24, or for grid identifiers that would need more than 128
- * bits (eps too small for the data's extent); GD_EUNSUPPORTED if one grid
- * holds more than 262144 core points (the merge step keeps each core set
- * as a bitmap in LDS); GD_ENOMEM if the workspace cannot be allocated or
- * exceeds GD_OPT_WORKSPACE_LIMIT; GD_EDEVICE for a failed HIP call.
+ * bits (eps too small for the data's extent); GD_ENOMEM if the workspace
+ * cannot be allocated or exceeds GD_OPT_WORKSPACE_LIMIT; GD_EDEVICE for a
+ * failed HIP call.
+ *
+ * Core sets of more than 262144 points (beyond the merge kernels' LDS
+ * bitmaps) are merged by a second pass with bitmaps in device memory; such
+ * calls run eagerly (no graph replay).
  */
 int dbscan(gd_ctx *ctx, const float *points, int64_t n, int32_t d, double eps,
            int32_t minpts, int32_t *labels, uint8_t *core_flags, void *stream);

@@ -42,6 +42,15 @@ struct Bufs {
     DevBuf nei;     // the neighbour lists, sized by their total
     DevBuf table;   // identifier -> label hash table of the output pass
     DevBuf sumbuf;  // CellSummary per grid (learned proposal)
+    DevBuf huge;    // queue and device-memory bitmaps for core sets beyond the LDS bitmaps
+};
+
+// Pairs with a core set beyond the LDS bitmaps: the queue the merge kernels
+// fill and the bitmaps of the waves that drain it.
+struct HugeMerge {
+    HugeQueue q{};
+    uint64_t* slabs = nullptr;
+    uint32_t words = 0, waves = 0;
 };
 
 enum Phase {
@@ -395,8 +404,8 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
 // followed by breadth-first levels until the frontier is empty; every level
 // reads its frontier size back (an eager run only).
 int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* nei_off, const uint32_t* nei,
-            int64_t max_core, uint32_t* state, uint32_t* front, uint32_t* next, uint32_t* cnt, uint32_t* parent,
-            MergeStats* stats, hipStream_t st) {
+            int64_t max_core, const HugeMerge& hm, uint32_t* state, uint32_t* front, uint32_t* next, uint32_t* cnt,
+            uint32_t* parent, MergeStats* stats, hipStream_t st) {
     GD_TRY(fill<uint32_t>(state, g.ncell, 0u, st));
     uint32_t h[3];
     for (;;) {
@@ -408,7 +417,11 @@ int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* n
         uint32_t nf = h[1];
         while (nf > 0) {
             GD_TRY(fill<uint32_t>(cnt + 2, 1, 0u, st));
-            GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, state, parent, stats, st));
+            if (hm.q.pairs) GD_TRY(fill<uint32_t>(hm.q.count, 1, 0u, st));
+            GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, hm.q, state, parent, stats,
+                                    st));
+            GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, true, state, next, cnt, parent, stats,
+                                     st));
             GD_TRY(hipMemcpyAsync(h + 2, cnt + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             GD_TRY(hipStreamSynchronize(st));
             nf = h[2];
@@ -627,10 +640,35 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     const int64_t ncore = plan ? 0 : (int64_t)H->counts[0];
     const int64_t ncc = plan ? plan->ncc : (int64_t)H->counts[1];
     const int64_t max_core = plan ? plan->max_core : (int64_t)H->counts[2];
-    if (max_core > kMaxCoreBits)
-        return ctx->fail(GD_EUNSUPPORTED, "a grid holds %lld core points; the merge step handles at most %lld",
-                         (long long)max_core, (long long)kMaxCoreBits);
     if (walk && (rc = build_lists(L.core_cnt, false))) return rc;
+    // core sets beyond the LDS bitmaps (never in a planned run: its plan
+    // caps them, and a replay that meets one runs again eagerly)
+    HugeMerge hm;
+    if (!plan && max_core > kMaxCoreBits) {
+        unsigned long long lists = 0;
+        GD_TRY(fill<unsigned long long>(ctx->counter_dev, 1, 0ull, st));
+        GD_TRY(launch_huge_scan(g, co, L.nei_off, ctx->counter_dev, st));
+        GD_TRY(hipMemcpyAsync(&lists, ctx->counter_dev, sizeof(lists), hipMemcpyDeviceToHost, st));
+        GD_TRY(hipStreamSynchronize(st));
+        const uint64_t cap = 2 * (uint64_t)lists + 64;
+        if (cap > 0xffffffffull)
+            return ctx->fail(GD_EUNSUPPORTED, "%llu neighbour pairs of oversized core sets", (unsigned long long)cap);
+        hm.words = (uint32_t)((max_core + kWave - 1) / kWave);
+        const size_t slab = (size_t)2 * hm.words * sizeof(uint64_t);
+        // as many waves as pairs, up to 1024 and 256 MiB of bitmaps
+        const uint64_t w = std::min<uint64_t>(std::min<uint64_t>(cap, 1024), std::max<size_t>((256u << 20) / slab, 4));
+        hm.waves = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock);
+        const size_t qbytes = align_up(cap * sizeof(uint2) + sizeof(uint32_t));
+        if ((rc = grow(ctx, ctx->cur->huge, qbytes + (size_t)hm.waves * slab,
+                       ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->table.cap + ctx->cur->sumbuf.cap)))
+            return rc;
+        char* b = (char*)ctx->cur->huge.p;
+        hm.q.pairs = (uint2*)b;
+        hm.q.cap = (uint32_t)cap;
+        hm.q.count = (uint32_t*)(b + cap * sizeof(uint2));
+        hm.slabs = (uint64_t*)(b + qbytes);
+        GD_TRY(fill<uint32_t>(hm.q.count, 1, 0u, st));
+    }
 
     // ---- merging (Algorithm 5 + union-find, LDF order)
     uint32_t* ldf = nullptr;
@@ -649,7 +687,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
             // Algorithm 6's order: the free sort buffers hold the grid states
             // and the two frontiers, the radix scratch the counters
             ctx->mark(P_MERGE, 0);
-            rc = run_bfs(ctx, g, co, L.nei_off, nei, max_core, ka, kb, vb, L.radix_scratch, L.parent,
+            rc = run_bfs(ctx, g, co, L.nei_off, nei, max_core, hm, ka, kb, vb, L.radix_scratch, L.parent,
                          stats ? ctx->stats_dev->merge : nullptr, st);
             if (rc) return rc;
             ctx->mark(P_MERGE, 1);
@@ -673,8 +711,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if (walk)
             GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
         GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves, walk,
-                            L.parent, stats ? ctx->stats_dev->merge : nullptr,
+                            hm.q, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                             ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
+        GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, false, nullptr, nullptr, nullptr,
+                                 L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
         ctx->mark(P_MERGE, 1);
     }
     ctx->mark(P_LABELS, 0);
@@ -685,7 +725,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     const int hbits = table_bits(ncell);
     if (!plan && kbytes <= 8 &&
         (rc = grow(ctx, ctx->cur->table, output_table_bytes(hbits, kbytes),
-                   ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap)))
+                   ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap + ctx->cur->huge.cap)))
         return rc;
     ctx->mark(P_OUTPUT, 0);
     if (kbytes == 4)
@@ -872,6 +912,7 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
 // Failure to capture is not an error: the call's result is already there.
 void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std::vector<int64_t>&& sig) {
     drop_graph(ctx);
+    if (ctx->last_max_core > kMaxCoreBits) return;  // oversized core sets run eagerly
     const gd_stats& e = ctx->last;
     Plan p{};
     const int kb = std::max(ctx->last_key_bits, 1);
@@ -1013,6 +1054,7 @@ void gd_destroy(gd_ctx* ctx) {
     if (ctx->counter_dev) (void)hipFree(ctx->counter_dev);
     if (ctx->own.sumbuf.p) (void)hipFree(ctx->own.sumbuf.p);
     if (ctx->own.table.p) (void)hipFree(ctx->own.table.p);
+    if (ctx->own.huge.p) (void)hipFree(ctx->own.huge.p);
     drop_graph(ctx);
     if (ctx->gev) (void)hipEventDestroy(ctx->gev);
     if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);

@@ -244,8 +244,17 @@ constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats
 struct MergeStats {
     unsigned long long pairs, skipped, tests, yes, iters, max_iters, dists, set_points;
 };
-// Largest core set a grid may hold (LDS bitmaps of the merge step).
+// Largest core set the merge kernels' LDS bitmaps hold.  A pair with a
+// larger set is queued (HugeQueue) and tested by merge_huge_kernel, whose
+// bitmaps live in device memory.
 constexpr int64_t kMaxCoreBits = 262144;
+// Pairs (g_i, g_j) deferred by the LDS kernels.  pairs == nullptr: no queue
+// (a planned run); meeting a larger set then raises kErrCoreCap.
+struct HugeQueue {
+    uint2* pairs;
+    uint32_t cap;
+    uint32_t* count;  // appended so far (may pass cap: then kErrCoreCap is raised)
+};
 struct CellSummary;
 // waves: waves per workgroup of the FastMerging kernel (1, 2 or 4; fewer
 // if the LDS bitmaps do not fit).  n_small: tiny core grids leading the
@@ -253,8 +262,19 @@ struct CellSummary;
 // tiny_done: the pairs of two tiny core sets were already merged (walk mode).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, int waves, bool tiny_done, uint32_t* parent, MergeStats* stats,
-                        const __half* proposal, const CellSummary* sum, hipStream_t st);
+                        int64_t max_core, int waves, bool tiny_done, const HugeQueue& huge, uint32_t* parent,
+                        MergeStats* stats, const __half* proposal, const CellSummary* sum, hipStream_t st);
+// Sum over core grids with more than kMaxCoreBits core points of |Nei(g)| + 1
+// (added to *sum; the caller clears it): with both orders no pair is queued
+// twice from one side, so twice this bounds the queue.
+hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t* nei_off, unsigned long long* sum,
+                            hipStream_t st);
+// Tests the queued pairs (FastMerging, union on yes) with `waves` waves, each
+// with 2 * words words of device memory at slabs.  bfs: the pair's second grid
+// is claimed for the search (state, next, cnt[2]) as in the BFS level kernel.
+hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
+                             uint32_t words, uint32_t waves, bool bfs, uint32_t* state, uint32_t* next,
+                             uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st);
 // The BFS order of Algorithm 6 (GD_OPT_MERGE_ORDER = 2), on the full lists.
 // state: ncell u32, cleared to 0 for every grid first.  cnt: 3 u32 (the
 // caller clears them): cnt[0] unclassified core grids seen by the seed pass,
@@ -263,7 +283,8 @@ hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t*
                             uint32_t* state, uint32_t* front, uint32_t* cnt, hipStream_t st);
 hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                             const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
-                            uint32_t* state, uint32_t* parent, MergeStats* stats, hipStream_t st);
+                            const HugeQueue& huge, uint32_t* state, uint32_t* parent, MergeStats* stats,
+                            hipStream_t st);
 // pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
                               int64_t npairs, int64_t eps, uint32_t max_count, uint8_t* answers, uint32_t* iterations,

@@ -153,6 +153,17 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     }
 }
 
+// Queues the pair (g_i, g_j) for merge_huge_kernel (one lane appends).
+__device__ __forceinline__ void defer_pair(const HugeQueue& q, uint32_t ci, uint32_t cj, Header* hdr) {
+    if (lane_id() == 0) {
+        const uint32_t k = q.pairs ? atomicAdd(q.count, 1u) : q.cap;
+        if (k < q.cap)
+            q.pairs[k] = make_uint2(ci, cj);
+        else
+            atomicOr(&hdr->err, kErrCoreCap);
+    }
+}
+
 // Every other pair: one wave per core grid g_i with more than kSmallSet core
 // points, in the visiting order.  It takes the neighbouring core grids g_j
 // that are tiny (those pairs are tested from this side) or that come later
@@ -183,8 +194,8 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
                                                            const uint4* __restrict__ rank, int64_t r0, int64_t r1,
-                                                           const uint32_t* split, uint32_t words, uint32_t* parent,
-                                                           MergeStats* stats, Proposal prop) {
+                                                           const uint32_t* split, uint32_t words, HugeQueue huge,
+                                                           uint32_t* parent, MergeStats* stats, Proposal prop) {
     extern __shared__ uint64_t smem[];
     using Weights = typename std::conditional<kLearned, MlpMfma, float>::type;
     using Scratch = typename std::conditional<kLearned, MlpMfmaScratch, float>::type;
@@ -211,7 +222,9 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, own.y, own.z, smem + (int64_t)w * 2 * words, 0};
     if (si.m <= kSmallSet) return;
-    if (si.m > 64u * words) {  // larger than the LDS bitmaps this launch was given
+    // larger than the LDS bitmaps this launch was given: every pair is queued
+    const bool si_huge = si.m > 64u * words;
+    if (si_huge && !huge.pairs) {
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
         return;
     }
@@ -296,8 +309,8 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
             sj.base = readlane(bj, l);
             sj.m = readlane(mj, l);
             sj.words = (sj.m + kWave - 1) / kWave;
-            if (sj.m > 64u * words) {
-                if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
+            if (si_huge || sj.m > 64u * words) {
+                defer_pair(huge, ci, readlane(cj, l), gv.b.hdr);
                 continue;
             }
             uint32_t it = 0;
@@ -341,8 +354,8 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
-                        int waves, bool tiny_done, uint32_t* parent, MergeStats* stats, const __half* proposal,
-                        const CellSummary* sum, hipStream_t st) {
+                        int waves, bool tiny_done, const HugeQueue& huge, uint32_t* parent, MergeStats* stats,
+                        const __half* proposal, const CellSummary* sum, hipStream_t st) {
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
     // n_small >= 0: the visiting order puts the n_small tiny core grids first
@@ -359,7 +372,7 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                                g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
-    const uint32_t words = (uint32_t)((max_core + kWave - 1) / kWave);
+    const uint32_t words = (uint32_t)((std::min<int64_t>(max_core, kMaxCoreBits) + kWave - 1) / kWave);
     int wpb = std::max(1, std::min(waves, kWavesPerBlock));
     while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
     const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
@@ -371,10 +384,10 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                                                                                  sizeof(float2) * kWave) <= 65536;
     if (learned) {
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, parent, stats, prop)));
+                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     } else {
         GD_DISPATCH_D(g.D, (merge_big_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, parent, stats, prop)));
+                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     }
     return hipGetLastError();
 }
@@ -432,7 +445,8 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ front, uint32_t nfront,
                                                            uint32_t* __restrict__ next, uint32_t* cnt, uint32_t words,
-                                                           uint32_t* state, uint32_t* parent, MergeStats* stats) {
+                                                           HugeQueue huge, uint32_t* state, uint32_t* parent,
+                                                           MergeStats* stats) {
     extern __shared__ uint64_t smem[];
     const int lane = lane_id();
     const int wpb = (int)(blockDim.x / kWave);
@@ -445,7 +459,8 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
     si.words = (si.m + kWave - 1) / kWave;
-    if (si.m > 64u * words) {
+    const bool si_huge = si.m > 64u * words;  // every pair is queued
+    if (si_huge && !huge.pairs) {
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
         return;
     }
@@ -480,13 +495,13 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
             sj.base = co.core_begin[cjl];
             sj.m = readlane(mj, l);
             sj.words = (sj.m + kWave - 1) / kWave;
-            if (sj.m > 64u * words) {
-                if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
-                continue;
-            }
             // a union since this round's roots were read may have joined them
             if (uf_find(parent, cjl) == uf_find(parent, ri) && load_acq(&state[cjl]) == kBfsClassified) {
                 ++n_skip;
+                continue;
+            }
+            if (si_huge || sj.m > 64u * words) {
+                defer_pair(huge, ci, cjl, gv.b.hdr);
                 continue;
             }
             uint32_t it = 0;
@@ -526,16 +541,104 @@ hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t*
 
 hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                             const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
-                            uint32_t* state, uint32_t* parent, MergeStats* stats, hipStream_t st) {
+                            const HugeQueue& huge, uint32_t* state, uint32_t* parent, MergeStats* stats,
+                            hipStream_t st) {
     if (nfront == 0) return hipSuccess;
-    const uint32_t words = (uint32_t)((std::max<int64_t>(max_core, 1) + kWave - 1) / kWave);
+    const uint32_t words =
+        (uint32_t)((std::min<int64_t>(std::max<int64_t>(max_core, 1), kMaxCoreBits) + kWave - 1) / kWave);
     int wpb = kWavesPerBlock;
     while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
     const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nfront + wpb - 1) / wpb);
     GD_DISPATCH_D(g.D, (bfs_level_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                           g, c, nei_off, nei, front, nfront, next, cnt, words, state, parent, stats)));
+                           g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
+    return hipGetLastError();
+}
+
+// ---- Core sets larger than the LDS bitmaps.  The merge and BFS kernels
+// queue every pair with such a set; the queue is then drained here with the
+// two bitmaps of a test in device memory (a slab of 2 * words words per
+// wave; each wave owns its slab, and the fences of wave_sync order its
+// lanes' accesses as they do in LDS).  The union-find makes the components
+// independent of the order of the tests (Theorem 4), so deferring a pair
+// changes no answer.
+
+__global__ __launch_bounds__(kBlock) void huge_scan_kernel(const uint32_t* ncell, const uint32_t* __restrict__ core_cnt,
+                                                           const uint64_t* __restrict__ nei_off,
+                                                           unsigned long long* sum) {
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c < (int64_t)*ncell && core_cnt[c] > (uint32_t)kMaxCoreBits)
+        atomicAdd(sum, (unsigned long long)(nei_off[c + 1] - nei_off[c] + 1));
+}
+
+// Persistent: wave k takes queued pairs k, k + waves, ... (every wave leaves
+// once it passes the queue's length, read once at entry).
+template <int D>
+__global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut co, HugeQueue q, uint64_t* slabs,
+                                                            uint32_t words, uint32_t waves, int bfs,
+                                                            uint32_t* state, uint32_t* next, uint32_t* cnt,
+                                                            uint32_t* parent, MergeStats* stats) {
+    const int lane = lane_id();
+    const int64_t wg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (wg >= (int64_t)waves) return;
+    const uint32_t npairs = min(*q.count, q.cap);
+    uint64_t* bits = slabs + wg * 2 * (int64_t)words;
+    unsigned long long n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
+    for (int64_t k = wg; k < (int64_t)npairs; k += waves) {
+        const uint2 pr = q.pairs[k];
+        const uint32_t ci = pr.x, cj = pr.y;
+        const uint32_t ri = uf_find(parent, ci), rj = uf_find(parent, cj);
+        if (ri == rj && (!bfs || load_acq(&state[cj]) == kBfsClassified)) {
+            ++n_skip;
+            continue;
+        }
+        const Inst& I = cell_inst(gv, ci);
+        PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], bits, 0};
+        PointSet sj{co.ccrd, co.core_begin[cj], co.core_cnt[cj], bits + words, 0};
+        si.words = (si.m + kWave - 1) / kWave;
+        sj.words = (sj.m + kWave - 1) / kWave;
+        if (si.words > words || sj.words > words) {
+            if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
+            continue;
+        }
+        uint32_t it = 0;
+        const int yes = fast_merging<D>(si, sj, 0u, I.T, I.Tm, (double)I.eps, n_dist, it);
+        ++n_test;
+        n_pts += si.m + sj.m;
+        n_iter += it;
+        max_it = it > max_it ? it : max_it;
+        if (yes < 0) {
+            if (lane == 0) atomicOr(&gv.b.hdr->err, kErrMergeRunaway);
+            continue;
+        }
+        if (yes) {
+            ++n_yes;
+            if (lane == 0) {
+                if (bfs && atomicCAS(&state[cj], kBfsNew, kBfsClassified) == kBfsNew)
+                    next[atomicAdd(&cnt[2], 1u)] = cj;
+                (void)uf_union_from(parent, uf_find(parent, ri), uf_find(parent, rj));
+            }
+        }
+        wave_sync();
+    }
+    if (stats && lane == 0) flush_stats(stats, wg, 0ull, n_skip, n_test, n_yes, n_iter, max_it, n_dist, n_pts);
+}
+
+hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t* nei_off, unsigned long long* sum,
+                            hipStream_t st) {
+    if (g.ncell == 0) return hipSuccess;
+    huge_scan_kernel<<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g.ncell_dev, c.core_cnt, nei_off, sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
+                             uint32_t words, uint32_t waves, bool bfs, uint32_t* state, uint32_t* next,
+                             uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st) {
+    if (!huge.pairs || waves == 0) return hipSuccess;
+    const unsigned blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    GD_DISPATCH_D(g.D, (merge_huge_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                           g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
     return hipGetLastError();
 }
 
