@@ -10,6 +10,12 @@ The K timed steps run the plain call; per-phase durations (for the
 rooflines) come from K more steps with HIP events around every phase.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload H]
+    python bench.py --sweep FILE [--sweep-dims 2,3,5,7] [--sweep-kinds simden,varden]
+                    [--sweep-axes eps,minpts,n]
+
+--sweep runs the paper's parameter sweeps (running time against eps, MinPts
+and n on seed-spreader data) instead, writes one JSON record per sweep point
+to FILE and prints a one-line summary.
 """
 import argparse
 import json
@@ -339,6 +345,97 @@ def bench_neighbor_modes(G, steps, warmup):
     return out
 
 
+def sweep_points(dims, kinds, axes):
+    """(kind, d, n, eps, minpts) of every sweep point, each once, grouped by
+    point set."""
+    D = W.SWEEP_DEFAULT
+    out = []
+    for kind in kinds:
+        for d in dims:
+            pts = []
+            if "eps" in axes:
+                pts += [(D["n"], e, D["minpts"]) for e in W.SWEEP_EPS]
+            if "minpts" in axes:
+                pts += [(D["n"], D["eps"], m) for m in W.SWEEP_MINPTS]
+            if "n" in axes:
+                pts += [(n, D["eps"], D["minpts"]) for n in W.SWEEP_N]
+            seen = set()
+            for p in sorted(pts):
+                if p not in seen:
+                    seen.add(p)
+                    out.append((kind, d) + p)
+    return out
+
+
+def bench_sweep(G, steps, warmup, dims, kinds, axes, path):
+    """The paper's sweeps (Section 5.2): every point timed with the LDF order
+    (GriT-DBSCAN-LDF) and with the breadth-first searches of Algorithm 6
+    (GriT-DBSCAN); the two must give the same labels (Theorem 4), and where
+    the oracle's digest of a point is stored the labels must equal it."""
+    import hashlib
+    import torch
+    digests = (oracle_digest("sweep") or {})
+    ctxs = {}
+    for order, v in (("ldf", 1), ("bfs", 2)):
+        ctxs[order] = G.Context(0)
+        ctxs[order].set_option(G.GD_OPT_MERGE_ORDER, v)
+    stat_ctx = G.Context(0)
+    stat_ctx.set_option(G.GD_OPT_STATS, 1)
+    cur_key, pts = None, None
+    recs = []
+    with open(path, "w") as f:
+        for kind, d, n, eps, minpts in sweep_points(dims, kinds, axes):
+            w = W.sweep_workload(kind, d, n, eps, minpts)
+            if (kind, d, n) != cur_key:
+                pts = None
+                torch.cuda.empty_cache()
+                log(f"sweep: generating {w.name}")
+                pts = torch.from_numpy(W.make_points(w).astype(np.float32)).cuda()
+                cur_key = (kind, d, n)
+            lab = torch.empty(n, dtype=torch.int32, device="cuda")
+            core = torch.empty(n, dtype=torch.uint8, device="cuda")
+            rec = {"kind": kind, "d": d, "n": n, "eps": eps, "minpts": minpts}
+            ref = None
+            for order, ctx in ctxs.items():
+                ms = []
+                for i in range(warmup + steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ctx.dbscan(pts, eps, minpts, lab, core)
+                    if i >= warmup:
+                        ms.append(1e3 * (time.perf_counter() - t0))
+                rec[f"ms_{order}"] = round(float(np.median(ms)), 3)
+                if ref is None:
+                    ref = (lab.clone(), core.clone())
+                elif not (torch.equal(ref[0], lab) and torch.equal(ref[1], core)):
+                    raise RuntimeError(f"sweep {W.sweep_name(w)}: the BFS order changed the labels")
+            rec["points_per_s_ldf"] = round(n / (rec["ms_ldf"] * 1e-3), 1)
+            stat_ctx.dbscan(pts, eps, minpts, lab, core)
+            st = stat_ctx.stats()
+            l_np = ref[0].cpu().numpy()
+            c_np = ref[1].cpu().numpy()
+            rec.update({"key_bits": st["key_bits"], "grids": st["grids"], "core_grids": st["core_grids"],
+                        "neighbor_entries": st["neighbor_entries"], "neighbor_walk": st["neighbor_walk"],
+                        "merge_tests": st["merge_tests"], "merge_distances": st["merge_distances"],
+                        "clusters": int(np.unique(l_np[l_np >= 0]).size), "core_points": int(c_np.sum()),
+                        "noise_points": int((l_np < 0).sum())})
+            dg = digests.get(W.sweep_name(w))
+            if dg is not None:
+                rec["labels_equal_oracle_digest"] = (
+                    hashlib.sha256(np.ascontiguousarray(l_np.astype("<i4")).tobytes()).hexdigest() ==
+                    dg["labels_sha256"] and
+                    hashlib.sha256(np.ascontiguousarray(c_np.astype(np.uint8)).tobytes()).hexdigest() ==
+                    dg["core_sha256"])
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            recs.append(rec)
+            log(f"sweep: {W.sweep_name(w)} ldf {rec['ms_ldf']} ms bfs {rec['ms_bfs']} ms "
+                f"clusters {rec['clusters']} bits {rec['key_bits']}")
+    for ctx in list(ctxs.values()) + [stat_ctx]:
+        ctx.close()
+    return recs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +448,10 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--neighbor-mode", type=int, default=0, choices=(0, 1, 2),
                     help="GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists for every grid, 2 walks in the consumers")
+    ap.add_argument("--sweep", metavar="FILE", help="run the parameter sweeps, one JSON record per point to FILE")
+    ap.add_argument("--sweep-dims", default="2,3,5,7")
+    ap.add_argument("--sweep-kinds", default="simden,varden")
+    ap.add_argument("--sweep-axes", default="eps,minpts,n")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -361,6 +462,17 @@ def main():
 
     import torch
     import paper_2210_07580_amd as G
+
+    if args.sweep:
+        recs = bench_sweep(G, args.steps, args.warmup, [int(v) for v in args.sweep_dims.split(",")],
+                           args.sweep_kinds.split(","), args.sweep_axes.split(","), args.sweep)
+        checked = [r["labels_equal_oracle_digest"] for r in recs if "labels_equal_oracle_digest" in r]
+        print(json.dumps({"sweep_points": len(recs), "records": args.sweep, "steps": args.steps,
+                          "warmup": args.warmup, "oracle_digests_checked": len(checked),
+                          "oracle_digests_equal": sum(checked),
+                          "total_ms_ldf": round(sum(r["ms_ldf"] for r in recs), 1),
+                          "total_ms_bfs": round(sum(r["ms_bfs"] for r in recs), 1)}))
+        return
 
     if args.copy_calibration:
         src = torch.ones(128 << 20, dtype=torch.int32, device="cuda")

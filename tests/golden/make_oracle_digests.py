@@ -7,9 +7,12 @@ int32 labels and uint8 core flags, and a few counts for diagnosis.
 
     python tests/golden/make_oracle_digests.py cfg1 H cfg4 cfg2 [--threads N]
     python tests/golden/make_oracle_digests.py cfg3 [--threads N]
+    python tests/golden/make_oracle_digests.py ss-varden-7d/n=2000000/eps=500/minpts=100 ...
 
 ``cfg3`` is the 256-instance batch workload: one record per instance, in
-instance order, under the key "cfg3".
+instance order, under the key "cfg3".  Names of the form
+``ss-<kind>-<d>d/n=../eps=../minpts=..`` are points of the parameter sweeps,
+stored under the key "sweep".
 """
 import argparse
 import hashlib
@@ -70,13 +73,18 @@ def main():
             with open(OUT, "w") as f:
                 json.dump(db, f, indent=1, sort_keys=True)
             continue
-        w = W.WORKLOADS[name]
+        sweep = name.startswith("ss-")
+        w = W.sweep_from_name(name) if sweep else W.WORKLOADS[name]
         x = W.make_points(w)
         t0 = time.time()
         labels, core = oracle.dbscan(x, w.eps, w.minpts, nthreads=threads)
         dt = time.time() - t0
-        db[name] = record(w, x, labels, core, dt, threads)
-        print(name, json.dumps(db[name]), flush=True)
+        rec = record(w, x, labels, core, dt, threads)
+        if sweep:
+            db.setdefault("sweep", {})[W.sweep_name(w)] = rec
+        else:
+            db[name] = rec
+        print(name, json.dumps(rec), flush=True)
         with open(OUT, "w") as f:
             json.dump(db, f, indent=1, sort_keys=True)
 

@@ -78,3 +78,24 @@ def test_full_size_matches_oracle_digest(ctx, name):
     # bit-exact against the oracle's stored result
     assert sha(core.astype(np.uint8)) == rec["core_sha256"]
     assert sha(lab.astype("<i4")) == rec["labels_sha256"]
+
+
+def _sweep_keys():
+    return sorted(_digests().get("sweep", {}))
+
+
+@pytest.mark.parametrize("key", _sweep_keys())
+def test_sweep_point_matches_oracle_digest(ctx, key):
+    rec = _digests()["sweep"][key]
+    w = W.sweep_from_name(key)
+    x = W.make_points(w)
+    assert sha(x) == rec["points_sha256"], "generator output changed: regenerate the digests"
+    print(f"case {key}", flush=True)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    lab, core = ctx.dbscan(t, w.eps, w.minpts)
+    lab = lab.cpu().numpy()
+    core = core.cpu().numpy()
+    assert int(core.sum()) == rec["core_points"]
+    assert np.unique(lab[lab >= 0]).size == rec["clusters"]
+    assert sha(core.astype(np.uint8)) == rec["core_sha256"]
+    assert sha(lab.astype("<i4")) == rec["labels_sha256"]

@@ -46,6 +46,7 @@ class Workload:
     step_len: float = 0.0
     ball_radius: float = 0.0
     restart_p: float = 0.0
+    radius_levels: int = 1   # >1: each walk segment scales its ball and step by 2**k, k < levels
 
     def with_n(self, n: int) -> "Workload":
         """Same recipe at a different size (used for small parity cases)."""
@@ -96,17 +97,25 @@ def _spreader(w: Workload, rng: np.random.Generator) -> np.ndarray:
     dirs /= np.maximum(np.linalg.norm(dirs, axis=1, keepdims=True), 1e-300)
     restart = rng.random(steps) < w.restart_p
     jumps = rng.random((steps, w.d)) * L
+    # variable density: a segment between restarts spreads its points over a
+    # ball (and moves by a step) 2**k times the base size; the extra draws
+    # come from a stream of their own so one-level recipes are unchanged
+    scale = np.ones(steps)
+    if w.radius_levels > 1:
+        seg = np.cumsum(restart)
+        k = np.random.default_rng(w.seed + 1).integers(0, w.radius_levels, size=int(seg[-1]) + 1)
+        scale = np.exp2(k[seg])
     centres = np.empty((steps, w.d))
     for s in range(steps):
         if restart[s]:
             loc = jumps[s].copy()
         centres[s] = loc
-        loc = loc + w.step_len * dirs[s]
+        loc = loc + w.step_len * scale[s] * dirs[s]
         # reflect at the walls of the domain
         loc = np.where(loc < 0.0, -loc, loc)
         loc = np.where(loc > L, 2.0 * L - loc, loc)
     owner = np.repeat(np.arange(steps), w.pts_per_step)[:n_walk]
-    walk = centres[owner] + _ball(rng, n_walk, w.d, w.ball_radius)
+    walk = centres[owner] + _ball(rng, n_walk, w.d, w.ball_radius) * scale[owner, None]
     noise = rng.random((n_noise, w.d)) * L
     return np.concatenate([walk, noise], axis=0)
 
@@ -162,6 +171,49 @@ def batch_workloads(count: int = BATCH_COUNT, seed_base: int = BATCH_SEED_BASE):
                             seed=seed + 7, kind="blobs", domain=10_000,
                             n_blobs=10, sigma=200.0, noise_frac=0.10))
     return out
+
+
+# The paper's sweeps (Section 5.2): seed-spreader data in [0, 1e5]^d with
+# similar (simden) or variable (varden) cluster density, d in {2, 3, 5, 7},
+# 2M points unless n is the swept quantity.  Defaults: eps 2000, MinPts 100.
+SWEEP_DIMS = (2, 3, 5, 7)
+SWEEP_KINDS = ("simden", "varden")
+SWEEP_EPS = (500, 1000, 2000, 3000, 4000, 5000)
+SWEEP_MINPTS = (10, 25, 50, 75, 100)
+SWEEP_N = (100_000, 500_000, 2_000_000, 5_000_000, 10_000_000)
+SWEEP_DEFAULT = {"n": 2_000_000, "eps": 2000, "minpts": 100}
+
+
+def sweep_workload(kind: str, d: int, n: int = SWEEP_DEFAULT["n"], eps: int = SWEEP_DEFAULT["eps"],
+                   minpts: int = SWEEP_DEFAULT["minpts"]) -> Workload:
+    """Seed-spreader data of the sweeps.  The spreader emits 100 points
+    uniformly in a ball of radius 100 around its location, then moves
+    50 d in a random direction; it jumps to a uniform random location about
+    ten times over the whole set (so about ten walks, whatever n), and 1e-4
+    of the points are uniform noise.  varden gives each walk a ball radius
+    and step of 1, 2, 4 or 8 times the base.  The points depend on
+    (kind, d, n) only, so an eps or MinPts sweep clusters one point set."""
+    if kind not in SWEEP_KINDS:
+        raise ValueError(f"unknown sweep kind {kind!r}")
+    seed = 20221100 + 100 * SWEEP_KINDS.index(kind) + 10 * d + SWEEP_N.index(n) if n in SWEEP_N else \
+        20221200 + 10 * d + SWEEP_KINDS.index(kind) + n
+    return Workload(f"ss-{kind}-{d}d@n={n}", n=int(n), d=int(d), eps=int(eps), minpts=int(minpts), seed=seed,
+                    kind="spreader", domain=100_000, pts_per_step=100, step_len=50.0 * d, ball_radius=100.0,
+                    restart_p=min(1.0, 10.0 * 100 / max(n, 1)), noise_frac=1e-4,
+                    radius_levels=4 if kind == "varden" else 1)
+
+
+def sweep_name(w: Workload) -> str:
+    """Key of a sweep point: 'ss-<kind>-<d>d/n=<n>/eps=<eps>/minpts=<minpts>'."""
+    return f"{w.name.split('@')[0]}/n={w.n}/eps={w.eps}/minpts={w.minpts}"
+
+
+def sweep_from_name(key: str) -> Workload:
+    """Inverse of sweep_name."""
+    head, *fields = key.split("/")
+    _, kind, dd = head.split("-")
+    kv = dict(f.split("=") for f in fields)
+    return sweep_workload(kind, int(dd[:-1]), int(kv["n"]), int(kv["eps"]), int(kv["minpts"]))
 
 
 def random_small(seed: int, n: int, d: int, domain: int) -> np.ndarray:
