@@ -25,7 +25,9 @@
  * Core flags and labels are therefore unique and bit-exact.
  *
  * Input rules: coordinates are float32 holding integers with |x| <= 2^24;
- * eps is a positive integer (so eps^2 is exact) with eps <= GD_EPS_MAX;
+ * eps is a positive integer (so eps^2 is exact); eps <= GD_EPS_MAX takes
+ * 32-bit squared distances, a larger eps 64-bit ones (any eps above 2^27
+ * clusters as 2^27 does: valid points are never further apart);
  * 1 <= d <= GD_D_MAX; the packed grid identifier (sum over dimensions of
  * the bit length of the largest identifier) must fit 128 bits (identifiers
  * of up to 64 bits are one word, wider ones two).
@@ -45,15 +47,16 @@ extern "C" {
 #endif
 
 #define GD_D_MAX 8
-#define GD_EPS_MAX 21845 /* 9 * eps^2 < 2^32: squared distances between points
-                            of neighbouring grids fit 32 bits exactly */
+#define GD_EPS_MAX 21845 /* largest eps of the 32-bit distance path: 9 eps^2 <
+                            2^32, so squared distances between points of
+                            neighbouring grids fit 32 bits exactly */
 
 typedef enum {
     GD_OK = 0,
     GD_EINVAL = -1,       /* bad argument: NULL pointer, n < 0, d out of range,
                              eps not a positive integer, minpts < 1          */
     GD_ERANGE = -2,       /* a coordinate is not an integer of magnitude <= 2^24,
-                             eps > GD_EPS_MAX, or identifiers need > 128 bits */
+                             or identifiers need > 128 bits                  */
     GD_ENOMEM = -3,       /* device workspace could not be allocated (or the
                              context's workspace limit would be exceeded)     */
     GD_EDEVICE = -4,      /* a HIP runtime call failed                        */
@@ -113,7 +116,7 @@ void gd_destroy(gd_ctx *ctx);
  *               points[i*d .. i*d+d-1]); integer-valued, |x| <= 2^24.
  *   n           number of points, 0 <= n < 2^31 (n == 0 returns GD_OK).
  *   d           dimension, 1 <= d <= GD_D_MAX.
- *   eps         radius; a positive integer <= GD_EPS_MAX.
+ *   eps         radius; a positive integer.
  *   minpts      density threshold, >= 1 (|N(p)| counts p itself).
  *   labels      DEVICE pointer, n int32 out: cluster id (smallest input index
  *               of the cluster's core points) or -1 for noise.
@@ -171,7 +174,7 @@ typedef struct {
     int64_t n;
     int32_t d;             /* 1 <= d <= GD_D_MAX; instances may differ */
     int32_t minpts;        /* >= 1 */
-    double eps;            /* positive integer <= GD_EPS_MAX */
+    double eps;            /* positive integer */
     int32_t *labels;       /* n int32 out: smallest core index of the cluster
                               (an index into this instance's points) or -1 */
     uint8_t *core_flags;   /* n uint8 out */
@@ -343,7 +346,9 @@ int gd_debug_core(gd_ctx *ctx, uint8_t *core_flags_sorted, int32_t *grid_label);
  *   iterations  DEVICE out, npairs uint32 (FastMerging iterations), or NULL.
  * The caller guarantees what holds for core sets of neighbouring grids:
  * every coordinate difference between the two sets, and within a set, is
- * below 2^24 in magnitude and every squared distance is below 2^32.
+ * below 2^24 in magnitude and every squared distance is below 2^32 (for
+ * eps <= GD_EPS_MAX; above it, differences below 2^25, distances in 64
+ * bits).  eps <= 2^27, else GD_ERANGE.
  * Counts must not exceed 262144.  Synchronous on `stream`.
  */
 int gd_merge_test(gd_ctx *ctx, const int32_t *points, int64_t m, int32_t d, double eps, const uint32_t *pairs,

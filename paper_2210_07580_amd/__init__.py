@@ -22,7 +22,7 @@ GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES, GD_OPT_NEIGHBOR_MODE, GD_OPT_MERGE_ORDER
 GD_OPT_APPROX_DELTA, GD_OPT_NEIGHBOR_QUERY = 10, 11
 NOALLOC_SCRATCH_BYTES = 256 << 20
 PHASE_COUNT = 14
-EPS_MAX = 21845
+EPS_MAX = 21845  # largest eps of the 32-bit distance path (GD_EPS_MAX); larger eps use 64 bits
 D_MAX = 8
 
 

@@ -114,6 +114,7 @@ struct gd_ctx {
     int64_t approx_delta = 0;      // GD_OPT_APPROX_DELTA (0: exact merging)
     int nei_query = kNeiTree;      // GD_OPT_NEIGHBOR_QUERY
     bool last_walk = false;        // the last eager call walked (no full lists)
+    bool last_wide = false;        // the last eager call took 64-bit distances
     gd_stats last{};
     // what the last successful call left in the workspace (for gd_debug_*)
     bool have_last = false;
@@ -255,6 +256,7 @@ struct Plan {
 
 // Largest delta of approximate merging: (eps + delta)^2 must fit 32 bits.
 constexpr int kApproxDeltaMax = 65535 - GD_EPS_MAX;
+constexpr int64_t kEpsClamp = (int64_t)1 << 27;
 
 // build_lists: the full lists do not fit the workspace (limit or fixed
 // scratch) and the consumers may walk the grid tree instead.
@@ -404,8 +406,8 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
 // followed by breadth-first levels until the frontier is empty; every level
 // reads its frontier size back (an eager run only).
 int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* nei_off, const uint32_t* nei,
-            int64_t max_core, const HugeMerge& hm, uint32_t* state, uint32_t* front, uint32_t* next, uint32_t* cnt,
-            uint32_t* parent, MergeStats* stats, hipStream_t st) {
+            int64_t max_core, const HugeMerge& hm, bool wide, uint32_t* state, uint32_t* front, uint32_t* next,
+            uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st) {
     GD_TRY(fill<uint32_t>(state, g.ncell, 0u, st));
     uint32_t h[3];
     for (;;) {
@@ -418,10 +420,10 @@ int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* n
         while (nf > 0) {
             GD_TRY(fill<uint32_t>(cnt + 2, 1, 0u, st));
             if (hm.q.pairs) GD_TRY(fill<uint32_t>(hm.q.count, 1, 0u, st));
-            GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, hm.q, state, parent, stats,
-                                    st));
-            GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, true, state, next, cnt, parent, stats,
-                                     st));
+            GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, hm.q, wide, state, parent,
+                                    stats, st));
+            GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, true, wide, state, next, cnt, parent,
+                                     stats, st));
             GD_TRY(hipMemcpyAsync(h + 2, cnt + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             GD_TRY(hipStreamSynchronize(st));
             nf = h[2];
@@ -614,8 +616,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
         min_minpts = std::min<int64_t>(min_minpts, ctx->inst_host[k].minpts);
     }
+    // eps above the 32-bit bound anywhere in the batch: 64-bit distances
+    const bool wide = max_eps > GD_EPS_MAX;
     if (walk)
-        GD_TRY(launch_core_walk(g, t, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, st));
+        GD_TRY(launch_core_walk(g, t, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, wide, st));
     else
         GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr,
                                 max_eps, min_minpts, st));
@@ -687,7 +691,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
             // Algorithm 6's order: the free sort buffers hold the grid states
             // and the two frontiers, the radix scratch the counters
             ctx->mark(P_MERGE, 0);
-            rc = run_bfs(ctx, g, co, L.nei_off, nei, max_core, hm, ka, kb, vb, L.radix_scratch, L.parent,
+            rc = run_bfs(ctx, g, co, L.nei_off, nei, max_core, hm, wide, ka, kb, vb, L.radix_scratch, L.parent,
                          stats ? ctx->stats_dev->merge : nullptr, st);
             if (rc) return rc;
             ctx->mark(P_MERGE, 1);
@@ -709,11 +713,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         }
         const int64_t n_small = !ctx->ldf ? -1 : plan ? -2 : (int64_t)H->counts[4];
         if (walk)
-            GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
+            GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, wide,
+                                     st));
         GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves, walk,
-                            hm.q, L.parent, stats ? ctx->stats_dev->merge : nullptr,
+                            hm.q, wide, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                             ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
-        GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, false, nullptr, nullptr, nullptr,
+        GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, false, wide, nullptr, nullptr, nullptr,
                                  L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
         ctx->mark(P_MERGE, 1);
     }
@@ -737,9 +742,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     else
         GD_TRY(launch_output_allcore(g, co, L.cell_label, st));
     if (walk)
-        GD_TRY(launch_border_walk(g, co, t, L.cell_label, st));
+        GD_TRY(launch_border_walk(g, co, t, L.cell_label, wide, st));
     else
-        GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, st));
+        GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, wide, st));
     ctx->mark(P_OUTPUT, 1);
     if (stats) GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
     if (plan) {
@@ -777,6 +782,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->last_max_core = max_core;
     ctx->last_key_bits = key_bits;
     ctx->last_walk = walk;
+    ctx->last_wide = wide;
 
     gd_stats& s = ctx->last;
     s.grids = ncell;
@@ -812,7 +818,6 @@ int check_params(gd_ctx* ctx, int k, int64_t n, int32_t d, double eps, int32_t m
     if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "instance %d: d = %d out of range [1, %d]", k, d, GD_D_MAX);
     if (!(eps > 0) || !std::isfinite(eps) || eps != std::floor(eps))
         return ctx->fail(GD_EINVAL, "instance %d: eps = %g must be a positive integer", k, eps);
-    if (eps > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "instance %d: eps = %g exceeds %d", k, eps, GD_EPS_MAX);
     if (minpts < 1) return ctx->fail(GD_EINVAL, "instance %d: minpts = %d must be >= 1", k, minpts);
     if (n > 0 && (!points || !labels || !core)) return ctx->fail(GD_EINVAL, "instance %d: NULL device pointer", k);
     return GD_OK;
@@ -855,9 +860,14 @@ void set_inst(Inst& I, const float* x, int64_t n, int32_t d, double eps, int32_t
     I.core = core;
     I.n = n;
     I.d = d;
-    I.eps = (int64_t)eps;
-    I.T = (uint32_t)(I.eps * I.eps);
-    I.Tm = (uint32_t)((I.eps + delta) * (I.eps + delta));  // eps + delta <= 65535
+    // any two valid points are less than 2^25 sqrt(8) < 2^27 apart, so a
+    // larger eps clusters exactly as 2^27 does
+    I.eps = (int64_t)std::min(eps, (double)kEpsClamp);
+    I.T64 = (uint64_t)(I.eps * I.eps);
+    I.Tm64 = (uint64_t)((I.eps + delta) * (I.eps + delta));
+    // the 32-bit path (eps <= GD_EPS_MAX, eps + delta <= 65535)
+    I.T = I.eps <= GD_EPS_MAX ? (uint32_t)I.T64 : 0u;
+    I.Tm = I.eps <= GD_EPS_MAX ? (uint32_t)I.Tm64 : 0u;
     I.minpts = minpts;
     for (int j = 0; j < kMaxD; ++j) {
         I.mn[j] = INT_MAX;
@@ -896,7 +906,7 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
     sig.push_back(count);
     int64_t max_eps = 0;
     for (int k = 0; k < count; ++k) max_eps = std::max<int64_t>(max_eps, ctx->inst_host[k].eps);
-    sig.push_back(core_mark_packed(max_eps) ? 1 : 0);
+    sig.push_back(max_eps > GD_EPS_MAX ? 2 : core_mark_packed(max_eps) ? 1 : 0);  // distance width
     sig.push_back(ctx->ldf ? 1 : 0);
     sig.push_back(ctx->proposal_on ? 1 : 0);
     sig.push_back(ctx->tile_pts);
@@ -1305,7 +1315,7 @@ int gd_merge_test(gd_ctx* ctx, const int32_t* points, int64_t m, int32_t d, doub
     if (d < 1 || d > GD_D_MAX) return ctx->fail(GD_EINVAL, "d = %d out of range [1, %d]", d, GD_D_MAX);
     if (!(eps > 0) || !std::isfinite(eps) || eps != std::floor(eps))
         return ctx->fail(GD_EINVAL, "eps = %g must be a positive integer", eps);
-    if (eps > GD_EPS_MAX) return ctx->fail(GD_ERANGE, "eps = %g exceeds %d", eps, GD_EPS_MAX);
+    if (eps > (double)kEpsClamp) return ctx->fail(GD_ERANGE, "eps = %g exceeds 2^27", eps);
     if (m < 0 || npairs < 0) return ctx->fail(GD_EINVAL, "negative size");
     if (npairs == 0) return GD_OK;
     if (!points || !pairs || !answers) return ctx->fail(GD_EINVAL, "NULL device pointer");
@@ -1358,6 +1368,8 @@ int gd_proposal_harvest(gd_ctx* ctx, uint32_t seed, uint32_t keep_mod, int64_t c
     if (ctx->last_walk)
         return ctx->fail(GD_EUNSUPPORTED, "harvesting needs the neighbour lists of every grid "
                                           "(GD_OPT_NEIGHBOR_MODE = 1)");
+    if (ctx->last_wide)
+        return ctx->fail(GD_EUNSUPPORTED, "harvesting takes eps <= %d (the scorer's 32-bit path)", GD_EPS_MAX);
     if (keep_mod < 1 || cap < 0 || (cap > 0 && (!features || !targets)) || !count)
         return ctx->fail(GD_EINVAL, "bad harvest arguments");
     DeviceGuard guard(ctx->device);

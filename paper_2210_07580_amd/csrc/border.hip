@@ -145,7 +145,7 @@ size_t output_table_bytes(int bits, int key_bytes) {
 }
 
 // Border and noise points of grid c (rows [st, st + k)), one wave.
-template <int D>
+template <int D, bool kWide>
 __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& co, const uint64_t* __restrict__ nei_off,
                                             const uint32_t* __restrict__ nei, const int32_t* __restrict__ cell_label,
                                             int64_t c, uint32_t st, uint32_t k, uint32_t* s_start, uint32_t* s_excl,
@@ -157,7 +157,7 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
     uint8_t GD_GLOBAL* __restrict__ core_flags = as_global(I.core);
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I);
     const uint64_t own_best = own_min == kNone ? ~0ull : (((uint64_t)own_min << 32) | (uint32_t)own_label);
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     for (uint32_t qb = 0; qb < k; qb += kWave) {
@@ -212,9 +212,9 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
                 while (act) {
                     const int qi = ffs64(act);
                     act &= act - 1ull;
-                    uint32_t dd = 0;
+                    typename Dist<kWide>::T dd = 0;
 #pragma unroll
-                    for (int jj = 0; jj < D; ++jj) dd += sq24(y[jj], readlane(qx[jj], qi));
+                    for (int jj = 0; jj < D; ++jj) dd += sqd<kWide>(y[jj], readlane(qx[jj], qi));
                     const bool in = tv && dd <= T;
                     if (ballot(in)) {
                         const uint64_t m = wave_min_u64(in ? cand : ~0ull);
@@ -241,7 +241,7 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
 // be the kernel's tail.
 constexpr int64_t kBorderGroupMinGrids = 1 << 20;
 
-template <int D, int G>
+template <int D, int G, bool kWide>
 __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                         const uint32_t* __restrict__ nei,
                                                         const int32_t* __restrict__ cell_label) {
@@ -260,20 +260,24 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
     }
     for (uint64_t todo = ballot(need); todo; todo &= todo - 1ull) {
         const int g = ffs64(todo);
-        border_grid<D>(gv, co, nei_off, nei, cell_label, c0 + g, readlane(st_l, g), readlane(k_l, g), s_start[w],
-                       s_excl[w], s_lab[w]);
+        border_grid<D, kWide>(gv, co, nei_off, nei, cell_label, c0 + g, readlane(st_l, g), readlane(k_l, g),
+                              s_start[w], s_excl[w], s_lab[w]);
     }
 }
 
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, hipStream_t st) {
+                         const int32_t* cell_label, bool wide, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    if (g.ncell >= kBorderGroupMinGrids) {
-        GD_DISPATCH_D(g.D, (output_kernel<D, kWave><<<dim3(grid_for(g.ncell, kWavesPerBlock * kWave)), dim3(kBlock), 0,
-                                                     st>>>(g, c, nei_off, nei, cell_label)));
+    const unsigned many = grid_for(g.ncell, kWavesPerBlock * kWave), one = grid_for(g.ncell, kWavesPerBlock);
+    if (wide) {
+        GD_DISPATCH_D(g.D, (output_kernel<D, 1, true><<<dim3(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+                                                                                          cell_label)));
+    } else if (g.ncell >= kBorderGroupMinGrids) {
+        GD_DISPATCH_D(g.D, (output_kernel<D, kWave, false><<<dim3(many), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+                                                                                                cell_label)));
     } else {
-        GD_DISPATCH_D(g.D, (output_kernel<D, 1><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(
-                               g, c, nei_off, nei, cell_label)));
+        GD_DISPATCH_D(g.D, (output_kernel<D, 1, false><<<dim3(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+                                                                                           cell_label)));
     }
     return hipGetLastError();
 }

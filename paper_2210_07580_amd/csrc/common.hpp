@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "launch.hpp"
+
 namespace gd {
 
 constexpr int kWave = 64;
@@ -107,6 +109,19 @@ __device__ __forceinline__ uint32_t sq24(int32_t a, int32_t b) {
     return __umul24(t, t);
 }
 
+// Squared distances of the wide path (eps above the 32-bit bound): any two
+// points differ by less than 2^25 per coordinate, so each square is below
+// 2^50 and a sum over at most eight coordinates below 2^53, exact in 64 bits.
+template <bool kWide>
+__device__ __forceinline__ typename Dist<kWide>::T sqd(int32_t a, int32_t b) {
+    if constexpr (kWide) {
+        const int64_t t = (int64_t)a - (int64_t)b;
+        return (uint64_t)(t * t);
+    } else {
+        return sq24(a, b);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -127,6 +142,15 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         uint64_t t = __shfl_xor(v, o);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t t = __shfl_xor(v, o);
         v = t < v ? t : v;
     }
     return v;
@@ -282,18 +306,20 @@ __device__ __forceinline__ int64_t xcd_runs(int64_t b, int64_t count) {
     return (j / kRun) * kGroup + x * kRun + j % kRun;
 }
 
-#define GD_DISPATCH_D(d, CALL)                         \
-    switch (d) {                                       \
-        case 1: { constexpr int D = 1; CALL; } break;  \
-        case 2: { constexpr int D = 2; CALL; } break;  \
-        case 3: { constexpr int D = 3; CALL; } break;  \
-        case 4: { constexpr int D = 4; CALL; } break;  \
-        case 5: { constexpr int D = 5; CALL; } break;  \
-        case 6: { constexpr int D = 6; CALL; } break;  \
-        case 7: { constexpr int D = 7; CALL; } break;  \
-        case 8: { constexpr int D = 8; CALL; } break;  \
-        default: return hipErrorInvalidValue;          \
-    }
+#define GD_DISPATCH_D(d, CALL)                             \
+    do {                                                   \
+        switch (d) {                                       \
+            case 1: { constexpr int D = 1; CALL; } break;  \
+            case 2: { constexpr int D = 2; CALL; } break;  \
+            case 3: { constexpr int D = 3; CALL; } break;  \
+            case 4: { constexpr int D = 4; CALL; } break;  \
+            case 5: { constexpr int D = 5; CALL; } break;  \
+            case 6: { constexpr int D = 6; CALL; } break;  \
+            case 7: { constexpr int D = 7; CALL; } break;  \
+            case 8: { constexpr int D = 8; CALL; } break;  \
+            default: return hipErrorInvalidValue;          \
+        }                                                  \
+    } while (0)
 
 inline unsigned grid_for(int64_t n, int per_block = kBlock) {
     int64_t b = (n + per_block - 1) / per_block;

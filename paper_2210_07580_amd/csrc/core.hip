@@ -25,11 +25,12 @@ namespace gd {
 // difference is below 2.13 eps < 2^16 in magnitude, so each square is an
 // exact unsigned 24-bit product, and the sum (below 9 eps^2 < 2^32 for
 // eps <= 21845) is exact in unsigned 32-bit arithmetic.
-template <int D>
-__device__ __forceinline__ uint32_t sqdist_nb(const int32_t (&a)[D], const int32_t (&b)[D]) {
-    uint32_t dd = 0;
+// Above that bound (the wide path) the sum is taken in 64 bits.
+template <int D, bool kWide>
+__device__ __forceinline__ typename Dist<kWide>::T sqdist_nb(const int32_t (&a)[D], const int32_t (&b)[D]) {
+    typename Dist<kWide>::T dd = 0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) dd += sq24(a[j], b[j]);
+    for (int j = 0; j < D; ++j) dd += sqd<kWide>(a[j], b[j]);
     return dd;
 }
 
@@ -76,7 +77,7 @@ __device__ __forceinline__ uint32_t sqdist_pk(const int32_t (&a)[packed_words<D>
 // MinPts (a query needs more hits than one 64-candidate step can give) a
 // step takes two rows; with a small MinPts most queries close within the
 // first 64 candidates and a second row would only add distance tests.
-template <int D, bool kStats, bool kPacked, int R>
+template <int D, bool kStats, bool kPacked, int R, bool kWide>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     const uint32_t en = gv.cell_start[c + 1];
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
     const uint32_t minpts = (uint32_t)I.minpts;
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I);
     const uint32_t k = en - st;
     if (kPacked && I.eps > kPackedEpsMax) {
         // a replayed graph met a larger eps than it was captured for: the
@@ -195,8 +196,8 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
                         load_row<D>(s_q[w], qb2, pb);
 #pragma unroll
                         for (int u = 0; u < R; ++u) {
-                            ha += (uint32_t)popc64(ballot(sqdist_nb<D>(y[u], pa) <= T) & tvm[u]);
-                            hb += (uint32_t)popc64(ballot(sqdist_nb<D>(y[u], pb) <= T) & tvm[u]);
+                            ha += (uint32_t)popc64(ballot(sqdist_nb<D, kWide>(y[u], pa) <= T) & tvm[u]);
+                            hb += (uint32_t)popc64(ballot(sqdist_nb<D, kWide>(y[u], pb) <= T) & tvm[u]);
                         }
                     }
                     step_hits = lane == qa ? ha : step_hits;
@@ -237,23 +238,30 @@ hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const ui
     const bool packed = core_mark_packed(max_eps);
     const bool two = min_minpts > kWave / 2;
     // the counting variant takes the same steps as the timed one
-    if (stats && two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+    if (max_eps > GD_EPS_MAX) {  // 64-bit distances, one row per step
+        if (stats)
+            GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                                   g, nei_off, nei, core, core_cnt, stats)));
+        else
+            GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                                   g, nei_off, nei, core, core_cnt, stats)));
+    } else if (stats && two) {
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else if (stats) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else if (packed && two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else if (packed) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else if (two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 2><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     } else {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
                                g, nei_off, nei, core, core_cnt, stats)));
     }
     return hipGetLastError();

@@ -33,6 +33,9 @@
 //   The start point p is the first core point of s_i (the paper picks one at
 //   random; the choice does not change the answer).  If a Pruning call
 //   empties a set the answer is "no" at once.
+//   Wide path (eps above the 32-bit bound): squared distances in 64 bits,
+//   the triangle rule's products in 128 bits, and the same single-precision
+//   cosines (their error bound is relative, so larger operands keep it).
 //   Approximate FastMerging (the remark on numerical error, Section 4.3.3):
 //   the two "yes" tests accept D(p, q) <= Tyes = (eps + delta)^2 while
 //   Pruning keeps eps; then every pair with MinDist <= eps still answers yes,
@@ -120,13 +123,46 @@ __device__ __forceinline__ void load_lane_point(const PointSet& s, uint32_t w, i
     load_point<D>(s, pos, x);
 }
 
-// argmin over live y of D(p, y): returns (D << 32 | position), and the
-// winning point's row in `row` (from the winning lane's registers: no second
-// load of it).  s must hold a live point.
-template <int D>
-__device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p)[D], unsigned long long& ndist,
-                                            int32_t (&row)[D]) {
+// argmin over live y of D(p, y): returns that distance, and the winning
+// point's row in `row` (from the winning lane's registers: no second load
+// of it); ties go to the lowest position.  s must hold a live point.  The
+// 32-bit path ranks (D << 32 | position) in one wave minimum; the wide path
+// takes the minimum distance, then the lowest position holding it.
+template <int D, bool kWide = false>
+__device__ __forceinline__ typename Dist<kWide>::T nearest(const PointSet& s, const int32_t (&p)[D],
+                                                           unsigned long long& ndist, int32_t (&row)[D]) {
     const int lane = lane_id();
+    if constexpr (kWide) {
+        uint64_t best = ~0ull;
+        uint32_t bpos = ~0u;
+        int32_t br[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) br[k] = 0;
+        for (uint32_t w = 0; w < s.words; ++w) {
+            const uint64_t mk = s.alive[w];
+            if (!mk) continue;
+            ndist += (unsigned long long)popc64(mk);
+            if ((mk >> lane) & 1ull) {
+                int32_t y[D];
+                load_point<D>(s, w * kWave + lane, y);
+                uint64_t dd = 0;
+#pragma unroll
+                for (int k = 0; k < D; ++k) dd += sqd<true>(y[k], p[k]);
+                if (dd < best) {  // later words only hold larger positions
+                    best = dd;
+                    bpos = w * kWave + lane;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) br[k] = y[k];
+                }
+            }
+        }
+        const uint64_t m = wave_min_u64(best);
+        const uint32_t pos = wave_min_u32(best == m ? bpos : ~0u);
+        const int wl = __builtin_amdgcn_readfirstlane((int)(pos & (uint32_t)(kWave - 1)));
+#pragma unroll
+        for (int k = 0; k < D; ++k) row[k] = readlane(br[k], wl);
+        return m;
+    } else {
     uint64_t best = ~0ull;
     int32_t br[D];
 #pragma unroll
@@ -161,7 +197,8 @@ __device__ __forceinline__ uint64_t nearest(const PointSet& s, const int32_t (&p
     const int wl = __builtin_amdgcn_readfirstlane((int)((uint32_t)m & (uint32_t)(kWave - 1)));
 #pragma unroll
     for (int k = 0; k < D; ++k) row[k] = readlane(br[k], wl);
-    return m;
+    return (uint32_t)(m >> 32);
+    }
 }
 
 __device__ __forceinline__ float wave_min_f32(float v) {
@@ -185,10 +222,11 @@ constexpr float kAngleMargin = 1e-4f;
 // Algorithm 4: remove from `a` the points that cannot be within eps of any
 // live point of `b`, given anchor p in a and q = argmin_{y in b} D(p, y) with
 // D(p, q) = dpq > T.  Returns whether `a` keeps any point.
-template <int D>
+template <int D, bool kWide = false>
 __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, const int32_t (&p)[D],
-                                        const int32_t (&q)[D], uint32_t dpq, uint32_t T, double eps_d,
-                                        unsigned long long& ndist) {
+                                        const int32_t (&q)[D], typename Dist<kWide>::T dpq,
+                                        typename Dist<kWide>::T T, double eps_d, unsigned long long& ndist) {
+    using DT = typename Dist<kWide>::T;
     const int lane = lane_id();
     int32_t pq[D];
 #pragma unroll
@@ -214,12 +252,12 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
             if (!((mk[u] >> lane) & 1ull)) continue;
             int32_t py[D];
             int64_t dot = 0;
-            uint32_t b2 = 0;
+            DT b2 = 0;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 py[k] = yy[u][k] - p[k];
                 dot += (int64_t)pq[k] * py[k];
-                b2 += sq24(yy[u][k], p[k]);
+                b2 += sqd<kWide>(yy[u][k], p[k]);
             }
             const float dotf = (float)dot;
             const float h2 = (float)(b2 - T);  // b^2 - eps^2 > 0 since b^2 >= dpq > T
@@ -260,15 +298,19 @@ __device__ __forceinline__ bool pruning(const PointSet& a, const PointSet& b, co
             ndist += (unsigned long long)popc64(mk[u]);
             bool keep = false;
             if ((mk[u] >> lane) & 1ull) {
-                uint32_t ax = 0;
+                DT ax = 0;
                 int64_t dotx = 0;
 #pragma unroll
                 for (int k = 0; k < D; ++k) {
-                    ax += sq24(xx[u][k], p[k]);
+                    ax += sqd<kWide>(xx[u][k], p[k]);
                     dotx += (int64_t)pq[k] * (xx[u][k] - p[k]);
                 }
                 const int64_t s = (int64_t)dpq - (int64_t)T - (int64_t)ax;
-                const bool tri = s > 0 && (uint64_t)4 * (uint64_t)T * (uint64_t)ax < (uint64_t)s * (uint64_t)s;
+                bool tri;
+                if constexpr (kWide)  // 4 eps^2 D(x,p) and s^2 reach 2^117: 128-bit products
+                    tri = s > 0 && (unsigned __int128)4 * T * ax < (unsigned __int128)s * (uint64_t)s;
+                else
+                    tri = s > 0 && (uint64_t)4 * (uint64_t)T * (uint64_t)ax < (uint64_t)s * (uint64_t)s;
                 keep = !tri;
                 if (keep && !off && ax > 0) {
                     const float cth = (float)dotx * rna * __builtin_amdgcn_rsqf((float)ax);
@@ -295,9 +337,11 @@ __device__ __forceinline__ void init_alive(const PointSet& s) {
 // Algorithm 5 from P0, the start point of si (its row, which a caller
 // testing several pairs from one si loads once).  Returns 1 (yes), 0 (no)
 // or -1 (iteration bound exceeded).
-template <int D>
-__device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D], uint32_t T, uint32_t Tyes,
-                                 double eps, unsigned long long& ndist, uint32_t& iters) {
+template <int D, bool kWide = false>
+__device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D], typename Dist<kWide>::T T,
+                                 typename Dist<kWide>::T Tyes, double eps, unsigned long long& ndist,
+                                 uint32_t& iters) {
+    using DT = typename Dist<kWide>::T;
     init_alive<D>(si);
     init_alive<D>(sj);
     wave_sync();
@@ -308,24 +352,22 @@ __device__ int fast_merging_from(PointSet si, PointSet sj, const int32_t (&P0)[D
     for (int k = 0; k < D; ++k) P[k] = P0[k];
     for (iters = 1;; ++iters) {
         if (iters > bound) return -1;
-        const uint64_t bq = nearest<D>(sj, P, ndist, Q);
-        const uint32_t dq = (uint32_t)(bq >> 32);
+        const DT dq = nearest<D, kWide>(sj, P, ndist, Q);
         if (dq <= Tyes) return 1;
-        if (!pruning<D>(si, sj, P, Q, dq, T, eps, ndist)) return 0;
-        const uint64_t bp = nearest<D>(si, Q, ndist, P);
-        const uint32_t dp = (uint32_t)(bp >> 32);
+        if (!pruning<D, kWide>(si, sj, P, Q, dq, T, eps, ndist)) return 0;
+        const DT dp = nearest<D, kWide>(si, Q, ndist, P);
         if (dp <= Tyes) return 1;
-        if (!pruning<D>(sj, si, Q, P, dp, T, eps, ndist)) return 0;
+        if (!pruning<D, kWide>(sj, si, Q, P, dp, T, eps, ndist)) return 0;
     }
 }
 
 // Algorithm 5 from position `start` of si.
-template <int D>
-__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, uint32_t T, uint32_t Tyes, double eps,
-                            unsigned long long& ndist, uint32_t& iters) {
+template <int D, bool kWide = false>
+__device__ int fast_merging(PointSet si, PointSet sj, uint32_t start, typename Dist<kWide>::T T,
+                            typename Dist<kWide>::T Tyes, double eps, unsigned long long& ndist, uint32_t& iters) {
     int32_t P0[D];
     load_point<D>(si, start, P0);
-    return fast_merging_from<D>(si, sj, P0, T, Tyes, eps, ndist, iters);
+    return fast_merging_from<D, kWide>(si, sj, P0, T, Tyes, eps, ndist, iters);
 }
 
 }  // namespace gd

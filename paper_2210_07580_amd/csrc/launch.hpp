@@ -14,7 +14,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gritdbscan.h"
+
 namespace gd {
+
+// Type a kernel compares squared distances with eps^2 in: 32 bits for eps
+// <= GD_EPS_MAX, 64 bits above (the wide path).
+template <bool kWide>
+struct Dist {
+    using T = uint32_t;
+};
+template <>
+struct Dist<true> {
+    using T = uint64_t;
+};
 
 constexpr int kMaxD = 8;
 constexpr int kMaxLevels = kMaxD + 1;  // grid tree: instance level + one level per dimension
@@ -42,8 +55,10 @@ struct Inst {
     int64_t eps;
     int32_t d;
     int32_t minpts;
-    uint32_t T;        // eps^2
+    uint32_t T;        // eps^2 (eps <= GD_EPS_MAX)
     uint32_t Tm;       // (eps + delta)^2: FastMerging's "yes" bound (delta 0: exact)
+    uint64_t T64;      // eps^2 and (eps + delta)^2 in 64 bits: the wide path, for any eps
+    uint64_t Tm64;
     uint32_t tile0;    // first point tile of the instance (tiles never straddle instances)
     // filled on the device
     int32_t mn[kMaxD];
@@ -53,6 +68,16 @@ struct Inst {
     int32_t key_bits;
     uint32_t err;
 };
+
+// eps^2 and FastMerging's "yes" bound in the width a kernel compares in.
+template <bool kWide>
+__device__ __forceinline__ typename Dist<kWide>::T inst_T(const Inst& I) {
+    if constexpr (kWide) return I.T64; else return I.T;
+}
+template <bool kWide>
+__device__ __forceinline__ typename Dist<kWide>::T inst_Tm(const Inst& I) {
+    if constexpr (kWide) return I.Tm64; else return I.Tm;
+}
 
 // Batch-wide identifier layout and counters (device).
 struct Header {
@@ -244,6 +269,8 @@ constexpr int kStatSlots = 64;  // copies of each device counter (see MergeStats
 struct MergeStats {
     unsigned long long pairs, skipped, tests, yes, iters, max_iters, dists, set_points;
 };
+// wide (here and below): the batch's largest eps exceeds GD_EPS_MAX, and
+// squared distances are taken in 64 bits against Inst::T64 / Tm64.
 // Largest core set the merge kernels' LDS bitmaps hold.  A pair with a
 // larger set is queued (HugeQueue) and tested by merge_huge_kernel, whose
 // bitmaps live in device memory.
@@ -262,8 +289,9 @@ struct CellSummary;
 // tiny_done: the pairs of two tiny core sets were already merged (walk mode).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, int waves, bool tiny_done, const HugeQueue& huge, uint32_t* parent,
-                        MergeStats* stats, const __half* proposal, const CellSummary* sum, hipStream_t st);
+                        int64_t max_core, int waves, bool tiny_done, const HugeQueue& huge, bool wide,
+                        uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
+                        hipStream_t st);
 // Sum over core grids with more than kMaxCoreBits core points of |Nei(g)| + 1
 // (added to *sum; the caller clears it): with both orders no pair is queued
 // twice from one side, so twice this bounds the queue.
@@ -273,7 +301,7 @@ hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t*
 // with 2 * words words of device memory at slabs.  bfs: the pair's second grid
 // is claimed for the search (state, next, cnt[2]) as in the BFS level kernel.
 hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
-                             uint32_t words, uint32_t waves, bool bfs, uint32_t* state, uint32_t* next,
+                             uint32_t words, uint32_t waves, bool bfs, bool wide, uint32_t* state, uint32_t* next,
                              uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st);
 // The BFS order of Algorithm 6 (GD_OPT_MERGE_ORDER = 2), on the full lists.
 // state: ncell u32, cleared to 0 for every grid first.  cnt: 3 u32 (the
@@ -283,7 +311,7 @@ hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t*
                             uint32_t* state, uint32_t* front, uint32_t* cnt, hipStream_t st);
 hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                             const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
-                            const HugeQueue& huge, uint32_t* state, uint32_t* parent, MergeStats* stats,
+                            const HugeQueue& huge, bool wide, uint32_t* state, uint32_t* parent, MergeStats* stats,
                             hipStream_t st);
 // pts: d x m SoA; rows: scratch of m rows (row_stride(d) int32 each).
 hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* rows, const uint32_t* pairs,
@@ -306,20 +334,20 @@ hipError_t launch_mlp_train(const TrainArgs& a, hipStream_t st);
 // Core flags and m_i per grid, each sparse grid's queries counting hits over
 // the neighbours its own tree walk finds, with early exit at MinPts.
 hipError_t launch_core_walk(const GridView& g, const TreeView& t, uint8_t* core, uint32_t* core_cnt, CoreStats* stats,
-                            hipStream_t st);
+                            bool wide, hipStream_t st);
 // Pairs of tiny core sets (both at most kTinyCore points), each tested once
 // from its lower grid; n_small as for launch_merge.  Pairs involving a larger
 // core set are left to launch_merge (with lists for those grids only).
 hipError_t launch_merge_walk(const GridView& g, const CoreOut& c, const TreeView& t, const uint32_t* ldf_list,
-                             int64_t n_small, uint32_t* parent, MergeStats* stats, hipStream_t st);
+                             int64_t n_small, uint32_t* parent, MergeStats* stats, bool wide, hipStream_t st);
 // Border and noise points of the grids holding a non-core point.
 hipError_t launch_border_walk(const GridView& g, const CoreOut& c, const TreeView& t, const int32_t* cell_label,
-                              hipStream_t st);
+                              bool wide, hipStream_t st);
 
 // ---- border.hip
 // Grids with a non-core point: border search and output through the permutation.
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, hipStream_t st);
+                         const int32_t* cell_label, bool wide, hipStream_t st);
 // All-core grids: output in input order through an identifier -> label hash
 // table of 2^bits slots (+1) in `table` (output_table_bytes).  keys_in: the
 // identifiers in input order; skeys: sorted.

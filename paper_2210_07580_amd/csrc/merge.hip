@@ -41,7 +41,7 @@ __device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsign
 // lane first resolves its candidate's root and skips the pair when both
 // grids are already in one set; a yes joins the two roots.  s_i lives in
 // scalar registers.
-template <int D>
+template <int D, bool kWide>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
                                                              const uint32_t* __restrict__ ldf,
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     const uint32_t ci = ldf[r];
     // every load that depends on ci alone is issued before the first use
     // the merge's "yes" bound: eps^2, or (eps + delta)^2 when approximate
-    const uint32_t T = cell_inst(gv, ci).Tm;
+    const typename Dist<kWide>::T T = inst_Tm<kWide>(cell_inst(gv, ci));
     const uint4 own = rank[ci];
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     const uint32_t pci = load_acq(&parent[ci]);
@@ -120,9 +120,9 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
 #pragma unroll
                         for (int a = 0; a < (int)kSmallSet; ++a) {
                             if ((uint32_t)a < mi) {
-                                uint32_t dd = 0;
+                                typename Dist<kWide>::T dd = 0;
 #pragma unroll
-                                for (int k = 0; k < D; ++k) dd += sq24(y[v][k], pi[a][k]);
+                                for (int k = 0; k < D; ++k) dd += sqd<kWide>(y[v][k], pi[a][k]);
                                 yes |= dd <= T;
                             }
                         }
@@ -189,7 +189,7 @@ __device__ __forceinline__ uint32_t orderable(float z) {
 // unrolling inside a wave.  The scorer's fragments, and rows of d >= 5, do
 // not fit in that budget (they would spill to scratch), so those variants
 // run four.
-template <int D, bool kLearned>
+template <int D, bool kLearned, bool kWide>
 __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_big_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ ldf,
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
     const uint4 own = rank[ci];
     const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
     const uint32_t pci = load_acq(&parent[ci]);
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I), Tm = inst_Tm<kWide>(I);
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, own.y, own.z, smem + (int64_t)w * 2 * words, 0};
     if (si.m <= kSmallSet) return;
@@ -317,11 +317,11 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
             int yes;
             if constexpr (kLearned) {
                 if (__shfl(my_z1, l) > 0.f)
-                    yes = fast_merging<D>(sj, si, readlane(my_rb, l), T, I.Tm, eps, n_dist, it);
+                    yes = fast_merging<D, kWide>(sj, si, readlane(my_rb, l), T, Tm, eps, n_dist, it);
                 else
-                    yes = fast_merging<D>(si, sj, readlane(my_ra, l), T, I.Tm, eps, n_dist, it);
+                    yes = fast_merging<D, kWide>(si, sj, readlane(my_ra, l), T, Tm, eps, n_dist, it);
             } else {
-                yes = fast_merging_from<D>(si, sj, p0, T, I.Tm, eps, n_dist, it);
+                yes = fast_merging_from<D, kWide>(si, sj, p0, T, Tm, eps, n_dist, it);
             }
             ++n_test;
             n_pts += si.m + sj.m;
@@ -354,8 +354,8 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
-                        int waves, bool tiny_done, const HugeQueue& huge, uint32_t* parent, MergeStats* stats,
-                        const __half* proposal, const CellSummary* sum, hipStream_t st) {
+                        int waves, bool tiny_done, const HugeQueue& huge, bool wide, uint32_t* parent,
+                        MergeStats* stats, const __half* proposal, const CellSummary* sum, hipStream_t st) {
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
     // n_small >= 0: the visiting order puts the n_small tiny core grids first
@@ -368,8 +368,12 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     const int64_t b0 = n_small >= 0 ? n_small : 0;
     if (s1 > 0 && !tiny_done) {
         const unsigned blocks = (unsigned)((s1 + kWavesPerBlock - 1) / kWavesPerBlock);
-        GD_DISPATCH_D(g.D, (merge_small_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+        if (wide)
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+        else
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
     const uint32_t words = (uint32_t)((std::min<int64_t>(max_core, kMaxCoreBits) + kWave - 1) / kWave);
@@ -379,14 +383,19 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((ncc - b0 + wpb - 1) / wpb);
     // the scorer's weights take static LDS beside the bitmaps; if both do not
-    // fit, run without the proposal (the answers are the same)
-    const bool learned = prop.weights && lds + sizeof(MlpMfma) + kWavesPerBlock * (sizeof(MlpMfmaScratch) +
-                                                                                 sizeof(float2) * kWave) <= 65536;
+    // fit, or on the wide path, run without the proposal (the answers are the
+    // same)
+    const bool learned = prop.weights && !wide &&
+                         lds + sizeof(MlpMfma) + kWavesPerBlock * (sizeof(MlpMfmaScratch) + sizeof(float2) * kWave) <=
+                             65536;
     if (learned) {
-        GD_DISPATCH_D(g.D, (merge_big_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, true, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                               g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
+    } else if (wide) {
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     } else {
-        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     }
     return hipGetLastError();
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void bfs_seed_kernel(const uint32_t* ncell,
 // One level: a wave per frontier grid tests its core neighbours that are
 // unclassified, or classified outside its set; claimed grids form the next
 // frontier (cnt[2]).
-template <int D>
+template <int D, bool kWide>
 __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei,
                                                            const uint32_t* __restrict__ front, uint32_t nfront,
@@ -455,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
     if (f >= (int64_t)nfront) return;
     const uint32_t ci = front[f];
     const Inst& I = cell_inst(gv, ci);
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I), Tm = inst_Tm<kWide>(I);
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
     si.words = (si.m + kWave - 1) / kWave;
@@ -505,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
                 continue;
             }
             uint32_t it = 0;
-            const int yes = fast_merging_from<D>(si, sj, p0, T, I.Tm, eps, n_dist, it);
+            const int yes = fast_merging_from<D, kWide>(si, sj, p0, T, Tm, eps, n_dist, it);
             ++n_test;
             n_pts += si.m + sj.m;
             n_iter += it;
@@ -541,7 +550,7 @@ hipError_t launch_bfs_seeds(const GridView& g, const CoreOut& c, const uint64_t*
 
 hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                             const uint32_t* front, uint32_t nfront, uint32_t* next, uint32_t* cnt, int64_t max_core,
-                            const HugeQueue& huge, uint32_t* state, uint32_t* parent, MergeStats* stats,
+                            const HugeQueue& huge, bool wide, uint32_t* state, uint32_t* parent, MergeStats* stats,
                             hipStream_t st) {
     if (nfront == 0) return hipSuccess;
     const uint32_t words =
@@ -551,8 +560,12 @@ hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t*
     const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((nfront + wpb - 1) / wpb);
-    GD_DISPATCH_D(g.D, (bfs_level_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                           g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
+    if (wide)
+        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                               g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
+    else
+        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                               g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
     return hipGetLastError();
 }
 
@@ -574,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void huge_scan_kernel(const uint32_t* ncell
 
 // Persistent: wave k takes queued pairs k, k + waves, ... (every wave leaves
 // once it passes the queue's length, read once at entry).
-template <int D>
+template <int D, bool kWide>
 __global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut co, HugeQueue q, uint64_t* slabs,
                                                             uint32_t words, uint32_t waves, int bfs,
                                                             uint32_t* state, uint32_t* next, uint32_t* cnt,
@@ -603,7 +616,8 @@ __global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut
             continue;
         }
         uint32_t it = 0;
-        const int yes = fast_merging<D>(si, sj, 0u, I.T, I.Tm, (double)I.eps, n_dist, it);
+        const int yes = fast_merging<D, kWide>(si, sj, 0u, inst_T<kWide>(I), inst_Tm<kWide>(I), (double)I.eps,
+                                               n_dist, it);
         ++n_test;
         n_pts += si.m + sj.m;
         n_iter += it;
@@ -633,12 +647,16 @@ hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t*
 }
 
 hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
-                             uint32_t words, uint32_t waves, bool bfs, uint32_t* state, uint32_t* next,
+                             uint32_t words, uint32_t waves, bool bfs, bool wide, uint32_t* state, uint32_t* next,
                              uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st) {
     if (!huge.pairs || waves == 0) return hipSuccess;
     const unsigned blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-    GD_DISPATCH_D(g.D, (merge_huge_kernel<D><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                           g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
+    if (wide)
+        GD_DISPATCH_D(g.D, (merge_huge_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
+    else
+        GD_DISPATCH_D(g.D, (merge_huge_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
     return hipGetLastError();
 }
 
@@ -655,10 +673,10 @@ __global__ __launch_bounds__(kBlock) void soa_rows_kernel(const int32_t* __restr
 }
 
 // FastMerging on caller-given pairs of point runs (one wave per pair).
-template <int D>
+template <int D, bool kWide>
 __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __restrict__ pts,
                                                              const uint32_t* __restrict__ pairs, int64_t npairs,
-                                                             uint32_t T, double eps, uint32_t words,
+                                                             uint64_t T64, double eps, uint32_t words,
                                                              uint8_t* __restrict__ answers, uint32_t* iterations) {
     extern __shared__ uint64_t smem[];
     const int wpb = (int)(blockDim.x / kWave);
@@ -671,7 +689,8 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     b.words = (b.m + kWave - 1) / kWave;
     unsigned long long nd = 0;
     uint32_t it = 0;
-    const int yes = fast_merging<D>(a, b, 0u, T, T, eps, nd, it);
+    const typename Dist<kWide>::T T = (typename Dist<kWide>::T)T64;
+    const int yes = fast_merging<D, kWide>(a, b, 0u, T, T, eps, nd, it);
     if (lane_id() == 0) {
         answers[r] = yes < 0 ? 2 : (uint8_t)yes;
         if (iterations) iterations[r] = it;
@@ -692,8 +711,12 @@ hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* row
     }
     if (lds > 65536) return hipErrorInvalidValue;
     const unsigned blocks = (unsigned)((npairs + wpb - 1) / wpb);
-    GD_DISPATCH_D(d, (merge_pairs_kernel<D><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
-                         rows, pairs, npairs, (uint32_t)(eps * eps), (double)eps, words, answers, iterations)));
+    if (eps > GD_EPS_MAX)
+        GD_DISPATCH_D(d, (merge_pairs_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                             rows, pairs, npairs, (uint64_t)(eps * eps), (double)eps, words, answers, iterations)));
+    else
+        GD_DISPATCH_D(d, (merge_pairs_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+                             rows, pairs, npairs, (uint64_t)(eps * eps), (double)eps, words, answers, iterations)));
     return hipGetLastError();
 }
 

@@ -27,11 +27,11 @@ namespace gd {
 
 constexpr int kWalkQueries = 4;  // queries of one grid evaluated per walk
 
-template <int D>
-__device__ __forceinline__ uint32_t sqdist_rows(const int32_t (&a)[D], const int32_t (&b)[D]) {
-    uint32_t dd = 0;
+template <int D, bool kWide>
+__device__ __forceinline__ typename Dist<kWide>::T sqdist_rows(const int32_t (&a)[D], const int32_t (&b)[D]) {
+    typename Dist<kWide>::T dd = 0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) dd += sq24(a[j], b[j]);
+    for (int j = 0; j < D; ++j) dd += sqd<kWide>(a[j], b[j]);
     return dd;
 }
 
@@ -42,7 +42,7 @@ __device__ __forceinline__ int64_t walk_grid(int64_t nblocks) {
     return xcd_runs<16>(blockIdx.x, nblocks) * kBlock + threadIdx.x;
 }
 
-template <int D, bool kStats>
+template <int D, bool kStats, bool kWide>
 __global__ __launch_bounds__(kBlock) void core_walk_kernel(GridView gv, TreeView t, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
     const int64_t c = walk_grid(gridDim.x);
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void core_walk_kernel(GridView gv, TreeView
         core_cnt[c] = k;
         return;
     }
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I);
     const uint32_t need = minpts - k;  // hits still needed beyond the own grid
     const int dk = I.d;
     int32_t g[D + 1];
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void core_walk_kernel(GridView gv, TreeView
                 for (int u = 0; u < kWalkQueries; ++u) {
                     if (!((open >> u) & 1u)) continue;
                     if constexpr (kStats) ++ndist;
-                    if (sqdist_rows<D>(q[u], y) <= T && ++hits[u] >= need) open &= ~(1u << u);
+                    if (sqdist_rows<D, kWide>(q[u], y) <= T && ++hits[u] >= need) open &= ~(1u << u);
                 }
                 if (!open) return false;  // every query reached MinPts
             }
@@ -112,14 +112,17 @@ __global__ __launch_bounds__(kBlock) void core_walk_kernel(GridView gv, TreeView
 }
 
 hipError_t launch_core_walk(const GridView& g, const TreeView& t, uint8_t* core, uint32_t* core_cnt, CoreStats* stats,
-                            hipStream_t st) {
+                            bool wide, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    const unsigned blocks = grid_for(g.ncell);
-    if (stats) {
-        GD_DISPATCH_D(g.D, (core_walk_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, t, core, core_cnt, stats)));
-    } else {
-        GD_DISPATCH_D(g.D, (core_walk_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(g, t, core, core_cnt, stats)));
-    }
+    const dim3 blocks(grid_for(g.ncell)), threads(kBlock);
+    if (stats && wide)
+        GD_DISPATCH_D(g.D, (core_walk_kernel<D, true, true><<<blocks, threads, 0, st>>>(g, t, core, core_cnt, stats)));
+    else if (stats)
+        GD_DISPATCH_D(g.D, (core_walk_kernel<D, true, false><<<blocks, threads, 0, st>>>(g, t, core, core_cnt, stats)));
+    else if (wide)
+        GD_DISPATCH_D(g.D, (core_walk_kernel<D, false, true><<<blocks, threads, 0, st>>>(g, t, core, core_cnt, stats)));
+    else
+        GD_DISPATCH_D(g.D, (core_walk_kernel<D, false, false><<<blocks, threads, 0, st>>>(g, t, core, core_cnt, stats)));
     return hipGetLastError();
 }
 
@@ -127,7 +130,7 @@ hipError_t launch_core_walk(const GridView& g, const TreeView& t, uint8_t* core,
 // visiting order: every neighbour with a larger identifier that is also a
 // tiny core grid is a candidate; a pair already in one set is skipped,
 // otherwise its |s_i| x |s_j| distances decide it.
-template <int D, bool kStats>
+template <int D, bool kStats, bool kWide>
 __global__ __launch_bounds__(kBlock) void merge_walk_kernel(GridView gv, CoreOut co, TreeView t,
                                                             const uint32_t* __restrict__ ldf, int64_t r1,
                                                             const uint32_t* split, uint32_t* parent,
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void merge_walk_kernel(GridView gv, CoreOut
     if (mi == 0 || mi > kTinyCore) return;
     const uint32_t bi = co.core_begin[ci];
     const Inst& I = cell_inst(gv, ci);
-    const uint32_t T = I.Tm;  // the merge's "yes" bound (eps^2 unless approximate)
+    const typename Dist<kWide>::T T = inst_Tm<kWide>(I);  // the merge's "yes" bound (eps^2 unless approximate)
     const int dk = I.d;
     int32_t pi[kTinyCore][D];
 #pragma unroll
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void merge_walk_kernel(GridView gv, CoreOut
             load_row<D>(co.ccrd, bj + b, y);
 #pragma unroll
             for (int a = 0; a < (int)kTinyCore; ++a)
-                if ((uint32_t)a < mi) yes |= sqdist_rows<D>(pi[a], y) <= T;
+                if ((uint32_t)a < mi) yes |= sqdist_rows<D, kWide>(pi[a], y) <= T;
         }
         if constexpr (kStats) {
             n_dist += (unsigned long long)mi * mj;
@@ -194,27 +197,32 @@ __global__ __launch_bounds__(kBlock) void merge_walk_kernel(GridView gv, CoreOut
 }
 
 hipError_t launch_merge_walk(const GridView& g, const CoreOut& c, const TreeView& t, const uint32_t* ldf_list,
-                             int64_t n_small, uint32_t* parent, MergeStats* stats, hipStream_t st) {
+                             int64_t n_small, uint32_t* parent, MergeStats* stats, bool wide, hipStream_t st) {
     // n_small >= 0: the first n_small ranks are the tiny core grids; -2: as
     // many as the device count says
     const uint32_t* split = n_small == -2 ? &c.counts[4] : nullptr;
     const int64_t r1 = n_small >= 0 ? n_small : g.ncell;
     if (r1 <= 0) return hipSuccess;
-    const unsigned blocks = grid_for(r1);
-    if (stats) {
-        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, t, ldf_list, r1, split, parent, stats)));
-    } else {
-        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, t, ldf_list, r1, split, parent, stats)));
-    }
+    const dim3 blocks(grid_for(r1)), threads(kBlock);
+    if (stats && wide)
+        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, true, true><<<blocks, threads, 0, st>>>(g, c, t, ldf_list, r1, split,
+                                                                                        parent, stats)));
+    else if (stats)
+        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, true, false><<<blocks, threads, 0, st>>>(g, c, t, ldf_list, r1, split,
+                                                                                         parent, stats)));
+    else if (wide)
+        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, false, true><<<blocks, threads, 0, st>>>(g, c, t, ldf_list, r1, split,
+                                                                                         parent, stats)));
+    else
+        GD_DISPATCH_D(g.D, (merge_walk_kernel<D, false, false><<<blocks, threads, 0, st>>>(g, c, t, ldf_list, r1,
+                                                                                          split, parent, stats)));
     return hipGetLastError();
 }
 
 // One thread per grid holding a non-core point: its core points take the
 // grid's label, its non-core points the label of their lowest-index core
 // neighbour (own grid first: all of its points are within eps), else -1.
-template <int D>
+template <int D, bool kWide>
 __global__ __launch_bounds__(kBlock) void border_walk_kernel(GridView gv, CoreOut co, TreeView t,
                                                              const int32_t* __restrict__ cell_label) {
     const int64_t c = walk_grid(gridDim.x);
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void border_walk_kernel(GridView gv, CoreOu
     uint8_t GD_GLOBAL* __restrict__ core_flags = as_global(I.core);
     const int32_t own_label = cell_label[c];
     const uint32_t own_min = co.cell_min_core[c];
-    const uint32_t T = I.T;
+    const typename Dist<kWide>::T T = inst_T<kWide>(I);
     const int dk = I.d;
     const uint64_t own_best = own_min == kNone ? ~0ull : (((uint64_t)own_min << 32) | (uint32_t)own_label);
     int32_t g[D + 1];
@@ -287,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void border_walk_kernel(GridView gv, CoreOu
                 const uint64_t cand = ((uint64_t)co.corig[r] << 32) | (uint32_t)lab;
 #pragma unroll
                 for (int u = 0; u < kWalkQueries; ++u)
-                    if (u < nq && cand < best[u] && sqdist_rows<D>(q[u], y) <= T) best[u] = cand;
+                    if (u < nq && cand < best[u] && sqdist_rows<D, kWide>(q[u], y) <= T) best[u] = cand;
             }
             return true;
         };
@@ -303,9 +311,13 @@ __global__ __launch_bounds__(kBlock) void border_walk_kernel(GridView gv, CoreOu
 }
 
 hipError_t launch_border_walk(const GridView& g, const CoreOut& c, const TreeView& t, const int32_t* cell_label,
-                              hipStream_t st) {
+                              bool wide, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    GD_DISPATCH_D(g.D, (border_walk_kernel<D><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, t, cell_label)));
+    const dim3 blocks(grid_for(g.ncell)), threads(kBlock);
+    if (wide)
+        GD_DISPATCH_D(g.D, (border_walk_kernel<D, true><<<blocks, threads, 0, st>>>(g, c, t, cell_label)));
+    else
+        GD_DISPATCH_D(g.D, (border_walk_kernel<D, false><<<blocks, threads, 0, st>>>(g, c, t, cell_label)));
     return hipGetLastError();
 }
 

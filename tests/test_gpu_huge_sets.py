@@ -19,22 +19,23 @@ EPS, MINPTS = 100, 5
 BIG = 300_000
 
 
-def boxes(seed):
+def boxes(seed, scale=1):
     """Points and their cluster by construction (-1: noise; the border point
-    gets the cluster of its core neighbours)."""
+    gets the cluster of its core neighbours), for eps = 100 * scale."""
     rng = np.random.default_rng(seed)
 
     def box(m, x0, x1, y0, y1):
-        return np.stack([rng.integers(x0, x1 + 1, m), rng.integers(y0, y1 + 1, m)], axis=1)
+        return np.stack([rng.integers(x0 * scale, x1 * scale + 1, m), rng.integers(y0 * scale, y1 * scale + 1, m)],
+                        axis=1)
 
     parts = [
         (box(BIG, 0, 40, 0, 40), 0),          # A
         (box(BIG, 81, 121, 0, 40), 0),        # B: 41 from A
         (box(BIG, 230, 270, 0, 40), 1),       # C: 109 from B, apart
         (box(50, 300, 310, 0, 10), 1),        # D: a small set inside C's reach
-        (np.array([[-50, 0], [-50, 1], [-50, 2]]), 0),   # E: tiny core set next to A
-        (np.array([[-140, 0]]), 0),           # border: 90 from E, 4 neighbours with itself
-        (np.array([[20_000 + 1000 * k, 5000] for k in range(10)]), -1),  # noise
+        (np.array([[-50, 0], [-50, 1], [-50, 2]]) * scale, 0),   # E: tiny core set next to A
+        (np.array([[-140, 0]]) * scale, 0),   # border: 90 from E, 4 neighbours with itself
+        (np.array([[20_000 + 1000 * k, 5000] for k in range(10)]) * scale, -1),  # noise
     ]
     x = np.concatenate([p for p, _ in parts]).astype(np.int32)
     cl = np.concatenate([np.full(len(p), c) for p, c in parts])
@@ -42,10 +43,10 @@ def boxes(seed):
     return np.ascontiguousarray(x[perm]), cl[perm]
 
 
-def expected(x, cl):
+def expected(x, cl, scale=1):
     """Canonical labels: a cluster's id is its smallest core index; the
     border point (the only non-core point of a cluster) takes its cluster's."""
-    border = np.nonzero((x[:, 0] == -140) & (x[:, 1] == 0))[0]
+    border = np.nonzero((x[:, 0] == -140 * scale) & (x[:, 1] == 0))[0]
     core = (cl >= 0).astype(np.uint8)
     core[border] = 0
     lab = np.full(len(x), -1, np.int64)
@@ -78,19 +79,20 @@ def run(ctx, x):
     return lab.cpu().numpy(), core.cpu().numpy()
 
 
-def test_construction_pinned_on_a_sample():
-    # the same recipe, boxes scaled down so the oracle's pair scan is quick:
+@pytest.mark.parametrize("seed,scale", [(3, 1), (4, 300)])
+def test_construction_pinned_on_a_sample(seed, scale):
+    # the same recipe, boxes thinned out so the oracle's pair scan is quick:
     # the clusters must be the ones the construction names
-    x, cl = boxes(3)
+    x, cl = boxes(seed, scale)
     keep = np.zeros(len(x), bool)
     rng = np.random.default_rng(0)
     for c in (0, 1):
         idx = np.nonzero(cl == c)[0]
         keep[rng.choice(idx, size=min(len(idx), 4000), replace=False)] = True
-    keep[(x[:, 0] <= -50) | (x[:, 0] >= 300)] = True  # every E, D, border and noise point
+    keep[(x[:, 0] <= -50 * scale) | (x[:, 0] >= 300 * scale)] = True  # every E, D, border and noise point
     xs, cs = x[keep], cl[keep]
-    lab, core = oracle.dbscan(xs, EPS, MINPTS)
-    want_l, want_c = expected(xs, cs)
+    lab, core = oracle.dbscan(xs, EPS * scale, MINPTS)
+    want_l, want_c = expected(xs, cs, scale)
     assert np.array_equal(core, want_c) and np.array_equal(lab, want_l)
 
 
@@ -144,5 +146,24 @@ def test_oversized_core_sets_without_allocation(G, data):
     core = torch.empty(len(x), dtype=torch.uint8, device="cuda")
     print("case oversized core sets through dbscan_noalloc", flush=True)
     ctx.dbscan_noalloc(t, EPS, MINPTS, lab, core)
+    assert np.array_equal(core.cpu().numpy(), want_c) and np.array_equal(lab.cpu().numpy(), want_l)
+    ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("order", [1, 2])
+def test_oversized_core_sets_with_wide_distances(G, order):
+    # the same construction at eps = 30000, above the 32-bit distance bound
+    scale = 300
+    x, cl = boxes(4, scale)
+    ids = steps.cell_ids(x, EPS * scale)
+    _, counts = np.unique(ids, axis=0, return_counts=True)
+    assert counts.max() > 262_144
+    want_l, want_c = expected(x, cl, scale)
+    ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_MERGE_ORDER, order)
+    print(f"case oversized core sets, eps {EPS * scale}, order {order}", flush=True)
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    lab, core = ctx.dbscan(t, EPS * scale, MINPTS)
     assert np.array_equal(core.cpu().numpy(), want_c) and np.array_equal(lab.cpu().numpy(), want_l)
     ctx.close()
