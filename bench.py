@@ -345,6 +345,118 @@ def bench_neighbor_modes(G, steps, warmup):
     return out
 
 
+def time_calls(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def bench_batched(G, steps, warmup, max_instances):
+    """The 256-instance workload: one dbscan_batched() call versus one
+    dbscan() call per instance, same GPU, identical results."""
+    import torch
+    ws = W.batch_workloads()[:max_instances]
+    log(f"bench: generating {len(ws)} batch instances")
+    probs = []
+    for w in ws:
+        x = W.make_points(w)
+        probs.append((torch.from_numpy(x.astype(np.float32)).cuda(), w.eps, w.minpts))
+    total = sum(int(p[0].shape[0]) for p in probs)
+    ctx = G.Context(0)
+    tuned, trials = ctx.autotune(probs)
+    log(f"bench: autotuned {tuned}")
+    outs = ctx.dbscan_batched(probs)
+    for (t, e, m), (lab, core) in zip(probs[:8], outs[:8]):
+        l1, c1 = ctx.dbscan(t, e, m)
+        if not (torch.equal(l1, lab) and torch.equal(c1, core)):
+            raise RuntimeError("batched and single-instance results differ")
+    t_batch = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
+    replayed = ctx.stats()["graph_replays"] == 1
+    log(f"bench: batched {1e3 * t_batch:.2f} ms (graph replay: {replayed})")
+    ctx.set_option(G.GD_OPT_GRAPH, 0)
+    t_batch_eager = time_calls(lambda: ctx.dbscan_batched(probs, outs=outs), steps, warmup)
+    log(f"bench: batched without graph {1e3 * t_batch_eager:.2f} ms")
+    ctx.set_option(G.GD_OPT_TIMING, 1)
+    ctx.dbscan_batched(probs, outs=outs)
+    batch_phases = {k: round(v, 4) for k, v in ctx.phase_times().items()}
+    ctx.set_option(G.GD_OPT_TIMING, 0)
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    ctx.dbscan_batched(probs, outs=outs)
+    bst = ctx.stats()
+    ctx.set_option(G.GD_OPT_STATS, 0)
+
+    def each():
+        for (t, e, m), (lab, core) in zip(probs, outs):
+            ctx.dbscan(t, e, m, lab, core)
+    t_each = time_calls(each, max(1, steps // 2), 1)
+    log(f"bench: one call per instance {1e3 * t_each:.2f} ms")
+    ctx.close()
+    return {
+        "workload": f"{len(ws)} instances: n log-uniform [1e3,1e6], d in {{2,3}}, gaussian blobs + 10% noise, "
+                    "eps in [50,300], minpts in [5,50]",
+        "instances": len(ws), "points": total,
+        "value": round(total / t_batch, 1), "ms_per_batch": round(1e3 * t_batch, 3),
+        "plain_value": round(total / t_each, 1), "plain_ms_per_batch": round(1e3 * t_each, 3),
+        "speedup_vs_plain": round(t_each / t_batch, 3), "unit": "points/s",
+        "autotuned": tuned, "autotune_trials_ms": {f"{r['tile_points']}x{r['merge_waves']}": round(r["ms"], 3)
+                                                   for r in trials},
+        "graph_replay": replayed, "no_graph_value": round(total / t_batch_eager, 1),
+        "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3), "phases_ms": batch_phases,
+        "work": {k: bst[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids", "merge_tests",
+                                     "merge_distances", "core_distances", "key_bits")},
+    }
+
+
+def bench_learned(G, steps, warmup):
+    """The dense seed-spreader workload (n=20M, d=3): the trained proposal
+    versus the plain merge, same GPU, identical labels."""
+    import torch
+    from paper_2210_07580_amd import proposal as P
+    w = W.WORKLOADS["cfg4"]
+    pts = points("cfg4")
+    n = int(pts.shape[0])
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    core = torch.empty(n, dtype=torch.uint8, device="cuda")
+    ctx = G.Context(0)
+    res = {}
+    ref = None
+    for name, blob in (("plain", None), ("learned", P.load_blob())):
+        ctx.set_proposal(blob)
+        t = time_calls(lambda: ctx.dbscan(pts, w.eps, w.minpts, lab, core), steps, warmup)
+        # the merge phase alone, from calls with phase events
+        ctx.set_option(G.GD_OPT_TIMING, 1)
+        merge_ms = []
+        for _ in range(steps):
+            ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+            merge_ms.append(ctx.phase_times()["merge"])
+        ctx.set_option(G.GD_OPT_TIMING, 0)
+        ctx.set_option(G.GD_OPT_STATS, 1)
+        ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+        st = ctx.stats()
+        ctx.set_option(G.GD_OPT_STATS, 0)
+        out = (lab.clone(), core.clone())
+        if ref is None:
+            ref = out
+        elif not (torch.equal(ref[0], out[0]) and torch.equal(ref[1], out[1])):
+            raise RuntimeError("learned proposal changed the labels")
+        res[name] = {"value": round(n / t, 1), "ms_per_step": round(1e3 * t, 3),
+                     "merge_ms": round(float(np.mean(merge_ms)), 4),
+                     "merge_tests": st["merge_tests"], "merge_distances": st["merge_distances"],
+                     "merge_iterations": st["merge_iterations"]}
+        log(f"bench: {name} {res[name]}")
+    ctx.close()
+    return {"workload": "seed-spreader n=20M d=3 eps=150 minpts=50 (300 pts/step)", "unit": "points/s",
+            "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
+            "speedup_vs_plain": round(res["learned"]["value"] / res["plain"]["value"], 3),
+            "plain": res["plain"], "learned": res["learned"]}
+
+
 def sweep_points(dims, kinds, axes):
     """(kind, d, n, eps, minpts) of every sweep point, each once, grouped by
     point set."""
