@@ -404,8 +404,10 @@ def bench_batched(G, steps, warmup, max_instances):
         "value": round(total / t_batch, 1), "ms_per_batch": round(1e3 * t_batch, 3),
         "plain_value": round(total / t_each, 1), "plain_ms_per_batch": round(1e3 * t_each, 3),
         "speedup_vs_plain": round(t_each / t_batch, 3), "unit": "points/s",
-        "autotuned": tuned, "autotune_trials_ms": {f"{r['tile_points']}x{r['merge_waves']}": round(r["ms"], 3)
-                                                   for r in trials},
+        "autotuned": tuned,
+        "autotune_trials_ms": {f"tile{r['tile_points']}_waves{r['merge_waves']}_lanes{r['grid_lanes']}":
+                               round(r["ms"], 3) for r in trials},
+        "autotune_spread": round(max(r["ms"] for r in trials) / min(r["ms"] for r in trials), 3) if trials else None,
         "graph_replay": replayed, "no_graph_value": round(total / t_batch_eager, 1),
         "no_graph_ms_per_batch": round(1e3 * t_batch_eager, 3), "phases_ms": batch_phases,
         "work": {k: bst[k] for k in ("grids", "neighbor_entries", "core_points", "core_grids", "merge_tests",

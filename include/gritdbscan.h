@@ -256,7 +256,7 @@ typedef enum {
                                  clusters and lies inside one component of the
                                  core points' (eps + delta)-graph.  Labels are
                                  then NOT those of dbscan(): an opt-in mode.  */
-    GD_OPT_NEIGHBOR_QUERY = 11 /* how the lists Nei(g) are found: 0 (default)
+    GD_OPT_NEIGHBOR_QUERY = 11, /* how the lists Nei(g) are found: 0 (default)
                                  the grid tree of Algorithm 3, lists ordered by
                                  offset (Eq. (2)) for at most 2^20 grids and in
                                  walk order above; 1 the grid tree, lists in
@@ -267,6 +267,11 @@ typedef enum {
                                  by offset (the query the grid tree avoids;
                                  candidates grow as (2 ceil(sqrt(d)) + 1)^d).
                                  The result is the same for every query.      */
+    GD_OPT_GRID_LANES = 12    /* lanes per grid in the kernels that serve
+                                 small grids (the merging of tiny core sets):
+                                 0 (default) chooses from the mean list length
+                                 (16 when it is at most 40, else 64), 16 (four
+                                 grids per wave) or 64 (one).  Same result.   */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);
@@ -275,21 +280,37 @@ int gd_set_option(gd_ctx *ctx, int option, int64_t value);
 typedef struct {
     int32_t tile_points;   /* GD_OPT_TILE_POINTS */
     int32_t merge_waves;   /* GD_OPT_MERGE_WAVES */
+    int32_t grid_lanes;    /* GD_OPT_GRID_LANES */
     double ms;             /* best wall time of the call, milliseconds */
 } gd_tuning;
 
 /*
  * gd_autotune: time dbscan_batched() on the caller's batch (HOST descriptor
  * array, as for dbscan_batched) under every tunable configuration (tile
- * points 1024/2048/4096/8192 x merge waves 1/2/4; two calls each, without
- * graph replay) and keep the fastest in the context.  Every configuration
- * gives the same result; the outputs hold the last run's.  `results` (HOST,
- * up to max_results entries, may be NULL) receives the timings and
- * *n_results their number.  The tunables are not saved across contexts: a
- * caller that wants to keep them reads the timings and sets the options.
+ * points 1024/4096 x merge waves 1/2/4 x lanes per small grid 16/64; the
+ * median of three calls each, after one untimed call, without graph replay)
+ * and keep the fastest in the context.  Every configuration gives the same
+ * result; the outputs hold the last run's.  `results` (HOST, up to
+ * max_results entries, may be NULL) receives the timings and *n_results
+ * their number.
+ *
+ * With a tuning file (gd_set_tuning_file) the batch's shape key (instance
+ * count, total points and largest n rounded to powers of two, the range of
+ * d) is looked up first: a stored configuration is applied without timing
+ * anything (*n_results = 0); otherwise the search runs and its winner is
+ * added to the file.
  */
 int gd_autotune(gd_ctx *ctx, const gd_instance *inst, int32_t count, void *stream, gd_tuning *results,
                 int32_t max_results, int32_t *n_results);
+
+/*
+ * gd_set_tuning_file: the JSON file of tuned configurations gd_autotune
+ * reads and extends, an object mapping shape keys to
+ * {"tile_points": .., "merge_waves": .., "grid_lanes": .., "ms": ..}
+ * (HOST string, copied; NULL or "" switches the file off).  A missing file
+ * is created on the first search; an unreadable entry is ignored.
+ */
+int gd_set_tuning_file(gd_ctx *ctx, const char *path);
 
 /* Copy the counters of the last successful dbscan() call. */
 int gd_get_stats(gd_ctx *ctx, gd_stats *out);

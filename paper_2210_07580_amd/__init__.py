@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
 GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES, GD_OPT_NEIGHBOR_MODE, GD_OPT_MERGE_ORDER = 6, 7, 8, 9
-GD_OPT_APPROX_DELTA, GD_OPT_NEIGHBOR_QUERY = 10, 11
+GD_OPT_APPROX_DELTA, GD_OPT_NEIGHBOR_QUERY, GD_OPT_GRID_LANES = 10, 11, 12
 NOALLOC_SCRATCH_BYTES = 256 << 20
 PHASE_COUNT = 14
 EPS_MAX = 21845  # largest eps of the 32-bit distance path (GD_EPS_MAX); larger eps use 64 bits
@@ -47,7 +47,8 @@ class Stats(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_points", ctypes.c_int32), ("merge_waves", ctypes.c_int32), ("ms", ctypes.c_double)]
+    _fields_ = [("tile_points", ctypes.c_int32), ("merge_waves", ctypes.c_int32), ("grid_lanes", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 class Instance(ctypes.Structure):
@@ -61,7 +62,8 @@ _lib = None
 EXPORTS = ("gd_create", "gd_destroy", "dbscan", "dbscan_noalloc", "dbscan_batched", "gd_set_option", "gd_get_stats",
            "gd_debug_grids", "gd_debug_neighbors", "gd_debug_core", "gd_merge_test",
            "gd_get_phase_times", "gd_phase_name", "gd_set_proposal", "gd_proposal_harvest",
-           "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string", "gd_autotune")
+           "gd_mlp_train", "gd_mlp_grad", "gd_mlp_forward", "gd_last_error", "gd_status_string", "gd_autotune",
+           "gd_set_tuning_file")
 MLP_PARAMS = 5378
 MLP_FEATURES = 16
 
@@ -116,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.gd_autotune.argtypes = [vp, ctypes.POINTER(Instance), i32, vp, ctypes.POINTER(Tuning), i32,
                                 ctypes.POINTER(i32)]
     lib.gd_autotune.restype = ctypes.c_int
+    lib.gd_set_tuning_file.argtypes = [vp, ctypes.c_char_p]
+    lib.gd_set_tuning_file.restype = ctypes.c_int
     lib.gd_last_error.argtypes = [vp]
     lib.gd_last_error.restype = ctypes.c_char_p
     lib.gd_status_string.argtypes = [ctypes.c_int]
@@ -232,15 +236,22 @@ class Context:
 
     def autotune(self, problems, stream=None):
         """Time the batch under every tunable configuration and keep the
-        fastest.  Returns (chosen {tile_points, merge_waves}, all timings)."""
+        fastest (or apply the tuning file's entry for this batch shape).
+        Returns (chosen {tile_points, merge_waves, grid_lanes} or None when
+        the file supplied it, all timings)."""
         descs, _, keep = self._descriptors(problems)
         res = (Tuning * 64)()
         cnt = ctypes.c_int32()
         self._check(load_library().gd_autotune(self._h, descs, len(problems), _stream_handle(stream), res, 64,
                                                ctypes.byref(cnt)))
-        rows = [{"tile_points": r.tile_points, "merge_waves": r.merge_waves, "ms": r.ms} for r in res[:cnt.value]]
+        rows = [{"tile_points": r.tile_points, "merge_waves": r.merge_waves, "grid_lanes": r.grid_lanes, "ms": r.ms}
+                for r in res[:cnt.value]]
         best = min(rows, key=lambda r: r["ms"]) if rows else None
-        return ({"tile_points": best["tile_points"], "merge_waves": best["merge_waves"]} if best else None), rows
+        return ({k: best[k] for k in ("tile_points", "merge_waves", "grid_lanes")} if best else None), rows
+
+    def set_tuning_file(self, path):
+        """JSON file of tuned configurations by batch shape (None: off)."""
+        self._check(load_library().gd_set_tuning_file(self._h, None if path is None else os.fsencode(path)))
 
     def dbscan_batched(self, problems, stream=None, outs=None):
         """Cluster many instances in one pass.  ``problems``: list of

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -142,6 +143,8 @@ struct gd_ctx {
     // launch tunables (gd_autotune)
     int tile_pts = kPointTile;       // points per workgroup of the point kernels
     int merge_waves = kWavesPerBlock; // waves per workgroup of the FastMerging kernel
+    int grid_lanes = 0;               // GD_OPT_GRID_LANES (0: from the mean list length)
+    std::string tuning_file;          // gd_set_tuning_file (empty: none)
     uint64_t generation = 0;         // bumped whenever a buffer is reallocated
     hipStream_t gstream = nullptr;   // capture and replay stream
     hipEvent_t gev = nullptr;
@@ -498,6 +501,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if ((rc = grow(ctx, ctx->cur->arena, carve(nullptr, n, D, tiles, kbytes).bytes, ctx->cur->nei.cap))) return rc;
         L = carve((char*)ctx->cur->arena.p, n, D, tiles, kbytes);
     }
+    // the narrowest word that holds the identifiers (32-bit identifiers sort
+    // and carry packed rows as one-word keys; the buffers carved for a wider
+    // word hold them too)
+    kbytes = key_bytes_of(key_bits);
     if (kbytes > 8 && ctx->nei_query == kNeiHash)
         return ctx->fail(GD_EUNSUPPORTED, "the hashing neighbour query takes identifiers of at most 64 bits (%d here)",
                          key_bits);
@@ -715,7 +722,11 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if (walk)
             GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, wide,
                                      st));
-        GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves, walk,
+        // lanes per tiny grid: short lists leave most of a wave per grid idle
+        const int small_lanes = ctx->grid_lanes ? ctx->grid_lanes
+                                                : (nei_total <= 40 * (uint64_t)std::max<int64_t>(ncell, 1) ? 16 : 64);
+        GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves,
+                            small_lanes, walk,
                             hm.q, wide, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                             ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
         GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, false, wide, nullptr, nullptr, nullptr,
@@ -911,6 +922,7 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
     sig.push_back(ctx->proposal_on ? 1 : 0);
     sig.push_back(ctx->tile_pts);
     sig.push_back(ctx->merge_waves);
+    sig.push_back(ctx->grid_lanes);
     for (int k = 0; k < count; ++k) {
         sig.push_back(ctx->inst_host[k].n);
         sig.push_back(ctx->inst_host[k].d);
@@ -1012,6 +1024,93 @@ int run_call(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStream
 }
 
 }  // namespace
+
+// ---- Tuning file: a flat JSON object {"<shape key>": {"tile_points": t,
+// "merge_waves": w, "grid_lanes": l, "ms": m}, ...} written and read here.
+
+static int ilog2_ceil(int64_t v) {
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+// Shape key of a batch: instance count, total points and largest n as powers
+// of two (rounded up), and the range of d.
+static std::string tuning_key(const gd_instance* inst, int count) {
+    int64_t total = 0, nmax = 0;
+    int dmin = GD_D_MAX, dmax = 1;
+    for (int k = 0; k < count; ++k) {
+        total += inst[k].n;
+        nmax = std::max<int64_t>(nmax, inst[k].n);
+        dmin = std::min(dmin, (int)inst[k].d);
+        dmax = std::max(dmax, (int)inst[k].d);
+    }
+    char buf[128];
+    std::snprintf(buf, sizeof(buf), "count=%d;points=2^%d;nmax=2^%d;d=%d-%d", count, ilog2_ceil(total),
+                  ilog2_ceil(nmax), dmin, dmax);
+    return buf;
+}
+
+// Entries of a tuning file (an unreadable file or entry is skipped).
+static std::map<std::string, gd_tuning> read_tuning_file(const std::string& path) {
+    std::map<std::string, gd_tuning> out;
+    FILE* f = std::fopen(path.c_str(), "rb");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    auto field = [](const std::string& obj, const char* name, double& v) -> bool {
+        const std::string tag = std::string("\"") + name + "\"";
+        const size_t p = obj.find(tag);
+        if (p == std::string::npos) return false;
+        const size_t c = obj.find(':', p + tag.size());
+        if (c == std::string::npos) return false;
+        char* end = nullptr;
+        v = std::strtod(obj.c_str() + c + 1, &end);
+        return end != obj.c_str() + c + 1;
+    };
+    size_t pos = text.find('{');
+    while (pos != std::string::npos) {
+        const size_t k0 = text.find('"', pos + 1);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = text.find('"', k0 + 1);
+        const size_t o0 = k1 == std::string::npos ? k1 : text.find('{', k1);
+        const size_t o1 = o0 == std::string::npos ? o0 : text.find('}', o0);
+        if (o1 == std::string::npos) break;
+        const std::string key = text.substr(k0 + 1, k1 - k0 - 1), obj = text.substr(o0, o1 - o0 + 1);
+        double t = 0, w = 0, l = 0, ms = 0;
+        if (field(obj, "tile_points", t) && field(obj, "merge_waves", w) && field(obj, "grid_lanes", l)) {
+            (void)field(obj, "ms", ms);
+            out[key] = gd_tuning{(int32_t)t, (int32_t)w, (int32_t)l, ms};
+        }
+        pos = o1;
+    }
+    return out;
+}
+
+static bool write_tuning_file(const std::string& path, const std::map<std::string, gd_tuning>& entries) {
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& e : entries) {
+        std::fprintf(f, "  \"%s\": {\"tile_points\": %d, \"merge_waves\": %d, \"grid_lanes\": %d, \"ms\": %.4f}%s\n",
+                     e.first.c_str(), e.second.tile_points, e.second.merge_waves, e.second.grid_lanes, e.second.ms,
+                     ++i < entries.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+static bool valid_tuning(const gd_tuning& t) {
+    return t.tile_points >= 256 && t.tile_points <= 65536 && t.tile_points % 256 == 0 &&
+           (t.merge_waves == 1 || t.merge_waves == 2 || t.merge_waves == 4) &&
+           (t.grid_lanes == 0 || t.grid_lanes == 16 || t.grid_lanes == 64);
+}
 
 extern "C" {
 
@@ -1151,38 +1250,63 @@ int dbscan_batched(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* st
     return run_call(ctx, count, D, total, tiles, (hipStream_t)stream, true);
 }
 
+int gd_set_tuning_file(gd_ctx* ctx, const char* path) {
+    if (!ctx) return GD_EINVAL;
+    ctx->err.clear();
+    ctx->tuning_file = path ? path : "";
+    return GD_OK;
+}
+
 int gd_autotune(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* stream, gd_tuning* results,
                 int32_t max_results, int32_t* n_results) {
     if (!ctx) return GD_EINVAL;
     ctx->err.clear();
-    static const int kTiles[] = {1024, 2048, 4096, 8192};
+    if (n_results) *n_results = 0;
+    if (count < 0 || (count > 0 && !inst)) return ctx->fail(GD_EINVAL, "bad batch descriptor");
+    const std::string key = tuning_key(inst, count);
+    std::map<std::string, gd_tuning> file;
+    if (!ctx->tuning_file.empty()) {
+        file = read_tuning_file(ctx->tuning_file);
+        const auto it = file.find(key);
+        if (it != file.end() && valid_tuning(it->second)) {
+            ctx->tile_pts = it->second.tile_points;
+            ctx->merge_waves = it->second.merge_waves;
+            ctx->grid_lanes = it->second.grid_lanes;
+            return GD_OK;
+        }
+    }
+    static const int kTiles[] = {1024, 4096};
     static const int kWaves[] = {1, 2, 4};
-    const int saved_tile = ctx->tile_pts, saved_waves = ctx->merge_waves, saved_graph = ctx->graph_mode;
+    static const int kLanes[] = {16, 64};
+    const int saved_tile = ctx->tile_pts, saved_waves = ctx->merge_waves, saved_lanes = ctx->grid_lanes;
+    const int saved_graph = ctx->graph_mode;
     const bool saved_stats = ctx->stats, saved_timing = ctx->timing;
     ctx->graph_mode = 0;
     ctx->stats = false;
     ctx->timing = false;
-    double best = 1e300;
-    int best_tile = saved_tile, best_waves = saved_waves, k = 0, rc = GD_OK;
+    gd_tuning best{saved_tile, saved_waves, saved_lanes, 1e300};
+    int k = 0, rc = GD_OK;
     for (int tile : kTiles) {
         for (int waves : kWaves) {
-            ctx->tile_pts = tile;
-            ctx->merge_waves = waves;
-            double ms = 1e300;
-            for (int rep = 0; rep < 2 && rc == GD_OK; ++rep) {  // the first run also warms the workspace
-                const auto t0 = std::chrono::steady_clock::now();
-                rc = dbscan_batched(ctx, inst, count, stream);
-                const auto t1 = std::chrono::steady_clock::now();
-                ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+            for (int lanes : kLanes) {
+                ctx->tile_pts = tile;
+                ctx->merge_waves = waves;
+                ctx->grid_lanes = lanes;
+                double t[4];
+                for (int rep = 0; rep < 4 && rc == GD_OK; ++rep) {  // the first call also warms the workspace
+                    const auto t0 = std::chrono::steady_clock::now();
+                    rc = dbscan_batched(ctx, inst, count, stream);
+                    const auto t1 = std::chrono::steady_clock::now();
+                    t[rep] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+                }
+                if (rc != GD_OK) break;
+                std::sort(t + 1, t + 4);
+                const gd_tuning row{tile, waves, lanes, t[2]};
+                if (results && k < max_results) results[k] = row;
+                ++k;
+                if (row.ms < best.ms) best = row;
             }
             if (rc != GD_OK) break;
-            if (results && k < max_results) results[k] = gd_tuning{tile, waves, ms};
-            ++k;
-            if (ms < best) {
-                best = ms;
-                best_tile = tile;
-                best_waves = waves;
-            }
         }
         if (rc != GD_OK) break;
     }
@@ -1193,10 +1317,17 @@ int gd_autotune(gd_ctx* ctx, const gd_instance* inst, int32_t count, void* strea
     if (rc != GD_OK) {
         ctx->tile_pts = saved_tile;
         ctx->merge_waves = saved_waves;
+        ctx->grid_lanes = saved_lanes;
         return rc;
     }
-    ctx->tile_pts = best_tile;
-    ctx->merge_waves = best_waves;
+    ctx->tile_pts = best.tile_points;
+    ctx->merge_waves = best.merge_waves;
+    ctx->grid_lanes = best.grid_lanes;
+    if (!ctx->tuning_file.empty()) {
+        file[key] = best;
+        if (!write_tuning_file(ctx->tuning_file, file))
+            return ctx->fail(GD_EINVAL, "cannot write the tuning file %s", ctx->tuning_file.c_str());
+    }
     return GD_OK;
 }
 
@@ -1222,6 +1353,11 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
         case GD_OPT_MERGE_WAVES:
             if (value != 1 && value != 2 && value != 4) return ctx->fail(GD_EINVAL, "merge waves must be 1, 2 or 4");
             ctx->merge_waves = (int)value;
+            return GD_OK;
+        case GD_OPT_GRID_LANES:
+            if (value != 0 && value != 16 && value != 64)
+                return ctx->fail(GD_EINVAL, "lanes per grid must be 0, 16 or 64");
+            ctx->grid_lanes = (int)value;
             return GD_OK;
         case GD_OPT_GRAPH:
             if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "graph mode must be 0, 1 or 2");

@@ -284,12 +284,14 @@ struct HugeQueue {
 };
 struct CellSummary;
 // waves: waves per workgroup of the FastMerging kernel (1, 2 or 4; fewer
-// if the LDS bitmaps do not fit).  n_small: tiny core grids leading the
+// if the LDS bitmaps do not fit).  small_lanes: lanes per grid of the
+// tiny-set kernel (16: four grids per wave; else 64).  n_small: tiny core grids leading the
 // visiting order (-2: as many as the device count says, -1: not ordered).
 // tiny_done: the pairs of two tiny core sets were already merged (walk mode).
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
-                        int64_t max_core, int waves, bool tiny_done, const HugeQueue& huge, bool wide,
+                        int64_t max_core, int waves, int small_lanes, bool tiny_done, const HugeQueue& huge,
+                        bool wide,
                         uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
                         hipStream_t st);
 // Sum over core grids with more than kMaxCoreBits core points of |Nei(g)| + 1

@@ -31,56 +31,70 @@ __device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsign
     atomicAdd(&sl->set_points, pts);
 }
 
-// Pairs of tiny core sets (both at most kSmallSet points).  One wave per tiny
-// core grid g_i; every lane takes one neighbouring tiny core grid g_j with a
-// larger grid index (each pair once, from its lower grid: the tiny core
-// grids are all visited by this one launch, so their order among themselves
-// is immaterial, and half of the list needs no load at all) and decides the
-// pair by evaluating its |s_i| x |s_j| distances directly: the answer
-// FastMerging gives (Theorem 2), without its wave-level iteration.  Each
-// lane first resolves its candidate's root and skips the pair when both
-// grids are already in one set; a yes joins the two roots.  s_i lives in
-// scalar registers.
-template <int D, bool kWide>
+// Pairs of tiny core sets (both at most kSmallSet points).  S lanes per tiny
+// core grid g_i (a wave serves 64 / S grids: with short lists, as with
+// millions of sparse grids, most of a wave per grid would idle); every lane
+// takes one neighbouring tiny core grid g_j with a larger grid index (each
+// pair once, from its lower grid: the tiny core grids are all visited by
+// this one launch, so their order among themselves is immaterial, and half
+// of the list needs no load at all) and decides the pair by evaluating its
+// |s_i| x |s_j| distances directly: the answer FastMerging gives
+// (Theorem 2), without its wave-level iteration.  Each lane first resolves
+// its candidate's root and skips the pair when both grids are already in
+// one set; a yes joins the two roots.  With S = 64, s_i lives in scalar
+// registers.
+template <int D, bool kWide, int S>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
                                                              const uint32_t* __restrict__ ldf,
                                                              const uint4* __restrict__ rank, int64_t r0, int64_t r1,
                                                              const uint32_t* split, uint32_t* parent,
                                                              MergeStats* stats) {
+    constexpr int G = kWave / S;  // grids per wave
     const int lane = lane_id();
-    const int64_t r = r0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
-    if (r >= r1 || r >= (int64_t)co.counts[1] || (split && r >= (int64_t)*split)) return;
-    const uint32_t ci = ldf[r];
+    const int grp = lane / S, sub = lane % S;
+    const uint64_t gmask = (S == kWave ? ~0ull : ((1ull << S) - 1ull)) << (grp * S);
+    const int64_t r = r0 + ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * G + grp;
+    // lanes of a group without a tiny core grid take an empty list, so that
+    // every lane reaches the closing reductions
+    bool live = r < r1 && r < (int64_t)co.counts[1] && !(split && r >= (int64_t)*split);
+    const uint32_t ci = live ? ldf[r] : 0u;
     // every load that depends on ci alone is issued before the first use
     // the merge's "yes" bound: eps^2, or (eps + delta)^2 when approximate
     const typename Dist<kWide>::T T = inst_Tm<kWide>(cell_inst(gv, ci));
-    const uint4 own = rank[ci];
-    const uint64_t e0 = nei_off[ci], e1 = nei_off[ci + 1];
+    const uint4 own = live ? rank[ci] : make_uint4(0u, 0u, 0u, 0u);
+    uint64_t e0 = live ? nei_off[ci] : 0, e1 = live ? nei_off[ci + 1] : 0;
     const uint32_t pci = load_acq(&parent[ci]);
     const uint32_t bi = own.y;
     const uint32_t mi = own.z;
-    if (mi > kSmallSet) return;
+    if (mi > kSmallSet) live = false;
+    if (!live) e0 = e1 = 0;
     int32_t pi[kSmallSet][D];
 #pragma unroll
     for (int a = 0; a < (int)kSmallSet; ++a) {
         int32_t t[D];
         load_row<D>(co.ccrd, (uint32_t)a < mi ? bi + a : bi, t);
 #pragma unroll
-        for (int k = 0; k < D; ++k) pi[a][k] = uniform((uint32_t)a < mi ? t[k] : 0);
+        for (int k = 0; k < D; ++k) {
+            const int32_t v = (uint32_t)a < mi ? t[k] : 0;
+            if constexpr (S == kWave)
+                pi[a][k] = uniform(v);
+            else
+                pi[a][k] = v;
+        }
     }
     unsigned long long n_pairs = 0, n_skip = 0, n_yes = 0, n_dist = 0, n_pts = 0;
-    uint32_t ri = uf_find_at(parent, ci, pci);  // root hint of g_i's set
+    uint32_t ri = live ? uf_find_at(parent, ci, pci) : 0u;  // root hint of g_i's set
     // each round takes two list entries per lane, whose loads are issued
     // together: the rounds are chains of dependent loads, so half as many
     // rounds cost about half the time
     constexpr int U = 2;
-    for (uint64_t e = e0; e < e1; e += U * kWave) {
+    for (uint64_t e = e0; e < e1; e += U * S) {
         bool cand[U];
         uint32_t cj[U], bj[U], mj[U], pj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t idx = e + (uint64_t)u * kWave + lane;
+            const uint64_t idx = e + (uint64_t)u * S + sub;
             cand[u] = false;
             cj[u] = bj[u] = mj[u] = pj[u] = 0;
             if (idx < e1) cj[u] = nei[idx];
@@ -133,23 +147,27 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
             }
             any_yes |= yes;
             if (stats) {
-                const unsigned long long np = (unsigned long long)popc64(ballot(cand[u]));
-                const unsigned long long nt = (unsigned long long)popc64(ballot(test));
-                const unsigned long long sj = (unsigned long long)wave_sum(test ? mj[u] : 0u);
-                n_pairs += np;
-                n_skip += np - nt;
-                n_yes += (unsigned long long)popc64(ballot(yes));
-                n_dist += (unsigned long long)mi * sj;
-                n_pts += nt * mi + sj;
+                n_pairs += cand[u] ? 1u : 0u;
+                n_skip += cand[u] && !test ? 1u : 0u;
+                n_yes += yes ? 1u : 0u;
+                n_dist += test ? (unsigned long long)mi * mj[u] : 0ull;
+                n_pts += test ? (unsigned long long)(mi + mj[u]) : 0ull;
             }
         }
         // the unions may have put g_i's set under a smaller root
-        if (ballot(any_yes)) ri = uf_find(parent, ri);
+        if (ballot(any_yes) & gmask) ri = uf_find(parent, ri);
     }
     // each one-lane test counts as one FastMerging iteration
-    if (stats && lane == 0) {
-        const unsigned long long nt = n_pairs - n_skip;
-        flush_stats(stats, r, n_pairs, n_skip, nt, n_yes, nt, nt ? 1 : 0, n_dist, n_pts);
+    if (stats) {
+        n_pairs = wave_sum(n_pairs);
+        n_skip = wave_sum(n_skip);
+        n_yes = wave_sum(n_yes);
+        n_dist = wave_sum(n_dist);
+        n_pts = wave_sum(n_pts);
+        if (lane == 0) {
+            const unsigned long long nt = n_pairs - n_skip;
+            flush_stats(stats, r, n_pairs, n_skip, nt, n_yes, nt, nt ? 1 : 0, n_dist, n_pts);
+        }
     }
 }
 
@@ -354,8 +372,9 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
                         const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
-                        int waves, bool tiny_done, const HugeQueue& huge, bool wide, uint32_t* parent,
-                        MergeStats* stats, const __half* proposal, const CellSummary* sum, hipStream_t st) {
+                        int waves, int small_lanes, bool tiny_done, const HugeQueue& huge, bool wide,
+                        uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
+                        hipStream_t st) {
     const Proposal prop{proposal, sum};
     if (ncc == 0) return hipSuccess;
     // n_small >= 0: the visiting order puts the n_small tiny core grids first
@@ -367,12 +386,21 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     const int64_t s1 = n_small >= 0 ? n_small : ncc;
     const int64_t b0 = n_small >= 0 ? n_small : 0;
     if (s1 > 0 && !tiny_done) {
-        const unsigned blocks = (unsigned)((s1 + kWavesPerBlock - 1) / kWavesPerBlock);
-        if (wide)
-            GD_DISPATCH_D(g.D, (merge_small_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+        // lanes per tiny grid: 16 (four grids per wave) or 64
+        const int S = small_lanes == 16 ? 16 : kWave;
+        const int64_t per_block = (int64_t)kWavesPerBlock * (kWave / S);
+        const dim3 blocks((unsigned)((s1 + per_block - 1) / per_block)), threads(kBlock);
+        if (wide && S == 16)
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, true, 16><<<blocks, threads, 0, st>>>(
+                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+        else if (wide)
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, true, kWave><<<blocks, threads, 0, st>>>(
+                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+        else if (S == 16)
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, false, 16><<<blocks, threads, 0, st>>>(
                                    g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
         else
-            GD_DISPATCH_D(g.D, (merge_small_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+            GD_DISPATCH_D(g.D, (merge_small_kernel<D, false, kWave><<<blocks, threads, 0, st>>>(
                                    g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
