@@ -268,7 +268,8 @@ typedef enum {
                                  candidates grow as (2 ceil(sqrt(d)) + 1)^d).
                                  The result is the same for every query.      */
     GD_OPT_GRID_LANES = 12    /* lanes per grid in the kernels that serve
-                                 small grids (the merging of tiny core sets):
+                                 small grids (the merging of tiny core sets,
+                                 border assignment):
                                  0 (default) chooses from the mean list length
                                  (16 when it is at most 40, else 64), 16 (four
                                  grids per wave) or 64 (one).  Same result.   */

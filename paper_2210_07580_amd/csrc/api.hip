@@ -615,6 +615,10 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
             return rc;
     }
     ctx->last.neighbor_walk = walk ? 1 : 0;
+    // lanes per grid in the kernels that serve small grids (tiny-set merge,
+    // border points): short lists leave most of a wave per grid idle
+    const int small_lanes = ctx->grid_lanes ? ctx->grid_lanes
+                                            : (nei_total <= 40 * (uint64_t)std::max<int64_t>(ncell, 1) ? 16 : 64);
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);
@@ -722,9 +726,6 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if (walk)
             GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, wide,
                                      st));
-        // lanes per tiny grid: short lists leave most of a wave per grid idle
-        const int small_lanes = ctx->grid_lanes ? ctx->grid_lanes
-                                                : (nei_total <= 40 * (uint64_t)std::max<int64_t>(ncell, 1) ? 16 : 64);
         GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves,
                             small_lanes, walk,
                             hm.q, wide, L.parent, stats ? ctx->stats_dev->merge : nullptr,
@@ -755,7 +756,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     if (walk)
         GD_TRY(launch_border_walk(g, co, t, L.cell_label, wide, st));
     else
-        GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, wide, st));
+        GD_TRY(launch_output(g, co, L.nei_off, nei, L.cell_label, wide, small_lanes, st));
     ctx->mark(P_OUTPUT, 1);
     if (stats) GD_TRY(hipMemcpyAsync(ctx->stats_host, ctx->stats_dev, sizeof(StatBlock), hipMemcpyDeviceToHost, st));
     if (plan) {

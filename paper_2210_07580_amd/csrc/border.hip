@@ -232,6 +232,134 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
     }
 }
 
+// Reductions within groups of S lanes (S a power of two up to 64).
+template <int S>
+__device__ __forceinline__ uint32_t group_incl_scan(uint32_t v) {
+    const int sub = lane_id() % S;
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, S);
+        if (sub >= o) v += t;
+    }
+    return v;
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t group_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = S / 2; o > 0; o >>= 1) {
+        const uint64_t t = __shfl_xor(v, o, S);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+// Border and noise points with S lanes per grid (a wave serves 64 / S
+// grids side by side): the same search as border_grid, with every scan,
+// minimum and broadcast taken within the grid's group of lanes.  Loop
+// bounds are uniform within a group, so a group's lanes stay converged
+// around every cross-lane step.
+template <int D, bool kWide, int S>
+__global__ __launch_bounds__(kBlock) void output_group_kernel(GridView gv, CoreOut co,
+                                                              const uint64_t* __restrict__ nei_off,
+                                                              const uint32_t* __restrict__ nei,
+                                                              const int32_t* __restrict__ cell_label) {
+    constexpr int G = kWave / S;
+    __shared__ uint32_t s_start[kWavesPerBlock][kWave];
+    __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
+    __shared__ int32_t s_lab[kWavesPerBlock][kWave];
+    const int w = wave_id(), lane = lane_id();
+    const int grp = lane / S, sub = lane % S, g0 = grp * S;
+    const uint64_t gmask = (S == kWave ? ~0ull : ((1ull << S) - 1ull)) << g0;
+    const int64_t c = ((int64_t)blockIdx.x * kWavesPerBlock + w) * G + grp;
+    if (c >= (int64_t)*gv.ncell_dev) return;
+    const uint32_t st = gv.cell_start[c];
+    const uint32_t k = gv.cell_start[c + 1] - st;
+    if (co.core_cnt[c] == k) return;  // all core: written in input order by the hash pass
+    const Inst& I = cell_inst(gv, c);
+    const uint32_t off = (uint32_t)I.off;  // cluster ids and output slots are local to the instance
+    int32_t GD_GLOBAL* __restrict__ labels = as_global(I.labels);
+    uint8_t GD_GLOBAL* __restrict__ core_flags = as_global(I.core);
+    const int32_t own_label = cell_label[c];
+    const uint32_t own_min = co.cell_min_core[c];
+    const typename Dist<kWide>::T T = inst_T<kWide>(I);
+    const uint64_t own_best = own_min == kNone ? ~0ull : (((uint64_t)own_min << 32) | (uint32_t)own_label);
+    const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
+    uint32_t* sst = &s_start[w][g0];
+    uint32_t* sex = &s_excl[w][g0];
+    int32_t* slb = &s_lab[w][g0];
+    for (uint32_t qb = 0; qb < k; qb += S) {
+        const uint32_t s = st + qb + sub;
+        const bool v = qb + sub < k;
+        const uint8_t isc = v ? co.core[s] : 1;
+        if (v && isc) {
+            const uint32_t o = gv.sidx[s] - off;
+            labels[o] = own_label - (int32_t)off;
+            core_flags[o] = 1;
+        }
+        const uint64_t open = (ballot(v && !isc) & gmask) >> g0;  // the group's non-core queries
+        if (!open) continue;
+        int32_t qx[D];
+        load_row<D>(gv.crd, v ? s : st, qx);
+        uint64_t best = own_best;  // lane i of the group: best candidate of query i
+        for (uint64_t e = e0; e < e1; e += S) {
+            // largest best among open queries: grids whose smallest core index is not below it cannot help
+            const uint64_t worst = ~group_min_u64<S>(((open >> sub) & 1ull) ? ~best : ~0ull);
+            const uint32_t worst_idx = (uint32_t)(worst >> 32);
+            const uint64_t idx = e + sub;
+            uint32_t cs = 0, cn = 0;
+            int32_t lab = -1;
+            if (idx < e1) {
+                const uint32_t cc = nei[idx];
+                const uint32_t mc = co.cell_min_core[cc];
+                if (mc != kNone && (worst == ~0ull || mc < worst_idx)) {
+                    cs = co.core_begin[cc];
+                    cn = co.core_cnt[cc];
+                    lab = cell_label[cc];
+                }
+            }
+            const uint32_t incl = group_incl_scan<S>(cn);
+            const uint32_t tot = __shfl(incl, S - 1, S);
+            if (tot == 0) continue;
+            sst[sub] = cs;
+            sex[sub] = incl - cn;
+            slb[sub] = lab;
+            wave_sync();
+            for (uint32_t t0 = 0; t0 < tot; t0 += S) {
+                const uint32_t t = t0 + sub;
+                const bool tv = t < tot;
+                int j = 0;
+#pragma unroll
+                for (int step = S / 2; step > 0; step >>= 1)
+                    if (sex[j + step] <= t) j += step;
+                const uint32_t q = sst[j] + (t - sex[j]);
+                int32_t y[D];
+                load_row<D>(co.ccrd, tv ? q : 0u, y);
+                const uint64_t cand = tv ? (((uint64_t)co.corig[q] << 32) | (uint32_t)slb[j]) : ~0ull;
+                uint64_t act = open;
+                while (act) {
+                    const int qi = ffs64(act);
+                    act &= act - 1ull;
+                    typename Dist<kWide>::T dd = 0;
+#pragma unroll
+                    for (int jj = 0; jj < D; ++jj) dd += sqd<kWide>(y[jj], __shfl(qx[jj], qi, S));
+                    const bool in = tv && dd <= T;
+                    if (ballot(in) & gmask) {
+                        const uint64_t m = group_min_u64<S>(in ? cand : ~0ull);
+                        if (sub == qi && m < best) best = m;
+                    }
+                }
+            }
+            wave_sync();
+        }
+        if (v && !isc) {
+            const uint32_t o = gv.sidx[s] - off;
+            labels[o] = best == ~0ull ? -1 : (int32_t)((uint32_t)best - off);
+            core_flags[o] = 0;
+        }
+    }
+}
+
 // Each wave checks G grids at once (one lane each) and serves only those
 // holding a non-core point (the all-core grids were written in input order
 // by output_direct_kernel).  With millions of grids G = 64: a wave per grid
@@ -266,10 +394,18 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
 }
 
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, bool wide, hipStream_t st) {
+                         const int32_t* cell_label, bool wide, int lanes, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const unsigned many = grid_for(g.ncell, kWavesPerBlock * kWave), one = grid_for(g.ncell, kWavesPerBlock);
-    if (wide) {
+    if (lanes == 16) {  // four grids per wave, side by side
+        const unsigned four = grid_for(g.ncell, kWavesPerBlock * 4);
+        if (wide)
+            GD_DISPATCH_D(g.D, (output_group_kernel<D, true, 16><<<dim3(four), dim3(kBlock), 0, st>>>(
+                                   g, c, nei_off, nei, cell_label)));
+        else
+            GD_DISPATCH_D(g.D, (output_group_kernel<D, false, 16><<<dim3(four), dim3(kBlock), 0, st>>>(
+                                   g, c, nei_off, nei, cell_label)));
+    } else if (wide) {
         GD_DISPATCH_D(g.D, (output_kernel<D, 1, true><<<dim3(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
                                                                                           cell_label)));
     } else if (g.ncell >= kBorderGroupMinGrids) {

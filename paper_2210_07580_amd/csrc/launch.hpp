@@ -348,8 +348,10 @@ hipError_t launch_border_walk(const GridView& g, const CoreOut& c, const TreeVie
 
 // ---- border.hip
 // Grids with a non-core point: border search and output through the permutation.
+// lanes: 16 serves four grids per wave side by side; otherwise a wave per
+// grid (a wave checks 64 grids when there are millions of them).
 hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
-                         const int32_t* cell_label, bool wide, hipStream_t st);
+                         const int32_t* cell_label, bool wide, int lanes, hipStream_t st);
 // All-core grids: output in input order through an identifier -> label hash
 // table of 2^bits slots (+1) in `table` (output_table_bytes).  keys_in: the
 // identifiers in input order; skeys: sorted.
