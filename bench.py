@@ -562,6 +562,8 @@ def main():
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--neighbor-mode", type=int, default=0, choices=(0, 1, 2),
                     help="GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists for every grid, 2 walks in the consumers")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the 256-instance batched comparison and print its record")
     ap.add_argument("--sweep", metavar="FILE", help="run the parameter sweeps, one JSON record per point to FILE")
     ap.add_argument("--sweep-dims", default="2,3,5,7")
     ap.add_argument("--sweep-kinds", default="simden,varden")
@@ -576,6 +578,10 @@ def main():
 
     import torch
     import paper_2210_07580_amd as G
+
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(G, args.steps, args.warmup, args.batch_instances)}))
+        return
 
     if args.sweep:
         recs = bench_sweep(G, args.steps, args.warmup, [int(v) for v in args.sweep_dims.split(",")],
