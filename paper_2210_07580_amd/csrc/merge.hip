@@ -171,10 +171,15 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     }
 }
 
-// Queues the pair (g_i, g_j) for merge_huge_kernel (one lane appends).
-__device__ __forceinline__ void defer_pair(const HugeQueue& q, uint32_t ci, uint32_t cj, Header* hdr) {
-    if (lane_id() == 0) {
-        const uint32_t k = q.pairs ? atomicAdd(q.count, 1u) : q.cap;
+// Queues the pairs (g_i, g_j) of the lanes in `lanes` (each lane holds its
+// g_j) for merge_huge_kernel, with one append for the wave.
+__device__ __noinline__ void defer_pairs(const HugeQueue& q, uint64_t lanes, uint32_t ci, uint32_t cj, Header* hdr) {
+    const int lane = lane_id();
+    uint32_t base = 0;
+    if (lane == 0) base = q.pairs ? atomicAdd(q.count, (uint32_t)popc64(lanes)) : q.cap;
+    base = readlane(base, 0);
+    if ((lanes >> lane) & 1ull) {
+        const uint32_t k = base + (uint32_t)popc64(lanes & lanemask_lt());
         if (k < q.cap)
             q.pairs[k] = make_uint2(ci, cj);
         else
@@ -276,6 +281,12 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
         n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
+        // pairs with a core set beyond the LDS bitmaps go to the queue
+        const uint64_t over = ballot(pend_l && (si_huge || mj > 64u * words));
+        if (over) {
+            defer_pairs(huge, over, ci, cj, gv.b.hdr);
+            pend &= ~over;
+        }
         float my_z0 = 0.f, my_z1 = 0.f;
         uint32_t my_ra = 0, my_rb = 0;
         if constexpr (kLearned) {
@@ -327,10 +338,6 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
             sj.base = readlane(bj, l);
             sj.m = readlane(mj, l);
             sj.words = (sj.m + kWave - 1) / kWave;
-            if (si_huge || sj.m > 64u * words) {
-                defer_pair(huge, ci, readlane(cj, l), gv.b.hdr);
-                continue;
-            }
             uint32_t it = 0;
             int yes;
             if constexpr (kLearned) {
@@ -525,6 +532,12 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
         n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
+        // pairs with a core set beyond the LDS bitmaps go to the queue
+        const uint64_t over = ballot(pend_l && (si_huge || mj > 64u * words));
+        if (over) {
+            defer_pairs(huge, over, ci, cj, gv.b.hdr);
+            pend &= ~over;
+        }
         while (pend) {
             const int l = ffs64(pend);
             pend &= pend - 1ull;
@@ -535,10 +548,6 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
             // a union since this round's roots were read may have joined them
             if (uf_find(parent, cjl) == uf_find(parent, ri) && load_acq(&state[cjl]) == kBfsClassified) {
                 ++n_skip;
-                continue;
-            }
-            if (si_huge || sj.m > 64u * words) {
-                defer_pair(huge, ci, cjl, gv.b.hdr);
                 continue;
             }
             uint32_t it = 0;
