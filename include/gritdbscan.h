@@ -271,7 +271,8 @@ typedef enum {
                                  small grids (the merging of tiny core sets,
                                  border assignment):
                                  0 (default) chooses from the mean list length
-                                 (16 when it is at most 40, else 64), 16 (four
+                                 and grid size (16 when they are at most 40
+                                 entries and 32 points, else 64), 16 (four
                                  grids per wave) or 64 (one).  Same result.   */
 } gd_option;
 

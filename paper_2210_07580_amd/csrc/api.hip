@@ -617,8 +617,9 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->last.neighbor_walk = walk ? 1 : 0;
     // lanes per grid in the kernels that serve small grids (tiny-set merge,
     // border points): short lists leave most of a wave per grid idle
-    const int small_lanes = ctx->grid_lanes ? ctx->grid_lanes
-                                            : (nei_total <= 40 * (uint64_t)std::max<int64_t>(ncell, 1) ? 16 : 64);
+    const uint64_t grids = (uint64_t)std::max<int64_t>(ncell, 1);
+    const int small_lanes =
+        ctx->grid_lanes ? ctx->grid_lanes : (nei_total <= 40 * grids && (uint64_t)n <= 32 * grids ? 16 : 64);
 
     // ---- core points
     ctx->mark(P_CORE_MARK, 0);

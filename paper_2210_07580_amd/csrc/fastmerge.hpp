@@ -30,8 +30,10 @@
 //     cos(theta_x) < cos(lambda) - 1e-4: the margin is far above the
 //     rounding of these terms (see kAngleMargin), so rounding can only keep
 //     a point, never drop one wrongly, and the answer stays exact (Theorem 2).
-//   The start point p is the first core point of s_i (the paper picks one at
-//   random; the choice does not change the answer).  If a Pruning call
+//   The start point p is the first core point of the larger of the two sets
+//   (the paper picks a point of s_i at random; the choice does not change
+//   the answer), so that the first nearest-point search, which on a yes is
+//   the only one, runs over the smaller set.  If a Pruning call
 //   empties a set the answer is "no" at once.
 //   Wide path (eps above the 32-bit bound): squared distances in 64 bits,
 //   the triangle rule's products in 128 bits, and the same single-precision

@@ -346,7 +346,14 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
                 else
                     yes = fast_merging<D, kWide>(si, sj, readlane(my_ra, l), T, Tm, eps, n_dist, it);
             } else {
-                yes = fast_merging_from<D, kWide>(si, sj, p0, T, Tm, eps, n_dist, it);
+                // start in the larger set, so that the first nearest-point
+                // search (on a yes the only one) runs over the smaller set
+                const bool swap = sj.m > si.m;
+                int32_t ps[D];
+                if (swap) load_point<D>(sj, 0u, ps);
+#pragma unroll
+                for (int k = 0; k < D; ++k) ps[k] = swap ? ps[k] : p0[k];
+                yes = fast_merging_from<D, kWide>(swap ? sj : si, swap ? si : sj, ps, T, Tm, eps, n_dist, it);
             }
             ++n_test;
             n_pts += si.m + sj.m;
@@ -551,7 +558,13 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
                 continue;
             }
             uint32_t it = 0;
-            const int yes = fast_merging_from<D, kWide>(si, sj, p0, T, Tm, eps, n_dist, it);
+            // start in the larger set: the first nearest-point search runs over the smaller one
+            const bool swap = sj.m > si.m;
+            int32_t ps[D];
+            if (swap) load_point<D>(sj, 0u, ps);
+#pragma unroll
+            for (int k = 0; k < D; ++k) ps[k] = swap ? ps[k] : p0[k];
+            const int yes = fast_merging_from<D, kWide>(swap ? sj : si, swap ? si : sj, ps, T, Tm, eps, n_dist, it);
             ++n_test;
             n_pts += si.m + sj.m;
             n_iter += it;
@@ -653,8 +666,10 @@ __global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut
             continue;
         }
         uint32_t it = 0;
-        const int yes = fast_merging<D, kWide>(si, sj, 0u, inst_T<kWide>(I), inst_Tm<kWide>(I), (double)I.eps,
-                                               n_dist, it);
+        // start in the larger set: the first nearest-point search runs over the smaller one
+        const bool swap = sj.m > si.m;
+        const int yes = fast_merging<D, kWide>(swap ? sj : si, swap ? si : sj, 0u, inst_T<kWide>(I),
+                                               inst_Tm<kWide>(I), (double)I.eps, n_dist, it);
         ++n_test;
         n_pts += si.m + sj.m;
         n_iter += it;
