@@ -415,13 +415,11 @@ def bench_batched(G, steps, warmup, max_instances):
     }
 
 
-def bench_learned(G, steps, warmup):
-    """The dense seed-spreader workload (n=20M, d=3): the trained proposal
-    versus the plain merge, same GPU, identical labels."""
+def learned_pair(G, pts, eps, minpts, steps, warmup):
+    """Plain merge versus the trained proposal on one point set: call time,
+    merge-phase time and merge work, at identical labels."""
     import torch
     from paper_2210_07580_amd import proposal as P
-    w = W.WORKLOADS["cfg4"]
-    pts = points("cfg4")
     n = int(pts.shape[0])
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
     core = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -430,16 +428,16 @@ def bench_learned(G, steps, warmup):
     ref = None
     for name, blob in (("plain", None), ("learned", P.load_blob())):
         ctx.set_proposal(blob)
-        t = time_calls(lambda: ctx.dbscan(pts, w.eps, w.minpts, lab, core), steps, warmup)
+        t = time_calls(lambda: ctx.dbscan(pts, eps, minpts, lab, core), steps, warmup)
         # the merge phase alone, from calls with phase events
         ctx.set_option(G.GD_OPT_TIMING, 1)
         merge_ms = []
         for _ in range(steps):
-            ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+            ctx.dbscan(pts, eps, minpts, lab, core)
             merge_ms.append(ctx.phase_times()["merge"])
         ctx.set_option(G.GD_OPT_TIMING, 0)
         ctx.set_option(G.GD_OPT_STATS, 1)
-        ctx.dbscan(pts, w.eps, w.minpts, lab, core)
+        ctx.dbscan(pts, eps, minpts, lab, core)
         st = ctx.stats()
         ctx.set_option(G.GD_OPT_STATS, 0)
         out = (lab.clone(), core.clone())
@@ -448,15 +446,36 @@ def bench_learned(G, steps, warmup):
         elif not (torch.equal(ref[0], out[0]) and torch.equal(ref[1], out[1])):
             raise RuntimeError("learned proposal changed the labels")
         res[name] = {"value": round(n / t, 1), "ms_per_step": round(1e3 * t, 3),
-                     "merge_ms": round(float(np.mean(merge_ms)), 4),
+                     "merge_ms": round(float(np.median(merge_ms)), 4),
                      "merge_tests": st["merge_tests"], "merge_distances": st["merge_distances"],
                      "merge_iterations": st["merge_iterations"]}
         log(f"bench: {name} {res[name]}")
     ctx.close()
-    return {"workload": "seed-spreader n=20M d=3 eps=150 minpts=50 (300 pts/step)", "unit": "points/s",
-            "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
-            "speedup_vs_plain": round(res["learned"]["value"] / res["plain"]["value"], 3),
-            "plain": res["plain"], "learned": res["learned"]}
+    return res
+
+
+def bench_learned(G, steps, warmup):
+    """The dense seed-spreader workload (n=20M, d=3): the trained proposal
+    versus the plain merge, same GPU, identical labels; beside it a 2M-point
+    3-D sweep point at eps 2000 (619 core grids of about 3000 core points),
+    where FastMerging's scans over large core sets dominate the merge."""
+    w = W.WORKLOADS["cfg4"]
+    res = learned_pair(G, points("cfg4"), w.eps, w.minpts, steps, warmup)
+    out = {"workload": "seed-spreader n=20M d=3 eps=150 minpts=50 (300 pts/step)", "unit": "points/s",
+           "value": res["learned"]["value"], "plain_value": res["plain"]["value"],
+           "speedup_vs_plain": round(res["learned"]["value"] / res["plain"]["value"], 3),
+           "plain": res["plain"], "learned": res["learned"]}
+    import torch
+    ws = W.sweep_workload("simden", 3, eps=2000)
+    log(f"bench: generating {ws.name}")
+    pts = torch.from_numpy(W.make_points(ws).astype(np.float32)).cuda()
+    big = learned_pair(G, pts, ws.eps, ws.minpts, steps, warmup)
+    out["large_core_sets"] = {
+        "workload": "seed-spreader (simden) n=2M d=3 eps=2000 minpts=100, 817 grids",
+        "speedup_vs_plain": round(big["learned"]["value"] / big["plain"]["value"], 3),
+        "merge_speedup_vs_plain": round(big["plain"]["merge_ms"] / big["learned"]["merge_ms"], 3),
+        "plain": big["plain"], "learned": big["learned"]}
+    return out
 
 
 def sweep_points(dims, kinds, axes):

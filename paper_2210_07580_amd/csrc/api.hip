@@ -46,12 +46,13 @@ struct Bufs {
     DevBuf huge;    // queue and device-memory bitmaps for core sets beyond the LDS bitmaps
 };
 
-// Pairs with a core set beyond the LDS bitmaps: the queue the merge kernels
-// fill and the bitmaps of the waves that drain it.
+// Pairs with a heavy core set (at least kHeavyCore points, or beyond the LDS
+// bitmaps): the queue the merge kernels fill and the bitmaps of the
+// workgroups that drain it.
 struct HugeMerge {
     HugeQueue q{};
     uint64_t* slabs = nullptr;
-    uint32_t words = 0, waves = 0;
+    uint32_t words = 0, blocks = 0;
 };
 
 enum Phase {
@@ -425,7 +426,7 @@ int run_bfs(gd_ctx* ctx, const GridView& g, const CoreOut& co, const uint64_t* n
             if (hm.q.pairs) GD_TRY(fill<uint32_t>(hm.q.count, 1, 0u, st));
             GD_TRY(launch_bfs_level(g, co, nei_off, nei, front, nf, next, cnt, max_core, hm.q, wide, state, parent,
                                     stats, st));
-            GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, true, wide, state, next, cnt, parent,
+            GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.blocks, true, wide, state, next, cnt, parent,
                                      stats, st));
             GD_TRY(hipMemcpyAsync(h + 2, cnt + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             GD_TRY(hipStreamSynchronize(st));
@@ -657,10 +658,11 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     const int64_t ncc = plan ? plan->ncc : (int64_t)H->counts[1];
     const int64_t max_core = plan ? plan->max_core : (int64_t)H->counts[2];
     if (walk && (rc = build_lists(L.core_cnt, false))) return rc;
-    // core sets beyond the LDS bitmaps (never in a planned run: its plan
-    // caps them, and a replay that meets one runs again eagerly)
+    // heavy core sets: their pairs are queued and merged by whole workgroups
+    // (never in a planned run: a replay tests them on one wave each, and one
+    // that meets a set beyond the LDS bitmaps runs again eagerly)
     HugeMerge hm;
-    if (!plan && max_core > kMaxCoreBits) {
+    if (!plan && max_core >= kHeavyCore) {
         unsigned long long lists = 0;
         GD_TRY(fill<unsigned long long>(ctx->counter_dev, 1, 0ull, st));
         GD_TRY(launch_huge_scan(g, co, L.nei_off, ctx->counter_dev, st));
@@ -668,14 +670,14 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(hipStreamSynchronize(st));
         const uint64_t cap = 2 * (uint64_t)lists + 64;
         if (cap > 0xffffffffull)
-            return ctx->fail(GD_EUNSUPPORTED, "%llu neighbour pairs of oversized core sets", (unsigned long long)cap);
+            return ctx->fail(GD_EUNSUPPORTED, "%llu neighbour pairs of heavy core sets", (unsigned long long)cap);
         hm.words = (uint32_t)((max_core + kWave - 1) / kWave);
         const size_t slab = (size_t)2 * hm.words * sizeof(uint64_t);
-        // as many waves as pairs, up to 1024 and 256 MiB of bitmaps
-        const uint64_t w = std::min<uint64_t>(std::min<uint64_t>(cap, 1024), std::max<size_t>((256u << 20) / slab, 4));
-        hm.waves = (uint32_t)((w + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock);
+        // as many workgroups as pairs, up to 512 and 256 MiB of bitmaps
+        hm.blocks = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(cap, 512),
+                                                 std::max<size_t>((256u << 20) / slab, 1));
         const size_t qbytes = align_up(cap * sizeof(uint2) + sizeof(uint32_t));
-        if ((rc = grow(ctx, ctx->cur->huge, qbytes + (size_t)hm.waves * slab,
+        if ((rc = grow(ctx, ctx->cur->huge, qbytes + (size_t)hm.blocks * slab,
                        ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->table.cap + ctx->cur->sumbuf.cap)))
             return rc;
         char* b = (char*)ctx->cur->huge.p;
@@ -731,7 +733,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
                             small_lanes, walk,
                             hm.q, wide, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                             ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));
-        GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.waves, false, wide, nullptr, nullptr, nullptr,
+        GD_TRY(launch_merge_huge(g, co, hm.q, hm.slabs, hm.words, hm.blocks, false, wide, nullptr, nullptr, nullptr,
                                  L.parent, stats ? ctx->stats_dev->merge : nullptr, st));
         ctx->mark(P_MERGE, 1);
     }

@@ -272,9 +272,13 @@ struct MergeStats {
 // wide (here and below): the batch's largest eps exceeds GD_EPS_MAX, and
 // squared distances are taken in 64 bits against Inst::T64 / Tm64.
 // Largest core set the merge kernels' LDS bitmaps hold.  A pair with a
-// larger set is queued (HugeQueue) and tested by merge_huge_kernel, whose
+// larger set is queued (HugeQueue) and tested by merge_heavy_kernel, whose
 // bitmaps live in device memory.
 constexpr int64_t kMaxCoreBits = 262144;
+// Core sets from this size on are merged by a workgroup of kCoopWaves waves
+// per pair (in eager runs; graph replays keep one wave per grid).
+constexpr int64_t kHeavyCore = 8192;
+constexpr int kCoopWaves = 8;
 // Pairs (g_i, g_j) deferred by the LDS kernels.  pairs == nullptr: no queue
 // (a planned run); meeting a larger set then raises kErrCoreCap.
 struct HugeQueue {
@@ -294,16 +298,17 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                         bool wide,
                         uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
                         hipStream_t st);
-// Sum over core grids with more than kMaxCoreBits core points of |Nei(g)| + 1
+// Sum over core grids with at least kHeavyCore core points of |Nei(g)| + 1
 // (added to *sum; the caller clears it): with both orders no pair is queued
 // twice from one side, so twice this bounds the queue.
 hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t* nei_off, unsigned long long* sum,
                             hipStream_t st);
-// Tests the queued pairs (FastMerging, union on yes) with `waves` waves, each
-// with 2 * words words of device memory at slabs.  bfs: the pair's second grid
-// is claimed for the search (state, next, cnt[2]) as in the BFS level kernel.
+// Tests the queued pairs (FastMerging, union on yes) with `blocks`
+// workgroups of kCoopWaves waves, each with 2 * words words of device memory
+// at slabs.  bfs: the pair's second grid is claimed for the search (state,
+// next, cnt[2]) as in the BFS level kernel.
 hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
-                             uint32_t words, uint32_t waves, bool bfs, bool wide, uint32_t* state, uint32_t* next,
+                             uint32_t words, uint32_t blocks, bool bfs, bool wide, uint32_t* state, uint32_t* next,
                              uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st);
 // The BFS order of Algorithm 6 (GD_OPT_MERGE_ORDER = 2), on the full lists.
 // state: ncell u32, cleared to 0 for every grid first.  cnt: 3 u32 (the

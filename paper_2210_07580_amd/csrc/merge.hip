@@ -5,6 +5,7 @@
 #include <type_traits>
 
 #include "fastmerge.hpp"
+#include "fastmerge_block.hpp"
 #include "launch.hpp"
 #include "learned.hpp"
 #include "scan.hpp"
@@ -245,8 +246,10 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
     const double eps = (double)I.eps;
     PointSet si{co.ccrd, own.y, own.z, smem + (int64_t)w * 2 * words, 0};
     if (si.m <= kSmallSet) return;
-    // larger than the LDS bitmaps this launch was given: every pair is queued
+    // larger than the LDS bitmaps this launch was given (or heavy, with a
+    // queue): every pair is queued
     const bool si_huge = si.m > 64u * words;
+    const bool si_heavy = huge.pairs && si.m >= (uint32_t)kHeavyCore;
     if (si_huge && !huge.pairs) {
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
         return;
@@ -281,8 +284,10 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
         n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
-        // pairs with a core set beyond the LDS bitmaps go to the queue
-        const uint64_t over = ballot(pend_l && (si_huge || mj > 64u * words));
+        // pairs with a core set beyond the LDS bitmaps, or (eager runs) with
+        // a heavy one, go to the queue
+        const uint64_t over =
+            ballot(pend_l && (si_huge || si_heavy || mj > 64u * words || (huge.pairs && mj >= (uint32_t)kHeavyCore)));
         if (over) {
             defer_pairs(huge, over, ci, cj, gv.b.hdr);
             pend &= ~over;
@@ -511,6 +516,7 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
     PointSet si{co.ccrd, co.core_begin[ci], co.core_cnt[ci], smem + (int64_t)w * 2 * words, 0};
     si.words = (si.m + kWave - 1) / kWave;
     const bool si_huge = si.m > 64u * words;  // every pair is queued
+    const bool si_heavy = huge.pairs && si.m >= (uint32_t)kHeavyCore;
     if (si_huge && !huge.pairs) {
         if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
         return;
@@ -539,8 +545,10 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
         uint64_t pend = ballot(pend_l);
         n_pairs += (unsigned long long)popc64(cands);
         n_skip += (unsigned long long)(popc64(cands) - popc64(pend));
-        // pairs with a core set beyond the LDS bitmaps go to the queue
-        const uint64_t over = ballot(pend_l && (si_huge || mj > 64u * words));
+        // pairs with a core set beyond the LDS bitmaps, or (eager runs) with
+        // a heavy one, go to the queue
+        const uint64_t over =
+            ballot(pend_l && (si_huge || si_heavy || mj > 64u * words || (huge.pairs && mj >= (uint32_t)kHeavyCore)));
         if (over) {
             defer_pairs(huge, over, ci, cj, gv.b.hdr);
             pend &= ~over;
@@ -631,28 +639,39 @@ __global__ __launch_bounds__(kBlock) void huge_scan_kernel(const uint32_t* ncell
                                                            const uint64_t* __restrict__ nei_off,
                                                            unsigned long long* sum) {
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c < (int64_t)*ncell && core_cnt[c] > (uint32_t)kMaxCoreBits)
+    if (c < (int64_t)*ncell && core_cnt[c] >= (uint32_t)kHeavyCore)
         atomicAdd(sum, (unsigned long long)(nei_off[c + 1] - nei_off[c] + 1));
 }
 
-// Persistent: wave k takes queued pairs k, k + waves, ... (every wave leaves
-// once it passes the queue's length, read once at entry).
+// Persistent: workgroup k takes queued pairs k, k + blocks, ... (every
+// workgroup leaves once it passes the queue's length, read once at entry),
+// and runs FastMerging on each with all of its waves (fastmerge_block.hpp).
 template <int D, bool kWide>
-__global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut co, HugeQueue q, uint64_t* slabs,
-                                                            uint32_t words, uint32_t waves, int bfs,
-                                                            uint32_t* state, uint32_t* next, uint32_t* cnt,
-                                                            uint32_t* parent, MergeStats* stats) {
+__global__ __launch_bounds__(kCoopWaves * kWave) void merge_heavy_kernel(GridView gv, CoreOut co, HugeQueue q,
+                                                                         uint64_t* slabs, uint32_t words, int bfs,
+                                                                         uint32_t* state, uint32_t* next,
+                                                                         uint32_t* cnt, uint32_t* parent,
+                                                                         MergeStats* stats) {
+    __shared__ BlockScratch<D, kCoopWaves> sh;
+    __shared__ uint32_t s_go;
     const int lane = lane_id();
-    const int64_t wg = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (wg >= (int64_t)waves) return;
+    const bool t0 = threadIdx.x == 0;
     const uint32_t npairs = min(*q.count, q.cap);
-    uint64_t* bits = slabs + wg * 2 * (int64_t)words;
+    uint64_t* bits = slabs + (int64_t)blockIdx.x * 2 * (int64_t)words;
     unsigned long long n_skip = 0, n_test = 0, n_yes = 0, n_iter = 0, n_dist = 0, max_it = 0, n_pts = 0;
-    for (int64_t k = wg; k < (int64_t)npairs; k += waves) {
+    for (int64_t k = blockIdx.x; k < (int64_t)npairs; k += gridDim.x) {
         const uint2 pr = q.pairs[k];
         const uint32_t ci = pr.x, cj = pr.y;
-        const uint32_t ri = uf_find(parent, ci), rj = uf_find(parent, cj);
-        if (ri == rj && (!bfs || load_acq(&state[cj]) == kBfsClassified)) {
+        uint32_t ri = 0, rj = 0;
+        if (t0) {
+            ri = uf_find(parent, ci);
+            rj = uf_find(parent, cj);
+            s_go = (ri == rj && (!bfs || load_acq(&state[cj]) == kBfsClassified)) ? 0u : 1u;
+        }
+        __syncthreads();
+        const bool go = s_go != 0u;
+        __syncthreads();
+        if (!go) {
             ++n_skip;
             continue;
         }
@@ -662,33 +681,40 @@ __global__ __launch_bounds__(kBlock) void merge_huge_kernel(GridView gv, CoreOut
         si.words = (si.m + kWave - 1) / kWave;
         sj.words = (sj.m + kWave - 1) / kWave;
         if (si.words > words || sj.words > words) {
-            if (lane == 0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
+            if (t0) atomicOr(&gv.b.hdr->err, kErrCoreCap);
             continue;
         }
-        uint32_t it = 0;
         // start in the larger set: the first nearest-point search runs over the smaller one
         const bool swap = sj.m > si.m;
-        const int yes = fast_merging<D, kWide>(swap ? sj : si, swap ? si : sj, 0u, inst_T<kWide>(I),
-                                               inst_Tm<kWide>(I), (double)I.eps, n_dist, it);
+        const PointSet& sa = swap ? sj : si;
+        const PointSet& sb = swap ? si : sj;
+        int32_t p0[D];
+        load_point<D>(sa, 0u, p0);
+        uint32_t it = 0;
+        const int yes = fast_merging_block<D, kWide, kCoopWaves>(sa, sb, p0, inst_T<kWide>(I), inst_Tm<kWide>(I),
+                                                                  (double)I.eps, n_dist, it, sh);
         ++n_test;
         n_pts += si.m + sj.m;
         n_iter += it;
         max_it = it > max_it ? it : max_it;
-        if (yes < 0) {
-            if (lane == 0) atomicOr(&gv.b.hdr->err, kErrMergeRunaway);
-            continue;
-        }
-        if (yes) {
-            ++n_yes;
-            if (lane == 0) {
+        if (t0) {
+            if (yes < 0) {
+                atomicOr(&gv.b.hdr->err, kErrMergeRunaway);
+            } else if (yes) {
                 if (bfs && atomicCAS(&state[cj], kBfsNew, kBfsClassified) == kBfsNew)
                     next[atomicAdd(&cnt[2], 1u)] = cj;
                 (void)uf_union_from(parent, uf_find(parent, ri), uf_find(parent, rj));
             }
         }
-        wave_sync();
+        n_yes += yes > 0 ? 1u : 0u;
     }
-    if (stats && lane == 0) flush_stats(stats, wg, 0ull, n_skip, n_test, n_yes, n_iter, max_it, n_dist, n_pts);
+    // pair counts once per workgroup, distance evaluations once per wave
+    if (stats && lane == 0) {
+        if (t0)
+            flush_stats(stats, blockIdx.x, 0ull, n_skip, n_test, n_yes, n_iter, max_it, n_dist, n_pts);
+        else
+            flush_stats(stats, blockIdx.x, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, n_dist, 0ull);
+    }
 }
 
 hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t* nei_off, unsigned long long* sum,
@@ -699,16 +725,16 @@ hipError_t launch_huge_scan(const GridView& g, const CoreOut& c, const uint64_t*
 }
 
 hipError_t launch_merge_huge(const GridView& g, const CoreOut& c, const HugeQueue& huge, uint64_t* slabs,
-                             uint32_t words, uint32_t waves, bool bfs, bool wide, uint32_t* state, uint32_t* next,
+                             uint32_t words, uint32_t blocks, bool bfs, bool wide, uint32_t* state, uint32_t* next,
                              uint32_t* cnt, uint32_t* parent, MergeStats* stats, hipStream_t st) {
-    if (!huge.pairs || waves == 0) return hipSuccess;
-    const unsigned blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (!huge.pairs || blocks == 0) return hipSuccess;
+    const dim3 grid(blocks), threads(kCoopWaves * kWave);
     if (wide)
-        GD_DISPATCH_D(g.D, (merge_huge_kernel<D, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
+        GD_DISPATCH_D(g.D, (merge_heavy_kernel<D, true><<<grid, threads, 0, st>>>(
+                               g, c, huge, slabs, words, bfs ? 1 : 0, state, next, cnt, parent, stats)));
     else
-        GD_DISPATCH_D(g.D, (merge_huge_kernel<D, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, c, huge, slabs, words, waves, bfs ? 1 : 0, state, next, cnt, parent, stats)));
+        GD_DISPATCH_D(g.D, (merge_heavy_kernel<D, false><<<grid, threads, 0, st>>>(
+                               g, c, huge, slabs, words, bfs ? 1 : 0, state, next, cnt, parent, stats)));
     return hipGetLastError();
 }
 

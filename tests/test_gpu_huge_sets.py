@@ -1,6 +1,8 @@
 """Core sets larger than the merge kernels' LDS bitmaps (more than 262144
-core points in one grid).  The pairs with such a set are queued and tested
-with bitmaps in device memory; the result must be DBSCAN's.
+core points in one grid), and heavy ones (8192 or more) that eager calls
+merge with a workgroup per pair.  The pairs with such a set are queued and
+tested with bitmaps in device memory; the result must be DBSCAN's, also in
+graph replays (which test heavy sets on one wave each).
 
 The point sets are built so that the clustering follows from distances
 alone (the oracle's pair scan would take hours on them): boxes whose
@@ -19,7 +21,7 @@ EPS, MINPTS = 100, 5
 BIG = 300_000
 
 
-def boxes(seed, scale=1):
+def boxes(seed, scale=1, big=BIG):
     """Points and their cluster by construction (-1: noise; the border point
     gets the cluster of its core neighbours), for eps = 100 * scale."""
     rng = np.random.default_rng(seed)
@@ -29,9 +31,9 @@ def boxes(seed, scale=1):
                         axis=1)
 
     parts = [
-        (box(BIG, 0, 40, 0, 40), 0),          # A
-        (box(BIG, 81, 121, 0, 40), 0),        # B: 41 from A
-        (box(BIG, 230, 270, 0, 40), 1),       # C: 109 from B, apart
+        (box(big, 0, 40, 0, 40), 0),          # A
+        (box(big, 81, 121, 0, 40), 0),        # B: 41 from A
+        (box(big, 230, 270, 0, 40), 1),       # C: 109 from B, apart
         (box(50, 300, 310, 0, 10), 1),        # D: a small set inside C's reach
         (np.array([[-50, 0], [-50, 1], [-50, 2]]) * scale, 0),   # E: tiny core set next to A
         (np.array([[-140, 0]]) * scale, 0),   # border: 90 from E, 4 neighbours with itself
@@ -166,4 +168,34 @@ def test_oversized_core_sets_with_wide_distances(G, order):
     t = torch.from_numpy(x.astype(np.float32)).cuda()
     lab, core = ctx.dbscan(t, EPS * scale, MINPTS)
     assert np.array_equal(core.cpu().numpy(), want_c) and np.array_equal(lab.cpu().numpy(), want_l)
+    ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("mode", ["ldf", "bfs", "grid_order"])
+def test_heavy_core_sets(G, mode):
+    # 20000-point boxes: heavy (merged by a workgroup per pair in eager
+    # calls) but within the LDS bitmaps (one wave per pair in replays)
+    x, cl = boxes(5, 1, 20_000)
+    _, counts = np.unique(steps.cell_ids(x, EPS), axis=0, return_counts=True)
+    assert 8192 <= counts.max() <= 262_144
+    want_l, want_c = expected(x, cl)
+    ctx = G.Context(0)
+    if mode == "bfs":
+        ctx.set_option(G.GD_OPT_MERGE_ORDER, 2)
+    elif mode == "grid_order":
+        ctx.set_option(G.GD_OPT_LDF_ORDER, 0)
+    ctx.set_option(G.GD_OPT_STATS, 1)
+    print(f"case heavy core sets, {mode}", flush=True)
+    lab, core = run(ctx, x)
+    st = ctx.stats()
+    assert np.array_equal(core, want_c) and np.array_equal(lab, want_l)
+    assert st["merge_pairs"] == st["merge_tests"] + st["merge_skipped"]
+    ctx.set_option(G.GD_OPT_STATS, 0)
+    if mode == "ldf":
+        ctx.set_option(G.GD_OPT_GRAPH, 2)
+        for rep in range(3):
+            lab, core = run(ctx, x)
+            assert ctx.stats()["graph_replays"] == (1 if rep else 0)
+            assert np.array_equal(core, want_c) and np.array_equal(lab, want_l)
     ctx.close()

@@ -195,3 +195,34 @@ def test_trained_proposal_gain(ctx):
     print(f"plain: tests {s0['merge_tests']} distances {s0['merge_distances']}; "
           f"learned: tests {s1['merge_tests']} distances {s1['merge_distances']}", flush=True)
     assert s1["merge_distances"] < s0["merge_distances"]
+
+
+def test_trained_proposal_gain_on_large_core_sets(ctx):
+    """Where FastMerging's scans over large core sets dominate the merge (a
+    2M-point 3-D seed-spreader set at eps 2000: 619 core grids of about 3000
+    core points, below the size that is merged by whole workgroups), the
+    trained proposal makes the merge phase faster, at identical labels."""
+    import paper_2210_07580_amd as G
+    from paper_2210_07580_amd import proposal as P
+    if not os.path.exists(P.BLOB_PATH):
+        pytest.skip("no trained proposal committed")
+    w = W.sweep_workload("simden", 3, eps=2000)
+    t = torch.from_numpy(W.make_points(w).astype(np.float32)).cuda()
+    merge, labels = {}, {}
+    for name, blob in (("plain", None), ("learned", P.load_blob())):
+        ctx.set_proposal(blob)
+        try:
+            labels[name] = ctx.dbscan(t, w.eps, w.minpts)
+            ctx.set_option(G.GD_OPT_TIMING, 1)
+            ms = []
+            for _ in range(9):
+                ctx.dbscan(t, w.eps, w.minpts)
+                ms.append(ctx.phase_times()["merge"])
+            merge[name] = float(np.median(ms))
+        finally:
+            ctx.set_option(G.GD_OPT_TIMING, 0)
+            ctx.set_proposal(None)
+    print(f"merge phase: plain {merge['plain']:.3f} ms, learned {merge['learned']:.3f} ms", flush=True)
+    assert torch.equal(labels["plain"][0], labels["learned"][0])
+    assert torch.equal(labels["plain"][1], labels["learned"][1])
+    assert merge["learned"] < merge["plain"]
