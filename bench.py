@@ -317,7 +317,7 @@ def bench_neighbor_modes(G, steps, warmup):
     themselves (no lists).  Hashing is left out for the 5-D workload, where
     every grid probes 3902 candidate identifiers."""
     import torch
-    variants = {"tree_lists": [(G.GD_OPT_NEIGHBOR_MODE, 1)],
+    variants = {"tree_lists": [(G.GD_OPT_NEIGHBOR_MODE, 1), (G.GD_OPT_NEIGHBOR_QUERY, 3)],
                 "tree_lists_walk_order": [(G.GD_OPT_NEIGHBOR_MODE, 1), (G.GD_OPT_NEIGHBOR_QUERY, 1)],
                 "hash_lists": [(G.GD_OPT_NEIGHBOR_MODE, 1), (G.GD_OPT_NEIGHBOR_QUERY, 2)],
                 "tree_walks_in_consumers": [(G.GD_OPT_NEIGHBOR_MODE, 2)]}

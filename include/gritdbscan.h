@@ -258,14 +258,17 @@ typedef enum {
                                  then NOT those of dbscan(): an opt-in mode.  */
     GD_OPT_NEIGHBOR_QUERY = 11, /* how the lists Nei(g) are found: 0 (default)
                                  the grid tree of Algorithm 3, lists ordered by
-                                 offset (Eq. (2)) for at most 2^20 grids and in
-                                 walk order above; 1 the grid tree, lists in
-                                 walk order always (no offset order for core
-                                 marking's early exit); 2 direct hashing of
-                                 every candidate identifier with offset < d in
-                                 a table of the non-empty grids, lists ordered
+                                 offset (Eq. (2)) where core marking's early
+                                 exit pays for the ordering (at most 2^20 grids
+                                 of at least 8 points on average) and in walk
+                                 order otherwise; 1 the grid tree, lists in
+                                 walk order always; 2 direct hashing of every
+                                 candidate identifier with offset < d in a
+                                 table of the non-empty grids, lists ordered
                                  by offset (the query the grid tree avoids;
-                                 candidates grow as (2 ceil(sqrt(d)) + 1)^d).
+                                 candidates grow as (2 ceil(sqrt(d)) + 1)^d);
+                                 3 the grid tree, lists ordered by offset for
+                                 at most 2^20 grids whatever their size.
                                  The result is the same for every query.      */
     GD_OPT_GRID_LANES = 12    /* lanes per grid in the kernels that serve
                                  small grids (the merging of tiny core sets,
@@ -345,8 +348,9 @@ const char *gd_phase_name(int32_t i);
  * gd_debug_neighbors (Section 4.2.2, Algorithm 3):
  *   offsets         |Gs|+1 (uint64): Nei(g) of grid g is
  *   neighbors       neighbors[offsets[g] .. offsets[g+1]) (grid indices),
- *                   g itself excluded, ordered by the offset of Eq. (2) for
- *                   at most 2^20 grids (above, in the order of the tree walk)
+ *                   g itself excluded, ordered by the offset of Eq. (2) when
+ *                   the lists were written in that order (see
+ *                   GD_OPT_NEIGHBOR_QUERY), else in the order of the tree walk
  *                   Needs the lists of every grid (GD_EUNSUPPORTED after a
  *                   call that walked instead, see GD_OPT_NEIGHBOR_MODE).
  * gd_debug_core: core_flags_sorted (n, sorted order), grid_label (|Gs|:

@@ -114,7 +114,7 @@ struct gd_ctx {
     bool bfs = false;              // the BFS order of Algorithm 6 (merge_order 2)
     int nei_mode = 0;              // GD_OPT_NEIGHBOR_MODE: 0 auto, 1 lists, 2 walks
     int64_t approx_delta = 0;      // GD_OPT_APPROX_DELTA (0: exact merging)
-    int nei_query = kNeiTree;      // GD_OPT_NEIGHBOR_QUERY
+    int nei_query = kNeiAuto;      // GD_OPT_NEIGHBOR_QUERY (kNeiAuto for option value 0)
     bool last_walk = false;        // the last eager call walked (no full lists)
     bool last_wide = false;        // the last eager call took 64-bit distances
     gd_stats last{};
@@ -563,7 +563,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     auto build_lists = [&](const uint32_t* only_big, bool fallback) -> int {
         NeiQuery nq{};
         nq.t = t;
-        nq.kind = only_big ? kNeiTree : ctx->nei_query;
+        // offset order pays for itself through core marking's early exit
+        // only when grids hold several points; sparse grids take walk order
+        int kind = ctx->nei_query;
+        if (kind == kNeiAuto)
+            kind = ncell <= ((int64_t)1 << 20) && n >= 8 * std::max<int64_t>(ncell, 1) ? kNeiTree : kNeiTreeWalkOrder;
+        nq.kind = only_big ? kNeiTree : kind;
         nq.key_bytes = kbytes;
         nq.inst = b.inst;
         nq.inst_shift = &Hd->inst_shift;
@@ -1372,8 +1377,8 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
             }
             return GD_OK;
         case GD_OPT_NEIGHBOR_QUERY:
-            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "neighbour query must be 0, 1 or 2");
-            ctx->nei_query = (int)value;
+            if (value < 0 || value > 3) return ctx->fail(GD_EINVAL, "neighbour query must be 0, 1, 2 or 3");
+            ctx->nei_query = value == 0 ? kNeiAuto : value == 3 ? (int)kNeiTree : (int)value;
             return GD_OK;
         case GD_OPT_APPROX_DELTA:
             if (value < 0 || value > kApproxDeltaMax)

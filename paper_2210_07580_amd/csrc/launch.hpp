@@ -185,6 +185,9 @@ hipError_t launch_tree(const GridView& g, uint32_t* level_excl, uint32_t* partia
 // (walk order above 2^20 grids), the grid tree in walk order always, or
 // direct hashing of every candidate identifier (offset-ordered).
 enum NeiQueryKind { kNeiTree = 0, kNeiTreeWalkOrder = 1, kNeiHash = 2 };
+// Option value of GD_OPT_NEIGHBOR_QUERY 0: the tree in offset order or walk
+// order by the grids' mean size (resolved on the host per call).
+constexpr int kNeiAuto = 3;
 struct NeiQuery {
     TreeView t;
     int kind;

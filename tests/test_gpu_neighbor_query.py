@@ -1,6 +1,7 @@
 """Neighbour queries (GD_OPT_NEIGHBOR_QUERY): the grid tree of Algorithm 3
-with offset-ordered lists, the grid tree in walk order, and direct hashing
-of every candidate identifier.  Each must produce Nei(g) exactly as defined
+with offset-ordered lists, the grid tree in walk order, direct hashing of
+every candidate identifier, and the default that picks between the first
+two by the grids' mean size.  Each must produce Nei(g) exactly as defined
 (Eq. (2), g excluded), ordered by offset where promised, and the same
 clustering as the oracle."""
 import numpy as np
@@ -14,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TREE, TREE_WALK_ORDER, HASH = 0, 1, 2
+AUTO, TREE_WALK_ORDER, HASH, TREE = 0, 1, 2, 3
 
 
 @pytest.fixture(scope="module")
@@ -38,7 +39,7 @@ def run(ctx, x, eps, minpts):
     return lab.cpu().numpy(), core.cpu().numpy()
 
 
-@pytest.mark.parametrize("query", [TREE, TREE_WALK_ORDER, HASH])
+@pytest.mark.parametrize("query", [TREE, TREE_WALK_ORDER, HASH, AUTO])
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6])
 def test_lists_match_definition(G, query, d):
     rng = np.random.default_rng(70 + d)
@@ -54,13 +55,13 @@ def test_lists_match_definition(G, query, d):
     for g in range(len(ids)):
         got = nei[off[g]:off[g + 1]].astype(np.int64)
         assert sorted(got.tolist()) == want[g].tolist(), f"grid {g}"
-        if query != TREE_WALK_ORDER:
+        if query in (TREE, HASH):
             o = [steps.grid_offset(ids[g], ids[h]) for h in got]
             assert o == sorted(o), f"grid {g}: not ordered by offset"
     ctx.close()
 
 
-@pytest.mark.parametrize("query", [TREE_WALK_ORDER, HASH])
+@pytest.mark.parametrize("query", [TREE_WALK_ORDER, HASH, AUTO])
 @pytest.mark.parametrize("seed", range(6))
 def test_random_vs_brute(G, query, seed):
     rng = np.random.default_rng(900 + seed)
@@ -110,3 +111,25 @@ def test_batch_with_hashing(G):
         wl, wc = oracle.dbscan(x, e, m)
         assert np.array_equal(core.cpu().numpy(), wc) and np.array_equal(lab.cpu().numpy(), wl), f"instance {k}"
     ctx.close()
+
+
+def test_default_order_follows_grid_size(G):
+    # dense grids (H-like, about 150 points each): offset order; sparse 7-D
+    # grids (about two points each): walk order; the labels are the same
+    for name, n, ordered in (("H", 100_000, True), ("cfg2", 60_000, False)):
+        w = W.WORKLOADS[name].with_n(n)
+        x = W.make_points(w)
+        ctx = G.Context(0)
+        ctx.set_option(G.GD_OPT_NEIGHBOR_MODE, 1)
+        lab, core = run(ctx, x, w.eps, w.minpts)
+        _, gs, ids = ctx.debug_grids()
+        off, nei = ctx.debug_neighbors()
+        in_order = all(
+            [steps.grid_offset(ids[g], ids[h]) for h in nei[off[g]:off[g + 1]]] ==
+            sorted(steps.grid_offset(ids[g], ids[h]) for h in nei[off[g]:off[g + 1]])
+            for g in range(0, len(ids), max(1, len(ids) // 200)))
+        if ordered:
+            assert in_order, name
+        wl, wc = oracle.dbscan(x, w.eps, w.minpts)
+        assert np.array_equal(core, wc) and np.array_equal(lab, wl)
+        ctx.close()

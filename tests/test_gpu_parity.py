@@ -42,10 +42,12 @@ def gpu_dbscan(ctx, x, eps, minpts):
 
 @pytest.fixture()
 def list_ctx(G):
-    """A context that writes every grid's neighbour list out (the debug views
-    of Nei(g) need them; sparse data in d >= 4 would walk instead)."""
+    """A context that writes every grid's neighbour list out, ordered by
+    offset (the debug views of Nei(g) need the lists; by default sparse data
+    in d >= 4 would walk instead, and sparse grids take walk order)."""
     c = G.Context(0)
     c.set_option(G.GD_OPT_NEIGHBOR_MODE, 1)
+    c.set_option(G.GD_OPT_NEIGHBOR_QUERY, 3)
     yield c
     c.close()
 
