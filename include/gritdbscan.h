@@ -259,7 +259,7 @@ typedef enum {
     GD_OPT_NEIGHBOR_QUERY = 11, /* how the lists Nei(g) are found: 0 (default)
                                  the grid tree of Algorithm 3, lists ordered by
                                  offset (Eq. (2)) where core marking's early
-                                 exit pays for the ordering (at most 2^20 grids
+                                 exit pays for the ordering (at most 2^19 grids
                                  of at least 8 points on average) and in walk
                                  order otherwise; 1 the grid tree, lists in
                                  walk order always; 2 direct hashing of every

@@ -564,10 +564,12 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         NeiQuery nq{};
         nq.t = t;
         // offset order pays for itself through core marking's early exit
-        // only when grids hold several points; sparse grids take walk order
+        // only when grids hold several points; sparse grids take walk order,
+        // and so do more than 2^19 grids, whose ordered fill (scattered over
+        // the offset buckets) outweighs the early exit
         int kind = ctx->nei_query;
         if (kind == kNeiAuto)
-            kind = ncell <= ((int64_t)1 << 20) && n >= 8 * std::max<int64_t>(ncell, 1) ? kNeiTree : kNeiTreeWalkOrder;
+            kind = ncell <= ((int64_t)1 << 19) && n >= 8 * std::max<int64_t>(ncell, 1) ? kNeiTree : kNeiTreeWalkOrder;
         nq.kind = only_big ? kNeiTree : kind;
         nq.key_bytes = kbytes;
         nq.inst = b.inst;

@@ -86,10 +86,11 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     }
     unsigned long long n_pairs = 0, n_skip = 0, n_yes = 0, n_dist = 0, n_pts = 0;
     uint32_t ri = live ? uf_find_at(parent, ci, pci) : 0u;  // root hint of g_i's set
-    // each round takes two list entries per lane, whose loads are issued
-    // together: the rounds are chains of dependent loads, so half as many
-    // rounds cost about half the time
-    constexpr int U = 2;
+    // each round takes two list entries per lane (four with a wave per
+    // grid), whose loads are issued together: the rounds are chains of
+    // dependent loads, so fewer rounds cost less time (with a wave per grid
+    // the lists are long: cfg2's merge 40.6 -> 38.6 ms from two to four)
+    constexpr int U = S == kWave ? 4 : 2;
     for (uint64_t e = e0; e < e1; e += U * S) {
         bool cand[U];
         uint32_t cj[U], bj[U], mj[U], pj[U];
@@ -100,11 +101,19 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
             cj[u] = bj[u] = mj[u] = pj[u] = 0;
             if (idx < e1) cj[u] = nei[idx];
         }
+        // the root of each candidate first: a pair already in one set (most
+        // of them once the merge is under way) needs no 16-byte record load
+        // (it is still read when counting, so that the counts keep their
+        // meaning); the root found is the hint for the union
+        uint32_t root_j[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (cj[u] > ci) {
-                // the parent link loads beside the record (every grid has one)
-                pj[u] = load_acq(&parent[cj[u]]);
+            pj[u] = cj[u] > ci ? load_acq(&parent[cj[u]]) : 0u;
+            root_j[u] = cj[u] > ci ? uf_find_at(parent, cj[u], pj[u]) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (cj[u] > ci && (root_j[u] != ri || stats)) {
                 const uint4 rc = rank[cj[u]];
                 if (rc.x != kNone) {
                     bj[u] = rc.y;
@@ -113,11 +122,6 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
                 }
             }
         }
-        // pairs already in one set are skipped; the root found is the hint
-        // for the union
-        uint32_t root_j[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) root_j[u] = cand[u] ? uf_find_at(parent, cj[u], pj[u]) : 0u;
         bool any_yes = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) {

@@ -153,17 +153,33 @@ __device__ __forceinline__ bool wants_list(const uint32_t* only_big, int64_t c) 
 }
 
 // With lane_cnt (split queries only), each lane also keeps its own counts
-// for the fill pass, which then needs no second counting query.
-template <int D, int P, typename Q>
+// for the fill pass, which then needs no second counting query.  kTotal
+// (lists in walk order, one lane per grid): only the list length is needed,
+// kept in a register and stored as the offset-0 count (the others 0).
+template <int D, int P, bool kTotal, typename Q>
 __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, Q q, uint32_t* __restrict__ off_counts,
                                                            uint32_t* __restrict__ lane_cnt,
                                                            const uint32_t* __restrict__ only_big) {
-    __shared__ uint32_t sc[D][kBlock];
+    static_assert(!kTotal || P == 1, "totals are counted by one lane per grid");
+    __shared__ uint32_t sc[kTotal ? 1 : D][kBlock];
     const int64_t gt = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t c = gt / P;
     const int p = (int)(gt % P);
     const bool valid = c < (int64_t)*gv.ncell_dev;
     if (P == 1 && !valid) return;
+    if constexpr (kTotal) {
+        uint32_t total = 0;
+        if (wants_list(only_big, c)) {
+            int32_t g[D + 1];
+            load_grid_key<D>(gv, c, g);
+            const int dk = gv.b.inst[g[0]].d;
+            auto emit = [&](uint32_t a, int) { total += a != (uint32_t)c ? 1u : 0u; };
+            q.template part<D>(g, dk, -3, 3, emit);
+        }
+#pragma unroll
+        for (int o = 0; o < D; ++o) off_counts[c * D + o] = o == 0 ? total : 0u;
+        return;
+    }
 #pragma unroll
     for (int o = 0; o < D; ++o) sc[o][threadIdx.x] = 0;
     if (valid && wants_list(only_big, c)) count_part<D, P>(gv, q, c, p, sc);
@@ -183,7 +199,13 @@ __global__ __launch_bounds__(kBlock) void nei_count_kernel(GridView gv, Q q, uin
 // walk order (one lane per grid), found neighbours are staged in LDS and
 // stored kFillStage consecutive entries at a time, so that the stores fill
 // whole cache lines rather than scattering single words over offset buckets
-// (with millions of grids the stores dominated this pass).
+// (with millions of grids the stores dominated this pass).  These runs are
+// stored non-temporally: lists of millions of grids outgrow the caches, and
+// streaming them past L2 keeps the grid tree, which the walks re-read, in
+// cache (cfg2: 36 -> 33 ms).  The ordered lists' scattered single words are
+// not, since they need L2 to gather them into lines (H: 3x slower).
+// (Staging 32 entries and storing whole aligned lines with 16-byte stores
+// was slower: more LDS and registers per lane cost the walk occupancy.)
 constexpr int kFillStage = 16;
 
 template <int D, int P, bool kOrdered, typename Q>
@@ -249,7 +271,8 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, Q q, cons
         uint32_t run_pos = 0;
         int staged = 0;
         auto flush = [&]() {
-            for (int j = 0; j < staged; ++j) nei[base + run_pos + j] = stage_a[j][threadIdx.x];
+            for (int j = 0; j < staged; ++j)
+                __builtin_nontemporal_store(stage_a[j][threadIdx.x], &nei[base + run_pos + j]);
             run_pos += (uint32_t)staged;
             staged = 0;
         };
@@ -297,10 +320,14 @@ hipError_t launch_nei_count(const GridView& g, const NeiQuery& nq, uint32_t* off
     return with_query(nq, [&](auto q) -> hipError_t {
         using Q = decltype(q);
         if (sh.P > 1) {
-            GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit, Q><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock), 0,
-                                                                 st>>>(g, q, off_counts, lane_cnt, only_big)));
+            GD_DISPATCH_D(g.D, (nei_count_kernel<D, kSplit, false, Q><<<dim3(grid_for(g.ncell * kSplit)),
+                                                                        dim3(kBlock), 0, st>>>(g, q, off_counts,
+                                                                                               lane_cnt, only_big)));
+        } else if (!sh.ordered) {
+            GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1, true, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+                                   g, q, off_counts, nullptr, only_big)));
         } else {
-            GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
+            GD_DISPATCH_D(g.D, (nei_count_kernel<D, 1, false, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
                                    g, q, off_counts, nullptr, only_big)));
         }
         return hipGetLastError();

@@ -25,10 +25,10 @@
 
 namespace gd {
 
+// w = 1 + isqrt(budget - 1) for a budget of 1..9 (budgets never exceed the
+// instance dimension, at most 8): isqrt(b - 1) counts k >= 1 with k^2 <= b - 1.
 __device__ __forceinline__ int walk_window(int budget) {
-    int w = 0;
-    while ((w + 1) * (w + 1) <= budget - 1) ++w;
-    return w + 1;
+    return 1 + (budget >= 2 ? 1 : 0) + (budget >= 5 ? 1 : 0);
 }
 
 // First index in [lo, hi) whose key is >= want.
