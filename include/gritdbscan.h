@@ -270,13 +270,21 @@ typedef enum {
                                  3 the grid tree, lists ordered by offset for
                                  at most 2^20 grids whatever their size.
                                  The result is the same for every query.      */
-    GD_OPT_GRID_LANES = 12    /* lanes per grid in the kernels that serve
+    GD_OPT_GRID_LANES = 12,   /* lanes per grid in the kernels that serve
                                  small grids (the merging of tiny core sets,
                                  border assignment):
                                  0 (default) chooses from the mean list length
                                  and grid size (16 when they are at most 40
                                  entries and 32 points, else 64), 16 (four
                                  grids per wave) or 64 (one).  Same result.   */
+    GD_OPT_PACKED_ROWS = 13   /* 1 (default): the radix sort of Algorithm 1
+                                 carries each point's low coordinate bits
+                                 (beside its index, or inside a two-word
+                                 identifier's sort word when both fit 64
+                                 bits) and the sorted coordinate rows are
+                                 rebuilt in order from them and the grid;
+                                 0: the rows are gathered from the input in
+                                 sorted order.  Same result.                   */
 } gd_option;
 
 int gd_set_option(gd_ctx *ctx, int option, int64_t value);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
 GD_OPT_TILE_POINTS, GD_OPT_MERGE_WAVES, GD_OPT_NEIGHBOR_MODE, GD_OPT_MERGE_ORDER = 6, 7, 8, 9
-GD_OPT_APPROX_DELTA, GD_OPT_NEIGHBOR_QUERY, GD_OPT_GRID_LANES = 10, 11, 12
+GD_OPT_APPROX_DELTA, GD_OPT_NEIGHBOR_QUERY, GD_OPT_GRID_LANES, GD_OPT_PACKED_ROWS = 10, 11, 12, 13
 NOALLOC_SCRATCH_BYTES = 256 << 20
 PHASE_COUNT = 14
 EPS_MAX = 21845  # largest eps of the 32-bit distance path (GD_EPS_MAX); larger eps use 64 bits

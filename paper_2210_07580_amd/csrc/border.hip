@@ -42,10 +42,13 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
 }
 
 // Points in input order, instance tiles as in the identifier pass; each
-// thread resolves U points at a time so that their loads overlap.
+// thread resolves U points at a time so that their loads overlap.  The
+// identifier of input word w is w >> key_lo (key_lo > 0: packed rows in
+// two-word keys).
 template <typename K>
 __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
-                                                               const HashSlot<K>* __restrict__ tab, int bits) {
+                                                               const HashSlot<K>* __restrict__ tab, int bits,
+                                                               int key_lo) {
     constexpr int U = 8;
     if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
     const int k = tile_instance(b, blockIdx.x);
@@ -65,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + (int64_t)u * kBlock;
-            key[u] = i < hi ? keys[I.off + i] : ~K(0);
+            key[u] = i < hi ? keys[I.off + i] >> key_lo : ~K(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -98,20 +101,20 @@ __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K*
 
 template <typename K>
 hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* keys_in, const K* skeys,
-                                const int32_t* cell_label, void* table, int bits, hipStream_t st) {
+                                const int32_t* cell_label, void* table, int bits, int key_lo, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     HashSlot<K>* tab = reinterpret_cast<HashSlot<K>*>(table);
     const int64_t slots = (1ll << bits) + 1;
     hash_clear_kernel<K><<<dim3((unsigned)std::min<int64_t>(grid_for(slots), 4096)), dim3(kBlock), 0, st>>>(tab, slots,
                                                                                                       kDeferred);
     hash_build_kernel<K><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, skeys, cell_label, tab, bits);
-    output_direct_kernel<K><<<dim3(g.b.tiles), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits);
+    output_direct_kernel<K><<<dim3(g.b.tiles), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits, key_lo);
     return hipGetLastError();
 }
 template hipError_t launch_output_direct<uint32_t>(const GridView&, const CoreOut&, const uint32_t*, const uint32_t*,
-                                                   const int32_t*, void*, int, hipStream_t);
+                                                   const int32_t*, void*, int, int, hipStream_t);
 template hipError_t launch_output_direct<uint64_t>(const GridView&, const CoreOut&, const uint64_t*, const uint64_t*,
-                                                   const int32_t*, void*, int, hipStream_t);
+                                                   const int32_t*, void*, int, int, hipStream_t);
 
 // All-core grids without the hash table (identifiers of two words): their
 // points' labels go out through the sort permutation, one thread per grid.

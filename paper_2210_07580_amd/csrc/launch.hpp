@@ -161,6 +161,29 @@ __host__ __device__ constexpr int pack_bits(int d) { return 32 / d; }
 __host__ __device__ inline bool pack_fits(int d, int64_t eps) {
     return d >= 1 && d <= kMaxD && (double)eps / sqrt((double)d) + 4.0 < (double)(1ull << pack_bits(d));
 }
+// Packed rows with two-word keys: identifiers wider than 32 bits carry the
+// low bits of the coordinates in the same 64-bit sort word, below the
+// identifier: word = identifier << (D * B) | sum_j (u_j mod 2^B) << (j * B),
+// with one width B for the whole batch, and the sort orders on the
+// identifier bits alone.  pack64_bits(d, eps): the smallest B that holds a
+// grid of instance (d, eps), by the same bound as pack_fits; 0 if none up to
+// 31 does.
+__host__ __device__ inline bool pack_fits_bits(int d, int64_t eps, int bits) {
+    return d >= 1 && d <= kMaxD && bits >= 1 && bits <= 31 &&
+           (double)eps / sqrt((double)d) + 4.0 < (double)(1ull << bits);
+}
+inline int pack64_bits(int d, int64_t eps) {
+    for (int bits = 1; bits <= 31; ++bits)
+        if (pack_fits_bits(d, eps, bits)) return bits;
+    return 0;
+}
+// The words of the batch in input order (B bits per coordinate of the
+// batch's D).  A sync-free run whose instance table no longer fits B raises
+// kErrPlan.
+hipError_t launch_keys_packed64(const Batch& b, uint64_t* words, int bits, hipStream_t st);
+// After the sort: each sorted word becomes its identifier again (in place)
+// and the sorted rows are rebuilt from it (crd as for launch_unpack).
+hipError_t launch_unpack64(const Batch& b, uint64_t* words, int bits, int32_t* crd, hipStream_t st);
 // Grid identifiers in input order; with vals (n entries), also the packed
 // sort values (index | low coordinate bits << 32).
 template <typename K>
@@ -362,10 +385,11 @@ hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* ne
                          const int32_t* cell_label, bool wide, int lanes, hipStream_t st);
 // All-core grids: output in input order through an identifier -> label hash
 // table of 2^bits slots (+1) in `table` (output_table_bytes).  keys_in: the
-// identifiers in input order; skeys: sorted.
+// identifiers in input order, shifted up by key_lo bits (the packed-row
+// words of launch_keys_packed64; else 0); skeys: sorted.
 template <typename K>
 hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* keys_in, const K* skeys,
-                                const int32_t* cell_label, void* table, int bits, hipStream_t st);
+                                const int32_t* cell_label, void* table, int bits, int key_lo, hipStream_t st);
 size_t output_table_bytes(int bits, int key_bytes);
 // All-core grids of identifiers wider than 64 bits: output through the
 // sort permutation (no hash table).

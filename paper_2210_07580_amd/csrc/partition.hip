@@ -547,6 +547,131 @@ hipError_t launch_unpack(const Batch& b, const uint32_t* skeys, const uint64_t* 
     return hipGetLastError();
 }
 
+// Packed rows in two-word keys (launch.hpp, pack64_bits): the word of a
+// point is its identifier << W | its coordinates' low B bits (coordinate j at
+// j * B), W = D * B for the batch's D.  Four points' words go out as two
+// 16-byte stores when the instance starts on a multiple of four points.
+template <int D>
+__device__ __forceinline__ void keys64_tile(const Inst& I, int64_t lo, int64_t hi, uint64_t top, int B, int W,
+                                            uint64_t* __restrict__ words) {
+    int32_t mn[D], sh[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        mn[j] = I.mn[j];
+        sh[j] = I.shift[j];
+    }
+    const uint32_t eps = (uint32_t)I.eps;
+    const float scale = (float)(sqrt((double)D) / (double)I.eps);
+    const uint64_t low = (1ull << B) - 1ull;
+    uint64_t* __restrict__ out = words + I.off;
+    auto point = [&](const float (&row)[D]) -> uint64_t {
+        uint64_t key = top, packed = 0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const uint32_t u = (uint32_t)((int)row[j] - mn[j]);
+            key |= (uint64_t)grid_coord(u, D, eps, scale) << sh[j];
+            packed |= ((uint64_t)u & low) << (j * B);
+        }
+        return (key << W) | packed;
+    };
+    const bool vec = (I.off & 3) == 0;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    for_point_groups<D>(
+        I, lo, hi,
+        [&](int64_t i0, const float (&rows)[4][D]) {
+            uint64_t w[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) w[p] = point(rows[p]);
+            if (vec) {
+                u4* o = reinterpret_cast<u4*>(out + i0);
+                o[0] = u4{(uint32_t)w[0], (uint32_t)(w[0] >> 32), (uint32_t)w[1], (uint32_t)(w[1] >> 32)};
+                o[1] = u4{(uint32_t)w[2], (uint32_t)(w[2] >> 32), (uint32_t)w[3], (uint32_t)(w[3] >> 32)};
+            } else {
+#pragma unroll
+                for (int p = 0; p < 4; ++p) out[i0 + p] = w[p];
+            }
+        },
+        [&](int64_t i, const float (&row)[D]) { out[i] = point(row); });
+}
+
+template <int DB>
+__global__ __launch_bounds__(kBlock) void keys64_kernel(Batch b, uint64_t* __restrict__ words, int B) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
+    const int W = b.D * B;
+    // as keys_kernel: a sync-free run whose instances no longer fit B, or
+    // whose input failed, is discarded; the instance id keeps each
+    // instance's points in its own range through the sort
+    const bool bad_pack = !pack_fits_bits(I.d, I.eps, B);
+    if (bad_pack && threadIdx.x == 0) atomicOr(&b.hdr->err, kErrPlan);
+    if (bad_pack || (b.hdr->err & (kErrNotInteger | kErrKeyBits | kErrPlan))) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) words[I.off + i] = (uint64_t)k << W;
+        return;
+    }
+    const int ishift = b.hdr->inst_shift;
+    const uint64_t top = ishift >= 64 ? 0ull : (uint64_t)k << ishift;
+    with_d<DB>(I.d, [&](auto dc) { keys64_tile<decltype(dc)::value>(I, lo, hi, top, B, W, words); });
+}
+
+hipError_t launch_keys_packed64(const Batch& b, uint64_t* words, int bits, hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    GD_DISPATCH_D(b.D, (keys64_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, words, bits)));
+    return hipGetLastError();
+}
+
+// The rows from the sorted words, as unpack_kernel does from the identifier
+// and the packed value (the grid's centre a_j and the low B bits give u_j);
+// each word is replaced by its identifier for the passes that follow.
+template <int DB>
+__global__ __launch_bounds__(kBlock) void unpack64_kernel(Batch b, uint64_t* __restrict__ words, int B,
+                                                          int32_t* __restrict__ crd) {
+    const int k = tile_instance(b, blockIdx.x);
+    const Inst& I = b.inst[k];
+    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
+    const int64_t hi = min(I.n, lo + b.tile_pts);
+    const int W = b.D * B;
+    const uint64_t low = (1ull << B) - 1ull;
+    const int64_t half = (int64_t)1 << (B - 1);
+    with_d<DB>(I.d, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        int sh[D];
+        uint64_t fm[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            sh[j] = I.shift[j];
+            fm[j] = I.bits[j] >= 64 ? ~0ull : ((1ull << I.bits[j]) - 1ull);
+        }
+        const double side = (double)I.eps / sqrt((double)D);
+#pragma unroll 4
+        for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+            const int64_t s = I.off + i;
+            const uint64_t w = words[s];
+            const uint64_t key = w >> W;
+            int32_t y[DB];
+#pragma unroll
+            for (int j = 0; j < DB; ++j) y[j] = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const uint64_t g = (key >> sh[j]) & fm[j];
+                const int64_t a = (int64_t)floor(((double)g + 0.5) * side);
+                const uint64_t lb = (w >> (j * B)) & low;
+                const uint64_t t = ((uint64_t)((int64_t)lb - a + half)) & low;
+                y[j] = (int32_t)(a + (int64_t)t - half);
+            }
+            store_row<DB>(crd, s, y);
+            words[s] = key;
+        }
+    });
+}
+
+hipError_t launch_unpack64(const Batch& b, uint64_t* words, int bits, int32_t* crd, hipStream_t st) {
+    if (b.tiles == 0) return hipSuccess;
+    GD_DISPATCH_D(b.D, (unpack64_kernel<D><<<dim3(b.tiles), dim3(kBlock), 0, st>>>(b, words, bits, crd)));
+    return hipGetLastError();
+}
+
 template <int D>
 struct FRow {
     float v[D];

@@ -256,7 +256,7 @@ struct RadixResult {
     V* vals;
 };
 
-// Sorts keys[0..n) (and vals) on their low `bits` bits.  keys/vals and
+// Sorts keys[0..n) (and vals) on their bits [lo, lo + bits).  keys/vals and
 // keys_alt/vals_alt are ping-pong buffers; the result lands in one of them.
 // With keys_spare, the passes after the first alternate between keys_alt
 // and keys_spare, so keys[] keeps the input order.
@@ -265,7 +265,7 @@ struct RadixResult {
 template <typename K, typename V = uint32_t>
 hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t n, int bits,
                             bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K, V>* out,
-                            K* keys_spare = nullptr) {
+                            K* keys_spare = nullptr, int lo = 0) {
     K* kin = keys;
     V* vin = vals;
     K* kout = keys_alt;
@@ -279,7 +279,7 @@ hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t 
     bool iota = vals_iota;
     const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
     const int rbits = passes ? (bits + passes - 1) / passes : 0;
-    for (int p = 0, shift = 0; p < passes; ++p, shift += rbits) {
+    for (int p = 0, shift = lo; p < passes; ++p, shift += rbits) {
         if (n == 0) break;
         const int64_t bins = (int64_t)1 << rbits;
         const dim3 grid((unsigned)tiles), block(kBlock);
