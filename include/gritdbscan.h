@@ -358,7 +358,9 @@ const char *gd_phase_name(int32_t i);
  *   neighbors       neighbors[offsets[g] .. offsets[g+1]) (grid indices),
  *                   g itself excluded, ordered by the offset of Eq. (2) when
  *                   the lists were written in that order (see
- *                   GD_OPT_NEIGHBOR_QUERY), else in the order of the tree walk
+ *                   GD_OPT_NEIGHBOR_QUERY), else in walk order (first-level
+ *                   keys g_1, g_1 + 1, .., g_1 + 3, g_1 - 1, .., g_1 - 3,
+ *                   each subtree ascending).
  *                   Needs the lists of every grid (GD_EUNSUPPORTED after a
  *                   call that walked instead, see GD_OPT_NEIGHBOR_MODE).
  * gd_debug_core: core_flags_sorted (n, sorted order), grid_label (|Gs|:

@@ -292,6 +292,7 @@ struct Layout {
     int32_t* tkey[kMaxLevels];
     uint32_t* tchild[kMaxLevels];
     uint32_t* off_counts;
+    uint2* nei_up;
     uint64_t* nei_off;
     uint8_t* core;
     uint32_t* core_cnt;
@@ -335,6 +336,7 @@ Layout carve(char* base, int64_t n, int D, uint32_t tiles, int key_bytes = 8) {
     }
     L.off_counts = c.take<uint32_t>((int64_t)D * n);
     L.nei_off = c.take<uint64_t>(n + 1);
+    L.nei_up = c.take<uint2>(n);
     L.core = c.take<uint8_t>(n);
     L.core_cnt = c.take<uint32_t>(n);
     L.core_begin = c.take<uint32_t>(n);
@@ -607,6 +609,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     // hold the sorted identifiers (free until the LDF step), when they fit
     uint64_t nei_total = 0;
     uint32_t* nei = nullptr;
+    bool lists_up = false;  // L.nei_up holds each list's larger-index range
     // Nei(g) of every grid, or (walk mode) of the grids with more than
     // kTinyCore core points, known only after core marking
     auto build_lists = [&](const uint32_t* only_big, bool fallback) -> int {
@@ -660,7 +663,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         }
         nei = (uint32_t*)ctx->cur->nei.p;
         ctx->mark(P_NEI_FILL, 0);
-        GD_TRY(launch_nei_fill(g, nq, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, st));
+        GD_TRY(launch_nei_fill(g, nq, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, L.nei_up, st));
+        lists_up = nq.kind == kNeiTreeWalkOrder;
         ctx->mark(P_NEI_FILL, 1);
         return GD_OK;
     };
@@ -785,7 +789,8 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         if (walk)
             GD_TRY(launch_merge_walk(g, co, t, ldf, n_small, L.parent, stats ? ctx->stats_dev->merge : nullptr, wide,
                                      st));
-        GD_TRY(launch_merge(g, co, L.nei_off, nei, ldf, L.rank, ncc, n_small, max_core, ctx->merge_waves,
+        GD_TRY(launch_merge(g, co, L.nei_off, nei, lists_up && !walk ? L.nei_up : nullptr, ldf, L.rank, ncc,
+                            n_small, max_core, ctx->merge_waves,
                             small_lanes, walk,
                             hm.q, wide, L.parent, stats ? ctx->stats_dev->merge : nullptr,
                             ctx->proposal_on ? ctx->proposal_dev : nullptr, sum, st));

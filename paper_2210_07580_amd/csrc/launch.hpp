@@ -233,10 +233,12 @@ hipError_t launch_nei_count(const GridView& g, const NeiQuery& nq, uint32_t* off
 hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uint64_t* nei_off, uint64_t* partial,
                               hipStream_t st);
 // Pass 2: write Nei(g) (skipped, with kErrNeiOverflow, if the total exceeds
-// `capacity` entries).
+// `capacity` entries).  nei_up (ncell entries): for lists in walk order,
+// the range [x, y) of Nei(g), relative to its start, that holds exactly the
+// neighbours of larger index (the other orders leave it alone).
 hipError_t launch_nei_fill(const GridView& g, const NeiQuery& nq, const uint32_t* off_counts, const uint32_t* lane_cnt,
                            const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
-                           hipStream_t st);
+                           uint2* nei_up, hipStream_t st);
 // Identifier -> grid index table (2^bits + 1 slots of 8 or 16 bytes, as
 // output_table_bytes) for the hashing query; skeys: sorted identifiers.
 hipError_t launch_grid_table(const GridView& g, const void* skeys, int key_bytes, void* table, int bits,
@@ -318,7 +320,10 @@ struct CellSummary;
 // tiny-set kernel (16: four grids per wave; else 64).  n_small: tiny core grids leading the
 // visiting order (-2: as many as the device count says, -1: not ordered).
 // tiny_done: the pairs of two tiny core sets were already merged (walk mode).
+// nei_up (optional, lists in walk order): each list's range of larger-index
+// neighbours (launch_nei_fill), the only ones the tiny-set kernel tests.
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                        const uint2* nei_up,
                         const uint32_t* ldf_list, const uint4* rank, int64_t n_core_cells, int64_t n_small,
                         int64_t max_core, int waves, int small_lanes, bool tiny_done, const HugeQueue& huge,
                         bool wide,

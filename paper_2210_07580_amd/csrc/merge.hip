@@ -47,6 +47,7 @@ __device__ __forceinline__ void flush_stats(MergeStats* stats, int64_t r, unsign
 template <int D, bool kWide, int S>
 __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOut co, const uint64_t* __restrict__ nei_off,
                                                              const uint32_t* __restrict__ nei,
+                                                             const uint2* __restrict__ nei_up,
                                                              const uint32_t* __restrict__ ldf,
                                                              const uint4* __restrict__ rank, int64_t r0, int64_t r1,
                                                              const uint32_t* split, uint32_t* parent,
@@ -65,6 +66,12 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     const typename Dist<kWide>::T T = inst_Tm<kWide>(cell_inst(gv, ci));
     const uint4 own = live ? rank[ci] : make_uint4(0u, 0u, 0u, 0u);
     uint64_t e0 = live ? nei_off[ci] : 0, e1 = live ? nei_off[ci + 1] : 0;
+    if (nei_up && live) {
+        // lists in walk order: only the range of larger-index neighbours
+        const uint2 up = nei_up[ci];
+        e1 = e0 + up.y;
+        e0 += up.x;
+    }
     const uint32_t pci = load_acq(&parent[ci]);
     const uint32_t bi = own.y;
     const uint32_t mi = own.z;
@@ -394,6 +401,7 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
 }
 
 hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei_off, const uint32_t* nei,
+                        const uint2* nei_up,
                         const uint32_t* ldf_list, const uint4* rank, int64_t ncc, int64_t n_small, int64_t max_core,
                         int waves, int small_lanes, bool tiny_done, const HugeQueue& huge, bool wide,
                         uint32_t* parent, MergeStats* stats, const __half* proposal, const CellSummary* sum,
@@ -415,16 +423,16 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
         const dim3 blocks((unsigned)((s1 + per_block - 1) / per_block)), threads(kBlock);
         if (wide && S == 16)
             GD_DISPATCH_D(g.D, (merge_small_kernel<D, true, 16><<<blocks, threads, 0, st>>>(
-                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+                                   g, c, nei_off, nei, nei_up, ldf_list, rank, 0, s1, split, parent, stats)));
         else if (wide)
             GD_DISPATCH_D(g.D, (merge_small_kernel<D, true, kWave><<<blocks, threads, 0, st>>>(
-                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+                                   g, c, nei_off, nei, nei_up, ldf_list, rank, 0, s1, split, parent, stats)));
         else if (S == 16)
             GD_DISPATCH_D(g.D, (merge_small_kernel<D, false, 16><<<blocks, threads, 0, st>>>(
-                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+                                   g, c, nei_off, nei, nei_up, ldf_list, rank, 0, s1, split, parent, stats)));
         else
             GD_DISPATCH_D(g.D, (merge_small_kernel<D, false, kWave><<<blocks, threads, 0, st>>>(
-                                   g, c, nei_off, nei, ldf_list, rank, 0, s1, split, parent, stats)));
+                                   g, c, nei_off, nei, nei_up, ldf_list, rank, 0, s1, split, parent, stats)));
     }
     if (ncc - b0 <= 0 || max_core <= (int64_t)kSmallSet) return hipGetLastError();
     const uint32_t words = (uint32_t)((std::min<int64_t>(max_core, kMaxCoreBits) + kWave - 1) / kWave);

@@ -11,7 +11,10 @@
 // The result excludes g itself.  It is ordered by offset (the paper's
 // counting sort, nearest grids first, for early exit in core marking) when
 // the query splits over lanes or hashes; a one-lane tree walk over millions
-// of grids, or on request, keeps walk order (level 1 centre-out).
+// of grids, or on request, keeps walk order: level-1 keys g_1, g_1 + 1, ..,
+// g_1 + 3, then g_1 - 1, .., g_1 - 3, each subtree in ascending order, so
+// that the neighbours with a larger index form one range per list (kept in
+// nei_up for the merge of tiny core sets, which tests only those).
 #include <algorithm>
 #include <type_traits>
 
@@ -212,7 +215,8 @@ template <int D, int P, bool kOrdered, typename Q>
 __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, Q q, const uint32_t* __restrict__ off_counts,
                                                           const uint32_t* __restrict__ lane_cnt,
                                                           const uint64_t* __restrict__ nei_off, uint32_t* __restrict__ nei,
-                                                          uint64_t capacity, const uint32_t* __restrict__ only_big) {
+                                                          uint64_t capacity, const uint32_t* __restrict__ only_big,
+                                                          uint2* __restrict__ nei_up) {
     static_assert(kOrdered || P == 1, "walk order is written by one lane per grid");
     __shared__ uint32_t pos[D][kBlock];
     constexpr int kStage = kOrdered ? 1 : kFillStage;
@@ -276,14 +280,24 @@ __global__ __launch_bounds__(kBlock) void nei_fill_kernel(GridView gv, Q q, cons
             run_pos += (uint32_t)staged;
             staged = 0;
         };
-        auto visit = [&](uint32_t a, int) -> bool {
-            if (a == (uint32_t)c) return true;
+        // level-1 keys g_1, g_1 + 1, .., g_1 + 3, then g_1 - 1, .., g_1 - 3,
+        // each subtree ascending: the neighbours above g (larger identifier,
+        // larger index) are the entries after g's own place in the first
+        // run up to the start of the negative keys, one range [up_lo, up_hi)
+        uint32_t up_lo = 0;
+        auto emit = [&](uint32_t a, int) {
+            if (a == (uint32_t)c) {
+                up_lo = run_pos + (uint32_t)staged;
+                return;
+            }
             stage_a[staged][threadIdx.x] = a;
             if (++staged == kStage) flush();
-            return true;
         };
-        q.template walk<D>(g, dk, visit);
+        q.template part<D>(g, dk, 0, 3, emit);
+        const uint32_t up_hi = run_pos + (uint32_t)staged;
+        for (int dlt = -1; dlt >= -3; --dlt) q.template part<D>(g, dk, dlt, dlt, emit);
         flush();
+        nei_up[c] = make_uint2(up_lo, up_hi);
     }
 }
 
@@ -367,7 +381,7 @@ hipError_t launch_nei_offsets(const GridView& g, const uint32_t* off_counts, uin
 
 hipError_t launch_nei_fill(const GridView& g, const NeiQuery& nq, const uint32_t* off_counts, const uint32_t* lane_cnt,
                            const uint64_t* nei_off, uint32_t* nei, uint64_t capacity, const uint32_t* only_big,
-                           hipStream_t st) {
+                           uint2* nei_up, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
     const NeiShape sh = nei_shape(nq, g.ncell);
     return with_query(nq, [&](auto q) -> hipError_t {
@@ -375,13 +389,13 @@ hipError_t launch_nei_fill(const GridView& g, const NeiQuery& nq, const uint32_t
         if (sh.P > 1) {
             GD_DISPATCH_D(g.D, (nei_fill_kernel<D, kSplit, true, Q><<<dim3(grid_for(g.ncell * kSplit)), dim3(kBlock),
                                                                       0, st>>>(g, q, off_counts, lane_cnt, nei_off, nei,
-                                                                               capacity, only_big)));
+                                                                               capacity, only_big, nei_up)));
         } else if (sh.ordered) {
             GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1, true, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big)));
+                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big, nei_up)));
         } else if constexpr (std::is_same<Q, TreeQuery>::value) {
             GD_DISPATCH_D(g.D, (nei_fill_kernel<D, 1, false, Q><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(
-                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big)));
+                                   g, q, off_counts, nullptr, nei_off, nei, capacity, only_big, nei_up)));
         } else {
             return hipErrorInvalidValue;  // hashing always writes ordered lists
         }
