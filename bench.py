@@ -48,7 +48,8 @@ PHASE_KERNELS = {
     "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel (batches of several instances)"],
     "keys": ["keys_kernel"],
     "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel"],
-    "gather": ["unpack_kernel (rows rebuilt in order; gather_kernel when the low bits do not fit)"],
+    "gather": ["unpack_kernel or unpack64_kernel (rows rebuilt in order; gather_kernel when the low bits do "
+               "not fit)"],
     "core_mark": ["core_mark_kernel"],
     "merge": ["merge_small_kernel", "merge_big_kernel"],
     "output": ["hash_clear_kernel", "hash_build_kernel", "output_direct_kernel", "output_kernel"],
@@ -57,26 +58,39 @@ PHASE_KERNELS = {
 
 
 def packed_rows(d, eps, key_bits):
-    """Whether the library carries low coordinate bits through the sort and
-    rebuilds the sorted rows in order (the same rule as its pack_fits)."""
-    return key_bits <= 32 and eps / math.sqrt(d) + 4.0 < 2.0 ** (32 // d)
+    """How the library rebuilds the sorted rows of one instance (its pack_fits
+    and pack64_bits rules): "value" (32-bit identifiers, the low coordinate
+    bits in the 64-bit sort value beside the index), "word" (the low bits
+    below the identifier in a 64-bit sort word, the index as the value), or
+    None (the rows gathered from the input)."""
+    fits = lambda bits: eps / math.sqrt(d) + 4.0 < 2.0 ** bits
+    if key_bits <= 32 and fits(32 // d):
+        return "value"
+    b = next((bits for bits in range(1, 32) if fits(bits)), 0)
+    return "word" if b and key_bits + d * b <= 64 else None
 
 
 def algorithmic_bytes(phase, n, d, st, key_bytes, passes, packed):
-    """Bytes the phase must move at least (the method's own traffic), per call."""
+    """Bytes the phase must move at least (the method's own traffic), per
+    call; key_bytes: the sort word (8 with packed == "word")."""
     B = 4 * d  # coordinates per point
-    V = 8 if packed else 4  # sort value: index, with the packed low bits
+    V = 8 if packed == "value" else 4  # sort value: index, with the packed low bits
     if phase == "minmax":
         return n * B
     if phase == "keys":
-        return n * (B + key_bytes + (8 if packed else 0))
+        return n * (B + key_bytes + (8 if packed == "value" else 0))
     if phase == "radix_sort":
         # per pass: histogram read of the keys, then (key, value) read and written
         return passes * n * (key_bytes + 2 * (key_bytes + V))
     if phase == "gather":
-        # packed: sorted keys and values in, index and rows out; else the
-        # index, one row in and one row out
-        return n * (key_bytes + 8 + 4 + B) if packed else n * (4 + 2 * B)
+        # "value": sorted keys and values in, index and rows out; "word": the
+        # words in, rows and identifiers out; else the index, one row in and
+        # one row out
+        if packed == "value":
+            return n * (key_bytes + 8 + 4 + B)
+        if packed == "word":
+            return n * (2 * key_bytes + B)
+        return n * (4 + 2 * B)
     if phase == "core_mark":
         # flags, plus every neighbour point streamed for a sparse grid (8 B per neighbour grid opened)
         return n + st["core_candidates"] * B + 8 * st["core_neighbor_grids"]
@@ -679,13 +693,14 @@ def main():
     total = t1 - t0
     ms_per_step = 1000.0 * total / K
     phases = {k: v / K for k, v in phase_sum.items()}
-    key_bytes = 4 if st["key_bits"] <= 32 else 8
+    packing = packed_rows(d, w.eps, st["key_bits"])
+    key_bytes = 4 if st["key_bits"] <= 32 and packing != "word" else 8
 
     passes = (st["key_bits"] + 7) // 8
     traffic = measured_traffic(w.name)
     rooflines = {}
     for ph, ms in phases.items():
-        b = algorithmic_bytes(ph, n, d, st, key_bytes, passes, packed_rows(d, w.eps, st["key_bits"]))
+        b = algorithmic_bytes(ph, n, d, st, key_bytes, passes, packing)
         if b is None or ms <= 0:
             continue
         achieved = b / (ms * 1e-3) / 1e9
