@@ -267,12 +267,25 @@ constexpr int64_t kEpsClamp = (int64_t)1 << 27;
 // scratch) and the consumers may walk the grid tree instead.
 constexpr int kListsDoNotFit = 1;
 
-// Output hash table: 2^bits slots for ncell grids, load <= 1/8 up to 2^20
-// grids (fewer second probes), <= 1/4 above (the table stays modest).
+// Hash tables of the grids (the hashing neighbour query's, the output's):
+// 2^bits slots for ncell grids, load <= 1/8 up to 2^20 grids (fewer second
+// probes), <= 1/4 above (the table stays modest).  A planned run's table
+// buffer is sized by this bound, which covers both.
 int table_bits(int64_t ncell) {
     const int64_t slots = ncell <= (1 << 20) ? 8 * ncell : 4 * ncell;
     int b = 10;
     while (((int64_t)1 << b) < slots) ++b;
+    return b;
+}
+
+// The output table holds only the all-core grids, and above 2^20 grids it is
+// cleared in every call: 2 slots per grid there (load <= 1/2, in practice
+// the all-core share of that) halves the clearing of a table that outgrows
+// the caches anyway.
+int output_table_bits(int64_t ncell) {
+    if (ncell <= (1 << 20)) return table_bits(ncell);
+    int b = 10;
+    while (((int64_t)1 << b) < 2 * ncell) ++b;
     return b;
 }
 
@@ -803,7 +816,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
     ctx->mark(P_LABELS, 1);
 
     // ---- border / noise, output in input order
-    const int hbits = table_bits(ncell);
+    const int hbits = output_table_bits(ncell);
     if (!plan && kbytes <= 8 &&
         (rc = grow(ctx, ctx->cur->table, output_table_bytes(hbits, kbytes),
                    ctx->cur->arena.cap + ctx->cur->nei.cap + ctx->cur->sumbuf.cap + ctx->cur->huge.cap)))

@@ -72,11 +72,6 @@ struct TreeQuery {
             }
         }
     }
-    // Every neighbour in walk order (level 1 centre-out).
-    template <int D, typename V>
-    __device__ __forceinline__ void walk(const int32_t (&g)[D + 1], int dk, V& visit) const {
-        tree_walk<D>(t, g, dk, false, visit);
-    }
 };
 
 // Direct hashing of every candidate identifier.  Identifiers are packed as
