@@ -133,3 +133,34 @@ def test_default_order_follows_grid_size(G):
         wl, wc = oracle.dbscan(x, w.eps, w.minpts)
         assert np.array_equal(core, wc) and np.array_equal(lab, wl)
         ctx.close()
+
+
+@pytest.mark.parametrize("name,n", [("cfg2", 120_000), ("cfg1", 150_000)])
+def test_walk_order_ranges_of_larger_neighbours(G, name, n):
+    # walk-order lists keep each grid's larger-index neighbours in one range,
+    # which is all the tiny-set merge reads: every such list splits into
+    # smaller indices, then larger ones up to the range's end, then smaller
+    # ones again, and the merge considers exactly the pairs it considers
+    # with offset-ordered lists (filtered by index instead)
+    w = W.WORKLOADS[name].with_n(n)
+    x = W.make_points(w)
+    want = oracle.dbscan(x, w.eps, w.minpts)
+    pairs = {}
+    for query in (TREE_WALK_ORDER, TREE):
+        ctx = ctx_for(G, query)
+        ctx.set_option(G.GD_OPT_STATS, 1)
+        print(f"case {name} n={n} query={query}", flush=True)
+        lab, core = run(ctx, x, w.eps, w.minpts)
+        assert np.array_equal(core, want[1]) and np.array_equal(lab, want[0])
+        pairs[query] = ctx.stats()["merge_pairs"]
+        if query == TREE_WALK_ORDER:
+            _, gs, ids = ctx.debug_grids()
+            off, nei = ctx.debug_neighbors()
+            for g in range(0, len(ids), max(1, len(ids) // 300)):
+                lst = np.asarray(nei[off[g]:off[g + 1]], dtype=np.int64)
+                above = lst > g
+                if above.any():
+                    first, last = np.flatnonzero(above)[[0, -1]]
+                    assert above[first:last + 1].all(), f"grid {g}: larger neighbours not contiguous"
+        ctx.close()
+    assert pairs[TREE_WALK_ORDER] == pairs[TREE]
