@@ -147,6 +147,32 @@ size_t output_table_bytes(int bits, int key_bytes) {
     return (size_t)((1ll << bits) + 1) * (key_bytes == 4 ? 8 : 16);
 }
 
+// Whether some query of `open` (lanes of the wave, rows qx) lies within eps
+// of grid cc's cell: coordinate j of the cell spans [g_j s, (g_j + 1) s)
+// with s = eps / sqrt(d) (Eq. (1)).  Conservative: lim is eps^2 widened
+// beyond the rounding of the cell bounds, so a grid is only dropped when no
+// point of it can be within eps of any query.
+template <int D>
+__device__ __forceinline__ bool cell_near(const GridView& gv, uint32_t cc, uint64_t open, const int32_t (&qx)[D],
+                                          double side, double lim) {
+    double lo[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) lo[j] = (double)gv.ck[(int64_t)(j + 1) * gv.ck_stride + cc] * side;
+    bool near = false;
+    for (uint64_t m = open; m; m &= m - 1ull) {
+        const int qi = ffs64(m);
+        double d2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double q = (double)readlane(qx[j], qi);
+            const double g = q < lo[j] ? lo[j] - q : (q > lo[j] + side ? q - lo[j] - side : 0.0);
+            d2 += g * g;
+        }
+        near |= d2 <= lim;
+    }
+    return near;
+}
+
 // Border and noise points of grid c (rows [st, st + k)), one wave.
 template <int D, bool kWide>
 __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& co, const uint64_t* __restrict__ nei_off,
@@ -163,6 +189,8 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
     const typename Dist<kWide>::T T = inst_T<kWide>(I);
     const uint64_t own_best = own_min == kNone ? ~0ull : (((uint64_t)own_min << 32) | (uint32_t)own_label);
     const uint64_t e0 = nei_off[c], e1 = nei_off[c + 1];
+    const double side = D <= 4 ? (double)I.eps / sqrt((double)I.d) : 0.0;
+    const double lim = (double)I.eps * (double)I.eps * (1.0 + 1e-9) + 1.0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
         const uint32_t s = st + qb + lane;
         const bool v = qb + lane < k;
@@ -191,6 +219,14 @@ __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& c
                     cs = co.core_begin[cc];
                     cn = co.core_cnt[cc];
                     lab = cell_label[cc];
+                    // a query without a hit scans every core point around it;
+                    // a grid of a step or more is dropped when no open query
+                    // comes within eps of its cell (low d only, where grids
+                    // are large: at d = 7 the test cost more than it saved)
+                    if constexpr (D <= 4) {
+                        if (worst == ~0ull && cn >= (uint32_t)kWave && !cell_near<D>(gv, cc, open, qx, side, lim))
+                            cn = 0;
+                    }
                 }
             }
             const uint32_t incl = wave_incl_scan(cn);
