@@ -708,7 +708,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         GD_TRY(launch_core_walk(g, t, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr, wide, st));
     else
         GD_TRY(launch_core_mark(g, L.nei_off, nei, L.core, L.core_cnt, stats ? ctx->stats_dev->core : nullptr,
-                                max_eps, min_minpts, st));
+                                max_eps, min_minpts, n >= 1024 * std::max<int64_t>(ncell, 1), st));
     ctx->mark(P_CORE_MARK, 1);
     CoreOut co{};
     co.core = L.core;

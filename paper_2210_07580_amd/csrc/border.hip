@@ -147,32 +147,6 @@ size_t output_table_bytes(int bits, int key_bytes) {
     return (size_t)((1ll << bits) + 1) * (key_bytes == 4 ? 8 : 16);
 }
 
-// Whether some query of `open` (lanes of the wave, rows qx) lies within eps
-// of grid cc's cell: coordinate j of the cell spans [g_j s, (g_j + 1) s)
-// with s = eps / sqrt(d) (Eq. (1)).  Conservative: lim is eps^2 widened
-// beyond the rounding of the cell bounds, so a grid is only dropped when no
-// point of it can be within eps of any query.
-template <int D>
-__device__ __forceinline__ bool cell_near(const GridView& gv, uint32_t cc, uint64_t open, const int32_t (&qx)[D],
-                                          double side, double lim) {
-    double lo[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) lo[j] = (double)gv.ck[(int64_t)(j + 1) * gv.ck_stride + cc] * side;
-    bool near = false;
-    for (uint64_t m = open; m; m &= m - 1ull) {
-        const int qi = ffs64(m);
-        double d2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const double q = (double)readlane(qx[j], qi);
-            const double g = q < lo[j] ? lo[j] - q : (q > lo[j] + side ? q - lo[j] - side : 0.0);
-            d2 += g * g;
-        }
-        near |= d2 <= lim;
-    }
-    return near;
-}
-
 // Border and noise points of grid c (rows [st, st + k)), one wave.
 template <int D, bool kWide>
 __device__ __forceinline__ void border_grid(const GridView& gv, const CoreOut& co, const uint64_t* __restrict__ nei_off,

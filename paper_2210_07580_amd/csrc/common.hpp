@@ -306,6 +306,32 @@ __device__ __forceinline__ int64_t xcd_runs(int64_t b, int64_t count) {
     return (j / kRun) * kGroup + x * kRun + j % kRun;
 }
 
+// Whether some query of `open` (lanes of the wave, rows qx: x - mn) lies within eps
+// of grid cc's cell: coordinate j of the cell spans [g_j s, (g_j + 1) s)
+// with s = eps / sqrt(d) (Eq. (1)).  Conservative: lim is eps^2 widened
+// beyond the rounding of the cell bounds, so a grid is only dropped when no
+// point of it can be within eps of any query.
+template <int D>
+__device__ __forceinline__ bool cell_near(const GridView& gv, uint32_t cc, uint64_t open, const int32_t (&qx)[D],
+                                          double side, double lim) {
+    double lo[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) lo[j] = (double)gv.ck[(int64_t)(j + 1) * gv.ck_stride + cc] * side;
+    bool near = false;
+    for (uint64_t m = open; m; m &= m - 1ull) {
+        const int qi = ffs64(m);
+        double d2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double q = (double)readlane(qx[j], qi);
+            const double g = q < lo[j] ? lo[j] - q : (q > lo[j] + side ? q - lo[j] - side : 0.0);
+            d2 += g * g;
+        }
+        near |= d2 <= lim;
+    }
+    return near;
+}
+
 #define GD_DISPATCH_D(d, CALL)                             \
     do {                                                   \
         switch (d) {                                       \

@@ -77,7 +77,7 @@ __device__ __forceinline__ uint32_t sqdist_pk(const int32_t (&a)[packed_words<D>
 // MinPts (a query needs more hits than one 64-candidate step can give) a
 // step takes two rows; with a small MinPts most queries close within the
 // first 64 candidates and a second row would only add distance tests.
-template <int D, bool kStats, bool kPacked, int R, bool kWide>
+template <int D, bool kStats, bool kPacked, int R, bool kWide, bool kPrune>
 __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const uint64_t* __restrict__ nei_off,
                                                            const uint32_t* __restrict__ nei, uint8_t* __restrict__ core,
                                                            uint32_t* __restrict__ core_cnt, CoreStats* stats) {
@@ -109,13 +109,15 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
         return;
     }
     const uint32_t need = minpts - k;
+    const double side = kPrune && D <= 4 ? (double)I.eps / sqrt((double)I.d) : 0.0;
+    const double lim = (double)I.eps * (double)I.eps * (1.0 + 1e-9) + 1.0;
     unsigned long long ndist = 0, npts = 0, ncells = 0;
     uint32_t m = 0;
     for (uint32_t qb = 0; qb < k; qb += kWave) {
         const uint32_t nq = min((uint32_t)kWave, k - qb);
         uint64_t active = nq == (uint32_t)kWave ? ~0ull : ((1ull << nq) - 1ull);
+        int32_t qx[D];
         {
-            int32_t qx[D];
             load_row<D>(gv.crd, (uint32_t)lane < nq ? st + qb + lane : st, qx);
             if constexpr (kPacked) {
                 int32_t pq[PW];
@@ -131,7 +133,14 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
             const bool v = idx < e1;
             const uint32_t cc = v ? nei[idx] : 0u;
             const uint32_t cs = v ? gv.cell_start[cc] : 0u;
-            const uint32_t cn = v ? gv.cell_start[cc + 1] - cs : 0u;
+            uint32_t cn = v ? gv.cell_start[cc + 1] - cs : 0u;
+            if constexpr (kPrune && D <= 4) {
+                // kPrune (low d, grids of a thousand points and more on
+                // average): a grid of 16 steps or more is dropped when no
+                // open query comes within eps of its cell, since the noise
+                // points of a sparse grid stream every neighbour
+                if (cn >= 16u * kWave && !cell_near<D>(gv, cc, active, qx, side, lim)) cn = 0;
+            }
             const uint32_t incl = wave_incl_scan(cn);
             const uint32_t tot = __shfl(incl, kWave - 1);
             s_start[w][lane] = cs;
@@ -230,41 +239,38 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     }
 }
 
+template <bool kStats, bool kPacked, int R, bool kWide>
+hipError_t launch_core_mark_as(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
+                               uint32_t* core_cnt, CoreStats* stats, bool prune, hipStream_t st) {
+    const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
+    if (prune)
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
+                               g, nei_off, nei, core, core_cnt, stats)));
+    else
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, false><<<dim3(blocks), dim3(kBlock), 0,
+                                                                                   st>>>(g, nei_off, nei, core,
+                                                                                         core_cnt, stats)));
+    return hipGetLastError();
+}
+
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts,
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts, bool prune,
                             hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
     const bool packed = core_mark_packed(max_eps);
     const bool two = min_minpts > kWave / 2;
+    prune = prune && g.D <= 4;
     // the counting variant takes the same steps as the timed one
     if (max_eps > GD_EPS_MAX) {  // 64-bit distances, one row per step
-        if (stats)
-            GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                                   g, nei_off, nei, core, core_cnt, stats)));
-        else
-            GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                                   g, nei_off, nei, core, core_cnt, stats)));
-    } else if (stats && two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
-    } else if (stats) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, true, false, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
-    } else if (packed && two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
-    } else if (packed) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, true, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
-    } else if (two) {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 2, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
-    } else {
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, false, false, 1, false><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
+        if (stats) return launch_core_mark_as<true, false, 1, true>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+        return launch_core_mark_as<false, false, 1, true>(g, nei_off, nei, core, core_cnt, stats, prune, st);
     }
-    return hipGetLastError();
+    if (stats && two) return launch_core_mark_as<true, false, 2, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+    if (stats) return launch_core_mark_as<true, false, 1, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+    if (packed && two) return launch_core_mark_as<false, true, 2, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+    if (packed) return launch_core_mark_as<false, true, 1, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+    if (two) return launch_core_mark_as<false, false, 2, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
+    return launch_core_mark_as<false, false, 1, false>(g, nei_off, nei, core, core_cnt, stats, prune, st);
 }
 
 // Side rows of grid c: its core count if it also holds non-core points.

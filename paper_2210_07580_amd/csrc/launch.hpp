@@ -270,9 +270,11 @@ struct CoreStats {
 // Core flags (sorted order) and m_i per grid.  max_eps: the largest eps in
 // the batch (small ones allow packed 16-bit coordinate differences);
 // min_minpts: the smallest MinPts in the batch (large ones take two
-// candidate rows per lane per step).
+// candidate rows per lane per step).  prune (used at d <= 4): test large
+// neighbour grids' cells against the open queries before streaming them,
+// for data whose grids hold a thousand points and more.
 hipError_t launch_core_mark(const GridView& g, const uint64_t* nei_off, const uint32_t* nei, uint8_t* core,
-                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts,
+                            uint32_t* core_cnt, CoreStats* stats, int64_t max_eps, int64_t min_minpts, bool prune,
                             hipStream_t st);
 // Whether core marking compares coordinates as packed 16-bit differences
 // for a batch whose largest eps is max_eps (exact for eps <= 10000: points
