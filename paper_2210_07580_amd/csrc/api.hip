@@ -677,7 +677,7 @@ int run_batch(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, hipStrea
         nei = (uint32_t*)ctx->cur->nei.p;
         ctx->mark(P_NEI_FILL, 0);
         GD_TRY(launch_nei_fill(g, nq, L.off_counts, lane_cnt, L.nei_off, nei, nei_total, only_big, L.nei_up, st));
-        lists_up = nq.kind == kNeiTreeWalkOrder;
+        lists_up = nei_walk_order(nq, ncell);
         ctx->mark(P_NEI_FILL, 1);
         return GD_OK;
     };

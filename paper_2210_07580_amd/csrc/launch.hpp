@@ -227,6 +227,9 @@ struct NeiQuery {
 // only_big (optional): per-grid core counts; then only grids with more than
 // kTinyCore core points get a list, the others an empty one.
 int64_t nei_lane_count_words(const NeiQuery& nq, int64_t ncell, int D);
+// Whether the lists of this query come out in walk order (then the fill
+// also writes each list's larger-index range, nei_up).
+bool nei_walk_order(const NeiQuery& nq, int64_t ncell);
 hipError_t launch_nei_count(const GridView& g, const NeiQuery& nq, uint32_t* off_counts, uint32_t* lane_cnt,
                             const uint32_t* only_big, hipStream_t st);
 // Exclusive scan of the per-grid totals into nei_off (u64, ncell + 1); total into the header.

@@ -307,6 +307,8 @@ inline NeiShape nei_shape(const NeiQuery& nq, int64_t ncell) {
     return {P, nq.kind == kNeiHash || P > 1};
 }
 
+bool nei_walk_order(const NeiQuery& nq, int64_t ncell) { return !nei_shape(nq, ncell).ordered; }
+
 int64_t nei_lane_count_words(const NeiQuery& nq, int64_t ncell, int D) {
     return nei_shape(nq, ncell).P > 1 ? ncell * kSplit * D : 0;
 }
