@@ -47,7 +47,8 @@ WORKLOAD_DESC = {
 PHASE_KERNELS = {
     "minmax": ["minmax_kernel", "minmax_finish_kernel", "layout_kernel (batches of several instances)"],
     "keys": ["keys_kernel"],
-    "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel"],
+    "radix_sort": ["per pass: radix_hist_kernel", "scan_reduce_kernel", "scan_down_kernel", "radix_scatter_kernel "
+                   "(one instance with packed values: the last pass also writes the sorted rows)"],
     "gather": ["unpack_kernel or unpack64_kernel (rows rebuilt in order; gather_kernel when the low bits do "
                "not fit)"],
     "core_mark": ["core_mark_kernel"],
@@ -72,7 +73,9 @@ def packed_rows(d, eps, key_bits):
 
 def algorithmic_bytes(phase, n, d, st, key_bytes, passes, packed):
     """Bytes the phase must move at least (the method's own traffic), per
-    call; key_bytes: the sort word (8 with packed == "word")."""
+    call; key_bytes: the sort word (8 with packed == "word").  A single
+    instance with packed values ("value") has its rows written by the sort's
+    last pass (no row phase of its own)."""
     B = 4 * d  # coordinates per point
     V = 8 if packed == "value" else 4  # sort value: index, with the packed low bits
     if phase == "minmax":
@@ -80,8 +83,11 @@ def algorithmic_bytes(phase, n, d, st, key_bytes, passes, packed):
     if phase == "keys":
         return n * (B + key_bytes + (8 if packed == "value" else 0))
     if phase == "radix_sort":
-        # per pass: histogram read of the keys, then (key, value) read and written
-        return passes * n * (key_bytes + 2 * (key_bytes + V))
+        # per pass: histogram read of the keys, then (key, value) read and
+        # written; with "value" the last pass writes the row and the index
+        # instead of the value
+        fused = n * (B + 4 - V) if packed == "value" and passes > 0 else 0
+        return passes * n * (key_bytes + 2 * (key_bytes + V)) + fused
     if phase == "gather":
         # "value": sorted keys and values in, index and rows out; "word": the
         # words in, rows and identifiers out; else the index, one row in and

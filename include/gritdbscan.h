@@ -282,8 +282,11 @@ typedef enum {
                                  (beside its index, or inside a two-word
                                  identifier's sort word when both fit 64
                                  bits) and the sorted coordinate rows are
-                                 rebuilt in order from them and the grid;
-                                 0: the rows are gathered from the input in
+                                 rebuilt in order from them and the grid (for
+                                 a single instance with 32-bit identifiers by
+                                 the sort's last pass itself); 2: the same,
+                                 always with a separate rebuilding pass; 0:
+                                 the rows are gathered from the input in
                                  sorted order.  Same result.                   */
 } gd_option;
 

@@ -20,6 +20,7 @@
 #include "launch.hpp"
 #include "learned.hpp"
 #include "radix.hpp"
+#include "rows.hpp"
 #include "scan.hpp"
 
 using namespace gd;
@@ -146,6 +147,7 @@ struct gd_ctx {
     int merge_waves = kWavesPerBlock; // waves per workgroup of the FastMerging kernel
     int grid_lanes = 0;               // GD_OPT_GRID_LANES (0: from the mean list length)
     bool pack_rows = true;            // GD_OPT_PACKED_ROWS
+    bool fuse_rows = true;            // single instances: rows written by the sort's last pass
     std::string tuning_file;          // gd_set_tuning_file (empty: none)
     uint64_t generation = 0;         // bumped whenever a buffer is reallocated
     hipStream_t gstream = nullptr;   // capture and replay stream
@@ -372,6 +374,21 @@ int readback(gd_ctx* ctx, hipStream_t st) {
     return GD_OK;
 }
 
+// The identifier sort of one instance with packed rows, its last pass
+// writing the sorted rows, index and identifiers (PackedRowsOut).
+hipError_t sort_packed_rows(const Batch& b, uint32_t* ka, uint64_t* va, uint32_t* kb, uint64_t* vb, int key_bits,
+                            const Layout& L, hipStream_t st, RadixResult<uint32_t, uint64_t>* r) {
+    GD_DISPATCH_D(b.D, ({
+                      PackedRowsOut<D> o{};
+                      o.inst = b.inst;
+                      o.crd = L.crd;
+                      return radix_sort_pairs<uint32_t, uint64_t, PackedRowsOut<D>>(
+                          ka, va, kb, vb, b.n, key_bits, false, L.radix_scratch, st, r,
+                          reinterpret_cast<uint32_t*>(L.keys_c), 0, &o);
+                  }));
+    return hipErrorInvalidValue;
+}
+
 // Bits per coordinate that every instance's grids fit (pack64_bits), 0 if
 // some instance's do not fit 31 bits.
 int pack64_width(const gd_ctx* ctx, int count) {
@@ -428,18 +445,30 @@ int run_partition(gd_ctx* ctx, const Batch& b, int key_bits, Layout& L, const ui
         ctx->mark(P_KEYS, 0);
         GD_TRY(launch_keys<K>(b, ka, va, st));
         ctx->mark(P_KEYS, 1);
-        RadixResult<K, uint64_t> r64;
+        RadixResult<K, uint64_t> r64{};
         ctx->mark(P_SORT, 0);
-        GD_TRY((radix_sort_pairs<K, uint64_t>(ka, va, kb, vb, b.n, key_bits, false, L.radix_scratch, st, &r64,
-                                              (K*)L.keys_c)));
+        if constexpr (std::is_same<K, uint32_t>::value) {
+            if (b.count == 1 && ctx->fuse_rows)
+                // one instance: the last pass writes the rows, the index and
+                // the identifiers itself
+                GD_TRY(sort_packed_rows(b, ka, va, kb, vb, key_bits, L, st, &r64));
+            else
+                GD_TRY((radix_sort_pairs<K, uint64_t>(ka, va, kb, vb, b.n, key_bits, false, L.radix_scratch, st,
+                                                      &r64, (K*)L.keys_c)));
+        }
         ctx->mark(P_SORT, 1);
-        // sidx goes to the value buffer the sorted values are not in
-        uint32_t* sidx = r64.vals == va ? L.vals_b : L.vals_a;
-        ctx->mark(P_GATHER, 0);
-        GD_TRY(launch_unpack(b, reinterpret_cast<const uint32_t*>(r64.keys), r64.vals, sidx, L.crd, st));
-        ctx->mark(P_GATHER, 1);
-        res.keys = r64.keys;
-        res.vals = sidx;
+        if (r64.last_fused) {
+            res.keys = r64.keys;
+            res.vals = reinterpret_cast<uint32_t*>(r64.vals);
+        } else {
+            // sidx goes to the value buffer the sorted values are not in
+            uint32_t* sidx = r64.vals == va ? L.vals_b : L.vals_a;
+            ctx->mark(P_GATHER, 0);
+            GD_TRY(launch_unpack(b, reinterpret_cast<const uint32_t*>(r64.keys), r64.vals, sidx, L.crd, st));
+            ctx->mark(P_GATHER, 1);
+            res.keys = r64.keys;
+            res.vals = sidx;
+        }
     } else {
         ctx->mark(P_KEYS, 0);
         GD_TRY(launch_keys<K>(b, ka, nullptr, st));
@@ -1001,7 +1030,7 @@ std::vector<int64_t> batch_signature(const gd_ctx* ctx, int count) {
     sig.push_back(ctx->tile_pts);
     sig.push_back(ctx->merge_waves);
     sig.push_back(ctx->grid_lanes);
-    sig.push_back(ctx->pack_rows ? 1 : 0);
+    sig.push_back(ctx->pack_rows ? (ctx->fuse_rows ? 1 : 2) : 0);
     for (int k = 0; k < count; ++k) {
         sig.push_back(ctx->inst_host[k].n);
         sig.push_back(ctx->inst_host[k].d);
@@ -1445,8 +1474,9 @@ int gd_set_option(gd_ctx* ctx, int option, int64_t value) {
             ctx->grid_lanes = (int)value;
             return GD_OK;
         case GD_OPT_PACKED_ROWS:
-            if (value != 0 && value != 1) return ctx->fail(GD_EINVAL, "packed rows must be 0 or 1");
-            ctx->pack_rows = value == 1;
+            if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "packed rows must be 0, 1 or 2");
+            ctx->pack_rows = value != 0;
+            ctx->fuse_rows = value == 1;
             return GD_OK;
         case GD_OPT_GRAPH:
             if (value < 0 || value > 2) return ctx->fail(GD_EINVAL, "graph mode must be 0, 1 or 2");

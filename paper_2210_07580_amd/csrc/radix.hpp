@@ -125,10 +125,27 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const K* __restrict_
     }
 }
 
-template <typename K, typename V, bool kIota, int kItems>
+// Where a scatter pass puts each (key, value) at its sorted slot: the next
+// pass's buffers, or (PackedRowsOut, the last pass of the identifier sort)
+// something derived from them.
+template <typename K, typename V>
+struct PairOut {
+    K* keys;
+    V* vals;
+    void bind(K* k, V* v) {
+        keys = k;
+        vals = v;
+    }
+    __device__ void begin() {}
+    __device__ void store(uint32_t pos, const K& k, const V& v) const {
+        keys[pos] = k;
+        vals[pos] = v;
+    }
+};
+
+template <typename K, typename V, bool kIota, int kItems, typename Out>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restrict__ keys, const V* __restrict__ vals,
-                                                               K* __restrict__ keys_out, V* __restrict__ vals_out,
-                                                               int64_t n, int shift, int rbits,
+                                                               Out out, int64_t n, int shift, int rbits,
                                                                const uint32_t* __restrict__ offs, int64_t tiles) {
     constexpr int kMaxBins = radix_max_bins<K>();
     constexpr int kDigitsPerThread = kMaxBins / kBlock;  // 4 or 2
@@ -235,12 +252,12 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const K* __restri
     }
     __syncthreads();
     // 4. write the digit runs out in order: consecutive threads, consecutive slots
+    out.begin();
     for (int j = t; j < tile_n; j += kBlock) {
         const K kk = skey[j];
         const uint32_t dg = (uint32_t)(kk >> shift) & mask;
         const uint32_t pos = gbase[dg] + (uint32_t)j;
-        keys_out[pos] = kk;
-        vals_out[pos] = sval[j];
+        out.store(pos, kk, sval[j]);
     }
 }
 
@@ -254,6 +271,7 @@ template <typename K, typename V = uint32_t>
 struct RadixResult {
     K* keys;
     V* vals;
+    bool last_fused;  // the last pass wrote through `last` (false: no pass ran, or none was given)
 };
 
 // Sorts keys[0..n) (and vals) on their bits [lo, lo + bits).  keys/vals and
@@ -261,11 +279,12 @@ struct RadixResult {
 // With keys_spare, the passes after the first alternate between keys_alt
 // and keys_spare, so keys[] keeps the input order.
 // If vals_iota, vals[] is not read and the values start as 0..n-1.
-// `scratch` needs radix_scratch_words(n) u32.
-template <typename K, typename V = uint32_t>
+// `scratch` needs radix_scratch_words(n) u32.  With `last`, the last pass
+// stores through a copy of it, bound to that pass's output buffers.
+template <typename K, typename V = uint32_t, typename Last = PairOut<K, V>>
 hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t n, int bits,
                             bool vals_iota, uint32_t* scratch, hipStream_t st, RadixResult<K, V>* out,
-                            K* keys_spare = nullptr, int lo = 0) {
+                            K* keys_spare = nullptr, int lo = 0, const Last* last = nullptr) {
     K* kin = keys;
     V* vin = vals;
     K* kout = keys_alt;
@@ -277,6 +296,7 @@ hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t 
     uint32_t* offs = scratch + (int64_t)radix_max_bins<uint32_t>() * tiles;
     uint32_t* partial = offs + (int64_t)radix_max_bins<uint32_t>() * tiles;
     bool iota = vals_iota;
+    bool fused = false;
     const int passes = bits <= 0 ? 0 : (bits + radix_max_bits<K>() - 1) / radix_max_bits<K>();
     const int rbits = passes ? (bits + passes - 1) / passes : 0;
     for (int p = 0, shift = lo; p < passes; ++p, shift += rbits) {
@@ -292,27 +312,40 @@ hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t 
         hipError_t e = scan_exclusive<uint32_t>(ArrayInput<uint32_t>{hist}, bins * tiles, offs, (uint32_t*)nullptr,
                                                 partial, st);
         if (e != hipSuccess) return e;
-        if (items == kRadixItemsSmall) {
-            if (iota)
-                radix_scatter_kernel<K, V, true, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                          shift, rbits, offs, tiles);
-            else
-                radix_scatter_kernel<K, V, false, kRadixItemsSmall><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                           shift, rbits, offs, tiles);
-        } else if (items == kRadixItemsWide) {
-            if (iota)
-                radix_scatter_kernel<K, V, true, kRadixItemsWide><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                         shift, rbits, offs, tiles);
-            else
-                radix_scatter_kernel<K, V, false, kRadixItemsWide><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                          shift, rbits, offs, tiles);
+        auto scatter = [&](auto o) {
+            using O = decltype(o);
+            if (items == kRadixItemsSmall) {
+                if (iota)
+                    radix_scatter_kernel<K, V, true, kRadixItemsSmall, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+                else
+                    radix_scatter_kernel<K, V, false, kRadixItemsSmall, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+            } else if (items == kRadixItemsWide) {
+                if (iota)
+                    radix_scatter_kernel<K, V, true, kRadixItemsWide, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+                else
+                    radix_scatter_kernel<K, V, false, kRadixItemsWide, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+            } else {
+                if (iota)
+                    radix_scatter_kernel<K, V, true, kRadixItemsBig, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+                else
+                    radix_scatter_kernel<K, V, false, kRadixItemsBig, O><<<grid, block, 0, st>>>(
+                        kin, vin, o, n, shift, rbits, offs, tiles);
+            }
+        };
+        if (last && p == passes - 1) {
+            Last o = *last;
+            o.bind(kout, vout);
+            scatter(o);
+            fused = true;
         } else {
-            if (iota)
-                radix_scatter_kernel<K, V, true, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                        shift, rbits, offs, tiles);
-            else
-                radix_scatter_kernel<K, V, false, kRadixItemsBig><<<grid, block, 0, st>>>(kin, vin, kout, vout, n,
-                                                                                         shift, rbits, offs, tiles);
+            PairOut<K, V> o;
+            o.bind(kout, vout);
+            scatter(o);
         }
         iota = false;
         K* tk = kin; kin = kout; kout = (first && keys_spare) ? keys_spare : tk;
@@ -324,6 +357,7 @@ hipError_t radix_sort_pairs(K* keys, V* vals, K* keys_alt, V* vals_alt, int64_t 
     }
     out->keys = kin;
     out->vals = vin;
+    out->last_fused = fused;
     return hipGetLastError();
 }
 

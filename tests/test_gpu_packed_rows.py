@@ -85,7 +85,7 @@ def test_one_word_identifiers_of_wide_grids(G, d, eps, half):
 def test_bad_option_value(G):
     ctx = G.Context(0)
     with pytest.raises(G.GDError):
-        ctx.set_option(G.GD_OPT_PACKED_ROWS, 2)
+        ctx.set_option(G.GD_OPT_PACKED_ROWS, 3)
     ctx.close()
 
 
@@ -126,3 +126,23 @@ def test_replay_with_an_eps_beyond_the_captured_width(G):
         if rep == 1:
             assert ctx.stats()["graph_replays"] == 1
     ctx.close()
+
+
+# 32-bit identifiers with packed values: one instance rebuilds its rows in
+# the sort's last pass (1), or in a pass of its own (2); batches always in a
+# pass of their own
+ONE_WORD = [(3, 200, 50_000), (2, 700, 1 << 20), (1, 50, 1 << 22), (4, 300, 5_000)]
+
+
+@pytest.mark.parametrize("d,eps,half", ONE_WORD)
+def test_rows_rebuilt_by_the_last_sort_pass(G, d, eps, half):
+    x = clumps(600 + d + eps, 5000, d, eps, half)
+    want = oracle.dbscan(x, eps, 5)
+    for packed in (1, 2, 0):
+        ctx = G.Context(0)
+        ctx.set_option(G.GD_OPT_PACKED_ROWS, packed)
+        print(f"case d={d} eps={eps} half={half} packed={packed}", flush=True)
+        for rep in range(2):
+            same(run(ctx, x, eps, 5), want, f"packed={packed} call {rep}")
+        assert ctx.stats()["key_bits"] <= 32
+        ctx.close()
