@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgritdbscan.so")
+# GRITDBSCAN_LIBRARY selects another build of the same library (for example
+# the host-sanitizer variant of build.py); the default is the in-tree one
+LIB_PATH = os.environ.get("GRITDBSCAN_LIBRARY") or os.path.join(_HERE, "libgritdbscan.so")
 
 GD_OK, GD_EINVAL, GD_ERANGE, GD_ENOMEM, GD_EDEVICE, GD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GD_OPT_STATS, GD_OPT_LDF_ORDER, GD_OPT_WORKSPACE_LIMIT, GD_OPT_TIMING, GD_OPT_GRAPH = 1, 2, 3, 4, 5
