@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void output_group_kernel(GridView gv, CoreO
     const int w = wave_id(), lane = lane_id();
     const int grp = lane / S, sub = lane % S, g0 = grp * S;
     const uint64_t gmask = (S == kWave ? ~0ull : ((1ull << S) - 1ull)) << g0;
-    const int64_t c = ((int64_t)blockIdx.x * kWavesPerBlock + w) * G + grp;
+    const int64_t c = (block_id() * kWavesPerBlock + w) * G + grp;
     if (c >= (int64_t)*gv.ncell_dev) return;
     const uint32_t st = gv.cell_start[c];
     const uint32_t k = gv.cell_start[c + 1] - st;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void output_kernel(GridView gv, CoreOut co,
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     __shared__ int32_t s_lab[kWavesPerBlock][kWave];
     const int w = wave_id(), lane = lane_id();
-    const int64_t c0 = ((int64_t)blockIdx.x * kWavesPerBlock + w) * G;
+    const int64_t c0 = (block_id() * kWavesPerBlock + w) * G;
     const int64_t ncell = *gv.ncell_dev;
     uint32_t st_l = 0, k_l = 0;
     bool need = false;
@@ -413,19 +413,19 @@ hipError_t launch_output(const GridView& g, const CoreOut& c, const uint64_t* ne
     if (lanes == 16) {  // four grids per wave, side by side
         const unsigned four = grid_for(g.ncell, kWavesPerBlock * 4);
         if (wide)
-            GD_DISPATCH_D(g.D, (output_group_kernel<D, true, 16><<<dim3(four), dim3(kBlock), 0, st>>>(
+            GD_DISPATCH_D(g.D, (output_group_kernel<D, true, 16><<<grid_of(four), dim3(kBlock), 0, st>>>(
                                    g, c, nei_off, nei, cell_label)));
         else
-            GD_DISPATCH_D(g.D, (output_group_kernel<D, false, 16><<<dim3(four), dim3(kBlock), 0, st>>>(
+            GD_DISPATCH_D(g.D, (output_group_kernel<D, false, 16><<<grid_of(four), dim3(kBlock), 0, st>>>(
                                    g, c, nei_off, nei, cell_label)));
     } else if (wide) {
-        GD_DISPATCH_D(g.D, (output_kernel<D, 1, true><<<dim3(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+        GD_DISPATCH_D(g.D, (output_kernel<D, 1, true><<<grid_of(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
                                                                                           cell_label)));
     } else if (g.ncell >= kBorderGroupMinGrids) {
-        GD_DISPATCH_D(g.D, (output_kernel<D, kWave, false><<<dim3(many), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+        GD_DISPATCH_D(g.D, (output_kernel<D, kWave, false><<<grid_of(many), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
                                                                                                 cell_label)));
     } else {
-        GD_DISPATCH_D(g.D, (output_kernel<D, 1, false><<<dim3(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
+        GD_DISPATCH_D(g.D, (output_kernel<D, 1, false><<<grid_of(one), dim3(kBlock), 0, st>>>(g, c, nei_off, nei,
                                                                                            cell_label)));
     }
     return hipGetLastError();

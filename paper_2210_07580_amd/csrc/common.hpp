@@ -352,4 +352,20 @@ inline unsigned grid_for(int64_t n, int per_block = kBlock) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+// A dispatch counts its work-items in 32 bits per grid dimension: a grid of
+// 2^32 work-items or more in x wraps silently and runs only the remainder.
+// Kernels with several lanes per grid (a wave per grid reaches that bound at
+// 2^26 grids) are launched with grid_of(): at most 2^21 workgroups (of at most
+// 1024 lanes) in x, the rest as rows in y, and they number their workgroups
+// with block_id() / block_count(), which are blockIdx.x / gridDim.x whenever
+// y is 1.  The last row may hold workgroups past the count asked for; the
+// kernels' range checks drop them.
+constexpr int64_t kMaxGridX = int64_t(1) << 21;
+inline dim3 grid_of(int64_t blocks) {
+    if (blocks <= kMaxGridX) return dim3((unsigned)(blocks < 1 ? 1 : blocks));
+    return dim3((unsigned)kMaxGridX, (unsigned)((blocks + kMaxGridX - 1) / kMaxGridX));
+}
+__device__ __forceinline__ int64_t block_id() { return (int64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+__device__ __forceinline__ int64_t block_count() { return (int64_t)gridDim.y * gridDim.x; }
+
 }  // namespace gd

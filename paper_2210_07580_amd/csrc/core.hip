@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void core_mark_kernel(GridView gv, const ui
     __shared__ uint32_t s_excl[kWavesPerBlock][kWave];
     __shared__ __align__(16) int32_t s_q[kWavesPerBlock][kWave * S];  // the query rows of the batch
     const int w = wave_id(), lane = lane_id();
-    const int64_t c = xcd_runs<16>(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    const int64_t c = xcd_runs<16>(block_id(), block_count()) * kWavesPerBlock + w;
     if (c >= (int64_t)*gv.ncell_dev) return;
     // every load that depends on c alone is issued before the first use
     const Inst& I = cell_inst(gv, c);
@@ -244,10 +244,11 @@ hipError_t launch_core_mark_as(const GridView& g, const uint64_t* nei_off, const
                                uint32_t* core_cnt, CoreStats* stats, bool prune, hipStream_t st) {
     const unsigned blocks = grid_for(g.ncell, kWavesPerBlock);
     if (prune)
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, true><<<dim3(blocks), dim3(kBlock), 0, st>>>(
-                               g, nei_off, nei, core, core_cnt, stats)));
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, true><<<grid_of(blocks), dim3(kBlock), 0,
+                                                                                  st>>>(g, nei_off, nei, core,
+                                                                                        core_cnt, stats)));
     else
-        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, false><<<dim3(blocks), dim3(kBlock), 0,
+        GD_DISPATCH_D(g.D, (core_mark_kernel<D, kStats, kPacked, R, kWide, false><<<grid_of(blocks), dim3(kBlock), 0,
                                                                                    st>>>(g, nei_off, nei, core,
                                                                                          core_cnt, stats)));
     return hipGetLastError();

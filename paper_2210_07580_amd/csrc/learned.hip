@@ -13,7 +13,7 @@ namespace gd {
 template <int D>
 __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co, CellSummary* __restrict__ out) {
     const int lane = lane_id();
-    const int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t c = block_id() * kWavesPerBlock + wave_id();
     if (c >= (int64_t)*gv.ncell_dev || c >= gv.ncell) return;  // out[] holds gv.ncell summaries
     const uint32_t b = co.core_begin[c], m = co.core_cnt[c];
     if (m == 0) return;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void summary_kernel(GridView gv, CoreOut co
 
 hipError_t launch_summaries(const GridView& g, const CoreOut& c, CellSummary* out, hipStream_t st) {
     if (g.ncell == 0) return hipSuccess;
-    GD_DISPATCH_D(g.D, (summary_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(g, c,
+    GD_DISPATCH_D(g.D, (summary_kernel<D><<<grid_of(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), 0, st>>>(g, c,
                                                                                                           out)));
     return hipGetLastError();
 }
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void harvest_kernel(GridView gv, CoreOut co
     extern __shared__ uint64_t smem[];
     const int lane = lane_id();
     const int w = wave_id();
-    const int64_t a = (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t a = block_id() * kWavesPerBlock + w;
     if (a >= (int64_t)*gv.ncell_dev) return;
     const uint32_t ba = co.core_begin[a], ma = co.core_cnt[a];
     if (ma == 0 || ma > 64u * words) return;
@@ -154,7 +154,7 @@ hipError_t launch_harvest(const GridView& g, const CoreOut& c, const CellSummary
     if (g.ncell == 0) return hipSuccess;
     const uint32_t words = (uint32_t)((std::min<int64_t>(max_core, 16384) + kWave - 1) / kWave);
     const size_t lds = (size_t)kWavesPerBlock * 2 * words * sizeof(uint64_t);
-    GD_DISPATCH_D(g.D, (harvest_kernel<D><<<dim3(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), lds, st>>>(
+    GD_DISPATCH_D(g.D, (harvest_kernel<D><<<grid_of(grid_for(g.ncell, kWavesPerBlock)), dim3(kBlock), lds, st>>>(
                            g, c, sum, nei_off, nei, seed, keep_mod, cap, words, X, Tg, C, counter)));
     return hipGetLastError();
 }

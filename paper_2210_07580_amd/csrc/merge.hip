@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void merge_small_kernel(GridView gv, CoreOu
     const int lane = lane_id();
     const int grp = lane / S, sub = lane % S;
     const uint64_t gmask = (S == kWave ? ~0ull : ((1ull << S) - 1ull)) << (grp * S);
-    const int64_t r = r0 + ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * G + grp;
+    const int64_t r = r0 + (block_id() * kWavesPerBlock + wave_id()) * G + grp;
     // lanes of a group without a tiny core grid take an empty list, so that
     // every lane reaches the closing reductions
     bool live = r < r1 && r < (int64_t)co.counts[1] && !(split && r >= (int64_t)*split);
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kBlock, (kLearned || D >= 5) ? 4 : 6) void merge_bi
     const int wpb = (int)(blockDim.x / kWave);
     const int w = wave_id();
     // with a device split the big core sets start right after the tiny ones
-    const int64_t r = (split ? (int64_t)*split : r0) + (int64_t)blockIdx.x * wpb + w;
+    const int64_t r = (split ? (int64_t)*split : r0) + block_id() * wpb + w;
     if (r >= r1 || r >= (int64_t)co.counts[1]) return;
     const uint32_t ci = ldf[r];
     // every load that depends on ci alone is issued before the first use
@@ -420,7 +420,7 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
         // lanes per tiny grid: 16 (four grids per wave) or 64
         const int S = small_lanes == 16 ? 16 : kWave;
         const int64_t per_block = (int64_t)kWavesPerBlock * (kWave / S);
-        const dim3 blocks((unsigned)((s1 + per_block - 1) / per_block)), threads(kBlock);
+        const dim3 blocks = grid_of((s1 + per_block - 1) / per_block), threads(kBlock);
         if (wide && S == 16)
             GD_DISPATCH_D(g.D, (merge_small_kernel<D, true, 16><<<blocks, threads, 0, st>>>(
                                    g, c, nei_off, nei, nei_up, ldf_list, rank, 0, s1, split, parent, stats)));
@@ -440,7 +440,7 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
     while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
     const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
     if (lds > 65536) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)((ncc - b0 + wpb - 1) / wpb);
+    const dim3 blocks = grid_of((ncc - b0 + wpb - 1) / wpb);
     // the scorer's weights take static LDS beside the bitmaps; if both do not
     // fit, or on the wide path, run without the proposal (the answers are the
     // same)
@@ -448,13 +448,13 @@ hipError_t launch_merge(const GridView& g, const CoreOut& c, const uint64_t* nei
                          lds + sizeof(MlpMfma) + kWavesPerBlock * (sizeof(MlpMfmaScratch) + sizeof(float2) * kWave) <=
                              65536;
     if (learned) {
-        GD_DISPATCH_D(g.D, (merge_big_kernel<D, true, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, true, false><<<blocks, dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     } else if (wide) {
-        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, true><<<blocks, dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     } else {
-        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (merge_big_kernel<D, false, false><<<blocks, dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, ldf_list, rank, b0, ncc, split, words, huge, parent, stats, prop)));
     }
     return hipGetLastError();
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void bfs_level_kernel(GridView gv, CoreOut 
     const int lane = lane_id();
     const int wpb = (int)(blockDim.x / kWave);
     const int w = wave_id();
-    const int64_t f = (int64_t)blockIdx.x * wpb + w;
+    const int64_t f = block_id() * wpb + w;
     if (f >= (int64_t)nfront) return;
     const uint32_t ci = front[f];
     const Inst& I = cell_inst(gv, ci);
@@ -629,12 +629,12 @@ hipError_t launch_bfs_level(const GridView& g, const CoreOut& c, const uint64_t*
     while (wpb > 1 && (size_t)wpb * 2 * words * sizeof(uint64_t) > 65536) wpb >>= 1;
     const size_t lds = (size_t)wpb * 2 * words * sizeof(uint64_t);
     if (lds > 65536) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)((nfront + wpb - 1) / wpb);
+    const dim3 blocks = grid_of(((int64_t)nfront + wpb - 1) / wpb);
     if (wide)
-        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, true><<<blocks, dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
     else
-        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(g.D, (bfs_level_kernel<D, false><<<blocks, dim3(wpb * kWave), lds, st>>>(
                                g, c, nei_off, nei, front, nfront, next, cnt, words, huge, state, parent, stats)));
     return hipGetLastError();
 }
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void merge_pairs_kernel(const int32_t* __re
     extern __shared__ uint64_t smem[];
     const int wpb = (int)(blockDim.x / kWave);
     const int w = wave_id();
-    const int64_t r = (int64_t)blockIdx.x * wpb + w;
+    const int64_t r = block_id() * wpb + w;
     if (r >= npairs) return;
     PointSet a{pts, pairs[4 * r], pairs[4 * r + 1], smem + (int64_t)w * 2 * words, 0};
     PointSet b{pts, pairs[4 * r + 2], pairs[4 * r + 3], smem + (int64_t)w * 2 * words + words, 0};
@@ -800,12 +800,12 @@ hipError_t launch_merge_pairs(const int32_t* pts, int64_t m, int d, int32_t* row
         lds = (size_t)2 * words * sizeof(uint64_t);
     }
     if (lds > 65536) return hipErrorInvalidValue;
-    const unsigned blocks = (unsigned)((npairs + wpb - 1) / wpb);
+    const dim3 blocks = grid_of((npairs + wpb - 1) / wpb);
     if (eps > GD_EPS_MAX)
-        GD_DISPATCH_D(d, (merge_pairs_kernel<D, true><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(d, (merge_pairs_kernel<D, true><<<blocks, dim3(wpb * kWave), lds, st>>>(
                              rows, pairs, npairs, (uint64_t)(eps * eps), (double)eps, words, answers, iterations)));
     else
-        GD_DISPATCH_D(d, (merge_pairs_kernel<D, false><<<dim3(blocks), dim3(wpb * kWave), lds, st>>>(
+        GD_DISPATCH_D(d, (merge_pairs_kernel<D, false><<<blocks, dim3(wpb * kWave), lds, st>>>(
                              rows, pairs, npairs, (uint64_t)(eps * eps), (double)eps, words, answers, iterations)));
     return hipGetLastError();
 }
