@@ -1,14 +1,14 @@
 """400 million points in one call: every per-point array then passes 2^32
 bytes (the input alone is 4.8 GB, the sorted rows 6.4 GB), so any 32-bit
-offset or index product in the path would show, and its 84M grids take
-kernels of one wave per grid past the 2^32 work-items a one-dimensional
-launch can count.  The data are 20000 copies
-of one 20000-point block (blobs plus noise, 1000 units wide) placed on a
-lattice of pitch 1100, so that points of different copies are more than eps
-apart.  DBSCAN (Definitions 1-5) then clusters each copy on its own, and
-with canonical labels (smallest core index of a cluster) copy k's labels
-are the block's plus k * 20000: the oracle clusters the block once and the
-whole result is checked element by element against that."""
+offset or index product in the path would show, and the grids (84M of them
+in blobs, 284M when sparse) take kernels of several lanes per grid past the
+2^32 work-items a one-dimensional launch can count.  The data are 20000
+copies of one 20000-point block placed on a lattice whose pitch exceeds the
+block's width by more than eps, so that points of different copies are more
+than eps apart.  DBSCAN (Definitions 1-5) then clusters each copy on its
+own, and with canonical labels (smallest core index of a cluster) copy k's
+labels are the block's plus k * 20000: the oracle clusters the block once
+and the whole result is checked element by element against that."""
 import numpy as np
 import pytest
 
@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-EPS, MINPTS, PITCH, COPIES = 60, 12, 1100, 20000
+COPIES = 20000
 
 
 @pytest.fixture(scope="module")
@@ -30,6 +30,7 @@ def G():
 
 
 def block(seed=11, m=20000, extent=1000):
+    """Eight blobs and 12% noise, 1000 units wide."""
     rng = np.random.default_rng(seed)
     centres = rng.integers(100, extent - 100, size=(8, 3))
     x = centres[rng.integers(0, 8, size=m)] + rng.normal(0, 45, size=(m, 3))
@@ -38,33 +39,51 @@ def block(seed=11, m=20000, extent=1000):
     return np.clip(np.rint(x), 0, extent).astype(np.int32)
 
 
+def sparse_block(seed=21, m=20000, extent=1790):
+    """Uniform points at about 1.4 per grid of eps = 100 (a tenth of them in
+    a denser corner), nearly all core at MinPts 5: hundreds of millions of
+    tiny core grids once copied."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, extent + 1, size=(m, 3))
+    x[: m // 10] = rng.integers(0, extent + 1, size=(m // 10, 3)) // 3
+    return x.astype(np.int32)
+
+
 def lattice(k, pitch):
     side = int(np.ceil(k ** (1 / 3)))
     i = np.arange(k)
     return np.stack([i % side, (i // side) % side, i // (side * side)], 1).astype(np.int32) * pitch
 
 
-def test_four_hundred_million_points(G):
-    b = block()
+# (block, eps, MinPts, lattice pitch)
+CASES = {"blobs": (block, 60, 12, 1100), "sparse": (sparse_block, 100, 5, 1900)}
+
+
+@pytest.mark.parametrize("kind", sorted(CASES))
+def test_four_hundred_million_points(G, kind):
+    make, eps, minpts, pitch = CASES[kind]
+    b = make()
     m = len(b)
     n = COPIES * m
     free, _ = torch.cuda.mem_get_info()
     if free < 200 * 2**30:
         pytest.skip(f"needs about 200 GiB of free device memory, {free / 2**30:.0f} GiB free")
-    want_l, want_c = oracle.dbscan(b, EPS, MINPTS)
-    assert (want_l == -1).any() and ((want_l >= 0) & (want_c == 0)).any()
-    off = torch.from_numpy(lattice(COPIES, PITCH)).cuda()
+    want_l, want_c = oracle.dbscan(b, eps, minpts)
+    assert want_c.any() and ((want_l >= 0) & (want_c == 0)).any()
+    off = torch.from_numpy(lattice(COPIES, pitch)).cuda()
     x = (torch.from_numpy(b).cuda()[None] + off[:, None, :]).reshape(n, 3).float()
     del off
-    print(f"case n={n} d=3 eps={EPS} minpts={MINPTS}, {free / 2**30:.0f} GiB free", flush=True)
+    print(f"case {kind} n={n} d=3 eps={eps} minpts={minpts}, {free / 2**30:.0f} GiB free", flush=True)
     ctx = G.Context(0)
-    lab, core = ctx.dbscan(x, EPS, MINPTS)
+    lab, core = ctx.dbscan(x, eps, minpts)
     torch.cuda.synchronize()
     st = ctx.stats()
-    print(f"grids {st['grids']} key_bits {st['key_bits']}", flush=True)
+    print(f"grids {st['grids']} core grids {st['core_grids']} entries {st['neighbor_entries']}", flush=True)
     # more than 2^26 grids: a launch of one wave per grid passes 2^32
     # work-items, which a one-dimensional grid cannot count
     assert st["grids"] > 2**26
+    if kind == "sparse":  # the tiny-set merge too, and lists past 2^32 entries
+        assert st["core_grids"] > 2**26 and st["neighbor_entries"] > 2**32
     del x
     wl = torch.from_numpy(want_l).cuda()
     base = (torch.arange(COPIES, device="cuda", dtype=torch.int32) * m)[:, None]
