@@ -1087,7 +1087,13 @@ void capture_graph(gd_ctx* ctx, int count, int D, int64_t n, uint32_t tiles, std
         (void)hipGetLastError();
         return;
     }
+    // the captured run only records work: the eager call's counters and
+    // debug views stay those of the call that just ran
+    const gd_stats saved_last = ctx->last;
+    const bool saved_have = ctx->have_last;
     const int rc = run_batch(ctx, count, D, n, tiles, ctx->gstream, &p);
+    ctx->last = saved_last;
+    ctx->have_last = saved_have;
     const hipError_t ce = hipStreamEndCapture(ctx->gstream, &graph);
     hipGraphExec_t exec = nullptr;
     if (rc == GD_OK && ce == hipSuccess && graph &&

@@ -231,3 +231,28 @@ def test_instance_table_growth_drops_graph(G):
     outs = ctx.dbscan_batched(_dev(small))
     assert ctx.stats()["graph_replays"] == 1
     ctx.close()
+
+
+def test_capturing_call_keeps_its_stats(G):
+    """The call that captures a graph reports the sizes of its own eager run
+    (grids, neighbour entries, core counts), as a call without graphs does,
+    and so does the replay after it."""
+    x, eps, minpts = _problems(71, count=1)[0]
+    t = torch.from_numpy(x.astype(np.float32)).cuda()
+    plain = G.Context(0)
+    plain.dbscan(t, eps, minpts)
+    want = plain.stats()
+    plain.close()
+    ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_GRAPH, 2)
+    for rep in range(2):
+        ctx.dbscan(t, eps, minpts)
+        st = ctx.stats()
+        print(f"case call {rep}: grids {st['grids']} replays {st['graph_replays']}", flush=True)
+        for k in ("n", "grids", "neighbor_entries", "core_points", "core_grids", "dense_grids", "key_bits"):
+            assert st[k] == want[k], (rep, k, st[k], want[k])
+        assert st["graph_replays"] == rep
+    # the debug views describe eager calls only
+    with pytest.raises(G.GDError):
+        ctx.debug_grids()
+    ctx.close()
