@@ -96,3 +96,40 @@ def test_four_hundred_million_points(G, kind):
     ctx.close()
     del lab, core
     torch.cuda.empty_cache()
+
+
+def test_batch_of_four_hundred_million_points(G):
+    """Ten instances of 40M points each (2000 blob copies, each instance
+    shifted) in one batched call, then again as a graph replay: every
+    instance's labels are the block's shifted by the copy's first index
+    within that instance."""
+    free, _ = torch.cuda.mem_get_info()
+    if free < 200 * 2**30:
+        pytest.skip(f"needs about 200 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    make, eps, minpts, pitch = CASES["blobs"]
+    b = make()
+    m = len(b)
+    want_l, want_c = oracle.dbscan(b, eps, minpts)
+    inst, k = 10, 2000
+    off = torch.from_numpy(lattice(k, pitch)).cuda()
+    xs = [((torch.from_numpy(b).cuda()[None] + off[:, None, :]).reshape(k * m, 3) + 7 * i).float() for i in range(inst)]
+    del off
+    wl = torch.from_numpy(want_l).cuda()
+    wc = torch.from_numpy(want_c).cuda()
+    base = (torch.arange(k, device="cuda", dtype=torch.int32) * m)[:, None]
+    exp = torch.where(wl[None] >= 0, wl[None] + base, torch.full_like(wl[None], -1))
+    ctx = G.Context(0)
+    ctx.set_option(G.GD_OPT_GRAPH, 1)
+    for rep in range(2):
+        print(f"case batch of {inst} x {k * m} points, call {rep}", flush=True)
+        outs = ctx.dbscan_batched([(x, eps, minpts) for x in xs])
+        torch.cuda.synchronize()
+        st = ctx.stats()
+        assert st["graph_replays"] == rep and st["grids"] > 2**26
+        for i, (lab, core) in enumerate(outs):
+            assert torch.equal(lab.view(k, m), exp), f"call {rep} instance {i}: labels differ"
+            assert torch.equal(core.view(k, m), wc[None].expand(k, m)), f"call {rep} instance {i}: core flags differ"
+        del outs
+    ctx.close()
+    del xs
+    torch.cuda.empty_cache()
