@@ -133,3 +133,58 @@ def test_batch_of_four_hundred_million_points(G):
     ctx.close()
     del xs
     torch.cuda.empty_cache()
+
+
+def blobs_d(seed, m, d, extent, sigma, k=12, noise=0.1):
+    """k Gaussian blobs plus uniform noise in [0, extent]^d."""
+    rng = np.random.default_rng(seed)
+    centres = rng.integers(int(3 * sigma), extent - int(3 * sigma), size=(k, d))
+    x = centres[rng.integers(0, k, size=m)] + rng.normal(0, sigma, size=(m, d))
+    nz = rng.random(m) < noise
+    x[nz] = rng.integers(0, extent, size=(nz.sum(), d))
+    return np.clip(np.rint(x), 0, extent).astype(np.int32)
+
+
+def lattice_d(k, d, pitch):
+    side = 1
+    while side ** d < k:
+        side += 1
+    i = np.arange(k)
+    return np.stack([(i // side ** j) % side for j in range(d)], 1).astype(np.int32) * pitch
+
+
+# d = 8 with identifiers of 72 bits (two words; 100M grids, 1.9e10 neighbour
+# entries) and d = 1 (copies along one axis up to 1.6e7, below 2^24)
+OTHER = {"d8_two_words": (dict(seed=5, m=20000, d=8, extent=1000, sigma=12), 20, 5, 1100, 64),
+         "d1": (dict(seed=6, m=20000, d=1, extent=2800, sigma=3, k=20, noise=0.3), 2, 20, 3000, 0)}
+
+
+@pytest.mark.parametrize("kind", sorted(OTHER))
+def test_hundred_million_points_at_d8_and_d1(G, kind):
+    kw, eps, minpts, pitch, min_bits = OTHER[kind]
+    copies = 5000
+    free, _ = torch.cuda.mem_get_info()
+    if free < 200 * 2**30:
+        pytest.skip(f"needs about 200 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    b = blobs_d(**kw)
+    m, d = b.shape
+    want_l, want_c = oracle.dbscan(b, eps, minpts)
+    assert want_c.any() and (want_l == -1).any() and ((want_l >= 0) & (want_c == 0)).any()
+    off = torch.from_numpy(lattice_d(copies, d, pitch)).cuda()
+    x = (torch.from_numpy(b).cuda()[None] + off[:, None, :]).reshape(copies * m, d).float()
+    del off
+    print(f"case {kind} n={copies * m} d={d} eps={eps} minpts={minpts}", flush=True)
+    ctx = G.Context(0)
+    lab, core = ctx.dbscan(x, eps, minpts)
+    torch.cuda.synchronize()
+    assert ctx.stats()["key_bits"] > min_bits
+    del x
+    wl = torch.from_numpy(want_l).cuda()
+    base = (torch.arange(copies, device="cuda", dtype=torch.int32) * m)[:, None]
+    exp = torch.where(wl[None] >= 0, wl[None] + base, torch.full_like(wl[None], -1))
+    assert torch.equal(lab.view(copies, m), exp), "labels differ"
+    wc = torch.from_numpy(want_c).cuda()
+    assert torch.equal(core.view(copies, m), wc[None].expand(copies, m)), "core flags differ"
+    ctx.close()
+    del lab, core, exp
+    torch.cuda.empty_cache()
