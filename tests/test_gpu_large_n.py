@@ -59,8 +59,10 @@ def lattice(k, pitch):
 CASES = {"blobs": (block, 60, 12, 1100), "sparse": (sparse_block, 100, 5, 1900)}
 
 
-@pytest.mark.parametrize("kind", sorted(CASES))
-def test_four_hundred_million_points(G, kind):
+# the learned proposal changes only the order of the merge's tests (its
+# per-grid summaries launch past 2^32 work-items here too)
+@pytest.mark.parametrize("kind,proposal", [("blobs", False), ("sparse", False), ("blobs", True)])
+def test_four_hundred_million_points(G, kind, proposal):
     make, eps, minpts, pitch = CASES[kind]
     b = make()
     m = len(b)
@@ -75,6 +77,9 @@ def test_four_hundred_million_points(G, kind):
     del off
     print(f"case {kind} n={n} d=3 eps={eps} minpts={minpts}, {free / 2**30:.0f} GiB free", flush=True)
     ctx = G.Context(0)
+    if proposal:
+        from paper_2210_07580_amd import proposal as P
+        ctx.set_proposal(P.load_blob())
     lab, core = ctx.dbscan(x, eps, minpts)
     torch.cuda.synchronize()
     st = ctx.stats()
