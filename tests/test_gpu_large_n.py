@@ -193,3 +193,38 @@ def test_hundred_million_points_at_d8_and_d1(G, kind):
     ctx.close()
     del lab, core, exp
     torch.cuda.empty_cache()
+
+
+def test_degenerate_inputs_at_scale(G):
+    """Closed-form cases: 100M identical points (one grid); 100M points on
+    two spots 1e6 apart; a chain of 2^24 points one unit apart in shuffled
+    input order at eps 1, MinPts 3 (16.8M grids merged end to end: the two
+    ends are border points, the rest core, one cluster named by the
+    smallest input index of an interior point); 50M points over the whole
+    accepted range [-2^24, 2^24]^2 at eps 2^28 (one grid, one cluster)."""
+    ctx = G.Context(0)
+    n = 100_000_000
+    x = torch.zeros((n, 3), device="cuda")
+    lab, core = ctx.dbscan(x, 5, 10)
+    assert bool((core == 1).all()) and bool((lab == 0).all()) and ctx.stats()["grids"] == 1
+    x[n // 2:, 0] = 1e6
+    lab, core = ctx.dbscan(x, 5, 10)
+    assert bool((core == 1).all()) and bool((lab[: n // 2] == 0).all()) and bool((lab[n // 2:] == n // 2).all())
+    del x, lab, core
+    m = 1 << 24
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    perm = torch.randperm(m, device="cuda", generator=g)
+    x = perm.float().view(m, 1) - (1 << 23)
+    lab, core = ctx.dbscan(x, 1, 3)
+    interior = (perm != 0) & (perm != m - 1)
+    assert torch.equal(core.bool(), interior)
+    assert bool((lab == int(torch.nonzero(interior)[0])).all())
+    assert ctx.stats()["grids"] == m
+    del x, lab, core, perm, interior
+    x = (torch.rand((50_000_000, 2), device="cuda", generator=g) * 2**25 - 2**24).round().clamp(-2**24, 2**24)
+    lab, core = ctx.dbscan(x, 2**28, 7)
+    assert bool((core == 1).all()) and bool((lab == 0).all())
+    ctx.close()
+    del x, lab, core
+    torch.cuda.empty_cache()
