@@ -41,20 +41,27 @@ __global__ __launch_bounds__(kBlock) void hash_build_kernel(GridView gv, CoreOut
     grid_table_insert<K>(tab, bits, skeys[st], cell_label[c]);
 }
 
-// Points in input order, instance tiles as in the identifier pass; each
-// thread resolves U points at a time so that their loads overlap.  The
-// identifier of input word w is w >> key_lo (key_lo > 0: packed rows in
-// two-word keys).
+// Points in input order, instance tiles as in the identifier pass, each
+// tile split into `parts` workgroups of at most kOutputPart points (the
+// lookups are latency-bound: with 4096-point tiles a call of 10M points
+// left about one wave per slot and a long tail; 1024-point parts cut the
+// pass by a tenth on such calls); each thread resolves U points at a time
+// so that their loads overlap.  The identifier of input word w is
+// w >> key_lo (key_lo > 0: packed rows in two-word keys).
+constexpr int kOutputPart = 1024;
 template <typename K>
 __global__ __launch_bounds__(kBlock) void output_direct_kernel(Batch b, const K* __restrict__ keys,
                                                                const HashSlot<K>* __restrict__ tab, int bits,
-                                                               int key_lo) {
+                                                               int key_lo, int parts) {
     constexpr int U = 8;
     if (b.hdr->err & kErrPlan) return;  // a sync-free run that stopped early (its result is discarded)
-    const int k = tile_instance(b, blockIdx.x);
+    const uint32_t tile = blockIdx.x / (uint32_t)parts, part = blockIdx.x % (uint32_t)parts;
+    const int k = tile_instance(b, tile);
     const Inst& I = b.inst[k];
-    const int64_t lo = (int64_t)(blockIdx.x - I.tile0) * b.tile_pts;
-    const int64_t hi = min(I.n, lo + b.tile_pts);
+    const int64_t sub = ((int64_t)b.tile_pts + parts - 1) / parts;
+    const int64_t t0 = (int64_t)(tile - I.tile0) * b.tile_pts;
+    const int64_t lo = t0 + (int64_t)part * sub;
+    const int64_t hi = min(I.n, min(lo + sub, t0 + (int64_t)b.tile_pts));
     const int bbits = bits - kBucketShift<K>;
     const uint64_t bmask = (1ull << bbits) - 1ull;
     const int32_t off = (int32_t)I.off;
@@ -108,7 +115,9 @@ hipError_t launch_output_direct(const GridView& g, const CoreOut& c, const K* ke
     hash_clear_kernel<K><<<dim3((unsigned)std::min<int64_t>(grid_for(slots), 4096)), dim3(kBlock), 0, st>>>(tab, slots,
                                                                                                       kDeferred);
     hash_build_kernel<K><<<dim3(grid_for(g.ncell)), dim3(kBlock), 0, st>>>(g, c, skeys, cell_label, tab, bits);
-    output_direct_kernel<K><<<dim3(g.b.tiles), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits, key_lo);
+    const int parts = (int)std::max<uint32_t>(1u, g.b.tile_pts / kOutputPart);
+    output_direct_kernel<K><<<dim3(g.b.tiles * (uint32_t)parts), dim3(kBlock), 0, st>>>(g.b, keys_in, tab, bits,
+                                                                                      key_lo, parts);
     return hipGetLastError();
 }
 template hipError_t launch_output_direct<uint32_t>(const GridView&, const CoreOut&, const uint32_t*, const uint32_t*,
