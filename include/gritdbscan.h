@@ -220,7 +220,7 @@ typedef enum {
                                  kernels: a multiple of 256 in [256, 65536]
                                  (default 4096)                               */
     GD_OPT_MERGE_WAVES = 7,   /* waves per workgroup of the FastMerging
-                                 kernel: 1, 2 or 4 (default 2)                */
+                                 kernel: 1, 2 or 4 (default 4)                */
     GD_OPT_NEIGHBOR_MODE = 8, /* how the consumers get Nei(g) (Algorithm 3):
                                  1 lists written out for every grid first;
                                  2 core marking, the merging of core sets of at

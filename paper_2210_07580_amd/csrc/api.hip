@@ -144,7 +144,7 @@ struct gd_ctx {
     int graph_mode = 1;              // 0 never, 1 dbscan_batched, 2 every call
     // launch tunables (gd_autotune)
     int tile_pts = kPointTile;       // points per workgroup of the point kernels
-    int merge_waves = 2;              // waves per workgroup of the FastMerging kernel (measured best)
+    int merge_waves = kWavesPerBlock; // waves per workgroup of the FastMerging kernel
     int grid_lanes = 0;               // GD_OPT_GRID_LANES (0: from the mean list length)
     bool pack_rows = true;            // GD_OPT_PACKED_ROWS
     bool fuse_rows = true;            // single instances: rows written by the sort's last pass
