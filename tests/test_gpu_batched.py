@@ -111,3 +111,30 @@ def test_full_batch_workload_matches_oracle_digests(ctx):
         for k, ((lab, core), rec) in enumerate(zip(outs, recs)):
             assert sha(core.cpu().numpy().astype(np.uint8)) == rec["core_sha256"], f"instance {k}: core flags"
             assert sha(lab.cpu().numpy().astype("<i4")) == rec["labels_sha256"], f"instance {k}: labels"
+
+
+def test_batch_mixing_every_dimension(ctx):
+    """One batch holding instances of every d from 1 to 8 (the kernels run
+    for d = 8, shorter rows padded), eagerly, replayed from a graph, and with
+    the consumers walking the tree: every instance must be the oracle's."""
+    rng = np.random.default_rng(123)
+    problems = []
+    for k in range(24):
+        d = k % 8 + 1
+        n = int(rng.integers(1, 3000))
+        centres = rng.integers(0, 4000, size=(max(1, n // 60), d))
+        x = (centres[rng.integers(0, len(centres), size=n)] + rng.integers(-90, 91, size=(n, d))).astype(np.int32)
+        x[: n // 10] = rng.integers(0, 4000, size=(n // 10, d))
+        problems.append((x, int(rng.integers(20, 120)), int(rng.integers(2, 12))))
+    tens = [(torch.from_numpy(x.astype(np.float32)).cuda(), e, m) for x, e, m in problems]
+    for graph, mode in ((1, 0), (0, 2)):
+        import paper_2210_07580_amd as G
+        c = G.Context(0)
+        c.set_option(G.GD_OPT_GRAPH, graph)
+        c.set_option(G.GD_OPT_NEIGHBOR_MODE, mode)
+        for rep in range(2 if graph else 1):
+            print(f"case: d 1..8 batch, graph {graph} mode {mode} call {rep}", flush=True)
+            _check(c.dbscan_batched(tens), problems)
+            if graph:
+                assert c.stats()["graph_replays"] == rep
+        c.close()
